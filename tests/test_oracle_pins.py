@@ -1,0 +1,519 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test names the passage it pins and the independent fact used:
+a boundary-value problem solved numerically from its defining conditions,
+a textbook closed form (Kelvin image, charged hemispheres, induced charge),
+an independent library (scipy Legendre / spherical harmonics, numpy Philox),
+finite differences, or an exact dynamical invariant.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import oracle as O
+from paper_2111_13072_amd import workload as W
+
+RNG = np.random.default_rng(20211126)
+
+
+# --------------------------------------------------------------------------
+# Coefficients (Sec. 3 and App. A)
+# --------------------------------------------------------------------------
+
+def _green_bvp(l, eps, a, rp):
+    """Radial Green's function of App. A solved from its defining conditions:
+    d/dr(r^2 eps R') - eps l(l+1) R = -delta(r - r'), R(a) = 0, R -> 0 at
+    infinity, R and eps R' continuous at r = 1, unit jump at r'.  Returns the
+    coefficients (A2, B2) of A2 r^l + B2 r^-(l+1) on 1 < r < r'."""
+    # unknowns: A1, B1 (dielectric), A2, B2 (1<r<r'), B3 (r>r')
+    M = np.zeros((5, 5))
+    rhs = np.zeros(5)
+    M[0, 0], M[0, 1] = a**l, a ** (-l - 1)
+    M[1, :4] = [1, 1, -1, -1]
+    M[2, :4] = [eps * l, -eps * (l + 1), -l, (l + 1)]
+    M[3, 2], M[3, 3], M[3, 4] = rp**l, rp ** (-l - 1), -(rp ** (-l - 1))
+    # [R']_{r'-}^{r'+} = -1/r'^2
+    M[4, 2] = -l * rp ** (l - 1)
+    M[4, 3] = (l + 1) * rp ** (-l - 2)
+    M[4, 4] = -(l + 1) * rp ** (-l - 2)
+    rhs[4] = -1.0 / rp**2
+    s = np.linalg.solve(M, rhs)
+    return s[2], s[3]
+
+
+def _electrode_bvp(l, eps, a):
+    """psi_l of Sec. 3 from its conditions: psi(a) = 1, psi and eps psi'
+    continuous at r = 1, decay outside.  Returns C of psi = C r^-(l+1), r > 1."""
+    M = np.array([[a**l, a ** (-l - 1), 0.0],
+                  [1.0, 1.0, -1.0],
+                  [eps * l, -eps * (l + 1), (l + 1)]])
+    s = np.linalg.solve(M, np.array([1.0, 0.0, 0.0]))
+    return s[2]
+
+
+@pytest.mark.parametrize("eps,d", [(4.0, 0.25), (1.0, 0.25), (2.5, 0.1), (10.0, 0.4)])
+def test_image_coefficient_f_solves_radial_bvp(eps, d):
+    a = 1.0 - d
+    f, b, c = O.coeffs(eps, d, 24)
+    for l in range(0, 25):
+        for rp in (1.3, 2.7):
+            A2, B2 = _green_bvp(l, eps, a, rp)
+            # R^(p,p)_l = (1/(2l+1)) (r^l / r'^(l+1) - f_l / (r r')^(l+1))
+            assert A2 == pytest.approx(1.0 / ((2 * l + 1) * rp ** (l + 1)), rel=1e-12)
+            f_bvp = -B2 * (2 * l + 1) * rp ** (l + 1)
+            assert f[l] == pytest.approx(f_bvp, rel=1e-10, abs=1e-14)
+
+
+@pytest.mark.parametrize("eps,d", [(4.0, 0.25), (1.0, 0.25), (2.5, 0.1), (10.0, 0.4)])
+def test_electrode_coefficient_bP_solves_laplace_bvp(eps, d):
+    a = 1.0 - d
+    f, b, c = O.coeffs(eps, d, 24)
+    for l in range(0, 25):
+        assert b[l] == pytest.approx(_electrode_bvp(l, eps, a), rel=1e-11, abs=1e-15)
+
+
+@pytest.mark.parametrize("eps,d", [(4.0, 0.25), (2.5, 0.1), (10.0, 0.4)])
+def test_l0_image_cancels_floating_term(eps, d):
+    """G~ = P^G + Psi_sym(r)/(4 pi r') (Sec. 3): the l = 0 image -f_0/(r r')
+    cancels Psi_sym/(4 pi r') = b^P_0 / (4 pi r r') exactly, so the l = 0 part
+    of G~ is 1/(4 pi r_>) for any dielectric."""
+    a = 1.0 - d
+    _, B2 = _green_bvp(0, eps, a, 2.0)
+    f0 = -B2 * 2.0
+    assert f0 == pytest.approx(_electrode_bvp(0, eps, a), rel=1e-12)
+    p = O.Params(eps_r=eps, d=d, l_max=0)
+    for _ in range(5):
+        x = RNG.normal(size=3) * 2
+        y = RNG.normal(size=3) * 2
+        x *= (1 + RNG.random() * 3) / np.linalg.norm(x)
+        y *= (1 + RNG.random() * 3) / np.linalg.norm(y)
+        G, _ = O.greens(p, x, y)
+        assert G == pytest.approx(1.0 / (4 * math.pi * max(np.linalg.norm(x), np.linalg.norm(y))),
+                                  rel=1e-14)
+
+
+def test_limits_of_coefficients():
+    a = 0.75
+    f, b, _ = O.coeffs(1.0, 0.25, 30)
+    l = np.arange(31)
+    np.testing.assert_allclose(f, a ** (2 * l + 1), rtol=1e-14)   # Kelvin image
+    np.testing.assert_allclose(b, a ** (l + 1), rtol=1e-14)       # vacuum multipole
+    f, b, _ = O.coeffs(4.0, 0.0, 30)
+    np.testing.assert_allclose(f, 1.0, rtol=1e-14)                # no dielectric: grounded R = 1
+    np.testing.assert_allclose(b, 1.0, rtol=1e-14)
+
+
+def test_hemisphere_legendre_coefficients():
+    """c_l of Sec. 3 (Rodrigues-formula closed form with l = 2l' - 1) against
+    the Legendre coefficients of 1/2 sgn(cos th) computed two other ways."""
+    _, _, c = O.coeffs(4.0, 0.25, 41)
+    for l in range(0, 42):
+        if l % 2 == 0:
+            assert c[l] == 0.0
+            continue
+        via_p0 = 0.5 * (special.eval_legendre(l - 1, 0.0) - special.eval_legendre(l + 1, 0.0))
+        quad, _ = integrate.quad(lambda u: special.eval_legendre(l, u), 0.0, 1.0, limit=200)
+        via_quad = (2 * l + 1) / 2.0 * quad
+        assert c[l] == pytest.approx(via_p0, rel=1e-13, abs=1e-16)
+        assert c[l] == pytest.approx(via_quad, rel=1e-9, abs=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Green's function (Sec. 3, App. A)
+# --------------------------------------------------------------------------
+
+def _g_iso(x, y, a):
+    """Isolated uncharged conducting sphere of radius a (Kelvin image, App. A
+    mirror form, plus the neutralising centre charge of a floating sphere)."""
+    rx, ry = np.linalg.norm(x), np.linalg.norm(y)
+    return (1 / np.linalg.norm(x - y) - (a / ry) / np.linalg.norm(x - a * a / ry**2 * y)
+            + a / (rx * ry)) / (4 * math.pi)
+
+
+def _grad_fd(fun, x, h=1e-5):
+    return np.array([(fun(x + h * e) - fun(x - h * e)) / (2 * h) for e in np.eye(3)])
+
+
+def _random_point(rmin, rmax):
+    v = RNG.normal(size=3)
+    return v / np.linalg.norm(v) * (rmin + (rmax - rmin) * RNG.random())
+
+
+@pytest.mark.parametrize("L", [1, 2, 4, 8, 16, 32, 64])
+def test_kelvin_limit_of_truncated_kernel(L):
+    """eps_r = 1: G~_L -> G_iso as L grows, within the tail bound
+    (1/4 pi) sum_{l>L} [rho^l / r_> + a^(2l+1) / (r_x r_y)^(l+1)]."""
+    a = 0.75
+    p = O.Params(eps_r=1.0, d=0.25, l_max=L)
+    for _ in range(20):
+        x, y = _random_point(1.0, 5.0), _random_point(1.0, 5.0)
+        rx, ry = np.linalg.norm(x), np.linalg.norm(y)
+        rho = min(rx, ry) / max(rx, ry)
+        if rho > 0.9:
+            continue
+        w = a * a / (rx * ry)
+        ls = np.arange(L + 1, L + 400)
+        bound_G = (np.sum(rho**ls) / max(rx, ry) + a * np.sum(w**ls) / (rx * ry)) / (4 * math.pi)
+        G, g = O.greens(p, x, y)
+        assert abs(G - _g_iso(x, y, a)) <= bound_G * 1.0001 + 1e-15
+        # gradient: |P_l| <= 1, |P'_l| <= l(l+1)/2, |grad u| <= 1/r_x
+        rmin = min(rx, ry)
+        bound_g = (np.sum(rho**ls * ((ls + 1) / rmin + ls * (ls + 1) / (2 * rx))) / max(rx, ry)
+                   + a * np.sum(w**ls * ((ls + 1) / rx + ls * (ls + 1) / (2 * rx))) / (rx * ry)
+                   ) / (4 * math.pi)
+        g_iso = _grad_fd(lambda xx: _g_iso(xx, y, a), x, 1e-6)
+        assert np.max(np.abs(g - g_iso)) <= bound_g + 1e-8
+
+
+def test_kelvin_limit_converges_at_l64():
+    p = O.Params(eps_r=1.0, d=0.25, l_max=64)
+    x = np.array([0.0, 1.3, 0.9])
+    y = np.array([2.2, -0.5, 1.4])
+    G, _ = O.greens(p, x, y)
+    assert abs(G - _g_iso(x, y, 0.75)) < 1e-11
+
+
+@pytest.mark.parametrize("eps,d", [(4.0, 0.25), (10.0, 0.4)])
+def test_dielectric_kernel_is_kelvin_plus_legendre_image_shift(eps, d):
+    """G~_L(eps) - G~_L(eps=1) = -(1/4 pi) sum_{l=1..L} (f_l(eps) - a^(2l+1))
+    P_l(xhat.yhat) / (r_x r_y)^(l+1): the dielectric enters only through the
+    image coefficient (R^(p,p)_l, App. A), with P_l from scipy."""
+    L = 12
+    a = 1.0 - d
+    f, _, _ = O.coeffs(eps, d, L)
+    p_eps = O.Params(eps_r=eps, d=d, l_max=L)
+    p_vac = O.Params(eps_r=1.0, d=d, l_max=L)
+    for _ in range(20):
+        x, y = _random_point(1.0, 5.0), _random_point(1.0, 5.0)
+        rx, ry = np.linalg.norm(x), np.linalg.norm(y)
+        u = np.dot(x, y) / (rx * ry)
+        ls = np.arange(1, L + 1)
+        shift = -np.sum((f[1:] - a ** (2 * ls + 1)) * special.eval_legendre(ls, u)
+                        / (rx * ry) ** (ls + 1)) / (4 * math.pi)
+        Ge, _ = O.greens(p_eps, x, y)
+        Gv, _ = O.greens(p_vac, x, y)
+        assert Ge - Gv == pytest.approx(shift, rel=1e-11, abs=1e-15)
+
+
+def test_addition_theorem_against_scipy_harmonics():
+    """P_l(xhat.yhat) = (4 pi/(2l+1)) sum_m Y*_lm(xhat) Y_lm(yhat) (the step
+    from the Y_lm series of G to the Legendre form), using scipy's Y_lm, read
+    off through the oracle's eps = 1 kernel at single l."""
+    for _ in range(5):
+        x, y = _random_point(1.0, 5.0), _random_point(1.0, 5.0)
+        rx, ry = np.linalg.norm(x), np.linalg.norm(y)
+        tx, px = math.acos(x[2] / rx), math.atan2(x[1], x[0])
+        ty, py = math.acos(y[2] / ry), math.atan2(y[1], y[0])
+        prev = 0.0
+        for L in range(0, 9):
+            G, _ = O.greens(O.Params(eps_r=1.0, d=0.25, l_max=L), x, y, x_outer=rx > ry)
+            term = G - prev
+            prev = G
+            m = np.arange(-L, L + 1)
+            s = np.sum(np.conj(special.sph_harm_y(L, m, tx, px)) * special.sph_harm_y(L, m, ty, py)).real
+            radial = min(rx, ry) ** L / max(rx, ry) ** (L + 1)
+            if L >= 1:
+                radial -= 0.75 ** (2 * L + 1) / (rx * ry) ** (L + 1)
+            assert term == pytest.approx(radial * s / (2 * L + 1), rel=1e-10, abs=1e-14)
+
+
+def test_axisymmetric_kernel_is_azimuthal_average():
+    """m = 0 projection (Sec. 3 dipole kernel) = average of the full kernel over
+    rotations of one argument about the probe axis (only m = 0 survives)."""
+    L = 7
+    for eps in (1.0, 4.0):
+        pf = O.Params(eps_r=eps, l_max=L, m_mode=O.M_FULL)
+        pa = O.Params(eps_r=eps, l_max=L, m_mode=O.M_AXISYM)
+        for _ in range(5):
+            x, y = _random_point(1.0, 5.0), _random_point(1.0, 5.0)
+            outer = np.linalg.norm(x) > np.linalg.norm(y)
+            nphi = 4 * L + 8
+            acc, gacc = 0.0, np.zeros(3)
+            for j in range(nphi):
+                ph = 2 * math.pi * j / nphi
+                R = np.array([[math.cos(ph), -math.sin(ph), 0], [math.sin(ph), math.cos(ph), 0],
+                              [0, 0, 1]])
+                G, g = O.greens(pf, x, R @ y, outer)
+                acc += G / nphi
+                gacc += g / nphi
+            Ga, ga = O.greens(pa, x, y, outer)
+            assert Ga == pytest.approx(acc, rel=1e-12, abs=1e-15)
+            np.testing.assert_allclose(ga, gacc, rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("mode", [O.M_FULL, O.M_AXISYM])
+def test_kernel_gradient_matches_finite_differences(mode):
+    p = O.Params(eps_r=4.0, l_max=10, m_mode=mode)
+    for _ in range(20):
+        x, y = _random_point(1.0, 5.0), _random_point(1.0, 5.0)
+        if abs(np.linalg.norm(x) - np.linalg.norm(y)) < 0.05:
+            continue
+        outer = np.linalg.norm(x) > np.linalg.norm(y)
+        _, g = O.greens(p, x, y, outer)
+        gfd = _grad_fd(lambda xx: O.greens(p, xx, y, outer)[0], x, 1e-6)
+        np.testing.assert_allclose(g, gfd, rtol=1e-6, atol=1e-9)
+
+
+def test_kernel_is_symmetric():
+    p = O.Params(eps_r=4.0, l_max=9)
+    for _ in range(10):
+        x, y = _random_point(1.0, 5.0), _random_point(1.0, 5.0)
+        assert O.greens(p, x, y)[0] == pytest.approx(O.greens(p, y, x)[0], rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Electrode drive and readout (Sec. 3, Sec. 4, App. C)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("z", [1.0, 1.5, 3.0, -1.2])
+def test_hemisphere_drive_on_axis_vacuum(z):
+    """eps_r = 1: Psi_anti on the axis equals the potential of two hemispheres
+    at +-1/2: (sgn z / 2) [1 - (z^2 - a^2) / (|z| sqrt(z^2 + a^2))], within the
+    alternating-series tail bound."""
+    a = 0.75
+    for L in (1, 3, 9, 21, 61):
+        p = O.Params(eps_r=1.0, d=0.25, l_max=L)
+        psi, _ = O.psi_anti(p, [0.0, 0.0, z])
+        az = abs(z)
+        exact = math.copysign(0.5, z) * (1 - (az * az - a * a) / (az * math.sqrt(az * az + a * a)))
+        _, _, c = O.coeffs(1.0, 0.25, L + 2)
+        bound = abs(c[L + 2]) * (a / az) ** (L + 3) if L % 2 == 1 else 1.0
+        assert abs(psi - exact) <= bound * 1.0001 + 1e-15
+
+
+def _psi_anti_quadrature(x, a):
+    """Exterior Dirichlet problem of a sphere (Poisson integral) with boundary
+    data +1/2 on the upper and -1/2 on the lower hemisphere."""
+    r = np.linalg.norm(x)
+
+    def integrand(ph, th):
+        xs = a * np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        dist = np.linalg.norm(x - xs)
+        return math.sin(th) * a * (r * r - a * a) / (4 * math.pi * dist**3)
+
+    up, _ = integrate.dblquad(integrand, 0, math.pi / 2, 0, 2 * math.pi, epsabs=1e-12, epsrel=1e-11)
+    lo, _ = integrate.dblquad(integrand, math.pi / 2, math.pi, 0, 2 * math.pi, epsabs=1e-12,
+                              epsrel=1e-11)
+    return 0.5 * up - 0.5 * lo, up, lo
+
+
+def test_hemisphere_drive_off_axis_vacuum():
+    a = 0.75
+    p = O.Params(eps_r=1.0, d=0.25, l_max=81)
+    for x in (np.array([0.8, 0.3, 0.7]), np.array([-1.5, 1.0, -0.4])):
+        psi, _ = O.psi_anti(p, x)
+        q, _, _ = _psi_anti_quadrature(x, a)
+        assert psi == pytest.approx(q, abs=2e-9)
+
+
+def test_readout_matches_induced_hemisphere_charge():
+    """Q_diff = -(1/nt) sum q Psi_anti (Sec. 4) against the charge induced on
+    each hemisphere of a conducting sphere by a point charge (vacuum, Green's
+    reciprocity): surface density -q (r^2 - a^2) / (4 pi a |x - x'|^3).  The
+    neutralising charge of a floating sphere is uniform and cancels in
+    (Q_1 - Q_2)/2."""
+    a = 0.75
+    p = O.Params(eps_r=1.0, d=0.25, l_max=81, ntilde=1.0)
+    for x in (np.array([0.4, -0.2, 1.1]), np.array([1.0, 1.0, -0.6]), np.array([0.0, 0.3, 2.5])):
+        r = np.linalg.norm(x)
+        q = -1.0
+
+        def sigma_area(ph, th):
+            xs = a * np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+            dist = np.linalg.norm(x - xs)
+            return -q * (r * r - a * a) / (4 * math.pi * a * dist**3) * a * a * math.sin(th)
+
+        q1, _ = integrate.dblquad(sigma_area, 0, math.pi / 2, 0, 2 * math.pi, epsabs=1e-12,
+                                  epsrel=1e-11)
+        q2, _ = integrate.dblquad(sigma_area, math.pi / 2, math.pi, 0, 2 * math.pi, epsabs=1e-12,
+                                  epsrel=1e-11)
+        assert q1 + q2 == pytest.approx(-q * a / r, rel=1e-9)  # total image charge
+        qd = O.qdiff(p, x[None, :])
+        assert qd == pytest.approx(0.5 * (q1 - q2), abs=2e-9)
+
+
+# --------------------------------------------------------------------------
+# Many-particle field (Sec. 2 Hamiltonian, Sec. 4 equations of motion)
+# --------------------------------------------------------------------------
+
+def _shell(n, seed, r_out=5.0, v=0.08):
+    st = W.uniform_shell(n, seed, r_out, v)
+    return st.pos, st.vel
+
+
+@pytest.mark.parametrize("mode", [O.M_FULL, O.M_AXISYM])
+def test_field_is_minus_gradient_of_potential(mode):
+    pos, _ = _shell(60, 11)
+    p = O.Params(l_max=6, m_mode=mode, ntilde=2.5, ion_density=0.7)
+    qs, u = -3.0, 0.4
+    E, _ = O.field(p, pos, q_surface=qs, u_asy=u)
+    r = np.linalg.norm(pos, axis=1)
+    checked = 0
+    for k in range(0, 60, 6):
+        gaps = np.abs(np.delete(r, k) - r[k])
+        if gaps.min() < 1e-3:
+            continue
+
+        def phi_at(xk):
+            pp = pos.copy()
+            pp[k] = xk
+            return O.field(p, pp, q_surface=qs, u_asy=u, targets=[k])[1][0]
+
+        gfd = _grad_fd(phi_at, pos[k], 1e-6)
+        np.testing.assert_allclose(E[k], -gfd, rtol=1e-6, atol=1e-8)
+        checked += 1
+    assert checked >= 5
+
+
+def test_field_superposes_single_pair_kernel_and_excludes_self():
+    pos, _ = _shell(12, 3)
+    p = O.Params(l_max=5, ntilde=3.0, ion_density=0.0)
+    alive = np.ones(12, np.uint8)
+    alive[4] = 0
+    E, _ = O.field(p, pos, alive=alive)
+    for k in (0, 7):
+        acc = np.zeros(3)
+        for i in range(12):
+            if i == k or not alive[i]:
+                continue
+            _, g = O.greens(p, pos[k], pos[i], np.dot(pos[k], pos[k]) > np.dot(pos[i], pos[i]))
+            acc += -(-1.0) * g / 3.0     # E = -(1/nt) q grad G~, q = -1
+        np.testing.assert_allclose(E[k], acc, rtol=1e-13, atol=1e-16)
+    assert np.all(E[4] == 0)
+
+
+def test_surface_charge_acts_as_centre_charge():
+    """Q_S / (4 pi eps0 r) (Sec. 3): with only l = 0, Q_S on the probe
+    surface pushes like Q_S particles inside the target's radius."""
+    p = O.Params(l_max=0, ntilde=2.0, ion_density=0.0)
+    target = np.array([[0.3, 2.0, -1.0]])
+    E_qs, _ = O.field(p, target, q_surface=-5.0)
+    inner = np.array([[1.01, 0, 0], [-1.01, 0, 0], [0, 1.01, 0], [0, -1.01, 0], [0, 0, 1.01]])
+    E_p, _ = O.field(p, np.vstack([target, inner]), targets=[0])
+    np.testing.assert_allclose(E_qs[0], E_p[0], rtol=1e-13)
+
+
+def _fit_frequency(t, y, w0):
+    from scipy.optimize import curve_fit
+
+    def f(t, a, w, ph, c):
+        return a * np.sin(w * t + ph) + c
+
+    popt, _ = curve_fit(f, t, y, p0=[np.ptp(y) / 2, w0, 0.0, y.mean()])
+    return popt[1]
+
+
+def test_bulk_plasma_oscillation_cold_shell():
+    """Cold uniform shell with unit ion background (L = 0): every shell
+    oscillates at omega_pe = 1 (Sec. 4 units); leapfrog turns this into
+    (2/dt) asin(dt/2).  Particles are placed at the radii enclosing k + 1/2
+    super-particles and Q_S = -1/2 so the unperturbed state is force-free;
+    this pins the 1/nt scaling, the ion background, Q_S and the pusher."""
+    n, r_out, dt = 1500, 5.0, 0.05
+    nt = W.ntilde_for(n, r_out)
+    st = W.quantile_shell(n, 7, r_out, nt, amplitude=0.01)
+    p = O.Params(ntilde=nt, l_max=0, probe_bc=O.BC_SPECULAR, wall_bc=O.BC_SPECULAR, dt=dt)
+    pos, vel, qs = st.pos.copy(), st.vel.copy(), -0.5
+    track = [100, 700, 1300]
+    nsteps = 300
+    u = np.zeros(nsteps)
+    rs = []
+    for s in range(nsteps):
+        res = O.run(p, pos, vel, u, 1, q_surface=qs, start_step=s)
+        pos, vel, qs = res.pos, res.vel, res.q_surface
+        rs.append(np.linalg.norm(pos[track], axis=1))
+    rs = np.array(rs)
+    t = np.arange(1, nsteps + 1) * dt
+    expect = 2.0 / dt * math.asin(dt / 2)
+    for j in range(len(track)):
+        assert _fit_frequency(t, rs[:, j], 1.0) == pytest.approx(expect, abs=1e-3)
+
+
+@pytest.mark.parametrize("mode", [O.M_FULL, O.M_AXISYM])
+def test_energy_error_is_second_order(mode):
+    """Hamiltonian of Sec. 2 (scaled as in Sec. 4) with a constant drive, a
+    surface charge and an ion background: away from radial crossings and
+    walls the leapfrog energy error falls 4x per halving of dt.  A force that
+    is not exactly minus the gradient of H (a wrong sign or factor in any
+    term) leaves an O(1) drift that does not converge."""
+    pos = np.array([[1.5, 0.3, 0.2], [0.1, -3.0, 1.0], [2.0, 2.0, -2.5], [-1.0, 3.5, 0.5]])
+    vel = np.array([[0.05, 0.1, 0.0], [-0.1, 0.0, 0.05], [0.0, 0.1, 0.1], [0.1, 0.0, -0.1]])
+    order0 = np.argsort(np.linalg.norm(pos, axis=1))
+    errs = []
+    for dt in (0.04, 0.02, 0.01):
+        p = O.Params(ntilde=2.0, l_max=3, m_mode=mode, ion_density=0.3, dt=dt,
+                     probe_bc=O.BC_SPECULAR, wall_bc=O.BC_SPECULAR)
+        nsteps = int(round(2.0 / dt))
+        u = np.full(nsteps, 0.5)
+        x, v = pos.copy(), vel.copy()
+        hs = []
+        for s in range(nsteps):
+            res = O.run(p, x, v, u, 1, start_step=s, q_surface=-1.0)
+            v2 = 0.5 * (np.sum(v * v, axis=1) + np.sum(res.vel * res.vel, axis=1))
+            hs.append(O.energy(p, x, v2, q_surface=-1.0, u_asy=0.5)[0])
+            x, v = res.pos, res.vel
+            r = np.linalg.norm(x, axis=1)
+            assert np.all(np.argsort(r) == order0) and r.min() > 1.0 and r.max() < p.r_out
+        errs.append(np.max(np.abs(np.array(hs) - hs[0])))
+    assert 3.6 < errs[0] / errs[1] < 4.4
+    assert 3.6 < errs[1] / errs[2] < 4.4
+
+
+# --------------------------------------------------------------------------
+# Boundaries (Sec. 4) and the counter-based generator
+# --------------------------------------------------------------------------
+
+def _free_params(**kw):
+    base = dict(l_max=0, ntilde=1e30, ion_density=0.0, dt=0.1, r_out=5.0)  # no forces
+    base.update(kw)
+    return O.Params(**base)
+
+
+def test_specular_wall_reflection_of_free_particle():
+    p = _free_params()
+    pos = np.array([[0.0, 0.6, 4.9]])
+    vel = np.array([[0.3, 0.0, 2.0]])
+    res = O.run(p, pos, vel, np.zeros(1), 1)
+    x1 = pos[0] + vel[0] * p.dt
+    r1 = np.linalg.norm(x1)
+    np.testing.assert_allclose(np.linalg.norm(res.pos[0]), 2 * p.r_out - r1, rtol=1e-14)
+    np.testing.assert_allclose(res.pos[0] / np.linalg.norm(res.pos[0]), x1 / r1, rtol=1e-14)
+    n = x1 / r1
+    np.testing.assert_allclose(res.vel[0], vel[0] - 2 * np.dot(vel[0], n) * n, rtol=1e-14)
+
+
+def test_probe_absorbs_and_charges_surface():
+    p = _free_params(probe_bc=O.BC_ABSORB)
+    pos = np.array([[0.0, 0.0, 1.05], [0.0, 2.0, 0.0]])
+    vel = np.array([[0.0, 0.0, -1.0], [0.0, 0.0, 0.0]])
+    res = O.run(p, pos, vel, np.zeros(1), 1, q_surface=-2.0)
+    assert list(res.alive) == [0, 1]
+    assert res.q_surface == -3.0
+    assert res.absorbed == 1
+
+
+def test_diffuse_reflection_keeps_speed_and_points_inward():
+    p = _free_params(wall_bc=O.BC_DIFFUSE, probe_bc=O.BC_DIFFUSE, seed=99)
+    pos = np.array([[0.0, 0.6, 4.9], [1.02, 0.0, 0.0]])
+    vel = np.array([[0.3, 0.0, 2.0], [-0.5, 0.2, 0.0]])
+    res = O.run(p, pos, vel, np.zeros(1), 1)
+    np.testing.assert_allclose(np.linalg.norm(res.vel, axis=1), np.linalg.norm(vel, axis=1),
+                               rtol=1e-14)
+    assert np.dot(res.vel[0], res.pos[0]) < 0      # back inside from the wall
+    assert np.dot(res.vel[1], res.pos[1]) > 0      # away from the probe
+
+
+@pytest.mark.parametrize("key,ctr", [((0, 0), (0, 0, 0, 0)), ((12345, 0), (7, 3, 1, 0)),
+                                     ((2**63 + 5, 2**40), (2**64 - 1, 2**64 - 1, 5, 0))])
+def test_philox4x64_10_matches_numpy(key, ctr):
+    """numpy's Philox bit generator is Philox-4x64-10; its first block is
+    the cipher of counter + 1."""
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(ctr, dtype=np.uint64))
+    raw = bg.random_raw(4)
+    v = sum(int(w) << (64 * i) for i, w in enumerate(ctr)) + 1
+    c = [(v >> (64 * i)) & (2**64 - 1) for i in range(4)]
+    np.testing.assert_array_equal(O.philox4x64_10(c, key), raw)
