@@ -1,0 +1,171 @@
+/*
+ * mrpsim — spectral kinetic simulation of the ideal Multipole Resonance Probe
+ * (Gong, Friedrichs, Oberrath, Brinkmann, arXiv:2111.13072) on one MI355X.
+ *
+ * C ABI of the HIP library libmrpsim.so.  Plain pointers and sizes only.
+ *
+ * Units are the paper's dimensionless ones (Sec. 4): lengths in the probe
+ * radius R, times in 1/omega_pe, charges in e, masses in m_e, densities in
+ * n_inf, potentials in e n_inf R^2 / eps0.  The particles are electrons
+ * (q = -1, m = 1); the ions are an immobile uniform background.
+ *
+ * Error convention: every int-returning call returns SIM_OK (0) or a
+ * negative SIM_E* code; no exception crosses the ABI.  A handle whose device
+ * work failed enters a failed state and answers SIM_ESTATE afterwards.
+ * sim_last_error() gives a human-readable message for the calling thread.
+ *
+ * Threading: one handle must not be used from two threads at once; distinct
+ * handles are independent.
+ */
+#ifndef MRPSIM_H
+#define MRPSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim sim_t;
+
+enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,   /* invalid parameter or particle state */
+    SIM_ENOMEM = -2,   /* device allocation failed or mem_limit_bytes exceeded */
+    SIM_ERANGE = -3,   /* step or response index outside [0, n_steps) */
+    SIM_ESTATE = -4,   /* NULL, destroyed or failed handle */
+    SIM_EDEVICE = -5   /* a HIP runtime call failed */
+};
+
+enum { SIM_M_FULL = 0, SIM_M_AXISYM = 1 };
+enum { SIM_BC_ABSORB = 0, SIM_BC_SPECULAR = 1, SIM_BC_DIFFUSE = 2 };
+enum { SIM_FP64 = 0, SIM_FP32_COMP = 1 };
+
+/*
+ * Simulation parameters.
+ *   d, eps_r    dielectric cover: thickness / R and permittivity; the
+ *               electrodes have radius a = 1 - d (Sec. 2).
+ *   r_out       outer wall of the particle domain (units of R); the field
+ *               domain itself is unbounded (potential -> 0 at infinity).
+ *   dt          leapfrog time step (units of 1/omega_pe).
+ *   ntilde      super-particles per unit volume R^3 (Sec. 4).
+ *   ion_density immobile uniform ion background filling 1 < r < r_out.
+ *   q_surface0  initial homogeneous surface charge Q_S (units of the
+ *               super-particle charge; absorbed electrons add -1 each).
+ *   l_max       truncation of the projection P^: 0 <= l <= l_max (Sec. 3).
+ *   m_mode      SIM_M_FULL: all m; SIM_M_AXISYM: m = 0 only (the paper's
+ *               dipole kernel of Sec. 3 is l_max = 1, SIM_M_AXISYM).
+ *   probe_bc    at r <= 1: absorb (charge goes to Q_S), specular or diffuse.
+ *   wall_bc     at r >= r_out: specular or diffuse.
+ *   precision   SIM_FP64, or SIM_FP32_COMP (FP32 terms with FP64 radial
+ *               scans and positions).
+ *   tile        particles per tile of the radial scan (0 = choose).
+ *   seed        key of the counter-based generator of diffuse walls.
+ *   mem_limit_bytes  0 = none; otherwise sim_create fails with SIM_ENOMEM
+ *               when sim_footprint_bytes exceeds it.
+ */
+typedef struct {
+    uint32_t struct_size; /* sizeof(sim_params) */
+    uint32_t reserved0;
+    double d;
+    double eps_r;
+    double r_out;
+    double dt;
+    double ntilde;
+    double ion_density;
+    double q_surface0;
+    int32_t l_max;
+    int32_t m_mode;
+    int32_t probe_bc;
+    int32_t wall_bc;
+    int32_t precision;
+    int32_t tile;
+    uint64_t seed;
+    uint64_t mem_limit_bytes;
+} sim_params;
+
+/* Fill *p with the defaults (d = 0.25, eps_r = 4, r_out = 5, dt = 0.05,
+ * ntilde = 1, ion_density = 1, l_max = 8, FULL, absorb / specular, FP64). */
+void sim_params_default(sim_params *p);
+
+/*
+ * Create a simulation and upload its state.
+ *   n          number of electrons (> 0).
+ *   pos, vel   host arrays [3n], particle-major (x0,y0,z0,x1,...); vel is the
+ *              leapfrog half-step velocity v(t_start - dt/2).  Every particle
+ *              must satisfy 1 < r < r_out.  Copied; the caller keeps them.
+ *   ids        host array [n] of distinct ids, or NULL for 0..n-1.  Ids break
+ *              ties of equal radius in the radial order (key (r^2, id)).
+ *   u_asy      host array [n_steps]: antisymmetric electrode voltage
+ *              u_1 - u_2 at t_s = s dt (Sec. 3); copied.
+ *   start_step first step to run (checkpoint resume); 0 <= start_step <= n_steps.
+ *   hip_stream hipStream_t to run on, or NULL for a stream of the handle's own.
+ * Returns SIM_EINVAL for invalid parameters or particles, SIM_ENOMEM when the
+ * footprint exceeds mem_limit_bytes or an allocation fails.
+ */
+int sim_create(const sim_params *p, int64_t n, const double *pos, const double *vel,
+               const uint32_t *ids, const double *u_asy, int64_t n_steps, int64_t start_step,
+               void *hip_stream, sim_t **out);
+
+/*
+ * Enqueue k time steps (asynchronous, on the handle's stream).  One step is
+ * the scheme of Sec. 3-4: radial sort, harmonic moments, prefix/suffix scans,
+ * boundary response + drive, field and leapfrog push with the wall rules;
+ * Q_diff(t_s) (Sec. 4) is recorded before the push.  SIM_ERANGE if the steps
+ * would pass n_steps.
+ */
+int sim_step(sim_t *h, int64_t k);
+
+/* Wait for all enqueued work of the handle. */
+int sim_sync(sim_t *h);
+
+/*
+ * Copy Q_diff[first .. first+count) to host (synchronises).  Q_diff(t_s) =
+ * -(1/ntilde) sum_i q_i Psi_anti,L(x_i(t_s)) (Sec. 4, odd l <= l_max), in
+ * units of e n_inf R^3.  SIM_ERANGE if any index is not yet computed.
+ */
+int sim_read_response(sim_t *h, int64_t first, int64_t count, double *q_diff);
+
+/*
+ * Copy the state at the current step boundary to host (synchronises), in the
+ * order of the arrays given to sim_create.  pos/vel [3n] (vel = v at t - dt/2),
+ * alive [n] (0 = absorbed; its pos/vel are those at absorption), q_surface
+ * and step may each be NULL.
+ */
+int sim_read_state(sim_t *h, double *pos, double *vel, uint8_t *alive, double *q_surface,
+                   int64_t *step);
+
+/*
+ * Electric field E = -grad Phi at every alive particle for the current state
+ * and step (Sec. 3 modified potential, truncated at l_max), in the order of
+ * the creation arrays, [3n]; zero for absorbed particles.  Does not advance
+ * the simulation.  Synchronises.
+ */
+int sim_eval_field(sim_t *h, double *E);
+
+/*
+ * Run k steps with a HIP event around every kernel and return the average
+ * duration in milliseconds of each kernel kind (indices as sim_kernel_name).
+ * kernel_ms has n_kernels entries; entries beyond sim_num_kernels() are left
+ * untouched.  Advances the simulation by k steps.
+ */
+int sim_profile(sim_t *h, int64_t k, double *kernel_ms, int32_t n_kernels);
+int32_t sim_num_kernels(void);
+const char *sim_kernel_name(int32_t i);
+
+/* Device bytes sim_create would allocate (for admission control); < 0 on
+ * invalid parameters. */
+int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps);
+
+/* Particle count, tile size and channel count actually used. */
+int sim_info(sim_t *h, int64_t *n, int32_t *tile, int32_t *channels);
+
+void sim_destroy(sim_t *h);
+const char *sim_strerror(int status);
+const char *sim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRPSIM_H */

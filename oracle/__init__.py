@@ -12,7 +12,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB, build as build_library
 
 M_FULL, M_AXISYM = 0, 1
 BC_ABSORB, BC_SPECULAR, BC_DIFFUSE = 0, 1, 2
@@ -53,7 +53,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
-            build()
+            build_library()
         L = C.CDLL(LIB)
         dp = C.POINTER(C.c_double)
         P = C.POINTER(_Params)

@@ -309,8 +309,11 @@ int orc_field(const orc_params *p, int64_t n, const double *pos, const uint32_t 
         }
         const double *xk = pos + 3 * k;
         double r2k = key_r2(xk);
-        double gsum[3] = {0.0, 0.0, 0.0};
-        double phi = 0.0;
+        /* Extended-precision accumulators keep the oracle's own rounding far
+         * below the parity tolerance when ~1e6 pair terms cancel against the
+         * ion background. */
+        long double gsum[3] = {0.0L, 0.0L, 0.0L};
+        long double phi = 0.0L;
         for (int64_t i = 0; i < n; ++i) {
             if (i == k) continue;
             if (alive && !alive[i]) continue;
@@ -328,10 +331,13 @@ int orc_field(const orc_params *p, int64_t n, const double *pos, const uint32_t 
         double e_surf = inv_nt * q_surface / (4.0 * ORC_PI * rk * rk);
         double e_ion = eion_r(p, rk);
         for (int j = 0; j < 3; ++j)
-            E[j] = -inv_nt * gsum[j] + (e_surf + e_ion) * xh[j] - u_asy * gpsi[j];
+            E[j] = (double)(-(long double)inv_nt * gsum[j] +
+                            (long double)((e_surf + e_ion) * xh[j]) -
+                            (long double)(u_asy * gpsi[j]));
         if (phi_out)
-            phi_out[t] = inv_nt * phi + inv_nt * q_surface / (4.0 * ORC_PI * rk) +
-                         phi_ion(p, rk) + u_asy * psi;
+            phi_out[t] = (double)((long double)inv_nt * phi +
+                                  (long double)(inv_nt * q_surface / (4.0 * ORC_PI * rk)) +
+                                  (long double)phi_ion(p, rk) + (long double)(u_asy * psi));
     }
     return 0;
 }

@@ -1,0 +1,1489 @@
+// mrpsim: spectral kinetic simulation of the ideal Multipole Resonance Probe
+// (Gong, Friedrichs, Oberrath, Brinkmann, arXiv:2111.13072) on one MI355X
+// (gfx950).  C ABI declared in include/mrpsim.h.
+//
+// One time step (Sec. 3 field solver + Sec. 4 pusher) runs as these kernels:
+//   sort:    key (r^2, id) -> bucket histogram -> bucket offsets -> scatter
+//            -> exact rank inside each bucket -> permuted SoA copy
+//   moments: per tile of 64 radially consecutive particles, the sums of
+//            q R_lm (regular solid harmonics) and q I_lm (irregular ones)
+//   carries: exclusive prefix of the interior sums and exclusive suffix of
+//            the exterior sums over tiles, totals T_lm, the boundary (image)
+//            response, the surface charge, the hemisphere drive and Q_diff
+//   field:   per particle, the far field of all other tiles from the tile's
+//            coefficient vector, the near field of its own tile pair by pair,
+//            the self-image correction and the ion background; then the
+//            leapfrog kick/drift and the wall rules
+// All work is on the handle's stream; one step is captured once into a HIP
+// graph and replayed.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mrpsim.h"
+
+namespace {
+
+constexpr double kQ = -1.0;   // electron charge, units of e (Sec. 4)
+constexpr double kM = 1.0;    // electron mass, units of m_e
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxL = 64;
+constexpr int kChunk = 64;        // tiles per chunk of the carry scan
+constexpr int kScanPerBlock = 1024;  // histogram entries per block of the bucket scan
+constexpr int kBucketOccupancy = 8;  // mean particles per sort bucket
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+// ---------------------------------------------------------------------------
+// Device-side structures
+// ---------------------------------------------------------------------------
+
+struct State {
+    double *x, *y, *z, *vx, *vy, *vz;
+    uint32_t *uid;
+};
+
+// Control block in device memory.
+struct Ctl {
+    int64_t step;       // absolute step of the state held in A
+    uint32_t n_cur;     // records in A (some may be flagged absorbed)
+    uint32_t n_live;    // alive particles sorted into B this step
+    uint32_t n_dead;    // particles absorbed so far (graveyard fill)
+    uint32_t pad;
+    double q_surface;   // Q_S used by this step's field
+};
+
+// Per-l and per-(l, m) constant tables (host-computed, read-only).
+struct Tables {
+    const double *ftil;     // image coefficient f_l, with f_0 = 0 (floating probe)
+    const double *wl;       // 1 / ((2l+1) ntilde)
+    const double *drive_w;  // c_l b^P_l sqrt(4 pi / (2l+1)) for odd l, else 0
+    const double *self_w;   // f_l / (4 pi ntilde)
+    const double *nfA;      // (2l+1)/(l+1)
+    const double *nfB;      // l/(l+1)
+    const double *qmm;      // sectoral normalisation Q_m^m
+    const double *alm;      // Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m
+    const double *blm;
+};
+
+struct KParams {
+    int L;          // l_max
+    int C;          // channels: (L+1)^2 (full) or L+1 (axisymmetric)
+    int C2;         // 2C: interior then exterior
+    int n_tiles;
+    int n_chunks;
+    int nb;         // sort buckets
+    int probe_bc, wall_bc;
+    double dt, r_out, ntilde, ion_density, q_surface0, inv_vol;
+    uint64_t seed;
+    int64_t n_steps;
+};
+
+__host__ __device__ inline int tri(int l, int m) { return l * (l + 1) / 2 + m; }
+
+// Channel index of (l, m, cos|sin) in the full basis; m = 0 has only cos.
+__host__ __device__ inline int chan_full(int l, int m, int sin_part)
+{
+    return m == 0 ? l * l : l * l + 2 * m - 1 + sin_part;
+}
+
+__device__ inline double sum_wave(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ inline uint32_t uniform_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// r^2 as (x*x + y*y) + z*z without contraction: the exact radial sort key.
+__device__ inline double key_r2(double x, double y, double z)
+{
+    return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
+}
+
+// ---------------------------------------------------------------------------
+// Sort: exact order by (r^2, id) through volume-uniform buckets
+// ---------------------------------------------------------------------------
+
+__global__ void k_sort_clear(uint32_t *hist, uint32_t *cursor, int nb)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= nb) hist[i] = 0;
+    if (i < nb) cursor[i] = 0;
+}
+
+__global__ void k_sort_key(const Ctl *ctl, State A, const uint8_t *dead, uint64_t *key,
+                           uint32_t *bkt, uint32_t *hist, KParams kp)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ctl->n_cur) return;
+    if (dead[i]) {
+        bkt[i] = 0xffffffffu;
+        return;
+    }
+    double r2 = key_r2(A.x[i], A.y[i], A.z[i]);
+    key[i] = (uint64_t)__double_as_longlong(r2);
+    // Monotone non-decreasing map of r^2 to [0, nb): enclosed shell volume.
+    double t = (r2 * sqrt(r2) - 1.0) * kp.inv_vol * (double)kp.nb;
+    int b;
+    if (!(t > 0.0)) b = 0;
+    else if (!(t < (double)(kp.nb - 1))) b = kp.nb - 1;
+    else b = (int)t;
+    bkt[i] = (uint32_t)b;
+    atomicAdd(&hist[b], 1u);
+}
+
+// Exclusive scan of a u32 array of length n into out[0..n], out[n] = total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[kWavesPerBlock];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int k = 0; k < kWavesPerBlock; ++k) {
+        if (k < w) off += wsum[k];
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_a(const uint32_t *in, uint32_t *bsum, int n)
+{
+    const int base = blockIdx.x * kScanPerBlock;
+    uint32_t s = 0;
+    for (int k = threadIdx.x; k < kScanPerBlock; k += kBlock) {
+        int i = base + k;
+        if (i < n) s += in[i];
+    }
+    uint32_t tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_b(uint32_t *bsum, int nblocks, Ctl *ctl)
+{
+    uint32_t carry = 0;
+    for (int base = 0; base < nblocks; base += kBlock) {
+        int i = base + threadIdx.x;
+        uint32_t v = i < nblocks ? bsum[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan(v, &tot);
+        if (i < nblocks) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) ctl->n_live = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_c(const uint32_t *in, const uint32_t *bsum,
+                                                   uint32_t *out, int n)
+{
+    constexpr int per = kScanPerBlock / kBlock;
+    const int base = blockIdx.x * kScanPerBlock + threadIdx.x * per;
+    uint32_t v[per];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = bsum[blockIdx.x] + block_exclusive_scan(s, &tot);
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+        if (base + k == n - 1) out[n] = run;
+    }
+}
+
+__global__ void k_sort_scatter(const Ctl *ctl, const uint32_t *bkt, const uint32_t *off,
+                               uint32_t *cursor, uint32_t *tmp)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ctl->n_cur) return;
+    uint32_t b = bkt[i];
+    if (b == 0xffffffffu) return;
+    uint32_t slot = off[b] + atomicAdd(&cursor[b], 1u);
+    tmp[slot] = i;
+}
+
+// Final position = bucket start + number of bucket mates with a smaller
+// (r^2, id) key; independent of the order the scatter produced.
+__global__ void k_sort_rank(const Ctl *ctl, const uint64_t *key, const uint32_t *uid,
+                            const uint32_t *bkt, const uint32_t *off, const uint32_t *tmp,
+                            uint32_t *perm)
+{
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ctl->n_live) return;
+    uint32_t i = tmp[p];
+    uint32_t b = bkt[i];
+    uint32_t lo = off[b], hi = off[b + 1];
+    uint64_t k = key[i];
+    uint32_t u = uid[i];
+    uint32_t rank = 0;
+    for (uint32_t j = lo; j < hi; ++j) {
+        uint32_t o = tmp[j];
+        uint64_t ko = key[o];
+        rank += (ko < k) || (ko == k && uid[o] < u);
+    }
+    perm[lo + rank] = i;
+}
+
+__global__ void k_sort_permute(const Ctl *ctl, const uint32_t *perm, State A, State B)
+{
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ctl->n_live) return;
+    uint32_t i = perm[p];
+    B.x[p] = A.x[i];
+    B.y[p] = A.y[i];
+    B.z[p] = A.z[i];
+    B.vx[p] = A.vx[i];
+    B.vy[p] = A.vy[i];
+    B.vz[p] = A.vz[i];
+    B.uid[p] = A.uid[i];
+}
+
+// ---------------------------------------------------------------------------
+// Moments: per-tile sums of q R_lm and q I_lm
+// ---------------------------------------------------------------------------
+//
+// Real solid harmonics through the polynomial Q_l^m(z, r^2) = r^l P~_l^m /
+// (r sin th)^m and (x + i y)^m = C_m + i S_m:
+//   R_lm^c = Q_l^m C_m,  R_lm^s = Q_l^m S_m,  I_lm = r^-(2l+1) R_lm,
+// normalised so that sum_m Y_lm(a) Y_lm(b) = (2l+1)/(4 pi) P_l(a.b).
+
+template <bool FULL>
+__global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tables tb,
+                                                    KParams kp, double *S)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    if ((int)tile >= kp.n_tiles) return;
+    const uint32_t n = ctl->n_live;
+    double *St = S + (size_t)tile * kp.C2;
+    if (tile * kWave >= n) {
+        for (int c = lane; c < kp.C2; c += kWave) St[c] = 0.0;
+        return;
+    }
+    const uint32_t p = tile * kWave + lane;
+    const bool valid = p < n;
+    double x = 0.0, y = 0.0, z = 2.0;
+    if (valid) {
+        x = B.x[p];
+        y = B.y[p];
+        z = B.z[p];
+    }
+    const double q = valid ? kQ : 0.0;
+    const double r2 = x * x + y * y + z * z;
+    const double inv_r2 = 1.0 / r2;
+    const double inv_r = 1.0 / sqrt(r2);
+    const int L = kp.L, C = kp.C;
+    const int m_top = FULL ? L : 0;
+
+    double Cm = 1.0, Sm = 0.0;
+    double s_mm = inv_r;  // r^-(2m+1)
+    for (int m = 0; m <= m_top; ++m) {
+        if (m > 0) {
+            double nc = x * Cm - y * Sm;
+            double ns = x * Sm + y * Cm;
+            Cm = nc;
+            Sm = ns;
+            s_mm *= inv_r2;
+        }
+        double Qp = 0.0, Qpp = 0.0;
+        double sl = s_mm;
+        for (int l = m; l <= L; ++l) {
+            double Qv;
+            if (l == m) Qv = tb.qmm[m];
+            else Qv = tb.alm[tri(l, m)] * z * Qp - tb.blm[tri(l, m)] * r2 * Qpp;
+            Qpp = Qp;
+            Qp = Qv;
+            const int cc = FULL ? chan_full(l, m, 0) : l;
+            if (l == 0) {   // monopole: Gauss's law over the radial order, not moments
+                if (lane == 0) {
+                    St[0] = 0.0;
+                    St[C] = 0.0;
+                }
+                sl *= inv_r2;
+                continue;
+            }
+            double rc = q * Qv * Cm;
+            double sr = sum_wave(rc);
+            double si = sum_wave(rc * sl);
+            if (lane == 0) {
+                St[cc] = sr;
+                St[C + cc] = si;
+            }
+            if (FULL && m > 0) {
+                double rs = q * Qv * Sm;
+                double sr2 = sum_wave(rs);
+                double si2 = sum_wave(rs * sl);
+                if (lane == 0) {
+                    St[cc + 1] = sr2;
+                    St[C + cc + 1] = si2;
+                }
+            }
+            sl *= inv_r2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Carries: prefix/suffix scans over tiles, totals, coefficients, Q_diff
+// ---------------------------------------------------------------------------
+
+__device__ inline int chan_l(int c, bool full)
+{
+    if (!full) return c;
+    int l = (int)sqrt((double)c);
+    while (l * l > c) --l;
+    while ((l + 1) * (l + 1) <= c) ++l;
+    return l;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(const double *S, double *chunkS, KParams kp)
+{
+    const int c = blockIdx.y * kBlock + threadIdx.x;
+    if (c >= kp.C2) return;
+    const int j = blockIdx.x;
+    const int t0 = j * kChunk, t1 = min(t0 + kChunk, kp.n_tiles);
+    double s = 0.0;
+    for (int t = t0; t < t1; ++t) s += S[(size_t)t * kp.C2 + c];
+    chunkS[(size_t)j * kp.C2 + c] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_scan(const double *chunkS, double *chunkC,
+                                                       double *T, Ctl *ctl, KParams kp)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    // Q_S = q_surface0 + q * (absorbed so far); it enters the field as an
+    // interior l = 0 charge (Q_S / (4 pi r), Sec. 3) in the field kernel.
+    const double qs = kp.q_surface0 + kQ * (double)ctl->n_dead;
+    if (c == 0) ctl->q_surface = qs;
+    if (c >= kp.C2) return;
+    if (c < kp.C) {
+        double run = 0.0;
+        for (int j = 0; j < kp.n_chunks; ++j) {
+            chunkC[(size_t)j * kp.C2 + c] = run;
+            run += chunkS[(size_t)j * kp.C2 + c];
+        }
+    } else {
+        double run = 0.0;
+        for (int j = kp.n_chunks - 1; j >= 0; --j) {
+            chunkC[(size_t)j * kp.C2 + c] = run;
+            run += chunkS[(size_t)j * kp.C2 + c];
+        }
+        T[c - kp.C] = run;
+    }
+}
+
+// Constant part of the interior coefficient: image response -f_l T_lm and the
+// hemisphere drive (odd l, m = 0); and the probe response Q_diff(t_step).
+template <bool FULL>
+__global__ __launch_bounds__(kBlock) void k_coef_prep(const double *T, Ctl *ctl,
+                                                      const double *u_asy, double *qdiff,
+                                                      Tables tb, KParams kp, double *Kc)
+{
+    const int64_t step = ctl->step;
+    const double u = (step >= 0 && step < kp.n_steps) ? u_asy[step] : 0.0;
+    for (int c = threadIdx.x; c < kp.C; c += kBlock) {
+        const int l = chan_l(c, FULL);
+        const bool m0 = FULL ? (c == l * l) : true;
+        double k = -tb.ftil[l] * T[c] * tb.wl[l];
+        if (m0) k += u * tb.drive_w[l];
+        Kc[c] = k;
+    }
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int l = 1; l <= kp.L; l += 2) s += tb.drive_w[l] * T[FULL ? l * l : l];
+        if (step >= 0 && step < kp.n_steps) qdiff[step] = -s / kp.ntilde;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_apply(const double *S, const double *chunkC,
+                                                        const double *Kc, Tables tb, KParams kp,
+                                                        bool full, double *coef)
+{
+    const int c = blockIdx.y * kBlock + threadIdx.x;
+    if (c >= kp.C2) return;
+    const int j = blockIdx.x;
+    const int t0 = j * kChunk, t1 = min(t0 + kChunk, kp.n_tiles);
+    double run = chunkC[(size_t)j * kp.C2 + c];
+    if (c < kp.C) {
+        const double w = tb.wl[chan_l(c, full)];
+        const double k = Kc[c];
+        for (int t = t0; t < t1; ++t) {
+            coef[(size_t)t * kp.C2 + c] = run * w + k;
+            run += S[(size_t)t * kp.C2 + c];
+        }
+    } else {
+        const double w = tb.wl[chan_l(c - kp.C, full)];
+        for (int t = t1 - 1; t >= t0; --t) {
+            coef[(size_t)t * kp.C2 + c] = run * w;
+            run += S[(size_t)t * kp.C2 + c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Counter-based generator for diffuse walls: Philox-4x64-10 (Salmon et al.,
+// SC'11), counter (step, id, wall, 0), key (seed, 0).
+// ---------------------------------------------------------------------------
+
+__device__ inline void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+// Unit vector uniform on the hemisphere around the unit normal n.
+__device__ inline void hemisphere_dir(uint64_t seed, uint32_t id, int64_t step, int wall,
+                                      const double n[3], double d[3])
+{
+    uint64_t c[4] = {(uint64_t)step, (uint64_t)id, (uint64_t)wall, 0ull};
+    philox4x64(c, seed, 0ull);
+    const double inv53 = 1.0 / 9007199254740992.0;
+    double ct = ((double)(c[0] >> 11) + 0.5) * inv53;
+    double ph = 2.0 * kPi * (((double)(c[1] >> 11) + 0.5) * inv53);
+    double st = sqrt(1.0 - ct * ct);
+    double t[3] = {0.0, 0.0, 1.0};
+    if (!(fabs(n[2]) < 0.9)) {
+        t[0] = 1.0;
+        t[2] = 0.0;
+    }
+    double ex[3] = {t[1] * n[2] - t[2] * n[1], t[2] * n[0] - t[0] * n[2], t[0] * n[1] - t[1] * n[0]};
+    double inv = 1.0 / sqrt(ex[0] * ex[0] + ex[1] * ex[1] + ex[2] * ex[2]);
+    ex[0] *= inv;
+    ex[1] *= inv;
+    ex[2] *= inv;
+    double ey[3] = {n[1] * ex[2] - n[2] * ex[1], n[2] * ex[0] - n[0] * ex[2],
+                    n[0] * ex[1] - n[1] * ex[0]};
+    double cp = cos(ph), sp = sin(ph);
+    for (int j = 0; j < 3; ++j) d[j] = ct * n[j] + st * (cp * ex[j] + sp * ey[j]);
+}
+
+// ---------------------------------------------------------------------------
+// Field and push
+// ---------------------------------------------------------------------------
+
+struct Grave {
+    double *x, *y, *z, *vx, *vy, *vz;
+    uint32_t *uid;
+};
+
+template <bool FULL, bool FIELD_ONLY>
+__global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State A, uint8_t *dead,
+                                                       Grave G, const double *coef, Tables tb,
+                                                       KParams kp, double *Eout, uint32_t *Eid)
+{
+    __shared__ double sh_xh[kWavesPerBlock][kWave], sh_yh[kWavesPerBlock][kWave],
+        sh_zh[kWavesPerBlock][kWave], sh_r[kWavesPerBlock][kWave], sh_r2[kWavesPerBlock][kWave];
+    __shared__ uint32_t sh_uid[kWavesPerBlock][kWave];
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + w);
+    const uint32_t n = ctl->n_live;
+    const bool tile_live = (int)tile < kp.n_tiles && tile * kWave < n;
+    const uint32_t p = tile * kWave + lane;
+    const bool valid = tile_live && p < n;
+    const int jn = tile_live ? (int)min((uint32_t)kWave, n - tile * kWave) : 0;
+
+    double x = 0.0, y = 0.0, z = 2.0, vx = 0.0, vy = 0.0, vz = 0.0;
+    uint32_t uid = 0xffffffffu;
+    if (valid) {
+        x = B.x[p];
+        y = B.y[p];
+        z = B.z[p];
+        vx = B.vx[p];
+        vy = B.vy[p];
+        vz = B.vz[p];
+        uid = B.uid[p];
+    }
+    const double r2 = key_r2(x, y, z);
+    const double r = sqrt(r2);
+    const double inv_r = 1.0 / r;
+    const double inv_r2 = 1.0 / r2;
+    const double xh = x * inv_r, yh = y * inv_r, zh = z * inv_r;
+    sh_xh[w][lane] = xh;
+    sh_yh[w][lane] = yh;
+    sh_zh[w][lane] = zh;
+    sh_r[w][lane] = r;
+    sh_r2[w][lane] = r2;
+    sh_uid[w][lane] = uid;
+    __syncthreads();
+    if (!tile_live) return;
+
+    const int L = kp.L, C = kp.C;
+
+    // ---- far field: all other tiles, through this tile's coefficients ----
+    // Phi_far(x) = sum_lm Q_l^m(z, r^2) U_lm(x, y),
+    // U_lm = (beta + s_l alpha)^c C_m + (beta + s_l alpha)^s S_m, s_l = r^-(2l+1);
+    // grad Phi = sum [U (2 D_s Q x_vec + D_z Q e_z) + Q grad_xy U]
+    //            - (x_vec / r^2) sum (2l+1) s_l Q (alpha^c C_m + alpha^s S_m).
+    const double *cf = coef + (size_t)tile * kp.C2;
+    double Gs = 0.0, Gz = 0.0, Gx = 0.0, Gy = 0.0, Gr = 0.0;
+    {
+        const int m_top = FULL ? L : 0;
+        double Cm = 1.0, Sm = 0.0, Cm1 = 0.0, Sm1 = 0.0;
+        double s_mm = inv_r;
+        for (int m = 0; m <= m_top; ++m) {
+            if (m > 0) {
+                Cm1 = Cm;
+                Sm1 = Sm;
+                Cm = x * Cm1 - y * Sm1;
+                Sm = x * Sm1 + y * Cm1;
+                s_mm *= inv_r2;
+            }
+            double Q1 = 0.0, Q2 = 0.0, Dz1 = 0.0, Dz2 = 0.0, Ds1 = 0.0, Ds2 = 0.0;
+            double sl = s_mm;
+            const double dm = (double)m;
+            for (int l = m; l <= L; ++l) {
+                double Qv, Dz, Ds;
+                if (l == m) {
+                    Qv = tb.qmm[m];
+                    Dz = 0.0;
+                    Ds = 0.0;
+                } else {
+                    const double a = tb.alm[tri(l, m)], b = tb.blm[tri(l, m)];
+                    Qv = a * z * Q1 - b * r2 * Q2;
+                    Dz = a * Q1 + a * z * Dz1 - b * r2 * Dz2;
+                    Ds = a * z * Ds1 - b * Q2 - b * r2 * Ds2;
+                }
+                Q2 = Q1;
+                Q1 = Qv;
+                Dz2 = Dz1;
+                Dz1 = Dz;
+                Ds2 = Ds1;
+                Ds1 = Ds;
+                if (l == 0) {
+                    sl *= inv_r2;
+                    continue;
+                }
+                const int cc = FULL ? chan_full(l, m, 0) : l;
+                const double ac = cf[cc], bc = cf[C + cc];
+                const double tc = bc + sl * ac;
+                const double two_l1 = 2.0 * l + 1.0;
+                if (!FULL || m == 0) {
+                    Gs += tc * Ds;
+                    Gz += tc * Dz;
+                    Gr += two_l1 * sl * Qv * ac;
+                } else {
+                    const double as = cf[cc + 1], bs = cf[C + cc + 1];
+                    const double ts = bs + sl * as;
+                    const double U = tc * Cm + ts * Sm;
+                    Gs += U * Ds;
+                    Gz += U * Dz;
+                    const double mq = dm * Qv;
+                    Gx += mq * (tc * Cm1 + ts * Sm1);
+                    Gy += mq * (ts * Cm1 - tc * Sm1);
+                    Gr += two_l1 * sl * Qv * (ac * Cm + as * Sm);
+                }
+                sl *= inv_r2;
+            }
+        }
+    }
+    double Ex = -(2.0 * Gs * x + Gx - Gr * x * inv_r2);
+    double Ey = -(2.0 * Gs * y + Gy - Gr * y * inv_r2);
+    double Ez = -(2.0 * Gs * z + Gz - Gr * z * inv_r2);
+
+    // ---- near field: own tile, pair by pair (direct part of G~_L) ----
+    // k outer: grad_k D = (1/r_k^2) sum_l rho^l [-(l+1) P_l xh_k + P'_l (xh_j - u xh_k)]
+    // k inner: grad_k D = (1/(r_j r_k)) sum_l rho^l [l P_l xh_k + P'_l (xh_j - u xh_k)]
+    // with rho = r_< / r_>; E += -(q / (4 pi nt)) grad_k D.
+    {
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int j = 0; j < jn; ++j) {
+            const double xj = sh_xh[w][j], yj = sh_yh[w][j], zj = sh_zh[w][j];
+            const double rj = sh_r[w][j], r2j = sh_r2[w][j];
+            const uint32_t uj = sh_uid[w][j];
+            if (j == lane) continue;
+            const bool outer = (r2 > r2j) || (r2 == r2j && uid > uj);
+            const double rho = outer ? rj * inv_r : r / rj;
+            const double scale = outer ? inv_r2 : 1.0 / (rj * r);
+            double u, vx_, vy_, vz_;   // angular argument and its direction vector
+            if (FULL) {
+                u = xh * xj + yh * yj + zh * zj;
+                vx_ = xj - u * xh;
+                vy_ = yj - u * yh;
+                vz_ = zj - u * zh;
+            } else {
+                u = zh;
+                vx_ = -zh * xh;
+                vy_ = -zh * yh;
+                vz_ = 1.0 - zh * zh;
+            }
+            // Legendre recurrences
+            double P0 = 1.0, P1 = u, dP0 = 0.0, dP1 = 1.0;
+            double Pj0 = 1.0, Pj1 = zj;   // partner P_l(cos th_j), axisymmetric only
+            double rl = 1.0;
+            double S1 = 0.0, Sl = 0.0, SB = 0.0;
+            rl = rho;    // l = 0 is handled by Gauss's law below
+            for (int l = 1; l <= L; ++l) {
+                double ang, dang;
+                if (FULL) {
+                    ang = P1;
+                    dang = dP1;
+                } else {
+                    ang = P1 * Pj1;
+                    dang = dP1 * Pj1;
+                }
+                S1 += rl * ang;
+                Sl += (double)l * rl * ang;
+                SB += rl * dang;
+                // advance to l + 1
+                const double A = tb.nfA[l], Bc = tb.nfB[l];
+                const double P2 = A * u * P1 - Bc * P0;
+                const double dP2 = dP0 + (2.0 * l + 1.0) * P1;
+                P0 = P1;
+                P1 = P2;
+                dP0 = dP1;
+                dP1 = dP2;
+                if (!FULL) {
+                    const double Pj2 = A * zj * Pj1 - Bc * Pj0;
+                    Pj0 = Pj1;
+                    Pj1 = Pj2;
+                }
+                rl *= rho;
+            }
+            const double SA = outer ? -(Sl + S1) : Sl;
+            ax += scale * (SA * xh + SB * vx_);
+            ay += scale * (SA * yh + SB * vy_);
+            az += scale * (SA * zh + SB * vz_);
+        }
+        const double cn = -kQ / (4.0 * kPi * kp.ntilde);
+        Ex += cn * ax;
+        Ey += cn * ay;
+        Ez += cn * az;
+    }
+
+    // ---- self-image correction: the totals T_lm include the particle's own
+    // image, which the pair sum i != k excludes ----
+    {
+        double sr = 0.0, sz = 0.0;   // radial and (e_z - c xh) parts of grad Phi_self
+        double rl = inv_r2 * inv_r2 * inv_r;   // r^-(2l+3) at l = 1
+        if (FULL) {
+            for (int l = 1; l <= L; ++l) {
+                sr += tb.self_w[l] * (l + 1.0) * rl;
+                rl *= inv_r2;
+            }
+            // grad Phi_self = -q sum f_l (l+1)/(4 pi nt) r^-(2l+3) xh; E = -grad
+            const double e = kQ * sr;
+            Ex += e * xh;
+            Ey += e * yh;
+            Ez += e * zh;
+        } else {
+            double P0 = 1.0, P1 = zh, dP0 = 0.0, dP1 = 1.0;
+            for (int l = 1; l <= L; ++l) {
+                sr += tb.self_w[l] * rl * P1 * (-(l + 1.0) * P1);
+                sz += tb.self_w[l] * rl * P1 * dP1;
+                const double P2 = tb.nfA[l] * zh * P1 - tb.nfB[l] * P0;
+                const double dP2 = dP0 + (2.0 * l + 1.0) * P1;
+                P0 = P1;
+                P1 = P2;
+                dP0 = dP1;
+                dP1 = dP2;
+                rl *= inv_r2;
+            }
+            // grad Phi_selfcorr = q sum (f_l/(4 pi nt)) r^-(2l+3) P_l [-(l+1) P_l xh + P'_l (e_z - c xh)]
+            const double gx = kQ * (sr * xh + sz * (-zh * xh));
+            const double gy = kQ * (sr * yh + sz * (-zh * yh));
+            const double gz = kQ * (sr * zh + sz * (1.0 - zh * zh));
+            Ex -= gx;
+            Ey -= gy;
+            Ez -= gz;
+        }
+    }
+
+    // ---- l = 0: Gauss's law.  The l = 0 part of G~ is 1/(4 pi r_>), so only
+    // the charge enclosed by r_k pushes: Q_S, the p particles before k in the
+    // radial order (p is the sorted position) and the ion background
+    // nt n_i (4 pi / 3)(r^3 - 1), all in super-particle units. ----
+    {
+        const double ions = kp.ntilde * kp.ion_density * (4.0 * kPi / 3.0) * (r2 * r - 1.0);
+        const double enclosed = (ctl->q_surface + kQ * (double)p) + ions;
+        const double e = enclosed / (4.0 * kPi * kp.ntilde * r2);
+        Ex += e * xh;
+        Ey += e * yh;
+        Ez += e * zh;
+    }
+
+    if (FIELD_ONLY) {
+        if (valid) {
+            Eout[3 * (size_t)p + 0] = Ex;
+            Eout[3 * (size_t)p + 1] = Ey;
+            Eout[3 * (size_t)p + 2] = Ez;
+            Eid[p] = uid;
+        }
+        return;
+    }
+    if (!valid) return;
+
+    // ---- leapfrog (Sec. 4 equations of motion) ----
+    const double qm = kQ / kM;
+    vx = __dadd_rn(vx, __dmul_rn(qm * Ex, kp.dt));
+    vy = __dadd_rn(vy, __dmul_rn(qm * Ey, kp.dt));
+    vz = __dadd_rn(vz, __dmul_rn(qm * Ez, kp.dt));
+    x = __dadd_rn(x, __dmul_rn(vx, kp.dt));
+    y = __dadd_rn(y, __dmul_rn(vy, kp.dt));
+    z = __dadd_rn(z, __dmul_rn(vz, kp.dt));
+
+    // ---- walls (tested on the new position) ----
+    const double rn = sqrt(key_r2(x, y, z));
+    uint8_t absorbed = 0;
+    const int64_t step = ctl->step;
+    if (rn <= 1.0 || rn >= kp.r_out) {
+        const bool probe = rn <= 1.0;
+        const int bc = probe ? kp.probe_bc : kp.wall_bc;
+        if (probe && bc == SIM_BC_ABSORB) {
+            absorbed = 1;
+        } else {
+            const double s = probe ? (2.0 - rn) / rn : (2.0 * kp.r_out - rn) / rn;
+            const double nrm[3] = {x / rn, y / rn, z / rn};
+            x = x * s;
+            y = y * s;
+            z = z * s;
+            if (bc == SIM_BC_DIFFUSE) {
+                const double sp = sqrt(__dadd_rn(__dadd_rn(__dmul_rn(vx, vx), __dmul_rn(vy, vy)),
+                                                 __dmul_rn(vz, vz)));
+                double inw[3] = {nrm[0], nrm[1], nrm[2]};
+                if (!probe) {
+                    inw[0] = -inw[0];
+                    inw[1] = -inw[1];
+                    inw[2] = -inw[2];
+                }
+                double d[3];
+                hemisphere_dir(kp.seed, uid, step, probe ? 0 : 1, inw, d);
+                vx = sp * d[0];
+                vy = sp * d[1];
+                vz = sp * d[2];
+            } else {
+                const double vn = __dadd_rn(__dadd_rn(__dmul_rn(vx, nrm[0]), __dmul_rn(vy, nrm[1])),
+                                            __dmul_rn(vz, nrm[2]));
+                const double two_vn = 2.0 * vn;
+                vx = __dsub_rn(vx, __dmul_rn(two_vn, nrm[0]));
+                vy = __dsub_rn(vy, __dmul_rn(two_vn, nrm[1]));
+                vz = __dsub_rn(vz, __dmul_rn(two_vn, nrm[2]));
+            }
+        }
+    }
+    A.x[p] = x;
+    A.y[p] = y;
+    A.z[p] = z;
+    A.vx[p] = vx;
+    A.vy[p] = vy;
+    A.vz[p] = vz;
+    A.uid[p] = uid;
+    dead[p] = absorbed;
+    if (absorbed) {
+        const uint32_t slot = atomicAdd(&ctl->n_dead, 1u);
+        G.x[slot] = x;
+        G.y[slot] = y;
+        G.z[slot] = z;
+        G.vx[slot] = vx;
+        G.vy[slot] = vy;
+        G.vz[slot] = vz;
+        G.uid[slot] = uid;
+    }
+}
+
+__global__ void k_step_finish(Ctl *ctl)
+{
+    ctl->step += 1;
+    ctl->n_cur = ctl->n_live;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+enum KernelId {
+    KN_SORT_CLEAR, KN_SORT_KEY, KN_SCAN_A, KN_SCAN_B, KN_SCAN_C, KN_SORT_SCATTER, KN_SORT_RANK,
+    KN_SORT_PERMUTE, KN_MOMENTS, KN_CHUNK_SUMS, KN_CHUNK_SCAN, KN_COEF_PREP, KN_CHUNK_APPLY,
+    KN_FIELD_PUSH, KN_STEP_FINISH, KN_COUNT
+};
+
+const char *kKernelNames[KN_COUNT] = {
+    "sort_clear", "sort_key", "bucket_scan_a", "bucket_scan_b", "bucket_scan_c", "sort_scatter",
+    "sort_rank", "sort_permute", "moments", "carry_chunk_sums", "carry_chunk_scan", "coef_prep",
+    "carry_apply", "field_push", "step_finish"};
+
+struct Layout {
+    int64_t n;
+    int L, C, C2, n_tiles, n_chunks, nb, nb_blocks;
+    int64_t n_steps;
+    bool full;
+};
+
+bool make_layout(const sim_params *p, int64_t n, int64_t n_steps, Layout *lo, std::string *why)
+{
+    if (!p) { *why = "params is NULL"; return false; }
+    if (p->struct_size != sizeof(sim_params)) { *why = "params struct_size mismatch"; return false; }
+    if (n <= 0 || n > 0x7fffffffLL) { *why = "n must be in [1, 2^31)"; return false; }
+    if (n_steps < 0) { *why = "n_steps < 0"; return false; }
+    if (p->l_max < 0 || p->l_max > kMaxL) { *why = "l_max must be in [0, 64]"; return false; }
+    if (!(p->d > 0.0 && p->d < 1.0)) { *why = "d must be in (0, 1)"; return false; }
+    if (!(p->eps_r > 0.0) || !std::isfinite(p->eps_r)) { *why = "eps_r must be > 0"; return false; }
+    if (!(p->r_out > 1.0) || !std::isfinite(p->r_out)) { *why = "r_out must be > 1"; return false; }
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) { *why = "dt must be > 0"; return false; }
+    if (!(p->ntilde > 0.0) || !std::isfinite(p->ntilde)) { *why = "ntilde must be > 0"; return false; }
+    if (!(p->ion_density >= 0.0) || !std::isfinite(p->ion_density)) {
+        *why = "ion_density must be >= 0";
+        return false;
+    }
+    if (!std::isfinite(p->q_surface0)) { *why = "q_surface0 must be finite"; return false; }
+    if (p->m_mode != SIM_M_FULL && p->m_mode != SIM_M_AXISYM) { *why = "bad m_mode"; return false; }
+    if (p->probe_bc < SIM_BC_ABSORB || p->probe_bc > SIM_BC_DIFFUSE) { *why = "bad probe_bc"; return false; }
+    if (p->wall_bc != SIM_BC_SPECULAR && p->wall_bc != SIM_BC_DIFFUSE) { *why = "bad wall_bc"; return false; }
+    if (p->precision != SIM_FP64) { *why = "precision: only SIM_FP64 is available"; return false; }
+    if (p->tile != 0 && p->tile != kWave) { *why = "tile must be 0 or 64"; return false; }
+    lo->n = n;
+    lo->L = p->l_max;
+    lo->full = p->m_mode == SIM_M_FULL;
+    lo->C = lo->full ? (p->l_max + 1) * (p->l_max + 1) : p->l_max + 1;
+    lo->C2 = 2 * lo->C;
+    lo->n_tiles = (int)((n + kWave - 1) / kWave);
+    lo->n_chunks = (lo->n_tiles + kChunk - 1) / kChunk;
+    lo->nb = (int)std::max<int64_t>(1, n / kBucketOccupancy);
+    lo->nb_blocks = (lo->nb + kScanPerBlock - 1) / kScanPerBlock;
+    lo->n_steps = n_steps;
+    return true;
+}
+
+struct Alloc {
+    std::vector<std::pair<void **, size_t>> items;
+    template <class T> void add(T **ptr, size_t count) { items.push_back({(void **)ptr, count * sizeof(T)}); }
+    size_t total() const {
+        size_t s = 0;
+        for (auto &it : items) s += (it.second + 255) & ~size_t(255);
+        return s;
+    }
+};
+
+}  // namespace
+
+struct sim {
+    sim_params prm;
+    Layout lo;
+    KParams kp;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    State A{}, B{};
+    Grave G{};
+    uint8_t *dead = nullptr;
+    uint64_t *key = nullptr;
+    uint32_t *bkt = nullptr, *tmp = nullptr, *perm = nullptr, *hist = nullptr, *cursor = nullptr,
+             *off = nullptr, *bsum = nullptr;
+    double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr, *Kc = nullptr,
+           *coef = nullptr, *u_asy = nullptr, *qdiff = nullptr, *tables = nullptr, *Eout = nullptr;
+    uint32_t *Eid = nullptr;
+    Ctl *ctl = nullptr;
+    Tables tb{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t step_host = 0;      // absolute step after all enqueued work
+    int64_t start_step = 0;
+    bool failed = false;
+    std::vector<void *> mem;
+    std::vector<std::pair<uint32_t, int64_t>> id_index;  // (uid, creation index), sorted
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            return fail(SIM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                                                                             \
+    } while (0)
+
+void plan_alloc(sim *h, Alloc &al)
+{
+    const Layout &lo = h->lo;
+    const size_t n = (size_t)lo.n;
+    for (State *s : {&h->A, &h->B}) {
+        al.add(&s->x, n); al.add(&s->y, n); al.add(&s->z, n);
+        al.add(&s->vx, n); al.add(&s->vy, n); al.add(&s->vz, n);
+        al.add(&s->uid, n);
+    }
+    al.add(&h->G.x, n); al.add(&h->G.y, n); al.add(&h->G.z, n);
+    al.add(&h->G.vx, n); al.add(&h->G.vy, n); al.add(&h->G.vz, n);
+    al.add(&h->G.uid, n);
+    al.add(&h->dead, n);
+    al.add(&h->key, n);
+    al.add(&h->bkt, n);
+    al.add(&h->tmp, n);
+    al.add(&h->perm, n);
+    al.add(&h->hist, (size_t)lo.nb + 1);
+    al.add(&h->cursor, (size_t)lo.nb);
+    al.add(&h->off, (size_t)lo.nb + 1);
+    al.add(&h->bsum, (size_t)lo.nb_blocks + 1);
+    al.add(&h->S, (size_t)lo.n_tiles * lo.C2);
+    al.add(&h->coef, (size_t)lo.n_tiles * lo.C2);
+    al.add(&h->chunkS, (size_t)lo.n_chunks * lo.C2);
+    al.add(&h->chunkC, (size_t)lo.n_chunks * lo.C2);
+    al.add(&h->T, (size_t)lo.C);
+    al.add(&h->Kc, (size_t)lo.C);
+    al.add(&h->u_asy, (size_t)std::max<int64_t>(lo.n_steps, 1));
+    al.add(&h->qdiff, (size_t)std::max<int64_t>(lo.n_steps, 1));
+    const int L = lo.L;
+    al.add(&h->tables, (size_t)7 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2));
+    al.add(&h->Eout, 3 * n);
+    al.add(&h->Eid, n);
+    al.add(&h->ctl, 1);
+}
+
+// Host-side coefficient tables.  f_l and b^P_l are the closed forms of App. A
+// and Sec. 3 (R = 1, R_E = a); c_l, the Legendre coefficients of the
+// electrode data 1/2 sgn(cos th), are taken as (P_{l-1}(0) - P_{l+1}(0))/2.
+std::vector<double> build_tables(const sim_params &p, const Layout &lo)
+{
+    const int L = lo.L;
+    const double a = 1.0 - p.d, eps = p.eps_r;
+    std::vector<double> t((size_t)7 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2), 0.0);
+    double *ftil = t.data(), *wl = ftil + (L + 1), *drive = wl + (L + 1), *selfw = drive + (L + 1),
+           *nfA = selfw + (L + 1), *nfB = nfA + (L + 1), *qmm = nfB + (L + 1), *alm = qmm + (L + 1),
+           *blm = alm + (L + 1) * (L + 2) / 2;
+    // Legendre values at 0 up to L + 1
+    std::vector<double> p0(L + 3, 0.0);
+    p0[0] = 1.0;
+    if (L + 2 >= 1) p0[1] = 0.0;
+    for (int l = 1; l + 1 <= L + 2; ++l) p0[l + 1] = -(double)l / (l + 1.0) * p0[l - 1];
+    for (int l = 0; l <= L; ++l) {
+        const double a2l1 = std::pow(a, 2.0 * l + 1.0);
+        const double f = (l * (eps - 1.0) + (l + eps + l * eps) * a2l1) /
+                         ((l + 1.0 + l * eps) + (l + 1.0) * (eps - 1.0) * a2l1);
+        const double bP = (2.0 * l + 1.0) * eps * std::pow(a, l + 1.0) /
+                          ((l + 1.0) * (eps - 1.0) * a2l1 + l * eps + l + 1.0);
+        const double c = (l % 2 == 1) ? 0.5 * (p0[l - 1] - p0[l + 1]) : 0.0;
+        ftil[l] = (l == 0) ? 0.0 : f;
+        wl[l] = 1.0 / ((2.0 * l + 1.0) * p.ntilde);
+        drive[l] = c * bP * std::sqrt(4.0 * kPi / (2.0 * l + 1.0));
+        selfw[l] = (l == 0) ? 0.0 : f / (4.0 * kPi * p.ntilde);
+        nfA[l] = (2.0 * l + 1.0) / (l + 1.0);
+        nfB[l] = (double)l / (l + 1.0);
+    }
+    // Q_m^m = sqrt((2m+1)/(4 pi) / (2m)!) (2m-1)!! (sqrt 2 for m > 0)
+    qmm[0] = 1.0 / std::sqrt(4.0 * kPi);
+    for (int m = 1; m <= L; ++m) {
+        double v = qmm[m - 1] * std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+        if (m == 1) v *= std::sqrt(2.0);
+        qmm[m] = v;
+    }
+    for (int m = 0; m <= L; ++m) {
+        for (int l = m + 1; l <= L; ++l) {
+            const double l2 = (double)l * l, m2 = (double)m * m;
+            alm[tri(l, m)] = std::sqrt((4.0 * l2 - 1.0) / (l2 - m2));
+            blm[tri(l, m)] = (l >= m + 2)
+                ? std::sqrt(((l - 1.0) * (l - 1.0) - m2) * (2.0 * l + 1.0) / ((l2 - m2) * (2.0 * l - 3.0)))
+                : 0.0;
+        }
+    }
+    return t;
+}
+
+int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
+{
+    const Layout &lo = h->lo;
+    const KParams &kp = h->kp;
+    const unsigned n = (unsigned)lo.n;
+    const unsigned gN = (n + kBlock - 1) / kBlock;
+    const unsigned gT = (unsigned)((lo.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    const unsigned gC = (unsigned)((lo.C2 + kBlock - 1) / kBlock);
+    int e = 0;
+    auto mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], s);
+    };
+    mark(KN_SORT_CLEAR);
+    k_sort_clear<<<(lo.nb + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(h->hist, h->cursor, lo.nb);
+    mark(KN_SORT_KEY);
+    k_sort_key<<<gN, kBlock, 0, s>>>(h->ctl, h->A, h->dead, h->key, h->bkt, h->hist, kp);
+    mark(KN_SCAN_A);
+    k_scan_a<<<lo.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, lo.nb);
+    mark(KN_SCAN_B);
+    k_scan_b<<<1, kBlock, 0, s>>>(h->bsum, lo.nb_blocks, h->ctl);
+    mark(KN_SCAN_C);
+    k_scan_c<<<lo.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, lo.nb);
+    mark(KN_SORT_SCATTER);
+    k_sort_scatter<<<gN, kBlock, 0, s>>>(h->ctl, h->bkt, h->off, h->cursor, h->tmp);
+    mark(KN_SORT_RANK);
+    k_sort_rank<<<gN, kBlock, 0, s>>>(h->ctl, h->key, h->A.uid, h->bkt, h->off, h->tmp, h->perm);
+    mark(KN_SORT_PERMUTE);
+    k_sort_permute<<<gN, kBlock, 0, s>>>(h->ctl, h->perm, h->A, h->B);
+    mark(KN_MOMENTS);
+    if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
+    else k_moments<false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
+    mark(KN_CHUNK_SUMS);
+    k_chunk_sums<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkS, kp);
+    mark(KN_CHUNK_SCAN);
+    k_chunk_scan<<<gC, kBlock, 0, s>>>(h->chunkS, h->chunkC, h->T, h->ctl, kp);
+    mark(KN_COEF_PREP);
+    if (lo.full) k_coef_prep<true><<<1, kBlock, 0, s>>>(h->T, h->ctl, h->u_asy, h->qdiff, h->tb, kp, h->Kc);
+    else k_coef_prep<false><<<1, kBlock, 0, s>>>(h->T, h->ctl, h->u_asy, h->qdiff, h->tb, kp, h->Kc);
+    mark(KN_CHUNK_APPLY);
+    k_chunk_apply<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkC, h->Kc, h->tb, kp, lo.full,
+                                                           h->coef);
+    mark(KN_FIELD_PUSH);
+    if (field_only) {
+        if (lo.full)
+            k_field_push<true, true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G, h->coef,
+                                                          h->tb, kp, h->Eout, h->Eid);
+        else
+            k_field_push<false, true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G, h->coef,
+                                                           h->tb, kp, h->Eout, h->Eid);
+    } else {
+        if (lo.full)
+            k_field_push<true, false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G,
+                                                           h->coef, h->tb, kp, h->Eout, h->Eid);
+        else
+            k_field_push<false, false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G,
+                                                            h->coef, h->tb, kp, h->Eout, h->Eid);
+        mark(KN_STEP_FINISH);
+        k_step_finish<<<1, 1, 0, s>>>(h->ctl);
+    }
+    if (ev) (void)hipEventRecord(ev[KN_COUNT], s);
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) e = fail(SIM_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
+    return e;
+}
+
+void release(sim *h)
+{
+    if (!h) return;
+    if (h->exec) (void)hipGraphExecDestroy(h->exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void *p : h->mem) (void)hipFree(p);
+    h->mem.clear();
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+int check_handle(sim *h)
+{
+    if (!h) return fail(SIM_ESTATE, "NULL handle");
+    if (h->failed) return fail(SIM_ESTATE, "handle is in the failed state");
+    return SIM_OK;
+}
+
+int mark_failed(sim *h, int code)
+{
+    if (code == SIM_EDEVICE) h->failed = true;
+    return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sim_params_default(sim_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(sim_params);
+    p->d = 0.25;
+    p->eps_r = 4.0;
+    p->r_out = 5.0;
+    p->dt = 0.05;
+    p->ntilde = 1.0;
+    p->ion_density = 1.0;
+    p->q_surface0 = 0.0;
+    p->l_max = 8;
+    p->m_mode = SIM_M_FULL;
+    p->probe_bc = SIM_BC_ABSORB;
+    p->wall_bc = SIM_BC_SPECULAR;
+    p->precision = SIM_FP64;
+    p->tile = 0;
+    p->seed = 0;
+    p->mem_limit_bytes = 0;
+}
+
+int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps)
+{
+    Layout lo;
+    std::string why;
+    if (!make_layout(p, n, n_steps, &lo, &why)) return fail(SIM_EINVAL, why);
+    sim tmp;
+    tmp.lo = lo;
+    Alloc al;
+    plan_alloc(&tmp, al);
+    return (int64_t)al.total();
+}
+
+int sim_create(const sim_params *p, int64_t n, const double *pos, const double *vel,
+               const uint32_t *ids, const double *u_asy, int64_t n_steps, int64_t start_step,
+               void *hip_stream, sim_t **out)
+{
+    if (!out) return fail(SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    Layout lo;
+    std::string why;
+    if (!make_layout(p, n, n_steps, &lo, &why)) return fail(SIM_EINVAL, why);
+    if (!pos || !vel) return fail(SIM_EINVAL, "pos and vel are required");
+    if (n_steps > 0 && !u_asy) return fail(SIM_EINVAL, "u_asy is required when n_steps > 0");
+    if (start_step < 0 || start_step > n_steps) return fail(SIM_EINVAL, "start_step outside [0, n_steps]");
+    for (int64_t i = 0; i < n; ++i) {
+        const double *x = pos + 3 * i, *v = vel + 3 * i;
+        for (int j = 0; j < 3; ++j)
+            if (!std::isfinite(x[j]) || !std::isfinite(v[j]))
+                return fail(SIM_EINVAL, "non-finite particle state at index " + std::to_string(i));
+        const double r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        if (!(r > 1.0 && r < p->r_out))
+            return fail(SIM_EINVAL, "particle " + std::to_string(i) + " not inside 1 < r < r_out");
+    }
+    for (int64_t s = 0; s < n_steps; ++s)
+        if (!std::isfinite(u_asy[s])) return fail(SIM_EINVAL, "non-finite u_asy");
+    std::vector<uint32_t> uid((size_t)n);
+    for (int64_t i = 0; i < n; ++i) uid[i] = ids ? ids[i] : (uint32_t)i;
+    std::vector<std::pair<uint32_t, int64_t>> idx((size_t)n);
+    for (int64_t i = 0; i < n; ++i) idx[i] = {uid[i], i};
+    std::sort(idx.begin(), idx.end());
+    for (int64_t i = 1; i < n; ++i)
+        if (idx[i].first == idx[i - 1].first) return fail(SIM_EINVAL, "ids are not distinct");
+
+    sim *h = new (std::nothrow) sim();
+    if (!h) return fail(SIM_ENOMEM, "host allocation failed");
+    h->prm = *p;
+    h->lo = lo;
+    h->id_index = std::move(idx);
+    Alloc al;
+    plan_alloc(h, al);
+    if (p->mem_limit_bytes && al.total() > p->mem_limit_bytes) {
+        delete h;
+        return fail(SIM_ENOMEM, "footprint " + std::to_string(al.total()) + " B exceeds mem_limit_bytes");
+    }
+    auto bail = [&](int code) {
+        release(h);
+        delete h;
+        return code;
+    };
+    for (auto &it : al.items) {
+        void *ptr = nullptr;
+        hipError_t e = hipMalloc(&ptr, std::max<size_t>(it.second, 1));
+        if (e != hipSuccess) {
+            fail(SIM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+            return bail(SIM_ENOMEM);
+        }
+        h->mem.push_back(ptr);
+        *it.first = ptr;
+    }
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(SIM_EDEVICE, "hipStreamCreate failed"));
+        h->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(SIM_EDEVICE, "hipStreamCreate failed"));
+
+    // tables
+    std::vector<double> tab = build_tables(*p, lo);
+    const int L = lo.L;
+    double *tb = h->tables;
+    h->tb.ftil = tb;
+    h->tb.wl = tb + (L + 1);
+    h->tb.drive_w = tb + 2 * (L + 1);
+    h->tb.self_w = tb + 3 * (L + 1);
+    h->tb.nfA = tb + 4 * (L + 1);
+    h->tb.nfB = tb + 5 * (L + 1);
+    h->tb.qmm = tb + 6 * (L + 1);
+    h->tb.alm = tb + 7 * (L + 1);
+    h->tb.blm = tb + 7 * (L + 1) + (L + 1) * (L + 2) / 2;
+
+    KParams &kp = h->kp;
+    kp.L = lo.L;
+    kp.C = lo.C;
+    kp.C2 = lo.C2;
+    kp.n_tiles = lo.n_tiles;
+    kp.n_chunks = lo.n_chunks;
+    kp.nb = lo.nb;
+    kp.probe_bc = p->probe_bc;
+    kp.wall_bc = p->wall_bc;
+    kp.dt = p->dt;
+    kp.r_out = p->r_out;
+    kp.ntilde = p->ntilde;
+    kp.ion_density = p->ion_density;
+    kp.q_surface0 = p->q_surface0;
+    kp.inv_vol = 1.0 / (p->r_out * p->r_out * p->r_out - 1.0);
+    kp.seed = p->seed;
+    kp.n_steps = n_steps;
+
+    // upload the initial state (A, creation order) and the drive
+    std::vector<double> col((size_t)n);
+    auto up = [&](double *dst, const double *src, int j) -> hipError_t {
+        for (int64_t i = 0; i < n; ++i) col[i] = src[3 * i + j];
+        return hipMemcpy(dst, col.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+    };
+    Ctl ctl{};
+    ctl.step = start_step;
+    ctl.n_cur = (uint32_t)n;
+    ctl.n_live = (uint32_t)n;
+    ctl.n_dead = 0;
+    ctl.q_surface = p->q_surface0;
+    std::vector<double> zeros((size_t)std::max<int64_t>(n_steps, 1), 0.0);
+    if (up(h->A.x, pos, 0) || up(h->A.y, pos, 1) || up(h->A.z, pos, 2) || up(h->A.vx, vel, 0) ||
+        up(h->A.vy, vel, 1) || up(h->A.vz, vel, 2) ||
+        hipMemcpy(h->A.uid, uid.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice) ||
+        hipMemset(h->dead, 0, (size_t)n) ||
+        hipMemcpy(h->tables, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->qdiff, zeros.data(), sizeof(double) * zeros.size(), hipMemcpyHostToDevice) ||
+        (n_steps > 0 &&
+         hipMemcpy(h->u_asy, u_asy, sizeof(double) * n_steps, hipMemcpyHostToDevice))) {
+        return bail(fail(SIM_EDEVICE, "upload failed"));
+    }
+    // capture one step into a graph
+    if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bail(fail(SIM_EDEVICE, "hipStreamBeginCapture failed"));
+    int le = launch_step(h, h->cap_stream, false, nullptr);
+    hipError_t ce = hipStreamEndCapture(h->cap_stream, &h->graph);
+    if (le != SIM_OK) return bail(le);
+    if (ce != hipSuccess) return bail(fail(SIM_EDEVICE, std::string("capture: ") + hipGetErrorString(ce)));
+    if (hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(fail(SIM_EDEVICE, "hipGraphInstantiate failed"));
+    if (hipDeviceSynchronize() != hipSuccess) return bail(fail(SIM_EDEVICE, "device sync failed"));
+    h->step_host = start_step;
+    h->start_step = start_step;
+    *out = h;
+    return SIM_OK;
+}
+
+int sim_step(sim_t *h, int64_t k)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (k < 0) return fail(SIM_EINVAL, "k < 0");
+    if (h->step_host + k > h->lo.n_steps) return fail(SIM_ERANGE, "steps beyond n_steps");
+    for (int64_t i = 0; i < k; ++i) {
+        hipError_t e = hipGraphLaunch(h->exec, h->stream);
+        if (e != hipSuccess) {
+            h->failed = true;
+            return fail(SIM_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        }
+    }
+    h->step_host += k;
+    return SIM_OK;
+}
+
+int sim_sync(sim_t *h)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        h->failed = true;
+        return fail(SIM_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    }
+    return SIM_OK;
+}
+
+int sim_read_response(sim_t *h, int64_t first, int64_t count, double *q_diff)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (count == 0) return SIM_OK;
+    if (!q_diff || count < 0 || first < h->start_step || first + count > h->step_host)
+        return fail(SIM_ERANGE, "response range not computed");
+    rc = sim_sync(h);
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(q_diff, h->qdiff + first, sizeof(double) * count, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return mark_failed(h, fail(SIM_EDEVICE, "copy of Q_diff failed"));
+    return SIM_OK;
+}
+
+int sim_read_state(sim_t *h, double *pos, double *vel, uint8_t *alive, double *q_surface,
+                   int64_t *step)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    rc = sim_sync(h);
+    if (rc) return rc;
+    Ctl ctl;
+    if (hipMemcpy(&ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess)
+        return mark_failed(h, fail(SIM_EDEVICE, "copy of control block failed"));
+    const int64_t n = h->lo.n;
+    const size_t na = ctl.n_cur, ng = ctl.n_dead;
+    std::vector<double> a[6], g[6];
+    std::vector<uint32_t> au(na), gu(ng);
+    std::vector<uint8_t> ad(na);
+    double *srcA[6] = {h->A.x, h->A.y, h->A.z, h->A.vx, h->A.vy, h->A.vz};
+    double *srcG[6] = {h->G.x, h->G.y, h->G.z, h->G.vx, h->G.vy, h->G.vz};
+    for (int j = 0; j < 6; ++j) {
+        a[j].resize(na);
+        g[j].resize(ng);
+        if ((na && hipMemcpy(a[j].data(), srcA[j], 8 * na, hipMemcpyDeviceToHost)) ||
+            (ng && hipMemcpy(g[j].data(), srcG[j], 8 * ng, hipMemcpyDeviceToHost)))
+            return mark_failed(h, fail(SIM_EDEVICE, "state copy failed"));
+    }
+    if ((na && (hipMemcpy(au.data(), h->A.uid, 4 * na, hipMemcpyDeviceToHost) ||
+                hipMemcpy(ad.data(), h->dead, na, hipMemcpyDeviceToHost))) ||
+        (ng && hipMemcpy(gu.data(), h->G.uid, 4 * ng, hipMemcpyDeviceToHost)))
+        return mark_failed(h, fail(SIM_EDEVICE, "state copy failed"));
+    auto find = [&](uint32_t u) -> int64_t {
+        auto it = std::lower_bound(h->id_index.begin(), h->id_index.end(),
+                                   std::make_pair(u, (int64_t)-1));
+        if (it == h->id_index.end() || it->first != u) return -1;
+        return it->second;
+    };
+    if (alive) std::memset(alive, 0, (size_t)n);
+    auto put = [&](int64_t k, std::vector<double> *src, size_t i) {
+        if (pos) for (int j = 0; j < 3; ++j) pos[3 * k + j] = src[j][i];
+        if (vel) for (int j = 0; j < 3; ++j) vel[3 * k + j] = src[3 + j][i];
+    };
+    for (size_t i = 0; i < ng; ++i) {
+        int64_t k = find(gu[i]);
+        if (k < 0) return fail(SIM_EDEVICE, "unknown id in graveyard");
+        put(k, g, i);
+    }
+    for (size_t i = 0; i < na; ++i) {
+        if (ad[i]) continue;
+        int64_t k = find(au[i]);
+        if (k < 0) return fail(SIM_EDEVICE, "unknown id in state");
+        put(k, a, i);
+        if (alive) alive[k] = 1;
+    }
+    if (q_surface) *q_surface = h->prm.q_surface0 + kQ * (double)ctl.n_dead;
+    if (step) *step = ctl.step;
+    return SIM_OK;
+}
+
+int sim_eval_field(sim_t *h, double *E)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!E) return fail(SIM_EINVAL, "E is NULL");
+    rc = launch_step(h, h->stream, true, nullptr);
+    if (rc) return mark_failed(h, rc);
+    rc = sim_sync(h);
+    if (rc) return rc;
+    Ctl ctl;
+    if (hipMemcpy(&ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess)
+        return mark_failed(h, fail(SIM_EDEVICE, "copy of control block failed"));
+    const size_t nl = ctl.n_live;
+    std::vector<double> e(3 * nl);
+    std::vector<uint32_t> u(nl);
+    if (nl && (hipMemcpy(e.data(), h->Eout, 8 * 3 * nl, hipMemcpyDeviceToHost) ||
+               hipMemcpy(u.data(), h->Eid, 4 * nl, hipMemcpyDeviceToHost)))
+        return mark_failed(h, fail(SIM_EDEVICE, "field copy failed"));
+    std::memset(E, 0, sizeof(double) * 3 * (size_t)h->lo.n);
+    for (size_t i = 0; i < nl; ++i) {
+        auto it = std::lower_bound(h->id_index.begin(), h->id_index.end(),
+                                   std::make_pair(u[i], (int64_t)-1));
+        if (it == h->id_index.end() || it->first != u[i]) return fail(SIM_EDEVICE, "unknown id");
+        for (int j = 0; j < 3; ++j) E[3 * it->second + j] = e[3 * i + j];
+    }
+    return SIM_OK;
+}
+
+int sim_profile(sim_t *h, int64_t k, double *kernel_ms, int32_t n_kernels)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (k <= 0 || !kernel_ms) return fail(SIM_EINVAL, "k must be > 0 and kernel_ms non-NULL");
+    if (h->step_host + k > h->lo.n_steps) return fail(SIM_ERANGE, "steps beyond n_steps");
+    hipEvent_t ev[KN_COUNT + 1];
+    for (int i = 0; i <= KN_COUNT; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) return fail(SIM_EDEVICE, "hipEventCreate failed");
+    std::vector<double> acc(KN_COUNT, 0.0);
+    for (int64_t s = 0; s < k && rc == SIM_OK; ++s) {
+        rc = launch_step(h, h->stream, false, ev);
+        if (rc == SIM_OK && hipEventSynchronize(ev[KN_COUNT]) != hipSuccess)
+            rc = fail(SIM_EDEVICE, "event sync failed");
+        for (int i = 0; i < KN_COUNT && rc == SIM_OK; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) acc[i] += ms;
+        }
+        if (rc == SIM_OK) h->step_host += 1;
+    }
+    for (int i = 0; i <= KN_COUNT; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc) return mark_failed(h, rc);
+    for (int i = 0; i < KN_COUNT && i < n_kernels; ++i) kernel_ms[i] = acc[i] / (double)k;
+    return SIM_OK;
+}
+
+int32_t sim_num_kernels(void) { return KN_COUNT; }
+
+const char *sim_kernel_name(int32_t i)
+{
+    if (i < 0 || i >= KN_COUNT) return "";
+    return kKernelNames[i];
+}
+
+int sim_info(sim_t *h, int64_t *n, int32_t *tile, int32_t *channels)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (n) *n = h->lo.n;
+    if (tile) *tile = kWave;
+    if (channels) *channels = h->lo.C;
+    return SIM_OK;
+}
+
+void sim_destroy(sim_t *h)
+{
+    if (!h) return;
+    release(h);
+    delete h;
+}
+
+const char *sim_strerror(int status)
+{
+    switch (status) {
+    case SIM_OK: return "ok";
+    case SIM_EINVAL: return "invalid argument";
+    case SIM_ENOMEM: return "out of memory or over the memory limit";
+    case SIM_ERANGE: return "index out of range";
+    case SIM_ESTATE: return "invalid or failed handle";
+    case SIM_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char *sim_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

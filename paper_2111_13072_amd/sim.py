@@ -1,0 +1,236 @@
+"""Thin ctypes binding of libmrpsim.so (C ABI in include/mrpsim.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of csrc/mrpsim.hip.  There is no CPU fallback; if the library is not
+built this module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from .build import LIB
+
+SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_ERANGE, SIM_ESTATE, SIM_EDEVICE = 0, -1, -2, -3, -4, -5
+SIM_M_FULL, SIM_M_AXISYM = 0, 1
+SIM_BC_ABSORB, SIM_BC_SPECULAR, SIM_BC_DIFFUSE = 0, 1, 2
+SIM_FP64, SIM_FP32_COMP = 0, 1
+
+# Every function include/mrpsim.h declares.
+EXPORTED = ("sim_params_default", "sim_create", "sim_step", "sim_sync", "sim_read_response",
+            "sim_read_state", "sim_eval_field", "sim_profile", "sim_num_kernels",
+            "sim_kernel_name", "sim_footprint_bytes", "sim_info", "sim_destroy",
+            "sim_strerror", "sim_last_error")
+
+
+class sim_params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("reserved0", C.c_uint32),
+        ("d", C.c_double), ("eps_r", C.c_double), ("r_out", C.c_double), ("dt", C.c_double),
+        ("ntilde", C.c_double), ("ion_density", C.c_double), ("q_surface0", C.c_double),
+        ("l_max", C.c_int32), ("m_mode", C.c_int32), ("probe_bc", C.c_int32),
+        ("wall_bc", C.c_int32), ("precision", C.c_int32), ("tile", C.c_int32),
+        ("seed", C.c_uint64), ("mem_limit_bytes", C.c_uint64),
+    ]
+
+
+class SimError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{message} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libmrpsim.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        raise ImportError(f"{LIB} is not built; run __graft_entry__.build() first")
+    L = C.CDLL(LIB)
+    dp = C.POINTER(C.c_double)
+    P = C.POINTER(sim_params)
+    H = C.c_void_p
+    L.sim_params_default.argtypes = [P]
+    L.sim_params_default.restype = None
+    L.sim_create.argtypes = [P, C.c_int64, dp, dp, C.POINTER(C.c_uint32), dp, C.c_int64,
+                             C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]
+    L.sim_step.argtypes = [H, C.c_int64]
+    L.sim_sync.argtypes = [H]
+    L.sim_read_response.argtypes = [H, C.c_int64, C.c_int64, dp]
+    L.sim_read_state.argtypes = [H, dp, dp, C.POINTER(C.c_uint8), dp, C.POINTER(C.c_int64)]
+    L.sim_eval_field.argtypes = [H, dp]
+    L.sim_profile.argtypes = [H, C.c_int64, dp, C.c_int32]
+    L.sim_num_kernels.argtypes = []
+    L.sim_num_kernels.restype = C.c_int32
+    L.sim_kernel_name.argtypes = [C.c_int32]
+    L.sim_kernel_name.restype = C.c_char_p
+    L.sim_footprint_bytes.argtypes = [P, C.c_int64, C.c_int64]
+    L.sim_footprint_bytes.restype = C.c_int64
+    L.sim_info.argtypes = [H, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.sim_destroy.argtypes = [H]
+    L.sim_destroy.restype = None
+    L.sim_strerror.argtypes = [C.c_int]
+    L.sim_strerror.restype = C.c_char_p
+    L.sim_last_error.argtypes = []
+    L.sim_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("sim_params_default", "sim_num_kernels", "sim_kernel_name",
+                        "sim_footprint_bytes", "sim_destroy", "sim_strerror", "sim_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != SIM_OK:
+        L = lib()
+        raise SimError(rc, f"{L.sim_strerror(rc).decode()}: {L.sim_last_error().decode()}")
+
+
+@dataclass
+class SimParams:
+    d: float = 0.25
+    eps_r: float = 4.0
+    r_out: float = 5.0
+    dt: float = 0.05
+    ntilde: float = 1.0
+    ion_density: float = 1.0
+    q_surface0: float = 0.0
+    l_max: int = 8
+    m_mode: int = SIM_M_FULL
+    probe_bc: int = SIM_BC_ABSORB
+    wall_bc: int = SIM_BC_SPECULAR
+    precision: int = SIM_FP64
+    tile: int = 0
+    seed: int = 0
+    mem_limit_bytes: int = 0
+
+    def to_c(self) -> sim_params:
+        p = sim_params()
+        lib().sim_params_default(C.byref(p))
+        for f, _ in sim_params._fields_:
+            if f in ("struct_size", "reserved0"):
+                continue
+            setattr(p, f, getattr(self, f))
+        return p
+
+
+def footprint_bytes(params: SimParams, n: int, n_steps: int) -> int:
+    p = params.to_c()
+    v = lib().sim_footprint_bytes(C.byref(p), n, n_steps)
+    if v < 0:
+        _check(int(v))
+    return int(v)
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _current_torch_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class Sim:
+    """One simulation handle (sim_create ... sim_destroy)."""
+
+    def __init__(self, params: SimParams, pos, vel, u_asy, ids=None, start_step: int = 0,
+                 stream=None, use_torch_stream: bool = True):
+        L = lib()
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        u = np.ascontiguousarray(u_asy, dtype=np.float64)
+        n = pos.shape[0]
+        if pos.shape != (n, 3) or vel.shape != (n, 3):
+            raise ValueError("pos and vel must have shape [n, 3]")
+        self.n = n
+        self.n_steps = u.shape[0]
+        self._ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
+        idp = None if self._ids is None else self._ids.ctypes.data_as(C.POINTER(C.c_uint32))
+        if stream is None and use_torch_stream:
+            stream = _current_torch_stream()
+        self._p = params.to_c()
+        h = C.c_void_p()
+        rc = L.sim_create(C.byref(self._p), n, _dp(pos), _dp(vel), idp,
+                          _dp(u) if u.size else None, self.n_steps, start_step, stream,
+                          C.byref(h))
+        _check(rc)
+        self._h = h
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sim_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _handle(self):
+        if not getattr(self, "_h", None):
+            raise SimError(SIM_ESTATE, "simulation is closed")
+        return self._h
+
+    # -- calls -------------------------------------------------------------
+    def step(self, k: int = 1):
+        _check(lib().sim_step(self._handle(), k))
+
+    def sync(self):
+        _check(lib().sim_sync(self._handle()))
+
+    def read_response(self, first: int, count: int) -> np.ndarray:
+        out = np.zeros(count)
+        _check(lib().sim_read_response(self._handle(), first, count, _dp(out)))
+        return out
+
+    def read_state(self) -> dict:
+        pos = np.zeros((self.n, 3))
+        vel = np.zeros((self.n, 3))
+        alive = np.zeros(self.n, dtype=np.uint8)
+        qs = C.c_double()
+        st = C.c_int64()
+        _check(lib().sim_read_state(self._handle(), _dp(pos), _dp(vel),
+                                    alive.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(qs),
+                                    C.byref(st)))
+        return dict(pos=pos, vel=vel, alive=alive, q_surface=qs.value, step=st.value)
+
+    def eval_field(self) -> np.ndarray:
+        E = np.zeros((self.n, 3))
+        _check(lib().sim_eval_field(self._handle(), _dp(E)))
+        return E
+
+    def profile(self, k: int) -> dict:
+        L = lib()
+        nk = L.sim_num_kernels()
+        ms = np.zeros(nk)
+        _check(L.sim_profile(self._handle(), k, _dp(ms), nk))
+        return {L.sim_kernel_name(i).decode(): float(ms[i]) for i in range(nk)}
+
+    def info(self) -> dict:
+        n = C.c_int64()
+        t = C.c_int32()
+        c = C.c_int32()
+        _check(lib().sim_info(self._handle(), C.byref(n), C.byref(t), C.byref(c)))
+        return dict(n=n.value, tile=t.value, channels=c.value)
