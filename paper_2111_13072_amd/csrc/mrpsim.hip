@@ -82,11 +82,15 @@ struct Tables {
     const double *qmm;      // sectoral normalisation Q_m^m
     const double *alm;      // Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m
     const double *blm;
+    const int *chl;         // degree l of each channel in stream order
 };
 
+// Channels are kept in "stream order": m = 0..m_top outer, l = max(m,1)..L
+// inner, cos then sin for m > 0.  l = 0 has no channel: its field is Gauss's
+// law over the radial order (computed in the field kernel).
 struct KParams {
     int L;          // l_max
-    int C;          // channels: (L+1)^2 (full) or L+1 (axisymmetric)
+    int C;          // channels: (L+1)^2 - 1 (full) or L (axisymmetric)
     int C2;         // 2C: interior then exterior
     int n_tiles;
     int n_chunks;
@@ -98,19 +102,6 @@ struct KParams {
 };
 
 __host__ __device__ inline int tri(int l, int m) { return l * (l + 1) / 2 + m; }
-
-// Channel index of (l, m, cos|sin) in the full basis; m = 0 has only cos.
-__host__ __device__ inline int chan_full(int l, int m, int sin_part)
-{
-    return m == 0 ? l * l : l * l + 2 * m - 1 + sin_part;
-}
-
-__device__ inline double sum_wave(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 
 __device__ inline uint32_t uniform_u32(uint32_t v)
 {
@@ -283,21 +274,25 @@ __global__ void k_sort_permute(const Ctl *ctl, const uint32_t *perm, State A, St
 //   R_lm^c = Q_l^m C_m,  R_lm^s = Q_l^m S_m,  I_lm = r^-(2l+1) R_lm,
 // normalised so that sum_m Y_lm(a) Y_lm(b) = (2l+1)/(4 pi) P_l(a.b).
 
+constexpr int kBatch = 16;       // channels per LDS batch of the tile reduction
+constexpr int kBatchPad = kWave + 1;
+
 template <bool FULL>
 __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tables tb,
                                                     KParams kp, double *S)
 {
+    // Per wave: the 64 particles of one tile write their terms of a batch of
+    // 16 channels into LDS rows; then lane (channel, kind, half) sums 32 rows
+    // and the two halves are combined across the wave.
+    __shared__ double bufR[kWavesPerBlock][kBatch][kBatchPad];
+    __shared__ double bufI[kWavesPerBlock][kBatch][kBatchPad];
     const int lane = threadIdx.x & 63;
-    const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
-    if ((int)tile >= kp.n_tiles) return;
+    const int w = threadIdx.x >> 6;
+    const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + w);
+    const bool tile_ok = (int)tile < kp.n_tiles;
     const uint32_t n = ctl->n_live;
-    double *St = S + (size_t)tile * kp.C2;
-    if (tile * kWave >= n) {
-        for (int c = lane; c < kp.C2; c += kWave) St[c] = 0.0;
-        return;
-    }
     const uint32_t p = tile * kWave + lane;
-    const bool valid = p < n;
+    const bool valid = tile_ok && p < n;
     double x = 0.0, y = 0.0, z = 2.0;
     if (valid) {
         x = B.x[p];
@@ -310,13 +305,31 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
     const double inv_r = 1.0 / sqrt(r2);
     const int L = kp.L, C = kp.C;
     const int m_top = FULL ? L : 0;
+    double *St = S + (size_t)tile * kp.C2;
+
+    const int cc = lane & (kBatch - 1);
+    const int kind = (lane >> 4) & 1;
+    const int half = lane >> 5;
+    int slot = 0, base = 0;
+    auto flush = [&](int count) {
+        __syncthreads();
+        double acc = 0.0;
+        const double *row = kind ? &bufI[w][cc][32 * half] : &bufR[w][cc][32 * half];
+        if (cc < count) {
+#pragma unroll 8
+            for (int r = 0; r < 32; ++r) acc += row[r];
+        }
+        acc += __shfl_xor(acc, 32);
+        if (tile_ok && half == 0 && cc < count) St[(kind ? C : 0) + base + cc] = acc;
+        __syncthreads();
+    };
 
     double Cm = 1.0, Sm = 0.0;
     double s_mm = inv_r;  // r^-(2m+1)
     for (int m = 0; m <= m_top; ++m) {
         if (m > 0) {
-            double nc = x * Cm - y * Sm;
-            double ns = x * Sm + y * Cm;
+            const double nc = x * Cm - y * Sm;
+            const double ns = x * Sm + y * Cm;
             Cm = nc;
             Sm = ns;
             s_mm *= inv_r2;
@@ -329,48 +342,35 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
             else Qv = tb.alm[tri(l, m)] * z * Qp - tb.blm[tri(l, m)] * r2 * Qpp;
             Qpp = Qp;
             Qp = Qv;
-            const int cc = FULL ? chan_full(l, m, 0) : l;
-            if (l == 0) {   // monopole: Gauss's law over the radial order, not moments
-                if (lane == 0) {
-                    St[0] = 0.0;
-                    St[C] = 0.0;
+            if (l > 0) {
+                const double rc = q * Qv * Cm;
+                bufR[w][slot][lane] = rc;
+                bufI[w][slot][lane] = rc * sl;
+                if (++slot == kBatch) {
+                    flush(kBatch);
+                    base += kBatch;
+                    slot = 0;
                 }
-                sl *= inv_r2;
-                continue;
-            }
-            double rc = q * Qv * Cm;
-            double sr = sum_wave(rc);
-            double si = sum_wave(rc * sl);
-            if (lane == 0) {
-                St[cc] = sr;
-                St[C + cc] = si;
-            }
-            if (FULL && m > 0) {
-                double rs = q * Qv * Sm;
-                double sr2 = sum_wave(rs);
-                double si2 = sum_wave(rs * sl);
-                if (lane == 0) {
-                    St[cc + 1] = sr2;
-                    St[C + cc + 1] = si2;
+                if (FULL && m > 0) {
+                    const double rs = q * Qv * Sm;
+                    bufR[w][slot][lane] = rs;
+                    bufI[w][slot][lane] = rs * sl;
+                    if (++slot == kBatch) {
+                        flush(kBatch);
+                        base += kBatch;
+                        slot = 0;
+                    }
                 }
             }
             sl *= inv_r2;
         }
     }
+    if (slot > 0) flush(slot);
 }
 
 // ---------------------------------------------------------------------------
 // Carries: prefix/suffix scans over tiles, totals, coefficients, Q_diff
 // ---------------------------------------------------------------------------
-
-__device__ inline int chan_l(int c, bool full)
-{
-    if (!full) return c;
-    int l = (int)sqrt((double)c);
-    while (l * l > c) --l;
-    while ((l + 1) * (l + 1) <= c) ++l;
-    return l;
-}
 
 __global__ __launch_bounds__(kBlock) void k_chunk_sums(const double *S, double *chunkS, KParams kp)
 {
@@ -389,28 +389,41 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(const double *chunkS, dou
     const int c = blockIdx.x * kBlock + threadIdx.x;
     // Q_S = q_surface0 + q * (absorbed so far); it enters the field as an
     // interior l = 0 charge (Q_S / (4 pi r), Sec. 3) in the field kernel.
-    const double qs = kp.q_surface0 + kQ * (double)ctl->n_dead;
-    if (c == 0) ctl->q_surface = qs;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        ctl->q_surface = kp.q_surface0 + kQ * (double)ctl->n_dead;
     if (c >= kp.C2) return;
+    constexpr int U = 16;   // loads kept in flight along the serial chain
+    const int nc = kp.n_chunks;
+    double run = 0.0;
     if (c < kp.C) {
-        double run = 0.0;
-        for (int j = 0; j < kp.n_chunks; ++j) {
-            chunkC[(size_t)j * kp.C2 + c] = run;
-            run += chunkS[(size_t)j * kp.C2 + c];
+        for (int j0 = 0; j0 < nc; j0 += U) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = (j0 + u < nc) ? chunkS[(size_t)(j0 + u) * kp.C2 + c] : 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (j0 + u < nc) chunkC[(size_t)(j0 + u) * kp.C2 + c] = run;
+                run += v[u];
+            }
         }
     } else {
-        double run = 0.0;
-        for (int j = kp.n_chunks - 1; j >= 0; --j) {
-            chunkC[(size_t)j * kp.C2 + c] = run;
-            run += chunkS[(size_t)j * kp.C2 + c];
+        for (int j0 = nc - 1; j0 >= 0; j0 -= U) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = (j0 - u >= 0) ? chunkS[(size_t)(j0 - u) * kp.C2 + c] : 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (j0 - u >= 0) chunkC[(size_t)(j0 - u) * kp.C2 + c] = run;
+                run += v[u];
+            }
         }
         T[c - kp.C] = run;
     }
 }
 
 // Constant part of the interior coefficient: image response -f_l T_lm and the
-// hemisphere drive (odd l, m = 0); and the probe response Q_diff(t_step).
-template <bool FULL>
+// hemisphere drive (odd l, m = 0; stream positions 0..L-1 hold m = 0, l = 1..L);
+// and the probe response Q_diff(t_step).
 __global__ __launch_bounds__(kBlock) void k_coef_prep(const double *T, Ctl *ctl,
                                                       const double *u_asy, double *qdiff,
                                                       Tables tb, KParams kp, double *Kc)
@@ -418,22 +431,21 @@ __global__ __launch_bounds__(kBlock) void k_coef_prep(const double *T, Ctl *ctl,
     const int64_t step = ctl->step;
     const double u = (step >= 0 && step < kp.n_steps) ? u_asy[step] : 0.0;
     for (int c = threadIdx.x; c < kp.C; c += kBlock) {
-        const int l = chan_l(c, FULL);
-        const bool m0 = FULL ? (c == l * l) : true;
+        const int l = tb.chl[c];
         double k = -tb.ftil[l] * T[c] * tb.wl[l];
-        if (m0) k += u * tb.drive_w[l];
+        if (c < kp.L) k += u * tb.drive_w[l];
         Kc[c] = k;
     }
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int l = 1; l <= kp.L; l += 2) s += tb.drive_w[l] * T[FULL ? l * l : l];
+        for (int l = 1; l <= kp.L; l += 2) s += tb.drive_w[l] * T[l - 1];
         if (step >= 0 && step < kp.n_steps) qdiff[step] = -s / kp.ntilde;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_chunk_apply(const double *S, const double *chunkC,
                                                         const double *Kc, Tables tb, KParams kp,
-                                                        bool full, double *coef)
+                                                        double *coef)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
     if (c >= kp.C2) return;
@@ -441,14 +453,14 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(const double *S, const d
     const int t0 = j * kChunk, t1 = min(t0 + kChunk, kp.n_tiles);
     double run = chunkC[(size_t)j * kp.C2 + c];
     if (c < kp.C) {
-        const double w = tb.wl[chan_l(c, full)];
+        const double w = tb.wl[tb.chl[c]];
         const double k = Kc[c];
         for (int t = t0; t < t1; ++t) {
             coef[(size_t)t * kp.C2 + c] = run * w + k;
             run += S[(size_t)t * kp.C2 + c];
         }
     } else {
-        const double w = tb.wl[chan_l(c - kp.C, full)];
+        const double w = tb.wl[tb.chl[c - kp.C]];
         for (int t = t1 - 1; t >= t0; --t) {
             coef[(size_t)t * kp.C2 + c] = run * w;
             run += S[(size_t)t * kp.C2 + c];
@@ -519,7 +531,8 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
                                                        KParams kp, double *Eout, uint32_t *Eid)
 {
     __shared__ double sh_xh[kWavesPerBlock][kWave], sh_yh[kWavesPerBlock][kWave],
-        sh_zh[kWavesPerBlock][kWave], sh_r[kWavesPerBlock][kWave], sh_r2[kWavesPerBlock][kWave];
+        sh_zh[kWavesPerBlock][kWave], sh_r[kWavesPerBlock][kWave], sh_r2[kWavesPerBlock][kWave],
+        sh_ir[kWavesPerBlock][kWave];
     __shared__ uint32_t sh_uid[kWavesPerBlock][kWave];
 
     const int lane = threadIdx.x & 63;
@@ -552,6 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     sh_zh[w][lane] = zh;
     sh_r[w][lane] = r;
     sh_r2[w][lane] = r2;
+    sh_ir[w][lane] = inv_r;
     sh_uid[w][lane] = uid;
     __syncthreads();
     if (!tile_live) return;
@@ -569,6 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
         const int m_top = FULL ? L : 0;
         double Cm = 1.0, Sm = 0.0, Cm1 = 0.0, Sm1 = 0.0;
         double s_mm = inv_r;
+        int k = 0;   // stream position of the channel
         for (int m = 0; m <= m_top; ++m) {
             if (m > 0) {
                 Cm1 = Cm;
@@ -602,16 +617,17 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
                     sl *= inv_r2;
                     continue;
                 }
-                const int cc = FULL ? chan_full(l, m, 0) : l;
-                const double ac = cf[cc], bc = cf[C + cc];
+                const double ac = cf[k], bc = cf[C + k];
                 const double tc = bc + sl * ac;
                 const double two_l1 = 2.0 * l + 1.0;
                 if (!FULL || m == 0) {
                     Gs += tc * Ds;
                     Gz += tc * Dz;
                     Gr += two_l1 * sl * Qv * ac;
+                    k += 1;
                 } else {
-                    const double as = cf[cc + 1], bs = cf[C + cc + 1];
+                    const double as = cf[k + 1], bs = cf[C + k + 1];
+                    k += 2;
                     const double ts = bs + sl * as;
                     const double U = tc * Cm + ts * Sm;
                     Gs += U * Ds;
@@ -637,12 +653,12 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
         double ax = 0.0, ay = 0.0, az = 0.0;
         for (int j = 0; j < jn; ++j) {
             const double xj = sh_xh[w][j], yj = sh_yh[w][j], zj = sh_zh[w][j];
-            const double rj = sh_r[w][j], r2j = sh_r2[w][j];
+            const double rj = sh_r[w][j], r2j = sh_r2[w][j], irj = sh_ir[w][j];
             const uint32_t uj = sh_uid[w][j];
             if (j == lane) continue;
             const bool outer = (r2 > r2j) || (r2 == r2j && uid > uj);
-            const double rho = outer ? rj * inv_r : r / rj;
-            const double scale = outer ? inv_r2 : 1.0 / (rj * r);
+            const double rho = outer ? rj * inv_r : r * irj;
+            const double scale = outer ? inv_r2 : irj * inv_r;
             double u, vx_, vy_, vz_;   // angular argument and its direction vector
             if (FULL) {
                 u = xh * xj + yh * yj + zh * zj;
@@ -882,7 +898,7 @@ bool make_layout(const sim_params *p, int64_t n, int64_t n_steps, Layout *lo, st
     lo->n = n;
     lo->L = p->l_max;
     lo->full = p->m_mode == SIM_M_FULL;
-    lo->C = lo->full ? (p->l_max + 1) * (p->l_max + 1) : p->l_max + 1;
+    lo->C = lo->full ? (p->l_max + 1) * (p->l_max + 1) - 1 : p->l_max;
     lo->C2 = 2 * lo->C;
     lo->n_tiles = (int)((n + kWave - 1) / kWave);
     lo->n_chunks = (lo->n_tiles + kChunk - 1) / kChunk;
@@ -919,6 +935,7 @@ struct sim {
              *off = nullptr, *bsum = nullptr;
     double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr, *Kc = nullptr,
            *coef = nullptr, *u_asy = nullptr, *qdiff = nullptr, *tables = nullptr, *Eout = nullptr;
+    int *chl = nullptr;
     uint32_t *Eid = nullptr;
     Ctl *ctl = nullptr;
     Tables tb{};
@@ -972,6 +989,7 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->qdiff, (size_t)std::max<int64_t>(lo.n_steps, 1));
     const int L = lo.L;
     al.add(&h->tables, (size_t)7 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2));
+    al.add(&h->chl, (size_t)std::max(lo.C, 1));
     al.add(&h->Eout, 3 * n);
     al.add(&h->Eid, n);
     al.add(&h->ctl, 1);
@@ -1055,18 +1073,20 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     mark(KN_SORT_PERMUTE);
     k_sort_permute<<<gN, kBlock, 0, s>>>(h->ctl, h->perm, h->A, h->B);
     mark(KN_MOMENTS);
-    if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
-    else k_moments<false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
+    if (lo.C > 0) {
+        if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
+        else k_moments<false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
+    }
     mark(KN_CHUNK_SUMS);
-    k_chunk_sums<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkS, kp);
+    if (lo.C > 0) k_chunk_sums<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkS, kp);
     mark(KN_CHUNK_SCAN);
-    k_chunk_scan<<<gC, kBlock, 0, s>>>(h->chunkS, h->chunkC, h->T, h->ctl, kp);
+    k_chunk_scan<<<std::max(gC, 1u), kBlock, 0, s>>>(h->chunkS, h->chunkC, h->T, h->ctl, kp);
     mark(KN_COEF_PREP);
-    if (lo.full) k_coef_prep<true><<<1, kBlock, 0, s>>>(h->T, h->ctl, h->u_asy, h->qdiff, h->tb, kp, h->Kc);
-    else k_coef_prep<false><<<1, kBlock, 0, s>>>(h->T, h->ctl, h->u_asy, h->qdiff, h->tb, kp, h->Kc);
+    k_coef_prep<<<1, kBlock, 0, s>>>(h->T, h->ctl, h->u_asy, h->qdiff, h->tb, kp, h->Kc);
     mark(KN_CHUNK_APPLY);
-    k_chunk_apply<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkC, h->Kc, h->tb, kp, lo.full,
-                                                           h->coef);
+    if (lo.C > 0)
+        k_chunk_apply<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkC, h->Kc, h->tb, kp,
+                                                               h->coef);
     mark(KN_FIELD_PUSH);
     if (field_only) {
         if (lo.full)
@@ -1234,6 +1254,14 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
     h->tb.qmm = tb + 6 * (L + 1);
     h->tb.alm = tb + 7 * (L + 1);
     h->tb.blm = tb + 7 * (L + 1) + (L + 1) * (L + 2) / 2;
+    h->tb.chl = h->chl;
+    // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
+    std::vector<int> chl;
+    for (int m = 0; m <= (lo.full ? L : 0); ++m)
+        for (int l = std::max(m, 1); l <= L; ++l)
+            for (int sc = 0; sc < (m > 0 ? 2 : 1); ++sc) chl.push_back(l);
+    if ((int)chl.size() != lo.C) return bail(fail(SIM_EDEVICE, "channel count mismatch"));
+    if (chl.empty()) chl.push_back(0);
 
     KParams &kp = h->kp;
     kp.L = lo.L;
@@ -1271,6 +1299,7 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
         hipMemcpy(h->A.uid, uid.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice) ||
         hipMemset(h->dead, 0, (size_t)n) ||
         hipMemcpy(h->tables, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->chl, chl.data(), sizeof(int) * chl.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice) ||
         hipMemcpy(h->qdiff, zeros.data(), sizeof(double) * zeros.size(), hipMemcpyHostToDevice) ||
         (n_steps > 0 &&
