@@ -79,6 +79,8 @@ struct Tables {
     const double *self_w;   // f_l / (4 pi ntilde)
     const double *nfA;      // (2l+1)/(l+1)
     const double *nfB;      // l/(l+1)
+    const double *lval;     // l
+    const double *tl1;      // 2l+1
     const double *qmm;      // sectoral normalisation Q_m^m
     const double *alm;      // Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m
     const double *blm;
@@ -277,15 +279,27 @@ __global__ void k_sort_permute(const Ctl *ctl, const uint32_t *perm, State A, St
 constexpr int kBatch = 16;       // channels per LDS batch of the tile reduction
 constexpr int kBatchPad = kWave + 1;
 
+// Exchange the upper 32 lanes of a with the lower 32 lanes of b.
+__device__ inline void swap_wave_halves(double &a, double &b)
+{
+    const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    const auto hi =
+        __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+    a = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | (uint64_t)lo[0]));
+    b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | (uint64_t)lo[1]));
+}
+
 template <bool FULL>
 __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tables tb,
                                                     KParams kp, double *S)
 {
-    // Per wave: the 64 particles of one tile write their terms of a batch of
-    // 16 channels into LDS rows; then lane (channel, kind, half) sums 32 rows
-    // and the two halves are combined across the wave.
-    __shared__ double bufR[kWavesPerBlock][kBatch][kBatchPad];
-    __shared__ double bufI[kWavesPerBlock][kBatch][kBatchPad];
+    // Per wave (one tile of 64 particles): for each channel, q R (interior)
+    // and q I (exterior) are first folded across the two wave halves with a
+    // lane swap (lanes 0-31 then hold R over particle pairs, lanes 32-63 I),
+    // written to an LDS row, and every 16 channels each lane (channel, kind,
+    // quarter) sums 16 rows; the quarters are combined across the wave.
+    __shared__ double buf[kWavesPerBlock][kBatch][kBatchPad];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + w);
@@ -308,20 +322,24 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
     double *St = S + (size_t)tile * kp.C2;
 
     const int cc = lane & (kBatch - 1);
-    const int kind = (lane >> 4) & 1;
+    const int kind = (lane >> 4) & 1;   // 0: interior (R), 1: exterior (I)
     const int half = lane >> 5;
     int slot = 0, base = 0;
-    auto flush = [&](int count) {
-        __syncthreads();
-        double acc = 0.0;
-        const double *row = kind ? &bufI[w][cc][32 * half] : &bufR[w][cc][32 * half];
-        if (cc < count) {
-#pragma unroll 8
-            for (int r = 0; r < 32; ++r) acc += row[r];
+    auto put = [&](double rv, double iv) {
+        swap_wave_halves(rv, iv);
+        buf[w][slot][lane] = rv + iv;
+        if (++slot == kBatch) {
+            __syncthreads();
+            double acc = 0.0;
+            const double *row = &buf[w][cc][kind * 32 + half * 16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc += row[r];
+            acc += __shfl_xor(acc, 32);
+            if (tile_ok && half == 0) St[(kind ? C : 0) + base + cc] = acc;
+            __syncthreads();
+            base += kBatch;
+            slot = 0;
         }
-        acc += __shfl_xor(acc, 32);
-        if (tile_ok && half == 0 && cc < count) St[(kind ? C : 0) + base + cc] = acc;
-        __syncthreads();
     };
 
     double Cm = 1.0, Sm = 0.0;
@@ -344,28 +362,27 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
             Qp = Qv;
             if (l > 0) {
                 const double rc = q * Qv * Cm;
-                bufR[w][slot][lane] = rc;
-                bufI[w][slot][lane] = rc * sl;
-                if (++slot == kBatch) {
-                    flush(kBatch);
-                    base += kBatch;
-                    slot = 0;
-                }
+                put(rc, rc * sl);
                 if (FULL && m > 0) {
                     const double rs = q * Qv * Sm;
-                    bufR[w][slot][lane] = rs;
-                    bufI[w][slot][lane] = rs * sl;
-                    if (++slot == kBatch) {
-                        flush(kBatch);
-                        base += kBatch;
-                        slot = 0;
-                    }
+                    put(rs, rs * sl);
                 }
             }
             sl *= inv_r2;
         }
     }
-    if (slot > 0) flush(slot);
+    if (slot > 0) {   // last, partial batch
+        const int count = slot;
+        __syncthreads();
+        double acc = 0.0;
+        const double *row = &buf[w][cc][kind * 32 + half * 16];
+        if (cc < count) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc += row[r];
+        }
+        acc += __shfl_xor(acc, 32);
+        if (tile_ok && half == 0 && cc < count) St[(kind ? C : 0) + base + cc] = acc;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -646,68 +663,86 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     double Ez = -(2.0 * Gs * z + Gz - Gr * z * inv_r2);
 
     // ---- near field: own tile, pair by pair (direct part of G~_L) ----
-    // k outer: grad_k D = (1/r_k^2) sum_l rho^l [-(l+1) P_l xh_k + P'_l (xh_j - u xh_k)]
-    // k inner: grad_k D = (1/(r_j r_k)) sum_l rho^l [l P_l xh_k + P'_l (xh_j - u xh_k)]
-    // with rho = r_< / r_>; E += -(q / (4 pi nt)) grad_k D.
+    // For the pair (k, j) with rho = r_< / r_>, u = angular argument:
+    //   outer one: grad D = (1/r_>^2)       sum_l rho^l [-(l+1) P_l xh + P'_l v]
+    //   inner one: grad D = (1/(r_< r_>))   sum_l rho^l [ l P_l xh     + P'_l v]
+    // where v = xh_other - u xh (full) or e_z - cos(th) xh (axisymmetric).
+    // The three sums are symmetric in (k, j), so each pair is evaluated once:
+    // at step s lane k takes partner (k + s) mod 64 and hands the partner's
+    // gradient to it through a lane rotation.  E += -(q / (4 pi nt)) grad D.
     {
         double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int j = 0; j < jn; ++j) {
+        for (int sft = 1; sft <= kWave / 2; ++sft) {
+            const int j = (lane + sft) & (kWave - 1);
+            const bool active = lane < jn && j < jn && (sft < kWave / 2 || lane < kWave / 2);
             const double xj = sh_xh[w][j], yj = sh_yh[w][j], zj = sh_zh[w][j];
             const double rj = sh_r[w][j], r2j = sh_r2[w][j], irj = sh_ir[w][j];
             const uint32_t uj = sh_uid[w][j];
-            if (j == lane) continue;
-            const bool outer = (r2 > r2j) || (r2 == r2j && uid > uj);
-            const double rho = outer ? rj * inv_r : r * irj;
-            const double scale = outer ? inv_r2 : irj * inv_r;
-            double u, vx_, vy_, vz_;   // angular argument and its direction vector
-            if (FULL) {
-                u = xh * xj + yh * yj + zh * zj;
-                vx_ = xj - u * xh;
-                vy_ = yj - u * yh;
-                vz_ = zj - u * zh;
-            } else {
-                u = zh;
-                vx_ = -zh * xh;
-                vy_ = -zh * yh;
-                vz_ = 1.0 - zh * zh;
-            }
-            // Legendre recurrences
-            double P0 = 1.0, P1 = u, dP0 = 0.0, dP1 = 1.0;
-            double Pj0 = 1.0, Pj1 = zj;   // partner P_l(cos th_j), axisymmetric only
-            double rl = 1.0;
-            double S1 = 0.0, Sl = 0.0, SB = 0.0;
-            rl = rho;    // l = 0 is handled by Gauss's law below
+            const bool k_outer = (r2 > r2j) || (r2 == r2j && uid > uj);
+            const double rho = k_outer ? rj * inv_r : r * irj;
+            const double sc_out = k_outer ? inv_r2 : irj * irj;   // 1 / r_>^2
+            const double sc_in = inv_r * irj;                    // 1 / (r_< r_>)
+            const double u = FULL ? xh * xj + yh * yj + zh * zj : zh;
+            double S1 = 0.0, Sl = 0.0, SBk = 0.0, SBj = 0.0;
+            double P0 = 1.0, P1 = u, dP0 = 0.0, dP1 = 1.0;        // P_l(u) (own cos th if axisym)
+            double Q0 = 1.0, Q1 = zj, dQ0 = 0.0, dQ1 = 1.0;       // partner P_l(cos th_j), axisym
+            double rl = rho;                                    // l = 0: Gauss's law below
             for (int l = 1; l <= L; ++l) {
-                double ang, dang;
+                const double A = tb.nfA[l], Bc = tb.nfB[l], tl1 = tb.tl1[l], dl = tb.lval[l];
                 if (FULL) {
-                    ang = P1;
-                    dang = dP1;
+                    const double t = rl * P1;
+                    S1 += t;
+                    Sl += dl * t;
+                    SBk += rl * dP1;
                 } else {
-                    ang = P1 * Pj1;
-                    dang = dP1 * Pj1;
+                    const double t = rl * P1 * Q1;
+                    S1 += t;
+                    Sl += dl * t;
+                    SBk += rl * dP1 * Q1;
+                    SBj += rl * P1 * dQ1;
+                    const double Q2 = A * zj * Q1 - Bc * Q0;
+                    const double dQ2 = dQ0 + tl1 * Q1;
+                    Q0 = Q1;
+                    Q1 = Q2;
+                    dQ0 = dQ1;
+                    dQ1 = dQ2;
                 }
-                S1 += rl * ang;
-                Sl += (double)l * rl * ang;
-                SB += rl * dang;
-                // advance to l + 1
-                const double A = tb.nfA[l], Bc = tb.nfB[l];
                 const double P2 = A * u * P1 - Bc * P0;
-                const double dP2 = dP0 + (2.0 * l + 1.0) * P1;
+                const double dP2 = dP0 + tl1 * P1;
                 P0 = P1;
                 P1 = P2;
                 dP0 = dP1;
                 dP1 = dP2;
-                if (!FULL) {
-                    const double Pj2 = A * zj * Pj1 - Bc * Pj0;
-                    Pj0 = Pj1;
-                    Pj1 = Pj2;
-                }
                 rl *= rho;
             }
-            const double SA = outer ? -(Sl + S1) : Sl;
-            ax += scale * (SA * xh + SB * vx_);
-            ay += scale * (SA * yh + SB * vy_);
-            az += scale * (SA * zh + SB * vz_);
+            if (FULL) SBj = SBk;
+            const double S_out = -(Sl + S1), S_in = Sl;
+            const double SAk = k_outer ? S_out : S_in, sck = k_outer ? sc_out : sc_in;
+            const double SAj = k_outer ? S_in : S_out, scj = k_outer ? sc_in : sc_out;
+            double vkx, vky, vkz, vjx, vjy, vjz;
+            if (FULL) {
+                vkx = xj - u * xh; vky = yj - u * yh; vkz = zj - u * zh;
+                vjx = xh - u * xj; vjy = yh - u * yj; vjz = zh - u * zj;
+            } else {
+                vkx = -zh * xh; vky = -zh * yh; vkz = 1.0 - zh * zh;
+                vjx = -zj * xj; vjy = -zj * yj; vjz = 1.0 - zj * zj;
+            }
+            double gjx = scj * (SAj * xj + SBj * vjx);
+            double gjy = scj * (SAj * yj + SBj * vjy);
+            double gjz = scj * (SAj * zj + SBj * vjz);
+            if (active) {
+                ax += sck * (SAk * xh + SBk * vkx);
+                ay += sck * (SAk * yh + SBk * vky);
+                az += sck * (SAk * zh + SBk * vkz);
+            } else {
+                gjx = 0.0;
+                gjy = 0.0;
+                gjz = 0.0;
+            }
+            const int src = (lane - sft) & (kWave - 1);
+            ax += __shfl(gjx, src);
+            ay += __shfl(gjy, src);
+            az += __shfl(gjz, src);
         }
         const double cn = -kQ / (4.0 * kPi * kp.ntilde);
         Ex += cn * ax;
@@ -988,7 +1023,7 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->u_asy, (size_t)std::max<int64_t>(lo.n_steps, 1));
     al.add(&h->qdiff, (size_t)std::max<int64_t>(lo.n_steps, 1));
     const int L = lo.L;
-    al.add(&h->tables, (size_t)7 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2));
+    al.add(&h->tables, (size_t)9 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2));
     al.add(&h->chl, (size_t)std::max(lo.C, 1));
     al.add(&h->Eout, 3 * n);
     al.add(&h->Eid, n);
@@ -1002,9 +1037,10 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
 {
     const int L = lo.L;
     const double a = 1.0 - p.d, eps = p.eps_r;
-    std::vector<double> t((size_t)7 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2), 0.0);
+    std::vector<double> t((size_t)9 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2), 0.0);
     double *ftil = t.data(), *wl = ftil + (L + 1), *drive = wl + (L + 1), *selfw = drive + (L + 1),
-           *nfA = selfw + (L + 1), *nfB = nfA + (L + 1), *qmm = nfB + (L + 1), *alm = qmm + (L + 1),
+           *nfA = selfw + (L + 1), *nfB = nfA + (L + 1), *lval = nfB + (L + 1), *tl1 = lval + (L + 1),
+           *qmm = tl1 + (L + 1), *alm = qmm + (L + 1),
            *blm = alm + (L + 1) * (L + 2) / 2;
     // Legendre values at 0 up to L + 1
     std::vector<double> p0(L + 3, 0.0);
@@ -1024,6 +1060,8 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
         selfw[l] = (l == 0) ? 0.0 : f / (4.0 * kPi * p.ntilde);
         nfA[l] = (2.0 * l + 1.0) / (l + 1.0);
         nfB[l] = (double)l / (l + 1.0);
+        lval[l] = (double)l;
+        tl1[l] = 2.0 * l + 1.0;
     }
     // Q_m^m = sqrt((2m+1)/(4 pi) / (2m)!) (2m-1)!! (sqrt 2 for m > 0)
     qmm[0] = 1.0 / std::sqrt(4.0 * kPi);
@@ -1251,9 +1289,11 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
     h->tb.self_w = tb + 3 * (L + 1);
     h->tb.nfA = tb + 4 * (L + 1);
     h->tb.nfB = tb + 5 * (L + 1);
-    h->tb.qmm = tb + 6 * (L + 1);
-    h->tb.alm = tb + 7 * (L + 1);
-    h->tb.blm = tb + 7 * (L + 1) + (L + 1) * (L + 2) / 2;
+    h->tb.lval = tb + 6 * (L + 1);
+    h->tb.tl1 = tb + 7 * (L + 1);
+    h->tb.qmm = tb + 8 * (L + 1);
+    h->tb.alm = tb + 9 * (L + 1);
+    h->tb.blm = tb + 9 * (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.chl = h->chl;
     // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
     std::vector<int> chl;
