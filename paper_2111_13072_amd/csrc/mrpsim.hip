@@ -81,6 +81,7 @@ struct Tables {
     const double *nfB;      // l/(l+1)
     const double *lval;     // l
     const double *tl1;      // 2l+1
+    const double4 *nf4;     // {(2l+1)/(l+1), l/(l+1), 2l+1, l}, one wide load per l
     const double *qmm;      // sectoral normalisation Q_m^m
     const double *alm;      // Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m
     const double *blm;
@@ -120,32 +121,54 @@ __device__ inline double key_r2(double x, double y, double z)
 // Sort: exact order by (r^2, id) through volume-uniform buckets
 // ---------------------------------------------------------------------------
 
-__global__ void k_sort_clear(uint32_t *hist, uint32_t *cursor, int nb)
+__global__ void k_sort_clear(uint32_t *hist, int nb)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i <= nb) hist[i] = 0;
-    if (i < nb) cursor[i] = 0;
 }
 
+// Key, bucket and slot inside the bucket.  Lanes of a wave that fall into the
+// same bucket (particles arrive nearly sorted, so a wave touches few buckets)
+// take one atomic add together; its return value is the group's first slot.
 __global__ void k_sort_key(const Ctl *ctl, State A, const uint8_t *dead, uint64_t *key,
-                           uint32_t *bkt, uint32_t *hist, KParams kp)
+                           uint32_t *bkt, uint32_t *sub, uint32_t *hist, KParams kp)
 {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ctl->n_cur) return;
-    if (dead[i]) {
-        bkt[i] = 0xffffffffu;
-        return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool in = i < ctl->n_cur;
+    const bool live = in && !dead[i];
+    uint32_t b = 0xffffffffu;
+    if (live) {
+        const double r2 = key_r2(A.x[i], A.y[i], A.z[i]);
+        key[i] = (uint64_t)__double_as_longlong(r2);
+        // Monotone non-decreasing map of r^2 to [0, nb): enclosed shell volume.
+        const double t = (r2 * sqrt(r2) - 1.0) * kp.inv_vol * (double)kp.nb;
+        if (!(t > 0.0)) b = 0;
+        else if (!(t < (double)(kp.nb - 1))) b = kp.nb - 1;
+        else b = (uint32_t)t;
     }
-    double r2 = key_r2(A.x[i], A.y[i], A.z[i]);
-    key[i] = (uint64_t)__double_as_longlong(r2);
-    // Monotone non-decreasing map of r^2 to [0, nb): enclosed shell volume.
-    double t = (r2 * sqrt(r2) - 1.0) * kp.inv_vol * (double)kp.nb;
-    int b;
-    if (!(t > 0.0)) b = 0;
-    else if (!(t < (double)(kp.nb - 1))) b = kp.nb - 1;
-    else b = (int)t;
-    bkt[i] = (uint32_t)b;
-    atomicAdd(&hist[b], 1u);
+    if (in) bkt[i] = b;
+    // Group the lanes by bucket (no memory traffic), then every group leader
+    // adds its group's count in one atomic instruction.
+    uint64_t todo = __ballot(live);
+    const uint64_t below = (1ull << lane) - 1ull;
+    int my_leader = lane;
+    uint32_t my_rank = 0, my_count = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t bl = (uint32_t)__builtin_amdgcn_readlane((int)b, leader);
+        const uint64_t grp = __ballot(live && b == bl) & todo;
+        if ((grp >> lane) & 1ull) {
+            my_leader = leader;
+            my_rank = (uint32_t)__popcll(grp & below);
+        }
+        if (lane == leader) my_count = (uint32_t)__popcll(grp);
+        todo &= ~grp;
+    }
+    uint32_t base = 0;
+    if (live && my_leader == lane) base = atomicAdd(&hist[b], my_count);
+    base = (uint32_t)__shfl((int)base, my_leader);
+    if (live) sub[i] = base + my_rank;
 }
 
 // Exclusive scan of a u32 array of length n into out[0..n], out[n] = total.
@@ -220,51 +243,75 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(const uint32_t *in, const uin
     }
 }
 
-__global__ void k_sort_scatter(const Ctl *ctl, const uint32_t *bkt, const uint32_t *off,
-                               uint32_t *cursor, uint32_t *tmp)
+// Bucket order (arbitrary inside a bucket): key, id and source index.
+__global__ void k_sort_scatter(const Ctl *ctl, const uint64_t *key, const uint32_t *uid,
+                               const uint32_t *bkt, const uint32_t *sub, const uint32_t *off,
+                               uint64_t *tkey, uint32_t *tuid, uint32_t *tidx, uint32_t *tbkt)
 {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ctl->n_cur) return;
-    uint32_t b = bkt[i];
+    const uint32_t b = bkt[i];
     if (b == 0xffffffffu) return;
-    uint32_t slot = off[b] + atomicAdd(&cursor[b], 1u);
-    tmp[slot] = i;
+    const uint32_t pos = off[b] + sub[i];
+    tkey[pos] = key[i];
+    tuid[pos] = uid[i];
+    tidx[pos] = i;
+    tbkt[pos] = b;
 }
 
 // Final position = bucket start + number of bucket mates with a smaller
-// (r^2, id) key; independent of the order the scatter produced.
-__global__ void k_sort_rank(const Ctl *ctl, const uint64_t *key, const uint32_t *uid,
-                            const uint32_t *bkt, const uint32_t *off, const uint32_t *tmp,
-                            uint32_t *perm)
-{
-    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= ctl->n_live) return;
-    uint32_t i = tmp[p];
-    uint32_t b = bkt[i];
-    uint32_t lo = off[b], hi = off[b + 1];
-    uint64_t k = key[i];
-    uint32_t u = uid[i];
-    uint32_t rank = 0;
-    for (uint32_t j = lo; j < hi; ++j) {
-        uint32_t o = tmp[j];
-        uint64_t ko = key[o];
-        rank += (ko < k) || (ko == k && uid[o] < u);
-    }
-    perm[lo + rank] = i;
-}
+// (r^2, id) key (independent of the order inside the bucket); the particle's
+// state moves there.  A block's positions cover a window of whole buckets,
+// staged in LDS when it fits.
+constexpr int kRankWindow = 2048;
 
-__global__ void k_sort_permute(const Ctl *ctl, const uint32_t *perm, State A, State B)
+__global__ __launch_bounds__(kBlock) void k_sort_rank_move(const Ctl *ctl, const uint64_t *tkey,
+                                                           const uint32_t *tuid, const uint32_t *tidx,
+                                                           const uint32_t *tbkt, const uint32_t *off,
+                                                           State A, State B)
 {
-    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= ctl->n_live) return;
-    uint32_t i = perm[p];
-    B.x[p] = A.x[i];
-    B.y[p] = A.y[i];
-    B.z[p] = A.z[i];
-    B.vx[p] = A.vx[i];
-    B.vy[p] = A.vy[i];
-    B.vz[p] = A.vz[i];
-    B.uid[p] = A.uid[i];
+    __shared__ uint64_t wkey[kRankWindow];
+    __shared__ uint32_t wuid[kRankWindow];
+    const uint32_t n = ctl->n_live;
+    const uint32_t p0 = blockIdx.x * kBlock;
+    if (p0 >= n) return;
+    const uint32_t p_last = min(p0 + kBlock, n) - 1;
+    const uint32_t w0 = off[tbkt[p0]], w1 = off[tbkt[p_last] + 1];
+    const bool staged = (w1 - w0) <= (uint32_t)kRankWindow;
+    if (staged) {
+        for (uint32_t j = w0 + threadIdx.x; j < w1; j += kBlock) {
+            wkey[j - w0] = tkey[j];
+            wuid[j - w0] = tuid[j];
+        }
+    }
+    __syncthreads();
+    const uint32_t p = p0 + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t b = tbkt[p];
+    const uint32_t lo = off[b], hi = off[b + 1];
+    const uint64_t k = tkey[p];
+    const uint32_t u = tuid[p];
+    uint32_t rank = 0;
+    if (staged) {
+        for (uint32_t j = lo - w0; j < hi - w0; ++j) {
+            const uint64_t kj = wkey[j];
+            rank += (kj < k) || (kj == k && wuid[j] < u);
+        }
+    } else {
+        for (uint32_t j = lo; j < hi; ++j) {
+            const uint64_t kj = tkey[j];
+            rank += (kj < k) || (kj == k && tuid[j] < u);
+        }
+    }
+    const uint32_t d = lo + rank;
+    const uint32_t i = tidx[p];
+    B.x[d] = A.x[i];
+    B.y[d] = A.y[i];
+    B.z[d] = A.z[i];
+    B.vx[d] = A.vx[i];
+    B.vy[d] = A.vy[i];
+    B.vz[d] = A.vz[i];
+    B.uid[d] = u;
 }
 
 // ---------------------------------------------------------------------------
@@ -275,6 +322,33 @@ __global__ void k_sort_permute(const Ctl *ctl, const uint32_t *perm, State A, St
 // (r sin th)^m and (x + i y)^m = C_m + i S_m:
 //   R_lm^c = Q_l^m C_m,  R_lm^s = Q_l^m S_m,  I_lm = r^-(2l+1) R_lm,
 // normalised so that sum_m Y_lm(a) Y_lm(b) = (2l+1)/(4 pi) P_l(a.b).
+
+// Coefficients of Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m (fully normalised
+// associated Legendre recurrence in solid-harmonic form); folded to constants
+// when l_max is a compile-time constant.
+template <int LT>
+__device__ inline double rec_a(const Tables &tb, int l, int m)
+{
+    if constexpr (LT > 0) {
+        const double l2 = (double)l * l, m2 = (double)m * m;
+        return __builtin_sqrt((4.0 * l2 - 1.0) / (l2 - m2));
+    } else {
+        return tb.alm[tri(l, m)];
+    }
+}
+
+template <int LT>
+__device__ inline double rec_b(const Tables &tb, int l, int m)
+{
+    if constexpr (LT > 0) {
+        if (l < m + 2) return 0.0;
+        const double l2 = (double)l * l, m2 = (double)m * m;
+        return __builtin_sqrt(((l - 1.0) * (l - 1.0) - m2) * (2.0 * l + 1.0) /
+                              ((l2 - m2) * (2.0 * l - 3.0)));
+    } else {
+        return tb.blm[tri(l, m)];
+    }
+}
 
 constexpr int kBatch = 16;       // channels per LDS batch of the tile reduction
 constexpr int kBatchPad = kWave + 1;
@@ -290,7 +364,7 @@ __device__ inline void swap_wave_halves(double &a, double &b)
     b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | (uint64_t)lo[1]));
 }
 
-template <bool FULL>
+template <bool FULL, int LT>
 __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tables tb,
                                                     KParams kp, double *S)
 {
@@ -317,7 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
     const double r2 = x * x + y * y + z * z;
     const double inv_r2 = 1.0 / r2;
     const double inv_r = 1.0 / sqrt(r2);
-    const int L = kp.L, C = kp.C;
+    const int L = LT > 0 ? LT : kp.L;
+    const int C = kp.C;
     const int m_top = FULL ? L : 0;
     double *St = S + (size_t)tile * kp.C2;
 
@@ -357,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
         for (int l = m; l <= L; ++l) {
             double Qv;
             if (l == m) Qv = tb.qmm[m];
-            else Qv = tb.alm[tri(l, m)] * z * Qp - tb.blm[tri(l, m)] * r2 * Qpp;
+            else Qv = rec_a<LT>(tb, l, m) * z * Qp - rec_b<LT>(tb, l, m) * r2 * Qpp;
             Qpp = Qp;
             Qp = Qv;
             if (l > 0) {
@@ -542,7 +617,9 @@ struct Grave {
     uint32_t *uid;
 };
 
-template <bool FULL, bool FIELD_ONLY>
+// LT > 0: l_max fixed at compile time (loops unrolled, recurrence constants
+// folded); LT = 0: l_max from kp.L.
+template <bool FULL, bool FIELD_ONLY, int LT>
 __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State A, uint8_t *dead,
                                                        Grave G, const double *coef, Tables tb,
                                                        KParams kp, double *Eout, uint32_t *Eid)
@@ -587,7 +664,9 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     __syncthreads();
     if (!tile_live) return;
 
-    const int L = kp.L, C = kp.C;
+    const int L = LT > 0 ? LT : kp.L;   // near field (unrolled when LT > 0)
+    const int Lf = kp.L;                 // far field and self-image (runtime loops)
+    const int C = kp.C;
 
     // ---- far field: all other tiles, through this tile's coefficients ----
     // Phi_far(x) = sum_lm Q_l^m(z, r^2) U_lm(x, y),
@@ -597,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     const double *cf = coef + (size_t)tile * kp.C2;
     double Gs = 0.0, Gz = 0.0, Gx = 0.0, Gy = 0.0, Gr = 0.0;
     {
-        const int m_top = FULL ? L : 0;
+        const int m_top = FULL ? Lf : 0;
         double Cm = 1.0, Sm = 0.0, Cm1 = 0.0, Sm1 = 0.0;
         double s_mm = inv_r;
         int k = 0;   // stream position of the channel
@@ -612,7 +691,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
             double Q1 = 0.0, Q2 = 0.0, Dz1 = 0.0, Dz2 = 0.0, Ds1 = 0.0, Ds2 = 0.0;
             double sl = s_mm;
             const double dm = (double)m;
-            for (int l = m; l <= L; ++l) {
+            for (int l = m; l <= Lf; ++l) {
                 double Qv, Dz, Ds;
                 if (l == m) {
                     Qv = tb.qmm[m];
@@ -687,8 +766,10 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
             double P0 = 1.0, P1 = u, dP0 = 0.0, dP1 = 1.0;        // P_l(u) (own cos th if axisym)
             double Q0 = 1.0, Q1 = zj, dQ0 = 0.0, dQ1 = 1.0;       // partner P_l(cos th_j), axisym
             double rl = rho;                                    // l = 0: Gauss's law below
+#pragma unroll 2
             for (int l = 1; l <= L; ++l) {
-                const double A = tb.nfA[l], Bc = tb.nfB[l], tl1 = tb.tl1[l], dl = tb.lval[l];
+                const double4 cl = tb.nf4[l];   // {(2l+1)/(l+1), l/(l+1), 2l+1, l}
+                const double A = cl.x, Bc = cl.y, tl1 = cl.z, dl = cl.w;
                 if (FULL) {
                     const double t = rl * P1;
                     S1 += t;
@@ -756,7 +837,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
         double sr = 0.0, sz = 0.0;   // radial and (e_z - c xh) parts of grad Phi_self
         double rl = inv_r2 * inv_r2 * inv_r;   // r^-(2l+3) at l = 1
         if (FULL) {
-            for (int l = 1; l <= L; ++l) {
+            for (int l = 1; l <= Lf; ++l) {
                 sr += tb.self_w[l] * (l + 1.0) * rl;
                 rl *= inv_r2;
             }
@@ -767,7 +848,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
             Ez += e * zh;
         } else {
             double P0 = 1.0, P1 = zh, dP0 = 0.0, dP1 = 1.0;
-            for (int l = 1; l <= L; ++l) {
+            for (int l = 1; l <= Lf; ++l) {
                 sr += tb.self_w[l] * rl * P1 * (-(l + 1.0) * P1);
                 sz += tb.self_w[l] * rl * P1 * dP1;
                 const double P2 = tb.nfA[l] * zh * P1 - tb.nfB[l] * P0;
@@ -892,14 +973,14 @@ __global__ void k_step_finish(Ctl *ctl)
 
 enum KernelId {
     KN_SORT_CLEAR, KN_SORT_KEY, KN_SCAN_A, KN_SCAN_B, KN_SCAN_C, KN_SORT_SCATTER, KN_SORT_RANK,
-    KN_SORT_PERMUTE, KN_MOMENTS, KN_CHUNK_SUMS, KN_CHUNK_SCAN, KN_COEF_PREP, KN_CHUNK_APPLY,
-    KN_FIELD_PUSH, KN_STEP_FINISH, KN_COUNT
+    KN_MOMENTS, KN_CHUNK_SUMS, KN_CHUNK_SCAN, KN_COEF_PREP, KN_CHUNK_APPLY, KN_FIELD_PUSH,
+    KN_STEP_FINISH, KN_COUNT
 };
 
 const char *kKernelNames[KN_COUNT] = {
     "sort_clear", "sort_key", "bucket_scan_a", "bucket_scan_b", "bucket_scan_c", "sort_scatter",
-    "sort_rank", "sort_permute", "moments", "carry_chunk_sums", "carry_chunk_scan", "coef_prep",
-    "carry_apply", "field_push", "step_finish"};
+    "sort_rank_move", "moments", "carry_chunk_sums", "carry_chunk_scan", "coef_prep", "carry_apply",
+    "field_push", "step_finish"};
 
 struct Layout {
     int64_t n;
@@ -966,8 +1047,9 @@ struct sim {
     Grave G{};
     uint8_t *dead = nullptr;
     uint64_t *key = nullptr;
-    uint32_t *bkt = nullptr, *tmp = nullptr, *perm = nullptr, *hist = nullptr, *cursor = nullptr,
-             *off = nullptr, *bsum = nullptr;
+    uint64_t *tkey = nullptr;
+    uint32_t *bkt = nullptr, *sub = nullptr, *tuid = nullptr, *tidx = nullptr, *tbkt = nullptr,
+             *hist = nullptr, *off = nullptr, *bsum = nullptr;
     double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr, *Kc = nullptr,
            *coef = nullptr, *u_asy = nullptr, *qdiff = nullptr, *tables = nullptr, *Eout = nullptr;
     int *chl = nullptr;
@@ -993,6 +1075,16 @@ namespace {
         }                                                                             \
     } while (0)
 
+// Layout of the table block: 9 per-l arrays, the two (l, m) triangles, then
+// the interleaved near-field constants at a 32-byte aligned offset.
+size_t nf4_offset(int L)
+{
+    const size_t base = (size_t)9 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2);
+    return (base + 3) & ~size_t(3);
+}
+
+size_t tables_len(int L) { return nf4_offset(L) + 4 * (size_t)(L + 1); }
+
 void plan_alloc(sim *h, Alloc &al)
 {
     const Layout &lo = h->lo;
@@ -1008,10 +1100,12 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->dead, n);
     al.add(&h->key, n);
     al.add(&h->bkt, n);
-    al.add(&h->tmp, n);
-    al.add(&h->perm, n);
+    al.add(&h->sub, n);
+    al.add(&h->tkey, n);
+    al.add(&h->tuid, n);
+    al.add(&h->tidx, n);
+    al.add(&h->tbkt, n);
     al.add(&h->hist, (size_t)lo.nb + 1);
-    al.add(&h->cursor, (size_t)lo.nb);
     al.add(&h->off, (size_t)lo.nb + 1);
     al.add(&h->bsum, (size_t)lo.nb_blocks + 1);
     al.add(&h->S, (size_t)lo.n_tiles * lo.C2);
@@ -1023,7 +1117,7 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->u_asy, (size_t)std::max<int64_t>(lo.n_steps, 1));
     al.add(&h->qdiff, (size_t)std::max<int64_t>(lo.n_steps, 1));
     const int L = lo.L;
-    al.add(&h->tables, (size_t)9 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2));
+    al.add(&h->tables, tables_len(L));
     al.add(&h->chl, (size_t)std::max(lo.C, 1));
     al.add(&h->Eout, 3 * n);
     al.add(&h->Eid, n);
@@ -1037,11 +1131,11 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
 {
     const int L = lo.L;
     const double a = 1.0 - p.d, eps = p.eps_r;
-    std::vector<double> t((size_t)9 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2), 0.0);
+    std::vector<double> t(tables_len(L), 0.0);
     double *ftil = t.data(), *wl = ftil + (L + 1), *drive = wl + (L + 1), *selfw = drive + (L + 1),
            *nfA = selfw + (L + 1), *nfB = nfA + (L + 1), *lval = nfB + (L + 1), *tl1 = lval + (L + 1),
            *qmm = tl1 + (L + 1), *alm = qmm + (L + 1),
-           *blm = alm + (L + 1) * (L + 2) / 2;
+           *blm = alm + (L + 1) * (L + 2) / 2, *nf4 = t.data() + nf4_offset(L);
     // Legendre values at 0 up to L + 1
     std::vector<double> p0(L + 3, 0.0);
     p0[0] = 1.0;
@@ -1062,6 +1156,10 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
         nfB[l] = (double)l / (l + 1.0);
         lval[l] = (double)l;
         tl1[l] = 2.0 * l + 1.0;
+        nf4[4 * l + 0] = nfA[l];
+        nf4[4 * l + 1] = nfB[l];
+        nf4[4 * l + 2] = tl1[l];
+        nf4[4 * l + 3] = lval[l];
     }
     // Q_m^m = sqrt((2m+1)/(4 pi) / (2m)!) (2m-1)!! (sqrt 2 for m > 0)
     qmm[0] = 1.0 / std::sqrt(4.0 * kPi);
@@ -1082,6 +1180,18 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
     return t;
 }
 
+// l_max values with compile-time specialisations of the hot kernels.
+#define MRP_DISPATCH_L(LV, MACRO) \
+    switch (LV) {                 \
+    case 1: MACRO(1); break;      \
+    case 2: MACRO(2); break;      \
+    case 4: MACRO(4); break;      \
+    case 8: MACRO(8); break;      \
+    case 16: MACRO(16); break;    \
+    case 32: MACRO(32); break;    \
+    default: MACRO(0); break;     \
+    }
+
 int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
 {
     const Layout &lo = h->lo;
@@ -1095,9 +1205,9 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
         if (ev) (void)hipEventRecord(ev[k], s);
     };
     mark(KN_SORT_CLEAR);
-    k_sort_clear<<<(lo.nb + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(h->hist, h->cursor, lo.nb);
+    k_sort_clear<<<(lo.nb + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(h->hist, lo.nb);
     mark(KN_SORT_KEY);
-    k_sort_key<<<gN, kBlock, 0, s>>>(h->ctl, h->A, h->dead, h->key, h->bkt, h->hist, kp);
+    k_sort_key<<<gN, kBlock, 0, s>>>(h->ctl, h->A, h->dead, h->key, h->bkt, h->sub, h->hist, kp);
     mark(KN_SCAN_A);
     k_scan_a<<<lo.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, lo.nb);
     mark(KN_SCAN_B);
@@ -1105,15 +1215,15 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     mark(KN_SCAN_C);
     k_scan_c<<<lo.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, lo.nb);
     mark(KN_SORT_SCATTER);
-    k_sort_scatter<<<gN, kBlock, 0, s>>>(h->ctl, h->bkt, h->off, h->cursor, h->tmp);
+    k_sort_scatter<<<gN, kBlock, 0, s>>>(h->ctl, h->key, h->A.uid, h->bkt, h->sub, h->off, h->tkey,
+                                         h->tuid, h->tidx, h->tbkt);
     mark(KN_SORT_RANK);
-    k_sort_rank<<<gN, kBlock, 0, s>>>(h->ctl, h->key, h->A.uid, h->bkt, h->off, h->tmp, h->perm);
-    mark(KN_SORT_PERMUTE);
-    k_sort_permute<<<gN, kBlock, 0, s>>>(h->ctl, h->perm, h->A, h->B);
+    k_sort_rank_move<<<gN, kBlock, 0, s>>>(h->ctl, h->tkey, h->tuid, h->tidx, h->tbkt, h->off, h->A,
+                                           h->B);
     mark(KN_MOMENTS);
     if (lo.C > 0) {
-        if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
-        else k_moments<false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
+        if (lo.full) k_moments<true, 0><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
+        else k_moments<false, 0><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
     }
     mark(KN_CHUNK_SUMS);
     if (lo.C > 0) k_chunk_sums<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkS, kp);
@@ -1126,20 +1236,15 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
         k_chunk_apply<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkC, h->Kc, h->tb, kp,
                                                                h->coef);
     mark(KN_FIELD_PUSH);
+#define MRP_FIELD(FULLV, FO, LT)                                                              \
+    k_field_push<FULLV, FO, LT><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G, h->coef, \
+                                                      h->tb, kp, h->Eout, h->Eid)
     if (field_only) {
-        if (lo.full)
-            k_field_push<true, true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G, h->coef,
-                                                          h->tb, kp, h->Eout, h->Eid);
-        else
-            k_field_push<false, true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G, h->coef,
-                                                           h->tb, kp, h->Eout, h->Eid);
+        if (lo.full) MRP_FIELD(true, true, 0);
+        else MRP_FIELD(false, true, 0);
     } else {
-        if (lo.full)
-            k_field_push<true, false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G,
-                                                           h->coef, h->tb, kp, h->Eout, h->Eid);
-        else
-            k_field_push<false, false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G,
-                                                            h->coef, h->tb, kp, h->Eout, h->Eid);
+        if (lo.full) MRP_FIELD(true, false, 0);
+        else MRP_FIELD(false, false, 0);
         mark(KN_STEP_FINISH);
         k_step_finish<<<1, 1, 0, s>>>(h->ctl);
     }
@@ -1294,6 +1399,7 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
     h->tb.qmm = tb + 8 * (L + 1);
     h->tb.alm = tb + 9 * (L + 1);
     h->tb.blm = tb + 9 * (L + 1) + (L + 1) * (L + 2) / 2;
+    h->tb.nf4 = reinterpret_cast<const double4 *>(tb + nf4_offset(L));
     h->tb.chl = h->chl;
     // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
     std::vector<int> chl;
