@@ -94,6 +94,106 @@ def cpu_baseline(wl, st, prm, E_gpu, u_now, q_s, budget_s: float):
     return rec, err, len(targets)
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries (profiles/)
+# ---------------------------------------------------------------------------
+
+def _read_csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _find(dirpath, suffix):
+    for root, _, files in os.walk(dirpath):
+        for fn in files:
+            if fn.endswith(suffix):
+                return os.path.join(root, fn)
+    raise FileNotFoundError(f"no *{suffix} under {dirpath}")
+
+
+def summarize_trace(trace_dir: str, out_md: str, command: str):
+    """Kernel-time table from `rocprofv3 --kernel-trace --stats` CSV output."""
+    rows = _read_csv(_find(trace_dir, "kernel_stats.csv"))
+    lines = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | average us | total % |", "|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"]
+        short = name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| {short[:60]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print(f"wrote {out_md}")
+
+
+def _counter_by_kernel(pmc_dir, counter):
+    rows = _read_csv(_find(pmc_dir, "counter_collection.csv"))
+    acc = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        k = r["Kernel_Name"]
+        acc.setdefault(k, []).append(float(r["Counter_Value"]))
+    return acc
+
+
+def summarize_traffic(fetch_dir: str, write_dir: str, out_json: str, workload: str,
+                      kernel: str, copy_bytes: int, commands: list):
+    """HBM bytes per launch of `kernel` from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by what the counter reads for a plain copy kernel
+    that moves copy_bytes in and copy_bytes out."""
+    f = _counter_by_kernel(fetch_dir, "FETCH_SIZE")
+    w = _counter_by_kernel(write_dir, "WRITE_SIZE")
+
+    def pick(d, key):
+        c = [v for k, v in d.items() if key in k]
+        if not c:
+            raise KeyError(key)
+        return float(np.mean(c[0]))
+
+    def pick_copy(d):
+        c = [v for k, v in d.items() if "UnaryFunctor" in k or "MulFunctor" in k]
+        return float(np.median(c[0])) if c else None
+
+    kf, kw = pick(f, kernel), pick(w, kernel)
+    cf, cw = pick_copy(f), pick_copy(w)
+    sf = copy_bytes / (cf * 1024.0) if cf else 1.0
+    sw = copy_bytes / (cw * 1024.0) if cw else 1.0
+    d = {"kernel": kernel, "workload": workload, "fetch_kib_per_launch": kf,
+         "write_kib_per_launch": kw, "copy_fetch_kib": cf, "copy_write_kib": cw,
+         "copy_bytes": copy_bytes, "fetch_scale": sf, "write_scale": sw,
+         "hbm_bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw,
+         "source_sha256_16": _kernel_source_hash(), "commands": commands}
+    json.dump(d, open(out_json, "w"), indent=1)
+    print(f"wrote {out_json}: {d['hbm_bytes_per_launch'] / 1e6:.1f} MB per launch")
+    # all kernels, as a table beside it
+    md = out_json.replace("_traffic.json", "_traffic.md")
+    lines = ["# HBM traffic per dispatch (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
+             f"Workload {workload}.  Counters are scaled by a plain copy of {copy_bytes} B in and "
+             f"out: fetch x{sf:.3f}, write x{sw:.3f}.", "", "Commands:", ""]
+    lines += ["```"] + commands + ["```", "",
+                                   "| kernel | fetch MB | write MB |", "|---|---|---|"]
+    for k in sorted(set(f) | set(w)):
+        if "at::native" in k or "rocclr" in k:
+            continue
+        fk = np.median(f.get(k, [0.0])) * 1024.0 * sf / 1e6
+        wk = np.median(w.get(k, [0.0])) * 1024.0 * sw / 1e6
+        short = k.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| {short} | {fk:.1f} | {wk:.1f} |")
+    open(md, "w").write("\n".join(lines) + "\n")
+    print(f"wrote {md}")
+
+
+def calibrate_copy(nbytes: int, reps: int = 3):
+    """A plain elementwise copy of known size, for counter calibration."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,7 +203,22 @@ def main(argv=None):
     ap.add_argument("--workload", default="large", choices=["large", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the run, launch a plain copy of this size (counter calibration)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"))
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
+    ap.add_argument("--command", default="", help="command recorded in a summary")
     args = ap.parse_args(argv)
+
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
+        return 0
+    if args.summarize_traffic:
+        wl_name = "shell-2e6-L16" if args.workload == "large" else "shell-1e4-L8"
+        summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1],
+                          args.summarize_traffic[2], wl_name, "field_push",
+                          args.calibrate_copy_mib * 2**20, args.command.split(" ;; "))
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -150,6 +265,8 @@ def main(argv=None):
 
     kms = sim.profile(args.profile_steps)
     sim.close()
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib * 2**20)
     dom = "field_push"
     t_dom = kms[dom] * 1e-3
     flops = algorithmic_flops_per_particle(wl.l_max) * 0.5 * (n_before + n_after)

@@ -111,6 +111,18 @@ __device__ inline uint32_t uniform_u32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Blocks are placed on the 8 XCDs round-robin (block b on XCD b % 8), and
+// each XCD has its own L2.  Kernels whose neighbouring blocks share cache
+// lines renumber their blocks so that every XCD walks one contiguous range.
+constexpr uint32_t kXcds = 8;
+
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nblocks)
+{
+    const uint32_t q = nblocks / kXcds, r = nblocks % kXcds;
+    const uint32_t x = b % kXcds, k = b / kXcds;
+    return x * q + min(x, r) + k;
+}
+
 // r^2 as (x*x + y*y) + z*z without contraction: the exact radial sort key.
 __device__ inline double key_r2(double x, double y, double z)
 {
@@ -248,7 +260,7 @@ __global__ void k_sort_scatter(const Ctl *ctl, const uint64_t *key, const uint32
                                const uint32_t *bkt, const uint32_t *sub, const uint32_t *off,
                                uint64_t *tkey, uint32_t *tuid, uint32_t *tidx, uint32_t *tbkt)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= ctl->n_cur) return;
     const uint32_t b = bkt[i];
     if (b == 0xffffffffu) return;
@@ -273,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(const Ctl *ctl, const
     __shared__ uint64_t wkey[kRankWindow];
     __shared__ uint32_t wuid[kRankWindow];
     const uint32_t n = ctl->n_live;
-    const uint32_t p0 = blockIdx.x * kBlock;
+    const uint32_t p0 = xcd_block(blockIdx.x, gridDim.x) * kBlock;
     if (p0 >= n) return;
     const uint32_t p_last = min(p0 + kBlock, n) - 1;
     const uint32_t w0 = off[tbkt[p0]], w1 = off[tbkt[p_last] + 1];
