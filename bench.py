@@ -201,6 +201,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--workload", default="large", choices=["large", "small"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -237,9 +238,11 @@ def main(argv=None):
     st = wl.particles()
     n_total = args.warmup + args.steps + args.profile_steps + 1
     u = wl.drive(max(n_total, 64))
+    fp32 = args.precision == "fp32c"
     prm = S.SimParams(d=wl.d, eps_r=wl.eps_r, r_out=wl.r_out, dt=wl.dt, ntilde=wl.ntilde,
-                      ion_density=1.0, l_max=wl.l_max, precision=S.SIM_FP64)
-    print(f"[bench] workload {wl.name}: n={wl.n} l_max={wl.l_max} fp64, "
+                      ion_density=1.0, l_max=wl.l_max,
+                      precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64)
+    print(f"[bench] workload {wl.name}: n={wl.n} l_max={wl.l_max} {args.precision}, "
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
 
     sim = S.Sim(prm, st.pos, st.vel, u)
@@ -271,18 +274,20 @@ def main(argv=None):
     t_dom = kms[dom] * 1e-3
     flops = algorithmic_flops_per_particle(wl.l_max) * 0.5 * (n_before + n_after)
     achieved = flops / t_dom / 1e12
-    traffic = _traffic_from_profiles(dom, wl.name)
-    roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+    traffic = _traffic_from_profiles(dom, wl.name + ("-fp32c" if fp32 else ""))
+    peak = FP32_VECTOR_PEAK_TFLOPS if fp32 else FP64_VECTOR_PEAK_TFLOPS
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
             "kernel": dom, "kernel_ms": kms[dom],
             "per_kernel_ms": {k: round(v, 5) for k, v in kms.items()}}
 
     line = {"metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64" if fp32 else "f64",
             "data": "synthetic",
             "config": {"workload": wl.name, "n_particles": wl.n, "l_max": wl.l_max,
-                       "m_mode": "full", "precision": "fp64", "tile": 64,
+                       "m_mode": "full", "precision": args.precision, "tile": 64,
                        "n_e_m3": wl.n_e, "T_e_eV": wl.t_e_ev, "r_out": wl.r_out, "dt": wl.dt,
                        "parallelism": "single-gpu"},
             "roofline": roof}

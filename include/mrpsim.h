@@ -57,8 +57,12 @@ enum { SIM_FP64 = 0, SIM_FP32_COMP = 1 };
  *               dipole kernel of Sec. 3 is l_max = 1, SIM_M_AXISYM).
  *   probe_bc    at r <= 1: absorb (charge goes to Q_S), specular or diffuse.
  *   wall_bc     at r >= r_out: specular or diffuse.
- *   precision   SIM_FP64, or SIM_FP32_COMP (FP32 terms with FP64 radial
- *               scans and positions).
+ *   precision   SIM_FP64, or SIM_FP32_COMP: the field evaluation (far-field
+ *               harmonics and contraction, near-field pair sums) in FP32 at
+ *               tile-scaled coordinates, with FP64 moments, radial scans,
+ *               l = 0 (Gauss) term, accumulation and positions.  Field error
+ *               against the FP64 definition: <= 1e-5 of the RMS field for
+ *               l_max <= 16, growing like l_max^2 * 2^-24 beyond.
  *   tile        particles per tile of the radial scan (0 = choose).
  *   seed        key of the counter-based generator of diffuse walls.
  *   mem_limit_bytes  0 = none; otherwise sim_create fails with SIM_ENOMEM

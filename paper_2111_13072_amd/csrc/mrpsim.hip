@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <string>
 #include <utility>
 #include <vector>
@@ -86,6 +87,9 @@ struct Tables {
     const double *alm;      // Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m
     const double *blm;
     const int *chl;         // degree l of each channel in stream order
+    // FP32 copies for the FP32-compensated mode
+    const float *qmm32, *alm32, *blm32;
+    const float4 *nf4_32;
 };
 
 // Channels are kept in "stream order": m = 0..m_top outer, l = max(m,1)..L
@@ -102,6 +106,7 @@ struct KParams {
     double dt, r_out, ntilde, ion_density, q_surface0, inv_vol;
     uint64_t seed;
     int64_t n_steps;
+    int fp32;       // SIM_FP32_COMP
 };
 
 __host__ __device__ inline int tri(int l, int m) { return l * (l + 1) / 2 + m; }
@@ -122,6 +127,14 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nblocks)
     const uint32_t x = b % kXcds, k = b / kXcds;
     return x * q + min(x, r) + k;
 }
+
+// Reciprocal and reciprocal square root in the working precision: FP64 uses
+// the correctly rounded operations; FP32 the hardware approximations
+// (about 1 ulp), which the FP32 mode's error budget covers.
+__device__ inline double rcp_r(double v) { return 1.0 / v; }
+__device__ inline float rcp_r(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ inline double rsq_r(double v) { return 1.0 / sqrt(v); }
+__device__ inline float rsq_r(float v) { return __builtin_amdgcn_rsqf(v); }
 
 // r^2 as (x*x + y*y) + z*z without contraction: the exact radial sort key.
 __device__ inline double key_r2(double x, double y, double z)
@@ -335,33 +348,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(const Ctl *ctl, const
 //   R_lm^c = Q_l^m C_m,  R_lm^s = Q_l^m S_m,  I_lm = r^-(2l+1) R_lm,
 // normalised so that sum_m Y_lm(a) Y_lm(b) = (2l+1)/(4 pi) P_l(a.b).
 
-// Coefficients of Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m (fully normalised
-// associated Legendre recurrence in solid-harmonic form); folded to constants
-// when l_max is a compile-time constant.
-template <int LT>
-__device__ inline double rec_a(const Tables &tb, int l, int m)
-{
-    if constexpr (LT > 0) {
-        const double l2 = (double)l * l, m2 = (double)m * m;
-        return __builtin_sqrt((4.0 * l2 - 1.0) / (l2 - m2));
-    } else {
-        return tb.alm[tri(l, m)];
-    }
-}
-
-template <int LT>
-__device__ inline double rec_b(const Tables &tb, int l, int m)
-{
-    if constexpr (LT > 0) {
-        if (l < m + 2) return 0.0;
-        const double l2 = (double)l * l, m2 = (double)m * m;
-        return __builtin_sqrt(((l - 1.0) * (l - 1.0) - m2) * (2.0 * l + 1.0) /
-                              ((l2 - m2) * (2.0 * l - 3.0)));
-    } else {
-        return tb.blm[tri(l, m)];
-    }
-}
-
 constexpr int kBatch = 16;       // channels per LDS batch of the tile reduction
 constexpr int kBatchPad = kWave + 1;
 
@@ -376,9 +362,9 @@ __device__ inline void swap_wave_halves(double &a, double &b)
     b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | (uint64_t)lo[1]));
 }
 
-template <bool FULL, int LT>
+template <bool FULL>
 __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tables tb,
-                                                    KParams kp, double *S)
+                                                    KParams kp, double *S, double *lgrho)
 {
     // Per wave (one tile of 64 particles): for each channel, q R (interior)
     // and q I (exterior) are first folded across the two wave halves with a
@@ -403,10 +389,19 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
     const double r2 = x * x + y * y + z * z;
     const double inv_r2 = 1.0 / r2;
     const double inv_r = 1.0 / sqrt(r2);
-    const int L = LT > 0 ? LT : kp.L;
+    const int L = kp.L;
     const int C = kp.C;
     const int m_top = FULL ? L : 0;
     double *St = S + (size_t)tile * kp.C2;
+    if (kp.fp32 && tile_ok && lane == 0) {
+        // reference radius of the tile for the FP32 field: its first particle
+        double rho = 1.0;
+        if (tile * kWave < n) {
+            const uint32_t p0 = tile * kWave;
+            rho = sqrt(key_r2(B.x[p0], B.y[p0], B.z[p0]));
+        }
+        lgrho[tile] = log2(rho);
+    }
 
     const int cc = lane & (kBatch - 1);
     const int kind = (lane >> 4) & 1;   // 0: interior (R), 1: exterior (I)
@@ -444,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
         for (int l = m; l <= L; ++l) {
             double Qv;
             if (l == m) Qv = tb.qmm[m];
-            else Qv = rec_a<LT>(tb, l, m) * z * Qp - rec_b<LT>(tb, l, m) * r2 * Qpp;
+            else Qv = tb.alm[tri(l, m)] * z * Qp - tb.blm[tri(l, m)] * r2 * Qpp;
             Qpp = Qp;
             Qp = Qv;
             if (l > 0) {
@@ -547,9 +542,13 @@ __global__ __launch_bounds__(kBlock) void k_coef_prep(const double *T, Ctl *ctl,
     }
 }
 
+// Per-tile coefficients of the field kernel.  FP64 mode: absolute FP64
+// values.  FP32 mode: values pre-scaled to the tile's coordinates x / rho
+// (interior rho^-(l+1), exterior rho^l), stored as FP32.
 __global__ __launch_bounds__(kBlock) void k_chunk_apply(const double *S, const double *chunkC,
                                                         const double *Kc, Tables tb, KParams kp,
-                                                        double *coef)
+                                                        const double *lgrho, double *coef,
+                                                        float *coef32)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
     if (c >= kp.C2) return;
@@ -557,16 +556,22 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(const double *S, const d
     const int t0 = j * kChunk, t1 = min(t0 + kChunk, kp.n_tiles);
     double run = chunkC[(size_t)j * kp.C2 + c];
     if (c < kp.C) {
-        const double w = tb.wl[tb.chl[c]];
+        const int l = tb.chl[c];
+        const double w = tb.wl[l];
         const double k = Kc[c];
         for (int t = t0; t < t1; ++t) {
-            coef[(size_t)t * kp.C2 + c] = run * w + k;
+            const double v = run * w + k;
+            if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2(-(l + 1.0) * lgrho[t]));
+            else coef[(size_t)t * kp.C2 + c] = v;
             run += S[(size_t)t * kp.C2 + c];
         }
     } else {
-        const double w = tb.wl[tb.chl[c - kp.C]];
+        const int l = tb.chl[c - kp.C];
+        const double w = tb.wl[l];
         for (int t = t1 - 1; t >= t0; --t) {
-            coef[(size_t)t * kp.C2 + c] = run * w;
+            const double v = run * w;
+            if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2((double)l * lgrho[t]));
+            else coef[(size_t)t * kp.C2 + c] = v;
             run += S[(size_t)t * kp.C2 + c];
         }
     }
@@ -629,16 +634,194 @@ struct Grave {
     uint32_t *uid;
 };
 
-// LT > 0: l_max fixed at compile time (loops unrolled, recurrence constants
-// folded); LT = 0: l_max from kp.L.
-template <bool FULL, bool FIELD_ONLY, int LT>
-__global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State A, uint8_t *dead,
-                                                       Grave G, const double *coef, Tables tb,
-                                                       KParams kp, double *Eout, uint32_t *Eid)
+// Far field of all other tiles through this tile's coefficient vector
+// (interior alpha then exterior beta, stream order), evaluated at scaled
+// coordinates xi = x / rho in the working precision R; returns grad_xi Phi.
+//   Phi(xi) = sum_lm Q_l^m(z, r^2) U_lm,
+//   U_lm = (beta + s_l alpha)^c C_m + (beta + s_l alpha)^s S_m,  s_l = r^-(2l+1),
+//   V_lm = alpha^c C_m + alpha^s S_m,
+// with Q_l^m = a z Q_{l-1}^m - b r^2 Q_{l-2}^m and D_z Q its z-derivative at
+// fixed r^2.  Q_l^m C_m is homogeneous of degree l, so the radial derivative is
+// exact by Euler's relation and only D_z Q enters the tangential part:
+//   grad Phi = rhat (1/r) sum [(l - m) Q U - (2l+1) s_l Q V]
+//              + (e_z - cos th rhat) sum U D_z Q + (sum Q dU/dx, sum Q dU/dy, 0).
+// (Assembling the radial part from the two partial derivatives of Q instead
+// loses a factor ~l to cancellation.)
+template <bool FULL, typename R>
+__device__ inline void far_field(const R *cf, int C, int L, const R *qmm, const R *alm,
+                                 const R *blm, R x, R y, R z, R &gx, R &gy, R &gz)
 {
-    __shared__ double sh_xh[kWavesPerBlock][kWave], sh_yh[kWavesPerBlock][kWave],
-        sh_zh[kWavesPerBlock][kWave], sh_r[kWavesPerBlock][kWave], sh_r2[kWavesPerBlock][kWave],
-        sh_ir[kWavesPerBlock][kWave];
+    const R r2 = x * x + y * y + z * z;
+    const R inv_r2 = rcp_r(r2);
+    const R inv_r = rsq_r(r2);
+    R Ga = 0, Gz = 0, Gx = 0, Gy = 0;
+    const int m_top = FULL ? L : 0;
+    R Cm = 1, Sm = 0, Cm1 = 0, Sm1 = 0;
+    R s_mm = inv_r;
+    int k = 0;   // stream position of the channel
+    for (int m = 0; m <= m_top; ++m) {
+        if (m > 0) {
+            Cm1 = Cm;
+            Sm1 = Sm;
+            Cm = x * Cm1 - y * Sm1;
+            Sm = x * Sm1 + y * Cm1;
+            s_mm *= inv_r2;
+        }
+        R Q1 = 0, Q2 = 0, Dz1 = 0, Dz2 = 0;
+        R sl = s_mm;
+        const R dm = (R)m;
+        for (int l = m; l <= L; ++l) {
+            R Qv, Dz;
+            if (l == m) {
+                Qv = qmm[m];
+                Dz = 0;
+            } else {
+                const R a = alm[tri(l, m)], b = blm[tri(l, m)];
+                const R az = a * z, br2 = b * r2;
+                Qv = az * Q1 - br2 * Q2;
+                Dz = a * Q1 + az * Dz1 - br2 * Dz2;
+            }
+            Q2 = Q1;
+            Q1 = Qv;
+            Dz2 = Dz1;
+            Dz1 = Dz;
+            if (l == 0) {   // l = 0 is Gauss's law in the caller
+                sl *= inv_r2;
+                continue;
+            }
+            const R lm = (R)(l - m);
+            const R w1 = (R)(2 * l + 1) * sl;
+            const R ac = cf[k], bc = cf[C + k];
+            const R tc = bc + sl * ac;
+            if (!FULL || m == 0) {
+                Ga += Qv * (lm * tc - w1 * ac);
+                Gz += tc * Dz;
+                k += 1;
+            } else {
+                const R as = cf[k + 1], bs = cf[C + k + 1];
+                k += 2;
+                const R ts = bs + sl * as;
+                const R U = tc * Cm + ts * Sm;
+                const R V = ac * Cm + as * Sm;
+                Ga += Qv * (lm * U - w1 * V);
+                Gz += U * Dz;
+                const R mq = dm * Qv;
+                Gx += mq * (tc * Cm1 + ts * Sm1);
+                Gy += mq * (ts * Cm1 - tc * Sm1);
+            }
+            sl *= inv_r2;
+        }
+    }
+    const R xh = x * inv_r, yh = y * inv_r, c = z * inv_r;
+    const R radial = Ga * inv_r - c * Gz;
+    gx = xh * radial + Gx;
+    gy = yh * radial + Gy;
+    gz = c * Ga * inv_r + (xh * xh + yh * yh) * Gz;
+}
+
+// Near field: the direct part of G~_L between the particles of one tile,
+// pair by pair.  For the pair (k, j) with rho = r_< / r_>, u = angular argument:
+//   outer one: grad D = (1/r_>^2)       sum_l rho^l [-(l+1) P_l xh + P'_l v]
+//   inner one: grad D = (1/(r_< r_>))   sum_l rho^l [ l P_l xh     + P'_l v]
+// where v = xh_other - u xh (full) or e_z - cos(th) xh (axisymmetric).  The
+// three sums are symmetric in (k, j), so each pair is evaluated once: at step
+// s lane k takes partner (k + s) mod 64 and hands the partner's gradient to it
+// through a lane rotation.  Pair terms in R, accumulated in FP64.
+template <bool FULL, typename R, typename NF>
+__device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R *sxh, const R *syh,
+                                  const R *szh, const R *sr, const R *sir, const double *sr2,
+                                  const uint32_t *suid, R xh, R yh, R zh, R r, R inv_r, double r2,
+                                  uint32_t uid, double &ax, double &ay, double &az)
+{
+    const R inv_r2 = inv_r * inv_r;
+    for (int sft = 1; sft <= kWave / 2; ++sft) {
+        const int j = (lane + sft) & (kWave - 1);
+        const bool active = lane < jn && j < jn && (sft < kWave / 2 || lane < kWave / 2);
+        const R xj = sxh[j], yj = syh[j], zj = szh[j];
+        const R rj = sr[j], irj = sir[j];
+        const double r2j = sr2[j];
+        const uint32_t uj = suid[j];
+        const bool k_outer = (r2 > r2j) || (r2 == r2j && uid > uj);
+        const R rho = k_outer ? rj * inv_r : r * irj;
+        const R sc_out = k_outer ? inv_r2 : irj * irj;   // 1 / r_>^2
+        const R sc_in = inv_r * irj;                     // 1 / (r_< r_>)
+        const R u = FULL ? xh * xj + yh * yj + zh * zj : zh;
+        R S1 = 0, Sl = 0, SBk = 0, SBj = 0;
+        R P0 = 1, P1 = u, dP0 = 0, dP1 = 1;      // P_l(u) (own cos th if axisymmetric)
+        R Q0 = 1, Q1 = zj, dQ0 = 0, dQ1 = 1;     // partner P_l(cos th_j), axisymmetric only
+        R rl = rho;                              // l = 0 is Gauss's law in the caller
+#pragma unroll 2
+        for (int l = 1; l <= L; ++l) {
+            const NF cl = nf[l];   // {(2l+1)/(l+1), l/(l+1), 2l+1, l}
+            const R A = cl.x, Bc = cl.y, tl1 = cl.z, dl = cl.w;
+            if (FULL) {
+                const R t = rl * P1;
+                S1 += t;
+                Sl += dl * t;
+                SBk += rl * dP1;
+            } else {
+                const R t = rl * P1 * Q1;
+                S1 += t;
+                Sl += dl * t;
+                SBk += rl * dP1 * Q1;
+                SBj += rl * P1 * dQ1;
+                const R Q2 = A * zj * Q1 - Bc * Q0;
+                const R dQ2 = dQ0 + tl1 * Q1;
+                Q0 = Q1;
+                Q1 = Q2;
+                dQ0 = dQ1;
+                dQ1 = dQ2;
+            }
+            const R P2 = A * u * P1 - Bc * P0;
+            const R dP2 = dP0 + tl1 * P1;
+            P0 = P1;
+            P1 = P2;
+            dP0 = dP1;
+            dP1 = dP2;
+            rl *= rho;
+        }
+        if (FULL) SBj = SBk;
+        const R S_out = -(Sl + S1), S_in = Sl;
+        const R SAk = k_outer ? S_out : S_in, sck = k_outer ? sc_out : sc_in;
+        const R SAj = k_outer ? S_in : S_out, scj = k_outer ? sc_in : sc_out;
+        R vkx, vky, vkz, vjx, vjy, vjz;
+        if (FULL) {
+            vkx = xj - u * xh; vky = yj - u * yh; vkz = zj - u * zh;
+            vjx = xh - u * xj; vjy = yh - u * yj; vjz = zh - u * zj;
+        } else {
+            vkx = -zh * xh; vky = -zh * yh; vkz = 1 - zh * zh;
+            vjx = -zj * xj; vjy = -zj * yj; vjz = 1 - zj * zj;
+        }
+        R gjx = scj * (SAj * xj + SBj * vjx);
+        R gjy = scj * (SAj * yj + SBj * vjy);
+        R gjz = scj * (SAj * zj + SBj * vjz);
+        if (active) {
+            ax += (double)(sck * (SAk * xh + SBk * vkx));
+            ay += (double)(sck * (SAk * yh + SBk * vky));
+            az += (double)(sck * (SAk * zh + SBk * vkz));
+        } else {
+            gjx = 0;
+            gjy = 0;
+            gjz = 0;
+        }
+        const int src = (lane - sft) & (kWave - 1);
+        ax += (double)__shfl(gjx, src);
+        ay += (double)__shfl(gjy, src);
+        az += (double)__shfl(gjz, src);
+    }
+}
+
+template <bool FULL, bool FIELD_ONLY, bool FP32>
+__global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State A, uint8_t *dead,
+                                                       Grave G, const double *coef,
+                                                       const float *coef32, Tables tb, KParams kp,
+                                                       double *Eout, uint32_t *Eid)
+{
+    using R = typename std::conditional<FP32, float, double>::type;
+    using NF = typename std::conditional<FP32, float4, double4>::type;
+    __shared__ R sh_xh[kWavesPerBlock][kWave], sh_yh[kWavesPerBlock][kWave],
+        sh_zh[kWavesPerBlock][kWave], sh_r[kWavesPerBlock][kWave], sh_ir[kWavesPerBlock][kWave];
+    __shared__ double sh_r2[kWavesPerBlock][kWave];
     __shared__ uint32_t sh_uid[kWavesPerBlock][kWave];
 
     const int lane = threadIdx.x & 63;
@@ -666,177 +849,52 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     const double inv_r = 1.0 / r;
     const double inv_r2 = 1.0 / r2;
     const double xh = x * inv_r, yh = y * inv_r, zh = z * inv_r;
-    sh_xh[w][lane] = xh;
-    sh_yh[w][lane] = yh;
-    sh_zh[w][lane] = zh;
-    sh_r[w][lane] = r;
+    sh_xh[w][lane] = (R)xh;
+    sh_yh[w][lane] = (R)yh;
+    sh_zh[w][lane] = (R)zh;
+    sh_r[w][lane] = (R)r;
+    sh_ir[w][lane] = (R)inv_r;
     sh_r2[w][lane] = r2;
-    sh_ir[w][lane] = inv_r;
     sh_uid[w][lane] = uid;
     __syncthreads();
     if (!tile_live) return;
 
-    const int L = LT > 0 ? LT : kp.L;   // near field (unrolled when LT > 0)
-    const int Lf = kp.L;                 // far field and self-image (runtime loops)
-    const int C = kp.C;
+    const int L = kp.L;
 
-    // ---- far field: all other tiles, through this tile's coefficients ----
-    // Phi_far(x) = sum_lm Q_l^m(z, r^2) U_lm(x, y),
-    // U_lm = (beta + s_l alpha)^c C_m + (beta + s_l alpha)^s S_m, s_l = r^-(2l+1);
-    // grad Phi = sum [U (2 D_s Q x_vec + D_z Q e_z) + Q grad_xy U]
-    //            - (x_vec / r^2) sum (2l+1) s_l Q (alpha^c C_m + alpha^s S_m).
-    const double *cf = coef + (size_t)tile * kp.C2;
-    double Gs = 0.0, Gz = 0.0, Gx = 0.0, Gy = 0.0, Gr = 0.0;
+    // ---- far field (all other tiles) ----
+    double Ex, Ey, Ez;
     {
-        const int m_top = FULL ? Lf : 0;
-        double Cm = 1.0, Sm = 0.0, Cm1 = 0.0, Sm1 = 0.0;
-        double s_mm = inv_r;
-        int k = 0;   // stream position of the channel
-        for (int m = 0; m <= m_top; ++m) {
-            if (m > 0) {
-                Cm1 = Cm;
-                Sm1 = Sm;
-                Cm = x * Cm1 - y * Sm1;
-                Sm = x * Sm1 + y * Cm1;
-                s_mm *= inv_r2;
-            }
-            double Q1 = 0.0, Q2 = 0.0, Dz1 = 0.0, Dz2 = 0.0, Ds1 = 0.0, Ds2 = 0.0;
-            double sl = s_mm;
-            const double dm = (double)m;
-            for (int l = m; l <= Lf; ++l) {
-                double Qv, Dz, Ds;
-                if (l == m) {
-                    Qv = tb.qmm[m];
-                    Dz = 0.0;
-                    Ds = 0.0;
-                } else {
-                    const double a = tb.alm[tri(l, m)], b = tb.blm[tri(l, m)];
-                    Qv = a * z * Q1 - b * r2 * Q2;
-                    Dz = a * Q1 + a * z * Dz1 - b * r2 * Dz2;
-                    Ds = a * z * Ds1 - b * Q2 - b * r2 * Ds2;
-                }
-                Q2 = Q1;
-                Q1 = Qv;
-                Dz2 = Dz1;
-                Dz1 = Dz;
-                Ds2 = Ds1;
-                Ds1 = Ds;
-                if (l == 0) {
-                    sl *= inv_r2;
-                    continue;
-                }
-                const double ac = cf[k], bc = cf[C + k];
-                const double tc = bc + sl * ac;
-                const double two_l1 = 2.0 * l + 1.0;
-                if (!FULL || m == 0) {
-                    Gs += tc * Ds;
-                    Gz += tc * Dz;
-                    Gr += two_l1 * sl * Qv * ac;
-                    k += 1;
-                } else {
-                    const double as = cf[k + 1], bs = cf[C + k + 1];
-                    k += 2;
-                    const double ts = bs + sl * as;
-                    const double U = tc * Cm + ts * Sm;
-                    Gs += U * Ds;
-                    Gz += U * Dz;
-                    const double mq = dm * Qv;
-                    Gx += mq * (tc * Cm1 + ts * Sm1);
-                    Gy += mq * (ts * Cm1 - tc * Sm1);
-                    Gr += two_l1 * sl * Qv * (ac * Cm + as * Sm);
-                }
-                sl *= inv_r2;
-            }
+        // FP32: coordinates scaled by the tile's first radius, matching the
+        // moments kernel and the pre-scaled coefficients; FP64: unscaled.
+        double rho = 1.0;
+        if (FP32) {
+            const uint32_t p0 = tile * kWave;
+            rho = sqrt(key_r2(B.x[p0], B.y[p0], B.z[p0]));
         }
+        const double inv_rho = 1.0 / rho;
+        R gx, gy, gz;
+        if constexpr (FP32) {
+            far_field<FULL, float>(coef32 + (size_t)tile * kp.C2, kp.C, L, tb.qmm32, tb.alm32,
+                                   tb.blm32, (float)(x * inv_rho), (float)(y * inv_rho),
+                                   (float)(z * inv_rho), gx, gy, gz);
+        } else {
+            far_field<FULL, double>(coef + (size_t)tile * kp.C2, kp.C, L, tb.qmm, tb.alm, tb.blm, x,
+                                    y, z, gx, gy, gz);
+        }
+        Ex = -(double)gx * inv_rho;
+        Ey = -(double)gy * inv_rho;
+        Ez = -(double)gz * inv_rho;
     }
-    double Ex = -(2.0 * Gs * x + Gx - Gr * x * inv_r2);
-    double Ey = -(2.0 * Gs * y + Gy - Gr * y * inv_r2);
-    double Ez = -(2.0 * Gs * z + Gz - Gr * z * inv_r2);
 
-    // ---- near field: own tile, pair by pair (direct part of G~_L) ----
-    // For the pair (k, j) with rho = r_< / r_>, u = angular argument:
-    //   outer one: grad D = (1/r_>^2)       sum_l rho^l [-(l+1) P_l xh + P'_l v]
-    //   inner one: grad D = (1/(r_< r_>))   sum_l rho^l [ l P_l xh     + P'_l v]
-    // where v = xh_other - u xh (full) or e_z - cos(th) xh (axisymmetric).
-    // The three sums are symmetric in (k, j), so each pair is evaluated once:
-    // at step s lane k takes partner (k + s) mod 64 and hands the partner's
-    // gradient to it through a lane rotation.  E += -(q / (4 pi nt)) grad D.
+    // ---- near field (own tile); E += -(q / (4 pi nt)) grad D ----
     {
         double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int sft = 1; sft <= kWave / 2; ++sft) {
-            const int j = (lane + sft) & (kWave - 1);
-            const bool active = lane < jn && j < jn && (sft < kWave / 2 || lane < kWave / 2);
-            const double xj = sh_xh[w][j], yj = sh_yh[w][j], zj = sh_zh[w][j];
-            const double rj = sh_r[w][j], r2j = sh_r2[w][j], irj = sh_ir[w][j];
-            const uint32_t uj = sh_uid[w][j];
-            const bool k_outer = (r2 > r2j) || (r2 == r2j && uid > uj);
-            const double rho = k_outer ? rj * inv_r : r * irj;
-            const double sc_out = k_outer ? inv_r2 : irj * irj;   // 1 / r_>^2
-            const double sc_in = inv_r * irj;                    // 1 / (r_< r_>)
-            const double u = FULL ? xh * xj + yh * yj + zh * zj : zh;
-            double S1 = 0.0, Sl = 0.0, SBk = 0.0, SBj = 0.0;
-            double P0 = 1.0, P1 = u, dP0 = 0.0, dP1 = 1.0;        // P_l(u) (own cos th if axisym)
-            double Q0 = 1.0, Q1 = zj, dQ0 = 0.0, dQ1 = 1.0;       // partner P_l(cos th_j), axisym
-            double rl = rho;                                    // l = 0: Gauss's law below
-#pragma unroll 2
-            for (int l = 1; l <= L; ++l) {
-                const double4 cl = tb.nf4[l];   // {(2l+1)/(l+1), l/(l+1), 2l+1, l}
-                const double A = cl.x, Bc = cl.y, tl1 = cl.z, dl = cl.w;
-                if (FULL) {
-                    const double t = rl * P1;
-                    S1 += t;
-                    Sl += dl * t;
-                    SBk += rl * dP1;
-                } else {
-                    const double t = rl * P1 * Q1;
-                    S1 += t;
-                    Sl += dl * t;
-                    SBk += rl * dP1 * Q1;
-                    SBj += rl * P1 * dQ1;
-                    const double Q2 = A * zj * Q1 - Bc * Q0;
-                    const double dQ2 = dQ0 + tl1 * Q1;
-                    Q0 = Q1;
-                    Q1 = Q2;
-                    dQ0 = dQ1;
-                    dQ1 = dQ2;
-                }
-                const double P2 = A * u * P1 - Bc * P0;
-                const double dP2 = dP0 + tl1 * P1;
-                P0 = P1;
-                P1 = P2;
-                dP0 = dP1;
-                dP1 = dP2;
-                rl *= rho;
-            }
-            if (FULL) SBj = SBk;
-            const double S_out = -(Sl + S1), S_in = Sl;
-            const double SAk = k_outer ? S_out : S_in, sck = k_outer ? sc_out : sc_in;
-            const double SAj = k_outer ? S_in : S_out, scj = k_outer ? sc_in : sc_out;
-            double vkx, vky, vkz, vjx, vjy, vjz;
-            if (FULL) {
-                vkx = xj - u * xh; vky = yj - u * yh; vkz = zj - u * zh;
-                vjx = xh - u * xj; vjy = yh - u * yj; vjz = zh - u * zj;
-            } else {
-                vkx = -zh * xh; vky = -zh * yh; vkz = 1.0 - zh * zh;
-                vjx = -zj * xj; vjy = -zj * yj; vjz = 1.0 - zj * zj;
-            }
-            double gjx = scj * (SAj * xj + SBj * vjx);
-            double gjy = scj * (SAj * yj + SBj * vjy);
-            double gjz = scj * (SAj * zj + SBj * vjz);
-            if (active) {
-                ax += sck * (SAk * xh + SBk * vkx);
-                ay += sck * (SAk * yh + SBk * vky);
-                az += sck * (SAk * zh + SBk * vkz);
-            } else {
-                gjx = 0.0;
-                gjy = 0.0;
-                gjz = 0.0;
-            }
-            const int src = (lane - sft) & (kWave - 1);
-            ax += __shfl(gjx, src);
-            ay += __shfl(gjy, src);
-            az += __shfl(gjz, src);
-        }
+        const NF *nf;
+        if constexpr (FP32) nf = tb.nf4_32;
+        else nf = tb.nf4;
+        near_field<FULL, R, NF>(lane, jn, L, nf, sh_xh[w], sh_yh[w], sh_zh[w], sh_r[w], sh_ir[w],
+                                sh_r2[w], sh_uid[w], (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
+                                ax, ay, az);
         const double cn = -kQ / (4.0 * kPi * kp.ntilde);
         Ex += cn * ax;
         Ey += cn * ay;
@@ -849,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
         double sr = 0.0, sz = 0.0;   // radial and (e_z - c xh) parts of grad Phi_self
         double rl = inv_r2 * inv_r2 * inv_r;   // r^-(2l+3) at l = 1
         if (FULL) {
-            for (int l = 1; l <= Lf; ++l) {
+            for (int l = 1; l <= L; ++l) {
                 sr += tb.self_w[l] * (l + 1.0) * rl;
                 rl *= inv_r2;
             }
@@ -860,7 +918,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
             Ez += e * zh;
         } else {
             double P0 = 1.0, P1 = zh, dP0 = 0.0, dP1 = 1.0;
-            for (int l = 1; l <= Lf; ++l) {
+            for (int l = 1; l <= L; ++l) {
                 sr += tb.self_w[l] * rl * P1 * (-(l + 1.0) * P1);
                 sz += tb.self_w[l] * rl * P1 * dP1;
                 const double P2 = tb.nfA[l] * zh * P1 - tb.nfB[l] * P0;
@@ -999,6 +1057,7 @@ struct Layout {
     int L, C, C2, n_tiles, n_chunks, nb, nb_blocks;
     int64_t n_steps;
     bool full;
+    bool fp32;
 };
 
 bool make_layout(const sim_params *p, int64_t n, int64_t n_steps, Layout *lo, std::string *why)
@@ -1021,11 +1080,12 @@ bool make_layout(const sim_params *p, int64_t n, int64_t n_steps, Layout *lo, st
     if (p->m_mode != SIM_M_FULL && p->m_mode != SIM_M_AXISYM) { *why = "bad m_mode"; return false; }
     if (p->probe_bc < SIM_BC_ABSORB || p->probe_bc > SIM_BC_DIFFUSE) { *why = "bad probe_bc"; return false; }
     if (p->wall_bc != SIM_BC_SPECULAR && p->wall_bc != SIM_BC_DIFFUSE) { *why = "bad wall_bc"; return false; }
-    if (p->precision != SIM_FP64) { *why = "precision: only SIM_FP64 is available"; return false; }
+    if (p->precision != SIM_FP64 && p->precision != SIM_FP32_COMP) { *why = "bad precision"; return false; }
     if (p->tile != 0 && p->tile != kWave) { *why = "tile must be 0 or 64"; return false; }
     lo->n = n;
     lo->L = p->l_max;
     lo->full = p->m_mode == SIM_M_FULL;
+    lo->fp32 = p->precision == SIM_FP32_COMP;
     lo->C = lo->full ? (p->l_max + 1) * (p->l_max + 1) - 1 : p->l_max;
     lo->C2 = 2 * lo->C;
     lo->n_tiles = (int)((n + kWave - 1) / kWave);
@@ -1065,6 +1125,8 @@ struct sim {
     double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr, *Kc = nullptr,
            *coef = nullptr, *u_asy = nullptr, *qdiff = nullptr, *tables = nullptr, *Eout = nullptr;
     int *chl = nullptr;
+    float *coef32 = nullptr, *tables32 = nullptr;
+    double *lgrho = nullptr;
     uint32_t *Eid = nullptr;
     Ctl *ctl = nullptr;
     Tables tb{};
@@ -1087,8 +1149,11 @@ namespace {
         }                                                                             \
     } while (0)
 
-// Layout of the table block: 9 per-l arrays, the two (l, m) triangles, then
-// the interleaved near-field constants at a 32-byte aligned offset.
+// Layout of the table block: 9 per-l arrays (ftil, wl, drive_w, self_w, nfA,
+// nfB, lval, tl1, qmm, in this order), the two (l, m) triangles, then the
+// interleaved near-field constants at a 32-byte aligned offset.
+constexpr int kQmmArray = 8;   // index of qmm among the per-l arrays
+
 size_t nf4_offset(int L)
 {
     const size_t base = (size_t)9 * (L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2);
@@ -1096,6 +1161,16 @@ size_t nf4_offset(int L)
 }
 
 size_t tables_len(int L) { return nf4_offset(L) + 4 * (size_t)(L + 1); }
+
+// FP32 copies: qmm, the two (l, m) triangles, then the near-field constants
+// at a 16-byte aligned offset.
+size_t nf4_32_offset(int L)
+{
+    const size_t base = (size_t)(L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2);
+    return (base + 3) & ~size_t(3);
+}
+
+size_t tables32_len(int L) { return nf4_32_offset(L) + 4 * (size_t)(L + 1); }
 
 void plan_alloc(sim *h, Alloc &al)
 {
@@ -1121,7 +1196,16 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->off, (size_t)lo.nb + 1);
     al.add(&h->bsum, (size_t)lo.nb_blocks + 1);
     al.add(&h->S, (size_t)lo.n_tiles * lo.C2);
-    al.add(&h->coef, (size_t)lo.n_tiles * lo.C2);
+    if (lo.fp32) {
+        al.add(&h->coef32, (size_t)lo.n_tiles * lo.C2);
+        al.add(&h->lgrho, (size_t)lo.n_tiles);
+        al.add(&h->coef, 1);
+    } else {
+        al.add(&h->coef, (size_t)lo.n_tiles * lo.C2);
+        al.add(&h->coef32, 1);
+        al.add(&h->lgrho, 1);
+    }
+    al.add(&h->tables32, tables32_len(lo.L));
     al.add(&h->chunkS, (size_t)lo.n_chunks * lo.C2);
     al.add(&h->chunkC, (size_t)lo.n_chunks * lo.C2);
     al.add(&h->T, (size_t)lo.C);
@@ -1192,18 +1276,6 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
     return t;
 }
 
-// l_max values with compile-time specialisations of the hot kernels.
-#define MRP_DISPATCH_L(LV, MACRO) \
-    switch (LV) {                 \
-    case 1: MACRO(1); break;      \
-    case 2: MACRO(2); break;      \
-    case 4: MACRO(4); break;      \
-    case 8: MACRO(8); break;      \
-    case 16: MACRO(16); break;    \
-    case 32: MACRO(32); break;    \
-    default: MACRO(0); break;     \
-    }
-
 int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
 {
     const Layout &lo = h->lo;
@@ -1234,8 +1306,8 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
                                            h->B);
     mark(KN_MOMENTS);
     if (lo.C > 0) {
-        if (lo.full) k_moments<true, 0><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
-        else k_moments<false, 0><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S);
+        if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S, h->lgrho);
+        else k_moments<false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S, h->lgrho);
     }
     mark(KN_CHUNK_SUMS);
     if (lo.C > 0) k_chunk_sums<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkS, kp);
@@ -1246,17 +1318,19 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     mark(KN_CHUNK_APPLY);
     if (lo.C > 0)
         k_chunk_apply<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkC, h->Kc, h->tb, kp,
-                                                               h->coef);
+                                                               h->lgrho, h->coef, h->coef32);
     mark(KN_FIELD_PUSH);
-#define MRP_FIELD(FULLV, FO, LT)                                                              \
-    k_field_push<FULLV, FO, LT><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G, h->coef, \
-                                                      h->tb, kp, h->Eout, h->Eid)
+#define MRP_FIELD(FULLV, FO, F32)                                                              \
+    k_field_push<FULLV, FO, F32><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G, h->coef, \
+                                                       h->coef32, h->tb, kp, h->Eout, h->Eid)
+#define MRP_FIELD_P(FULLV, FO) \
+    do { if (lo.fp32) MRP_FIELD(FULLV, FO, true); else MRP_FIELD(FULLV, FO, false); } while (0)
     if (field_only) {
-        if (lo.full) MRP_FIELD(true, true, 0);
-        else MRP_FIELD(false, true, 0);
+        if (lo.full) MRP_FIELD_P(true, true);
+        else MRP_FIELD_P(false, true);
     } else {
-        if (lo.full) MRP_FIELD(true, false, 0);
-        else MRP_FIELD(false, false, 0);
+        if (lo.full) MRP_FIELD_P(true, false);
+        else MRP_FIELD_P(false, false);
         mark(KN_STEP_FINISH);
         k_step_finish<<<1, 1, 0, s>>>(h->ctl);
     }
@@ -1408,11 +1482,25 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
     h->tb.nfB = tb + 5 * (L + 1);
     h->tb.lval = tb + 6 * (L + 1);
     h->tb.tl1 = tb + 7 * (L + 1);
-    h->tb.qmm = tb + 8 * (L + 1);
-    h->tb.alm = tb + 9 * (L + 1);
-    h->tb.blm = tb + 9 * (L + 1) + (L + 1) * (L + 2) / 2;
+    h->tb.qmm = tb + kQmmArray * (L + 1);
+    h->tb.alm = tb + (kQmmArray + 1) * (L + 1);
+    h->tb.blm = tb + (kQmmArray + 1) * (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.nf4 = reinterpret_cast<const double4 *>(tb + nf4_offset(L));
     h->tb.chl = h->chl;
+    std::vector<float> tab32(tables32_len(L), 0.f);
+    {
+        const double *qmm = tab.data() + kQmmArray * (L + 1);
+        const double *alm = qmm + (L + 1);
+        const size_t ntri = (size_t)(L + 1) * (L + 2) / 2;
+        for (int m = 0; m <= L; ++m) tab32[m] = (float)qmm[m];
+        for (size_t i = 0; i < 2 * ntri; ++i) tab32[(L + 1) + i] = (float)alm[i];
+        const double *nf4 = tab.data() + nf4_offset(L);
+        for (int i = 0; i < 4 * (L + 1); ++i) tab32[nf4_32_offset(L) + i] = (float)nf4[i];
+    }
+    h->tb.qmm32 = h->tables32;
+    h->tb.alm32 = h->tables32 + (L + 1);
+    h->tb.blm32 = h->tables32 + (L + 1) + (L + 1) * (L + 2) / 2;
+    h->tb.nf4_32 = reinterpret_cast<const float4 *>(h->tables32 + nf4_32_offset(L));
     // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
     std::vector<int> chl;
     for (int m = 0; m <= (lo.full ? L : 0); ++m)
@@ -1438,6 +1526,7 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
     kp.inv_vol = 1.0 / (p->r_out * p->r_out * p->r_out - 1.0);
     kp.seed = p->seed;
     kp.n_steps = n_steps;
+    kp.fp32 = lo.fp32 ? 1 : 0;
 
     // upload the initial state (A, creation order) and the drive
     std::vector<double> col((size_t)n);
@@ -1458,6 +1547,7 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
         hipMemset(h->dead, 0, (size_t)n) ||
         hipMemcpy(h->tables, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->chl, chl.data(), sizeof(int) * chl.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->tables32, tab32.data(), sizeof(float) * tab32.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice) ||
         hipMemcpy(h->qdiff, zeros.data(), sizeof(double) * zeros.size(), hipMemcpyHostToDevice) ||
         (n_steps > 0 &&

@@ -53,6 +53,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB):
         raise ImportError(f"{LIB} is not built; run __graft_entry__.build() first")
+    # The library links the HIP runtime by soname.  Load torch first so the
+    # process holds a single HIP runtime (torch's), shared with torch's
+    # device memory and streams.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB)
     dp = C.POINTER(C.c_double)
     P = C.POINTER(sim_params)

@@ -1,6 +1,7 @@
-"""GPU (HIP, FP64) against the CPU oracle on identical seeded inputs.
+"""GPU (HIP) against the CPU oracle on identical seeded inputs.
 
-Field metric: max_k |E_gpu - E_oracle| / RMS_k |E_oracle|, bar 1e-12 in FP64.
+Field metric: max_k |E_gpu - E_oracle| / RMS_k |E_oracle|; bar 1e-12 in FP64,
+1e-5 in the FP32-compensated mode (l_max <= 16).
 Every case prints its name, size and seed before touching the GPU.
 """
 from __future__ import annotations
@@ -193,3 +194,95 @@ def test_deterministic_and_resumable():
     np.testing.assert_array_equal(end["vel"], full["vel"][keep])
     np.testing.assert_array_equal(np.concatenate([q_first, q_second]), outs[0][1])
     assert end["q_surface"] == full["q_surface"]
+
+
+# --------------------------------------------------------------------------
+# FP32-compensated mode: same oracle, bar 1e-5 on the field
+# --------------------------------------------------------------------------
+
+FP32_FIELD_TOL = 1e-5
+# The FP32 field evaluation carries ~l * 2^-24 error per harmonic term, and the
+# m-sums of a near pair cancel by ~l, so the bound grows like l_max^2 * 2^-24:
+# it meets 1e-5 up to l_max = 16; at l_max = 32 the measured error is 4.3e-5
+# and the stated bound is 1e-4 (FP64 mode meets 1e-12 there).
+FP32_FIELD_TOL_L32 = 1e-4
+
+FP32_CASES = [
+    ("shell-3000-L8", 3000, 8, S.SIM_M_FULL, 61, FP32_FIELD_TOL),
+    ("ragged-777-L5", 777, 5, S.SIM_M_FULL, 62, FP32_FIELD_TOL),
+    ("shell-2000-L16", 2000, 16, S.SIM_M_FULL, 63, FP32_FIELD_TOL),
+    ("shell-1000-L32", 1000, 32, S.SIM_M_FULL, 64, FP32_FIELD_TOL_L32),
+    ("axisym-640-L6", 640, 6, S.SIM_M_AXISYM, 65, FP32_FIELD_TOL),
+    ("monopole-500-L0", 500, 0, S.SIM_M_FULL, 66, FP32_FIELD_TOL),
+]
+
+
+@pytest.mark.parametrize("name,n,L,mode,seed,tol", FP32_CASES, ids=[c[0] for c in FP32_CASES])
+def test_fp32_field_matches_oracle(name, n, L, mode, seed, tol):
+    _say(f"[gpu] fp32 field parity {name}: n={n} L={L} mode={mode} seed={seed}")
+    sp, op = _params(n, L, mode, q_surface0=-7.0, precision=S.SIM_FP32_COMP)
+    st = W.uniform_shell(n, seed, 5.0, 0.0831)
+    u = np.array([0.0, 0.0, 0.3, 0.0])
+    with S.Sim(sp, st.pos, st.vel, u, start_step=2) as sim:
+        E = sim.eval_field()
+    Eo, _ = O.field(op, st.pos, q_surface=-7.0, u_asy=0.3)
+    err = _rel_err(E, Eo)
+    _say(f"[gpu]   rel err {err:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [(S.SIM_FP64, FP64_FIELD_TOL),
+                                           (S.SIM_FP32_COMP, FP32_FIELD_TOL)])
+def test_near_probe_stress(precision, tol):
+    """A fifth of the particles in 1 < r < 1.05, where the direct exterior
+    term and the image term of the dielectric oppose each other."""
+    n, L = 2500, 16
+    _say(f"[gpu] near-probe stress precision={precision} n={n} L={L}")
+    st = W.uniform_shell(n, 71, 5.0, 0.0831)
+    pos = st.pos.copy()
+    rng = np.random.default_rng(71)
+    k = rng.choice(n, n // 5, replace=False)
+    rr = np.linalg.norm(pos[k], axis=1)
+    pos[k] *= ((1.0 + 0.05 * rng.random(k.size)) / rr)[:, None]
+    sp, op = _params(n, L, q_surface0=-30.0, precision=precision)
+    with S.Sim(sp, pos, st.vel, np.zeros(2)) as sim:
+        E = sim.eval_field()
+    Eo, _ = O.field(op, pos, q_surface=-30.0)
+    err = _rel_err(E, Eo)
+    near = _rel_err(E, Eo, mask=np.isin(np.arange(n), k))
+    _say(f"[gpu]   rel err {err:.3e} (near-probe subset {near:.3e})")
+    assert err <= tol
+
+
+def test_fp32_large_workload_sampled_field():
+    wl = W.LARGE
+    _say(f"[gpu] fp32 sampled field parity {wl.name}")
+    st = wl.particles()
+    sp, op = _params(wl.n, wl.l_max, q_surface0=-40.0, precision=S.SIM_FP32_COMP)
+    u = wl.drive(30)
+    with S.Sim(sp, st.pos, st.vel, u, start_step=20) as sim:
+        E = sim.eval_field()
+    rng = np.random.default_rng(5)
+    targets = np.sort(rng.choice(wl.n, 48, replace=False))
+    Eo, _ = O.field(op, st.pos, q_surface=-40.0, u_asy=u[20], targets=targets)
+    rms = np.sqrt(np.mean(np.sum(Eo * Eo, axis=1)))
+    err = float(np.max(np.abs(E[targets] - Eo)) / rms)
+    _say(f"[gpu]   rel err {err:.3e}")
+    assert err <= FP32_FIELD_TOL
+
+
+def test_fp32_steps_track_oracle():
+    n, L, steps = 2000, 8, 5
+    _say(f"[gpu] fp32 stepping n={n} L={L} steps={steps}")
+    sp, op = _params(n, L, q_surface0=-2.0, precision=S.SIM_FP32_COMP)
+    st = W.uniform_shell(n, 41, 5.0, 0.3)
+    u = W.gaussian_drive(steps, sp.dt, 50.0, 289.52, t_center=0.1)
+    with S.Sim(sp, st.pos, st.vel, u) as sim:
+        sim.step(steps)
+        qd = sim.read_response(0, steps)
+        out = sim.read_state()
+    ref = O.run(op, st.pos, st.vel, u, steps, q_surface=-2.0)
+    np.testing.assert_array_equal(out["alive"], ref.alive)
+    # a 1e-5 relative field error moves a particle by < 1e-5 |E| dt^2 per step
+    assert np.max(np.abs(out["pos"] - ref.pos)) <= 1e-7
+    assert np.max(np.abs(qd - ref.qdiff)) <= 1e-6 * np.max(np.abs(ref.qdiff))
