@@ -1,0 +1,112 @@
+"""Spectrum-level checks of the GPU path.
+
+* Cold-plasma dipole resonance: with T_e -> 0 and reflecting walls, the l = 1
+  response of a uniform plasma shell (1, r_out) around the dielectric-covered
+  electrodes is the layered-sphere mode (dielectric | plasma with
+  eps_p = 1 - 1/omega^2 | vacuum) found from electrostatics alone; the paper's
+  dipole kernel (l_max = 1, m = 0) must resonate there.
+* FP32-compensated against FP64: the resonance c and half-width 2b of the
+  damped-sine fit (Sec. 4) of the impulse response agree within 0.5% on the
+  same seeded 2e6-particle, l_max = 16 workload.
+Both use the difference of a driven run and an undriven twin from the same
+state (the static part of Q_diff is particle noise).
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from paper_2111_13072_amd import analysis as A
+from paper_2111_13072_amd import sim as S
+from paper_2111_13072_amd import workload as W
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def layered_sphere_det(w, l, a, eps_d, r_out):
+    """Determinant of the interface conditions for a mode l of potential
+    A (r^l - a^{2l+1} r^{-l-1}) in the dielectric (grounded electrode at a),
+    B r^l + C r^{-l-1} in the cold plasma, D r^{-l-1} in the outer vacuum;
+    potential and eps * dPhi/dr continuous at r = 1 and r = r_out."""
+    ep = 1.0 - 1.0 / w ** 2
+    f = lambda r: (r ** l, r ** (-l - 1))
+    g = lambda r: (l * r ** (l - 1), -(l + 1) * r ** (-l - 2))
+    k = a ** (2 * l + 1)
+    M = np.array([
+        [f(1)[0] - k * f(1)[1], -f(1)[0], -f(1)[1], 0.0],
+        [eps_d * (g(1)[0] - k * g(1)[1]), -ep * g(1)[0], -ep * g(1)[1], 0.0],
+        [0.0, f(r_out)[0], f(r_out)[1], -f(r_out)[1]],
+        [0.0, ep * g(r_out)[0], ep * g(r_out)[1], -g(r_out)[1]],
+    ])
+    return np.linalg.det(M)
+
+
+def cold_modes(l, a, eps_d, r_out):
+    ws = np.linspace(0.05, 0.999, 4000)
+    d = [layered_sphere_det(w, l, a, eps_d, r_out) for w in ws]
+    return [brentq(layered_sphere_det, ws[i], ws[i + 1], args=(l, a, eps_d, r_out))
+            for i in range(len(ws) - 1) if np.sign(d[i]) != np.sign(d[i + 1])]
+
+
+def _twin(params, st, n_steps, amplitude):
+    out = []
+    for drive in (True, False):
+        u = W.impulse_drive(n_steps, amplitude) if drive else np.zeros(n_steps)
+        with S.Sim(params, st.pos, st.vel, u) as sim:
+            sim.step(n_steps)
+            out.append(sim.read_response(0, n_steps))
+    return A.twin_difference(*out)
+
+
+def test_cold_modes_of_the_layered_sphere():
+    """The determinant roots themselves: inner dipole mode and the weak
+    outer-surface mode for eps_r = 4, d = 0.25, r_out = 5."""
+    modes = cold_modes(1, 0.75, 4.0, 5.0)
+    assert len(modes) == 2
+    assert modes[0] == pytest.approx(0.36193, abs=5e-5)
+    assert modes[1] == pytest.approx(0.58491, abs=5e-5)
+    # r_out -> infinity: the outer mode tends to the plasma-sphere value 1/sqrt(3)
+    assert cold_modes(1, 0.75, 4.0, 1e3)[1] == pytest.approx(1 / np.sqrt(3), rel=1e-4)
+
+
+@pytest.mark.gpu
+def test_cold_dipole_resonance():
+    n, seed, steps, amp = 2_000_000, 7, 1700, 0.01
+    _say(f"[gpu] cold dipole resonance: n={n} seed={seed} L=1 axisym steps={steps}")
+    st = W.uniform_shell(n, seed, 5.0, 0.0)
+    prm = S.SimParams(ntilde=W.ntilde_for(n, 5.0), l_max=1, m_mode=S.SIM_M_AXISYM,
+                      probe_bc=S.SIM_BC_SPECULAR, wall_bc=S.SIM_BC_SPECULAR)
+    diff = _twin(prm, st, steps, amp) / amp
+    t = np.arange(steps) * prm.dt
+    expect = cold_modes(1, 1.0 - prm.d, prm.eps_r, prm.r_out)[0]
+    m = t <= 80.0
+    fit = A.fit_damped_sine(t[m], diff[m], 1.0, expect)
+    _say(f"[gpu] cold dipole: fit c={fit.frequency:.5f} b={fit.damping:.5f} expect {expect:.5f}")
+    assert fit.frequency == pytest.approx(expect, rel=5e-3)
+    # cold and collisionless: the mode is nearly undamped
+    assert 0 <= fit.damping < 0.02
+
+
+@pytest.mark.gpu
+def test_spectrum_fp32c_matches_fp64():
+    wl = W.LARGE
+    steps = 420
+    st = wl.particles()
+    fits = {}
+    for prec in (S.SIM_FP64, S.SIM_FP32_COMP):
+        _say(f"[gpu] impulse spectrum {wl.name} seed={wl.seed} precision={prec} steps={steps}")
+        prm = S.SimParams(ntilde=wl.ntilde, l_max=wl.l_max, precision=prec)
+        diff = _twin(prm, st, steps, 1.0)
+        t = np.arange(steps) * wl.dt
+        m = t <= 20.0
+        fits[prec] = A.fit_damped_sine(t[m], diff[m], 1.0)
+        _say(f"[gpu]   c={fits[prec].frequency:.5f} 2b={fits[prec].fwhm:.5f}")
+    f64, f32 = fits[S.SIM_FP64], fits[S.SIM_FP32_COMP]
+    assert 0.3 < f64.frequency < 0.9 and f64.damping > 0
+    assert f32.frequency == pytest.approx(f64.frequency, rel=5e-3)
+    assert f32.fwhm == pytest.approx(f64.fwhm, rel=5e-3)
