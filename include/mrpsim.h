@@ -116,7 +116,7 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
  * the scheme of Sec. 3-4: radial sort, harmonic moments, prefix/suffix scans,
  * boundary response + drive, field and leapfrog push with the wall rules;
  * Q_diff(t_s) (Sec. 4) is recorded before the push.  SIM_ERANGE if the steps
- * would pass n_steps.
+ * would pass n_steps of any member.
  */
 int sim_step(sim_t *h, int64_t k);
 
@@ -161,10 +161,91 @@ const char *sim_kernel_name(int32_t i);
  * invalid parameters. */
 int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps);
 
-/* Particle count, tile size and channel count actually used. */
+/* Particle count, tile size and channel count actually used (member 0). */
 int sim_info(sim_t *h, int64_t *n, int32_t *tile, int32_t *channels);
 
 void sim_destroy(sim_t *h);
+
+/*
+ * Batches: one handle stepping many independent simulations ("members") in
+ * the same kernel launches.  Independent runs of the method (Sec. 4: every
+ * plasma and drive is its own run) share the probe (d, eps_r), l_max, m_mode
+ * and precision; everything else is per member.  A member's results do not
+ * depend on the other members: they equal, bit for bit, those of the same
+ * member run alone.  A handle from sim_create is a batch of one member
+ * (index 0), so every sim_member_* call also applies to it.
+ *
+ * Each member occupies ceil(n/64) tiles of 64 particle slots, ceil(tiles/64)
+ * carry chunks and max(1, n/8) sort buckets of the handle's capacity, plus
+ * 16 bytes per step for its drive and response.
+ */
+typedef struct {
+    uint32_t struct_size;  /* sizeof(sim_member) */
+    uint32_t reserved0;
+    int64_t n;             /* electrons (> 0) */
+    const double *pos;     /* host [3n], as in sim_create; copied */
+    const double *vel;     /* host [3n], v(t_start - dt/2); copied */
+    const uint32_t *ids;   /* host [n] distinct ids, or NULL for 0..n-1 */
+    const double *u_asy;   /* host [n_steps]; copied */
+    int64_t n_steps;
+    int64_t start_step;    /* 0 <= start_step <= n_steps */
+    double ntilde;         /* super-particles per unit volume R^3 */
+    double ion_density;
+    double q_surface0;
+    double r_out;
+    double dt;
+    uint64_t seed;
+    int32_t probe_bc;
+    int32_t wall_bc;
+} sim_member;
+
+/* Fill *m with the per-member defaults of sim_params_default (arrays NULL). */
+void sim_member_default(sim_member *m);
+
+/*
+ * Create a batch.  common supplies d, eps_r, l_max, m_mode, precision, tile
+ * and mem_limit_bytes (its per-member fields are ignored).  slot_capacity is
+ * the number of particle slots to reserve (0: exactly what the initial
+ * members need); max_members the size of the member table (0: n_members).
+ * members[0 .. n_members) are admitted in order as indices 0, 1, ...
+ * SIM_EINVAL on invalid parameters or members, SIM_ENOMEM when they do not
+ * fit the capacity or the memory limit, or an allocation fails.
+ */
+int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t max_members,
+                     int32_t n_members, const sim_member *members, void *hip_stream, sim_t **out);
+
+/* Device bytes of a batch's shared arrays (members add 16 B per step). */
+int64_t sim_batch_footprint_bytes(const sim_params *common, int64_t slot_capacity,
+                                  int32_t max_members);
+
+/*
+ * Admit a member between steps (synchronises the handle's stream).  *index
+ * receives its slot in the member table.  SIM_ENOMEM when its tiles, chunks
+ * or buckets find no free contiguous range, the member table is full or the
+ * memory limit would be exceeded; the handle is unchanged then.
+ */
+int sim_batch_add(sim_t *h, const sim_member *m, int32_t *index);
+
+/* Retire a member and free its ranges (synchronises).  Read its results first. */
+int sim_batch_remove(sim_t *h, int32_t index);
+
+/*
+ * Enqueue k steps of the batch: every member takes min(k, steps left) steps;
+ * members that reach their n_steps stop.  Asynchronous.
+ */
+int sim_batch_step(sim_t *h, int64_t k);
+
+/* Host view of a member, without synchronising: particle count, steps
+ * enqueued so far (absolute step after them) and n_steps.  SIM_ERANGE for an
+ * unused index. */
+int sim_member_info(sim_t *h, int32_t index, int64_t *n, int64_t *step, int64_t *n_steps);
+
+/* As sim_read_response / sim_read_state / sim_eval_field, for one member. */
+int sim_member_read_response(sim_t *h, int32_t index, int64_t first, int64_t count,
+                             double *q_diff);
+int sim_member_read_state(sim_t *h, int32_t index, double *pos, double *vel, uint8_t *alive,
+                          double *q_surface, int64_t *step);
+int sim_member_eval_field(sim_t *h, int32_t index, double *E);
 const char *sim_strerror(int status);
 const char *sim_last_error(void);
 

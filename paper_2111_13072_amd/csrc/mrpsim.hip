@@ -14,8 +14,14 @@
 //            coefficient vector, the near field of its own tile pair by pair,
 //            the self-image correction and the ion background; then the
 //            leapfrog kick/drift and the wall rules
-// All work is on the handle's stream; one step is captured once into a HIP
-// graph and replayed.
+// A handle holds one or more independent simulations ("members") that share
+// the probe geometry, the truncation l_max and the precision.  Each member
+// owns a tile-aligned range of particle slots, a range of carry chunks and a
+// range of sort buckets; every kernel maps its tile, chunk or bucket to the
+// member through a device table, so one launch of each kernel steps all
+// members, and members can be admitted and retired between steps.  A
+// member's arithmetic does not depend on the others.  All work is on the
+// handle's stream; one step is captured once into a HIP graph and replayed.
 
 #include <hip/hip_runtime.h>
 
@@ -24,6 +30,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -62,7 +69,7 @@ struct State {
     uint32_t *uid;
 };
 
-// Control block in device memory.
+// Per-member control block in device memory.
 struct Ctl {
     int64_t step;       // absolute step of the state held in A
     uint32_t n_cur;     // records in A (some may be flagged absorbed)
@@ -72,12 +79,31 @@ struct Ctl {
     double q_surface;   // Q_S used by this step's field
 };
 
-// Per-l and per-(l, m) constant tables (host-computed, read-only).
+// Per-member description (device table, written by the host between steps).
+struct Seg {
+    uint32_t p0, cap;   // particle slots [p0, p0 + cap); p0 is a multiple of 64
+    uint32_t t0, nt;    // tiles [t0, t0 + nt), t0 = p0 / 64
+    uint32_t c0, nc;    // carry chunks [c0, c0 + nc)
+    uint32_t b0, nb;    // sort buckets [b0, b0 + nb)
+    double inv_vol;     // 1 / (r_out^3 - 1)
+    double ntilde, inv_ntilde, ion_density, q_surface0, dt, r_out;
+    uint64_t seed;
+    int32_t probe_bc, wall_bc;
+    int64_t n_steps;
+    const double *u_asy;
+    double *qdiff;
+    int32_t used, pad;
+};
+
+constexpr uint32_t kNone = 0xffffffffu;
+
+// Per-l and per-(l, m) constant tables (host-computed, read-only).  The
+// super-particle density 1 / ntilde is a per-member factor applied at use.
 struct Tables {
     const double *ftil;     // image coefficient f_l, with f_0 = 0 (floating probe)
-    const double *wl;       // 1 / ((2l+1) ntilde)
+    const double *wl;       // 1 / (2l+1)
     const double *drive_w;  // c_l b^P_l sqrt(4 pi / (2l+1)) for odd l, else 0
-    const double *self_w;   // f_l / (4 pi ntilde)
+    const double *self_w;   // f_l / (4 pi)
     const double *nfA;      // (2l+1)/(l+1)
     const double *nfB;      // l/(l+1)
     const double *lval;     // l
@@ -99,15 +125,28 @@ struct KParams {
     int L;          // l_max
     int C;          // channels: (L+1)^2 - 1 (full) or L (axisymmetric)
     int C2;         // 2C: interior then exterior
-    int n_tiles;
-    int n_chunks;
-    int nb;         // sort buckets
-    int probe_bc, wall_bc;
-    double dt, r_out, ntilde, ion_density, q_surface0, inv_vol;
-    uint64_t seed;
-    int64_t n_steps;
+    int n_tiles;    // tile capacity (particle slots / 64)
+    int n_chunks;   // chunk capacity
+    int nb;         // bucket capacity
+    int n_members;  // member table size
     int fp32;       // SIM_FP32_COMP
+    int field_only; // evaluation without a step: every used member runs
 };
+
+// Device tables shared by the kernels.
+struct Map {
+    const Seg *seg;
+    Ctl *ctl;
+    const uint32_t *tile_member;   // [n_tiles], kNone for free tiles
+    const uint32_t *chunk_member;  // [n_chunks], kNone for free chunks
+};
+
+// A member takes part in this launch: it is in use and has steps left (or
+// the launch only evaluates the field).
+__device__ inline bool member_runs(const Seg &sg, const Ctl &c, const KParams &kp)
+{
+    return sg.used && (kp.field_only || c.step < sg.n_steps);
+}
 
 __host__ __device__ inline int tri(int l, int m) { return l * (l + 1) / 2 + m; }
 
@@ -152,27 +191,44 @@ __global__ void k_sort_clear(uint32_t *hist, int nb)
     if (i <= nb) hist[i] = 0;
 }
 
-// Key, bucket and slot inside the bucket.  Lanes of a wave that fall into the
+// Key, bucket and slot inside the bucket, over all particle slots.  A wave
+// is one tile and so lies in one member.  Lanes of a wave that fall into the
 // same bucket (particles arrive nearly sorted, so a wave touches few buckets)
 // take one atomic add together; its return value is the group's first slot.
-__global__ void k_sort_key(const Ctl *ctl, State A, const uint8_t *dead, uint64_t *key,
-                           uint32_t *bkt, uint32_t *sub, uint32_t *hist, KParams kp)
+__global__ void k_sort_key(Map mp, State A, const uint8_t *dead, uint64_t *key, uint32_t *bkt,
+                           uint32_t *sub, uint32_t *hist, KParams kp)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const bool in = i < ctl->n_cur;
-    const bool live = in && !dead[i];
-    uint32_t b = 0xffffffffu;
+    const uint32_t tile = i >> 6;
+    if ((int)tile >= kp.n_tiles) return;   // whole waves: i < 64 * n_tiles
+    const uint32_t mb = uniform_u32(mp.tile_member[tile]);
+    bool live = false;
+    double inv_vol = 0.0;
+    uint32_t b0 = 0, nb = 1;
+    if (mb != kNone) {
+        const Seg &sg = mp.seg[mb];
+        const Ctl &c = mp.ctl[mb];
+        if (member_runs(sg, c, kp)) {
+            live = (i - sg.p0) < c.n_cur && !dead[i];
+            inv_vol = sg.inv_vol;
+            b0 = sg.b0;
+            nb = sg.nb;
+        }
+    }
+    uint32_t b = kNone;
     if (live) {
         const double r2 = key_r2(A.x[i], A.y[i], A.z[i]);
         key[i] = (uint64_t)__double_as_longlong(r2);
         // Monotone non-decreasing map of r^2 to [0, nb): enclosed shell volume.
-        const double t = (r2 * sqrt(r2) - 1.0) * kp.inv_vol * (double)kp.nb;
-        if (!(t > 0.0)) b = 0;
-        else if (!(t < (double)(kp.nb - 1))) b = kp.nb - 1;
-        else b = (uint32_t)t;
+        const double t = (r2 * sqrt(r2) - 1.0) * inv_vol * (double)nb;
+        uint32_t lb;
+        if (!(t > 0.0)) lb = 0;
+        else if (!(t < (double)(nb - 1))) lb = nb - 1;
+        else lb = (uint32_t)t;
+        b = b0 + lb;
     }
-    if (in) bkt[i] = b;
+    bkt[i] = b;
     // Group the lanes by bucket (no memory traffic), then every group leader
     // adds its group's count in one atomic instruction.
     uint64_t todo = __ballot(live);
@@ -232,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_a(const uint32_t *in, uint32_t 
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_b(uint32_t *bsum, int nblocks, Ctl *ctl)
+__global__ __launch_bounds__(kBlock) void k_scan_b(uint32_t *bsum, int nblocks)
 {
     uint32_t carry = 0;
     for (int base = 0; base < nblocks; base += kBlock) {
@@ -243,7 +299,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_b(uint32_t *bsum, int nblocks, 
         if (i < nblocks) bsum[i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) ctl->n_live = carry;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_c(const uint32_t *in, const uint32_t *bsum,
@@ -268,15 +323,29 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(const uint32_t *in, const uin
     }
 }
 
+// Per member: alive count (its buckets' share of the global offsets) and the
+// surface charge Q_S = q_surface0 + q * (absorbed so far), which enters the
+// field as an interior l = 0 charge (Q_S / (4 pi r), Sec. 3).
+__global__ void k_member_live(Map mp, const uint32_t *off, KParams kp)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= kp.n_members) return;
+    const Seg &sg = mp.seg[s];
+    Ctl &c = mp.ctl[s];
+    if (!member_runs(sg, c, kp)) return;
+    c.n_live = off[sg.b0 + sg.nb] - off[sg.b0];
+    c.q_surface = sg.q_surface0 + kQ * (double)c.n_dead;
+}
+
 // Bucket order (arbitrary inside a bucket): key, id and source index.
-__global__ void k_sort_scatter(const Ctl *ctl, const uint64_t *key, const uint32_t *uid,
-                               const uint32_t *bkt, const uint32_t *sub, const uint32_t *off,
-                               uint64_t *tkey, uint32_t *tuid, uint32_t *tidx, uint32_t *tbkt)
+__global__ void k_sort_scatter(const uint64_t *key, const uint32_t *uid, const uint32_t *bkt,
+                               const uint32_t *sub, const uint32_t *off, uint64_t *tkey,
+                               uint32_t *tuid, uint32_t *tidx, uint32_t *tbkt, KParams kp)
 {
     const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= ctl->n_cur) return;
+    if (i >= (uint32_t)kp.n_tiles * kWave) return;
     const uint32_t b = bkt[i];
-    if (b == 0xffffffffu) return;
+    if (b == kNone) return;
     const uint32_t pos = off[b] + sub[i];
     tkey[pos] = key[i];
     tuid[pos] = uid[i];
@@ -285,19 +354,19 @@ __global__ void k_sort_scatter(const Ctl *ctl, const uint64_t *key, const uint32
 }
 
 // Final position = bucket start + number of bucket mates with a smaller
-// (r^2, id) key (independent of the order inside the bucket); the particle's
-// state moves there.  A block's positions cover a window of whole buckets,
-// staged in LDS when it fits.
+// (r^2, id) key (independent of the order inside the bucket), moved into the
+// member's slot range; the particle's state moves there.  A block's positions
+// cover a window of whole buckets, staged in LDS when it fits.
 constexpr int kRankWindow = 2048;
 
-__global__ __launch_bounds__(kBlock) void k_sort_rank_move(const Ctl *ctl, const uint64_t *tkey,
+__global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const uint64_t *tkey,
                                                            const uint32_t *tuid, const uint32_t *tidx,
                                                            const uint32_t *tbkt, const uint32_t *off,
-                                                           State A, State B)
+                                                           State A, State B, KParams kp)
 {
     __shared__ uint64_t wkey[kRankWindow];
     __shared__ uint32_t wuid[kRankWindow];
-    const uint32_t n = ctl->n_live;
+    const uint32_t n = off[kp.nb];   // alive particles of all running members
     const uint32_t p0 = xcd_block(blockIdx.x, gridDim.x) * kBlock;
     if (p0 >= n) return;
     const uint32_t p_last = min(p0 + kBlock, n) - 1;
@@ -328,8 +397,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(const Ctl *ctl, const
             rank += (kj < k) || (kj == k && tuid[j] < u);
         }
     }
-    const uint32_t d = lo + rank;
     const uint32_t i = tidx[p];
+    const Seg &sg = mp.seg[mp.tile_member[i >> 6]];
+    const uint32_t d = sg.p0 + (lo + rank - off[sg.b0]);
     B.x[d] = A.x[i];
     B.y[d] = A.y[i];
     B.z[d] = A.z[i];
@@ -363,8 +433,8 @@ __device__ inline void swap_wave_halves(double &a, double &b)
 }
 
 template <bool FULL>
-__global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tables tb,
-                                                    KParams kp, double *S, double *lgrho)
+__global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, KParams kp,
+                                                    double *S, double *lgrho)
 {
     // Per wave (one tile of 64 particles): for each channel, q R (interior)
     // and q I (exterior) are first folded across the two wave halves with a
@@ -375,10 +445,19 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + w);
-    const bool tile_ok = (int)tile < kp.n_tiles;
-    const uint32_t n = ctl->n_live;
+    // the tile's member; n = its alive count, lt = the tile's index in it
+    bool tile_ok = false;
+    uint32_t n = 0, lt = 0;
+    if ((int)tile < kp.n_tiles) {
+        const uint32_t mb = uniform_u32(mp.tile_member[tile]);
+        if (mb != kNone && member_runs(mp.seg[mb], mp.ctl[mb], kp)) {
+            tile_ok = true;
+            n = mp.ctl[mb].n_live;
+            lt = tile - mp.seg[mb].t0;
+        }
+    }
     const uint32_t p = tile * kWave + lane;
-    const bool valid = tile_ok && p < n;
+    const bool valid = tile_ok && lt * kWave + lane < n;
     double x = 0.0, y = 0.0, z = 2.0;
     if (valid) {
         x = B.x[p];
@@ -396,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
     if (kp.fp32 && tile_ok && lane == 0) {
         // reference radius of the tile for the FP32 field: its first particle
         double rho = 1.0;
-        if (tile * kWave < n) {
+        if (lt * kWave < n) {
             const uint32_t p0 = tile * kWave;
             rho = sqrt(key_r2(B.x[p0], B.y[p0], B.z[p0]));
         }
@@ -471,37 +550,56 @@ __global__ __launch_bounds__(kBlock) void k_moments(const Ctl *ctl, State B, Tab
 // Carries: prefix/suffix scans over tiles, totals, coefficients, Q_diff
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_chunk_sums(const double *S, double *chunkS, KParams kp)
+// The chunk's member and its tile range; false if the member does not run.
+__device__ inline bool chunk_tiles(const Map &mp, const KParams &kp, int j, uint32_t *mb,
+                                   int *t0, int *t1)
+{
+    const uint32_t m = mp.chunk_member[j];
+    if (m == kNone || !member_runs(mp.seg[m], mp.ctl[m], kp)) return false;
+    const Seg &sg = mp.seg[m];
+    *mb = m;
+    *t0 = (int)(sg.t0 + (uint32_t)(j - (int)sg.c0) * kChunk);
+    *t1 = min(*t0 + kChunk, (int)(sg.t0 + sg.nt));
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(Map mp, const double *S, double *chunkS,
+                                                       KParams kp)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
     if (c >= kp.C2) return;
     const int j = blockIdx.x;
-    const int t0 = j * kChunk, t1 = min(t0 + kChunk, kp.n_tiles);
+    uint32_t mb;
+    int t0, t1;
+    if (!chunk_tiles(mp, kp, j, &mb, &t0, &t1)) return;
     double s = 0.0;
     for (int t = t0; t < t1; ++t) s += S[(size_t)t * kp.C2 + c];
     chunkS[(size_t)j * kp.C2 + c] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_chunk_scan(const double *chunkS, double *chunkC,
-                                                       double *T, Ctl *ctl, KParams kp)
+// Per member (blockIdx.y) and channel: exclusive prefix of the interior chunk
+// sums, exclusive suffix of the exterior ones, and the totals T_lm.
+__global__ __launch_bounds__(kBlock) void k_chunk_scan(Map mp, const double *chunkS,
+                                                       double *chunkC, double *T, KParams kp)
 {
     const int c = blockIdx.x * kBlock + threadIdx.x;
-    // Q_S = q_surface0 + q * (absorbed so far); it enters the field as an
-    // interior l = 0 charge (Q_S / (4 pi r), Sec. 3) in the field kernel.
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        ctl->q_surface = kp.q_surface0 + kQ * (double)ctl->n_dead;
+    const int s = blockIdx.y;
     if (c >= kp.C2) return;
+    const Seg &sg = mp.seg[s];
+    if (!member_runs(sg, mp.ctl[s], kp)) return;
     constexpr int U = 16;   // loads kept in flight along the serial chain
-    const int nc = kp.n_chunks;
+    const int nc = (int)sg.nc;
+    const double *cS = chunkS + (size_t)sg.c0 * kp.C2;
+    double *cC = chunkC + (size_t)sg.c0 * kp.C2;
     double run = 0.0;
     if (c < kp.C) {
         for (int j0 = 0; j0 < nc; j0 += U) {
             double v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = (j0 + u < nc) ? chunkS[(size_t)(j0 + u) * kp.C2 + c] : 0.0;
+            for (int u = 0; u < U; ++u) v[u] = (j0 + u < nc) ? cS[(size_t)(j0 + u) * kp.C2 + c] : 0.0;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (j0 + u < nc) chunkC[(size_t)(j0 + u) * kp.C2 + c] = run;
+                if (j0 + u < nc) cC[(size_t)(j0 + u) * kp.C2 + c] = run;
                 run += v[u];
             }
         }
@@ -509,56 +607,64 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(const double *chunkS, dou
         for (int j0 = nc - 1; j0 >= 0; j0 -= U) {
             double v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = (j0 - u >= 0) ? chunkS[(size_t)(j0 - u) * kp.C2 + c] : 0.0;
+            for (int u = 0; u < U; ++u) v[u] = (j0 - u >= 0) ? cS[(size_t)(j0 - u) * kp.C2 + c] : 0.0;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (j0 - u >= 0) chunkC[(size_t)(j0 - u) * kp.C2 + c] = run;
+                if (j0 - u >= 0) cC[(size_t)(j0 - u) * kp.C2 + c] = run;
                 run += v[u];
             }
         }
-        T[c - kp.C] = run;
+        T[(size_t)s * kp.C + (c - kp.C)] = run;
     }
 }
 
-// Constant part of the interior coefficient: image response -f_l T_lm and the
-// hemisphere drive (odd l, m = 0; stream positions 0..L-1 hold m = 0, l = 1..L);
-// and the probe response Q_diff(t_step).
-__global__ __launch_bounds__(kBlock) void k_coef_prep(const double *T, Ctl *ctl,
-                                                      const double *u_asy, double *qdiff,
-                                                      Tables tb, KParams kp, double *Kc)
+// Per member (blockIdx.x): constant part of the interior coefficient, the
+// image response -f_l T_lm and the hemisphere drive (odd l, m = 0; stream
+// positions 0..L-1 hold m = 0, l = 1..L); and the probe response Q_diff(t_step).
+__global__ __launch_bounds__(kBlock) void k_coef_prep(Map mp, const double *T, Tables tb,
+                                                      KParams kp, double *Kc)
 {
-    const int64_t step = ctl->step;
-    const double u = (step >= 0 && step < kp.n_steps) ? u_asy[step] : 0.0;
+    const int s = blockIdx.x;
+    const Seg &sg = mp.seg[s];
+    const Ctl &ct = mp.ctl[s];
+    if (!member_runs(sg, ct, kp)) return;
+    const int64_t step = ct.step;
+    const bool in_run = step >= 0 && step < sg.n_steps;
+    const double u = in_run ? sg.u_asy[step] : 0.0;
+    const double *Ts = T + (size_t)s * kp.C;
     for (int c = threadIdx.x; c < kp.C; c += kBlock) {
         const int l = tb.chl[c];
-        double k = -tb.ftil[l] * T[c] * tb.wl[l];
+        double k = -tb.ftil[l] * Ts[c] * (tb.wl[l] * sg.inv_ntilde);
         if (c < kp.L) k += u * tb.drive_w[l];
-        Kc[c] = k;
+        Kc[(size_t)s * kp.C + c] = k;
     }
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int l = 1; l <= kp.L; l += 2) s += tb.drive_w[l] * T[l - 1];
-        if (step >= 0 && step < kp.n_steps) qdiff[step] = -s / kp.ntilde;
+        double acc = 0.0;
+        for (int l = 1; l <= kp.L; l += 2) acc += tb.drive_w[l] * Ts[l - 1];
+        if (in_run) sg.qdiff[step] = -acc / sg.ntilde;
     }
 }
 
 // Per-tile coefficients of the field kernel.  FP64 mode: absolute FP64
 // values.  FP32 mode: values pre-scaled to the tile's coordinates x / rho
 // (interior rho^-(l+1), exterior rho^l), stored as FP32.
-__global__ __launch_bounds__(kBlock) void k_chunk_apply(const double *S, const double *chunkC,
-                                                        const double *Kc, Tables tb, KParams kp,
-                                                        const double *lgrho, double *coef,
-                                                        float *coef32)
+__global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *S,
+                                                        const double *chunkC, const double *Kc,
+                                                        Tables tb, KParams kp, const double *lgrho,
+                                                        double *coef, float *coef32)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
     if (c >= kp.C2) return;
     const int j = blockIdx.x;
-    const int t0 = j * kChunk, t1 = min(t0 + kChunk, kp.n_tiles);
+    uint32_t mb;
+    int t0, t1;
+    if (!chunk_tiles(mp, kp, j, &mb, &t0, &t1)) return;
+    const double inv_nt = mp.seg[mb].inv_ntilde;
     double run = chunkC[(size_t)j * kp.C2 + c];
     if (c < kp.C) {
         const int l = tb.chl[c];
-        const double w = tb.wl[l];
-        const double k = Kc[c];
+        const double w = tb.wl[l] * inv_nt;
+        const double k = Kc[(size_t)mb * kp.C + c];
         for (int t = t0; t < t1; ++t) {
             const double v = run * w + k;
             if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2(-(l + 1.0) * lgrho[t]));
@@ -567,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(const double *S, const d
         }
     } else {
         const int l = tb.chl[c - kp.C];
-        const double w = tb.wl[l];
+        const double w = tb.wl[l] * inv_nt;
         for (int t = t1 - 1; t >= t0; --t) {
             const double v = run * w;
             if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2((double)l * lgrho[t]));
@@ -812,7 +918,7 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
 }
 
 template <bool FULL, bool FIELD_ONLY, bool FP32>
-__global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State A, uint8_t *dead,
+__global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A, uint8_t *dead,
                                                        Grave G, const double *coef,
                                                        const float *coef32, Tables tb, KParams kp,
                                                        double *Eout, uint32_t *Eid)
@@ -827,11 +933,22 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + w);
-    const uint32_t n = ctl->n_live;
-    const bool tile_live = (int)tile < kp.n_tiles && tile * kWave < n;
+    // the tile's member: n = its alive count, pl = this lane's position in
+    // its radial order
+    uint32_t mb = kNone, n = 0, lt = 0;
+    if ((int)tile < kp.n_tiles) {
+        const uint32_t m = uniform_u32(mp.tile_member[tile]);
+        if (m != kNone && member_runs(mp.seg[m], mp.ctl[m], kp)) {
+            mb = m;
+            n = mp.ctl[m].n_live;
+            lt = tile - mp.seg[m].t0;
+        }
+    }
+    const bool tile_live = mb != kNone && lt * kWave < n;
     const uint32_t p = tile * kWave + lane;
-    const bool valid = tile_live && p < n;
-    const int jn = tile_live ? (int)min((uint32_t)kWave, n - tile * kWave) : 0;
+    const uint32_t pl = lt * kWave + lane;
+    const bool valid = tile_live && pl < n;
+    const int jn = tile_live ? (int)min((uint32_t)kWave, n - lt * kWave) : 0;
 
     double x = 0.0, y = 0.0, z = 2.0, vx = 0.0, vy = 0.0, vz = 0.0;
     uint32_t uid = 0xffffffffu;
@@ -860,6 +977,9 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     if (!tile_live) return;
 
     const int L = kp.L;
+    const Seg &sg = mp.seg[mb];
+    Ctl &ct = mp.ctl[mb];
+    const double ntilde = sg.ntilde, inv_nt = sg.inv_ntilde;
 
     // ---- far field (all other tiles) ----
     double Ex, Ey, Ez;
@@ -895,7 +1015,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
         near_field<FULL, R, NF>(lane, jn, L, nf, sh_xh[w], sh_yh[w], sh_zh[w], sh_r[w], sh_ir[w],
                                 sh_r2[w], sh_uid[w], (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
                                 ax, ay, az);
-        const double cn = -kQ / (4.0 * kPi * kp.ntilde);
+        const double cn = -kQ / (4.0 * kPi * ntilde);
         Ex += cn * ax;
         Ey += cn * ay;
         Ez += cn * az;
@@ -912,7 +1032,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
                 rl *= inv_r2;
             }
             // grad Phi_self = -q sum f_l (l+1)/(4 pi nt) r^-(2l+3) xh; E = -grad
-            const double e = kQ * sr;
+            const double e = kQ * inv_nt * sr;
             Ex += e * xh;
             Ey += e * yh;
             Ez += e * zh;
@@ -930,9 +1050,10 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
                 rl *= inv_r2;
             }
             // grad Phi_selfcorr = q sum (f_l/(4 pi nt)) r^-(2l+3) P_l [-(l+1) P_l xh + P'_l (e_z - c xh)]
-            const double gx = kQ * (sr * xh + sz * (-zh * xh));
-            const double gy = kQ * (sr * yh + sz * (-zh * yh));
-            const double gz = kQ * (sr * zh + sz * (1.0 - zh * zh));
+            const double qn = kQ * inv_nt;
+            const double gx = qn * (sr * xh + sz * (-zh * xh));
+            const double gy = qn * (sr * yh + sz * (-zh * yh));
+            const double gz = qn * (sr * zh + sz * (1.0 - zh * zh));
             Ex -= gx;
             Ey -= gy;
             Ez -= gz;
@@ -944,9 +1065,9 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     // radial order (p is the sorted position) and the ion background
     // nt n_i (4 pi / 3)(r^3 - 1), all in super-particle units. ----
     {
-        const double ions = kp.ntilde * kp.ion_density * (4.0 * kPi / 3.0) * (r2 * r - 1.0);
-        const double enclosed = (ctl->q_surface + kQ * (double)p) + ions;
-        const double e = enclosed / (4.0 * kPi * kp.ntilde * r2);
+        const double ions = ntilde * sg.ion_density * (4.0 * kPi / 3.0) * (r2 * r - 1.0);
+        const double enclosed = (ct.q_surface + kQ * (double)pl) + ions;
+        const double e = enclosed / (4.0 * kPi * ntilde * r2);
         Ex += e * xh;
         Ey += e * yh;
         Ez += e * zh;
@@ -965,24 +1086,26 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
 
     // ---- leapfrog (Sec. 4 equations of motion) ----
     const double qm = kQ / kM;
-    vx = __dadd_rn(vx, __dmul_rn(qm * Ex, kp.dt));
-    vy = __dadd_rn(vy, __dmul_rn(qm * Ey, kp.dt));
-    vz = __dadd_rn(vz, __dmul_rn(qm * Ez, kp.dt));
-    x = __dadd_rn(x, __dmul_rn(vx, kp.dt));
-    y = __dadd_rn(y, __dmul_rn(vy, kp.dt));
-    z = __dadd_rn(z, __dmul_rn(vz, kp.dt));
+    const double dt = sg.dt;
+    vx = __dadd_rn(vx, __dmul_rn(qm * Ex, dt));
+    vy = __dadd_rn(vy, __dmul_rn(qm * Ey, dt));
+    vz = __dadd_rn(vz, __dmul_rn(qm * Ez, dt));
+    x = __dadd_rn(x, __dmul_rn(vx, dt));
+    y = __dadd_rn(y, __dmul_rn(vy, dt));
+    z = __dadd_rn(z, __dmul_rn(vz, dt));
 
     // ---- walls (tested on the new position) ----
     const double rn = sqrt(key_r2(x, y, z));
     uint8_t absorbed = 0;
-    const int64_t step = ctl->step;
-    if (rn <= 1.0 || rn >= kp.r_out) {
+    const int64_t step = ct.step;
+    const double r_out = sg.r_out;
+    if (rn <= 1.0 || rn >= r_out) {
         const bool probe = rn <= 1.0;
-        const int bc = probe ? kp.probe_bc : kp.wall_bc;
+        const int bc = probe ? sg.probe_bc : sg.wall_bc;
         if (probe && bc == SIM_BC_ABSORB) {
             absorbed = 1;
         } else {
-            const double s = probe ? (2.0 - rn) / rn : (2.0 * kp.r_out - rn) / rn;
+            const double s = probe ? (2.0 - rn) / rn : (2.0 * r_out - rn) / rn;
             const double nrm[3] = {x / rn, y / rn, z / rn};
             x = x * s;
             y = y * s;
@@ -997,7 +1120,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
                     inw[2] = -inw[2];
                 }
                 double d[3];
-                hemisphere_dir(kp.seed, uid, step, probe ? 0 : 1, inw, d);
+                hemisphere_dir(sg.seed, uid, step, probe ? 0 : 1, inw, d);
                 vx = sp * d[0];
                 vy = sp * d[1];
                 vz = sp * d[2];
@@ -1020,7 +1143,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     A.uid[p] = uid;
     dead[p] = absorbed;
     if (absorbed) {
-        const uint32_t slot = atomicAdd(&ctl->n_dead, 1u);
+        const uint32_t slot = sg.p0 + atomicAdd(&ct.n_dead, 1u);
         G.x[slot] = x;
         G.y[slot] = y;
         G.z[slot] = z;
@@ -1031,10 +1154,14 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Ctl *ctl, State B, State 
     }
 }
 
-__global__ void k_step_finish(Ctl *ctl)
+__global__ void k_step_finish(Map mp, KParams kp)
 {
-    ctl->step += 1;
-    ctl->n_cur = ctl->n_live;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= kp.n_members) return;
+    Ctl &c = mp.ctl[s];
+    if (!member_runs(mp.seg[s], c, kp)) return;
+    c.step += 1;
+    c.n_cur = c.n_live;
 }
 
 // ---------------------------------------------------------------------------
@@ -1042,57 +1169,94 @@ __global__ void k_step_finish(Ctl *ctl)
 // ---------------------------------------------------------------------------
 
 enum KernelId {
-    KN_SORT_CLEAR, KN_SORT_KEY, KN_SCAN_A, KN_SCAN_B, KN_SCAN_C, KN_SORT_SCATTER, KN_SORT_RANK,
-    KN_MOMENTS, KN_CHUNK_SUMS, KN_CHUNK_SCAN, KN_COEF_PREP, KN_CHUNK_APPLY, KN_FIELD_PUSH,
-    KN_STEP_FINISH, KN_COUNT
+    KN_SORT_CLEAR, KN_SORT_KEY, KN_SCAN_A, KN_SCAN_B, KN_SCAN_C, KN_MEMBER_LIVE, KN_SORT_SCATTER,
+    KN_SORT_RANK, KN_MOMENTS, KN_CHUNK_SUMS, KN_CHUNK_SCAN, KN_COEF_PREP, KN_CHUNK_APPLY,
+    KN_FIELD_PUSH, KN_STEP_FINISH, KN_COUNT
 };
 
 const char *kKernelNames[KN_COUNT] = {
-    "sort_clear", "sort_key", "bucket_scan_a", "bucket_scan_b", "bucket_scan_c", "sort_scatter",
-    "sort_rank_move", "moments", "carry_chunk_sums", "carry_chunk_scan", "coef_prep", "carry_apply",
-    "field_push", "step_finish"};
+    "sort_clear", "sort_key", "bucket_scan_a", "bucket_scan_b", "bucket_scan_c", "member_live",
+    "sort_scatter", "sort_rank_move", "moments", "carry_chunk_sums", "carry_chunk_scan",
+    "coef_prep", "carry_apply", "field_push", "step_finish"};
 
+// What all members of a handle share, and the handle's capacities.
 struct Layout {
-    int64_t n;
-    int L, C, C2, n_tiles, n_chunks, nb, nb_blocks;
-    int64_t n_steps;
-    bool full;
-    bool fp32;
+    int L, C, C2;
+    bool full, fp32;
+    int n_tiles;     // particle slots / 64
+    int n_chunks;
+    int nb, nb_blocks;
+    int n_members;
 };
 
-bool make_layout(const sim_params *p, int64_t n, int64_t n_steps, Layout *lo, std::string *why)
+// Per-member sizes.
+struct MemberShape {
+    uint32_t nt, nc, nb;
+};
+
+MemberShape member_shape(int64_t n)
+{
+    MemberShape m;
+    m.nt = (uint32_t)((n + kWave - 1) / kWave);
+    m.nc = (m.nt + kChunk - 1) / kChunk;
+    m.nb = (uint32_t)std::max<int64_t>(1, n / kBucketOccupancy);
+    return m;
+}
+
+bool check_common(const sim_params *p, std::string *why)
 {
     if (!p) { *why = "params is NULL"; return false; }
     if (p->struct_size != sizeof(sim_params)) { *why = "params struct_size mismatch"; return false; }
-    if (n <= 0 || n > 0x7fffffffLL) { *why = "n must be in [1, 2^31)"; return false; }
-    if (n_steps < 0) { *why = "n_steps < 0"; return false; }
     if (p->l_max < 0 || p->l_max > kMaxL) { *why = "l_max must be in [0, 64]"; return false; }
     if (!(p->d > 0.0 && p->d < 1.0)) { *why = "d must be in (0, 1)"; return false; }
     if (!(p->eps_r > 0.0) || !std::isfinite(p->eps_r)) { *why = "eps_r must be > 0"; return false; }
-    if (!(p->r_out > 1.0) || !std::isfinite(p->r_out)) { *why = "r_out must be > 1"; return false; }
-    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) { *why = "dt must be > 0"; return false; }
-    if (!(p->ntilde > 0.0) || !std::isfinite(p->ntilde)) { *why = "ntilde must be > 0"; return false; }
-    if (!(p->ion_density >= 0.0) || !std::isfinite(p->ion_density)) {
+    if (p->m_mode != SIM_M_FULL && p->m_mode != SIM_M_AXISYM) { *why = "bad m_mode"; return false; }
+    if (p->precision != SIM_FP64 && p->precision != SIM_FP32_COMP) { *why = "bad precision"; return false; }
+    if (p->tile != 0 && p->tile != kWave) { *why = "tile must be 0 or 64"; return false; }
+    return true;
+}
+
+// Scalar checks of a member (the particle arrays are checked at admission).
+bool check_member_scalars(const sim_member *m, std::string *why)
+{
+    if (!m) { *why = "member is NULL"; return false; }
+    if (m->struct_size != sizeof(sim_member)) { *why = "member struct_size mismatch"; return false; }
+    if (m->n <= 0 || m->n > 0x7fffffffLL) { *why = "n must be in [1, 2^31)"; return false; }
+    if (m->n_steps < 0) { *why = "n_steps < 0"; return false; }
+    if (m->start_step < 0 || m->start_step > m->n_steps) {
+        *why = "start_step outside [0, n_steps]";
+        return false;
+    }
+    if (!(m->r_out > 1.0) || !std::isfinite(m->r_out)) { *why = "r_out must be > 1"; return false; }
+    if (!(m->dt > 0.0) || !std::isfinite(m->dt)) { *why = "dt must be > 0"; return false; }
+    if (!(m->ntilde > 0.0) || !std::isfinite(m->ntilde)) { *why = "ntilde must be > 0"; return false; }
+    if (!(m->ion_density >= 0.0) || !std::isfinite(m->ion_density)) {
         *why = "ion_density must be >= 0";
         return false;
     }
-    if (!std::isfinite(p->q_surface0)) { *why = "q_surface0 must be finite"; return false; }
-    if (p->m_mode != SIM_M_FULL && p->m_mode != SIM_M_AXISYM) { *why = "bad m_mode"; return false; }
-    if (p->probe_bc < SIM_BC_ABSORB || p->probe_bc > SIM_BC_DIFFUSE) { *why = "bad probe_bc"; return false; }
-    if (p->wall_bc != SIM_BC_SPECULAR && p->wall_bc != SIM_BC_DIFFUSE) { *why = "bad wall_bc"; return false; }
-    if (p->precision != SIM_FP64 && p->precision != SIM_FP32_COMP) { *why = "bad precision"; return false; }
-    if (p->tile != 0 && p->tile != kWave) { *why = "tile must be 0 or 64"; return false; }
-    lo->n = n;
+    if (!std::isfinite(m->q_surface0)) { *why = "q_surface0 must be finite"; return false; }
+    if (m->probe_bc < SIM_BC_ABSORB || m->probe_bc > SIM_BC_DIFFUSE) { *why = "bad probe_bc"; return false; }
+    if (m->wall_bc != SIM_BC_SPECULAR && m->wall_bc != SIM_BC_DIFFUSE) { *why = "bad wall_bc"; return false; }
+    return true;
+}
+
+bool make_layout(const sim_params *p, int64_t slots, int32_t max_members, Layout *lo,
+                 std::string *why)
+{
+    if (!check_common(p, why)) return false;
+    if (slots <= 0 || slots > 0x7fffffffLL - kWave) { *why = "slot capacity must be in [1, 2^31 - 64)"; return false; }
+    if (max_members <= 0 || max_members > (1 << 20)) { *why = "max_members must be in [1, 2^20]"; return false; }
     lo->L = p->l_max;
     lo->full = p->m_mode == SIM_M_FULL;
     lo->fp32 = p->precision == SIM_FP32_COMP;
     lo->C = lo->full ? (p->l_max + 1) * (p->l_max + 1) - 1 : p->l_max;
     lo->C2 = 2 * lo->C;
-    lo->n_tiles = (int)((n + kWave - 1) / kWave);
-    lo->n_chunks = (lo->n_tiles + kChunk - 1) / kChunk;
-    lo->nb = (int)std::max<int64_t>(1, n / kBucketOccupancy);
+    lo->n_tiles = (int)((slots + kWave - 1) / kWave);
+    lo->n_members = max_members;
+    // every member rounds its chunks and buckets up by at most one
+    lo->n_chunks = (lo->n_tiles + kChunk - 1) / kChunk + (max_members > 1 ? max_members : 0);
+    lo->nb = (int)std::max<int64_t>(1, slots / kBucketOccupancy) + (max_members > 1 ? max_members : 0);
     lo->nb_blocks = (lo->nb + kScanPerBlock - 1) / kScanPerBlock;
-    lo->n_steps = n_steps;
     return true;
 }
 
@@ -1104,6 +1268,60 @@ struct Alloc {
         for (auto &it : items) s += (it.second + 255) & ~size_t(255);
         return s;
     }
+};
+
+size_t member_bytes(int64_t n_steps) { return 2 * (((size_t)std::max<int64_t>(n_steps, 1) * 8 + 255) & ~size_t(255)); }
+
+// First-fit allocator of ranges [start, start + len) of a capacity.
+class Ranges {
+public:
+    void reset(uint32_t capacity)
+    {
+        free_.clear();
+        if (capacity) free_[0] = capacity;
+    }
+    bool take(uint32_t len, uint32_t *start)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= len) {
+                *start = it->first;
+                const uint32_t rest = it->second - len, at = it->first + len;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void give(uint32_t start, uint32_t len)
+    {
+        auto it = free_.emplace(start, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<uint32_t, uint32_t> free_;
+};
+
+struct Member {
+    bool used = false;
+    Seg seg{};
+    int64_t n = 0;
+    int64_t step_host = 0;    // absolute step after all enqueued work
+    int64_t start_step = 0;
+    double q_surface0 = 0.0;
+    std::vector<std::pair<uint32_t, int64_t>> id_index;  // (uid, creation index), sorted
 };
 
 }  // namespace
@@ -1123,20 +1341,23 @@ struct sim {
     uint32_t *bkt = nullptr, *sub = nullptr, *tuid = nullptr, *tidx = nullptr, *tbkt = nullptr,
              *hist = nullptr, *off = nullptr, *bsum = nullptr;
     double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr, *Kc = nullptr,
-           *coef = nullptr, *u_asy = nullptr, *qdiff = nullptr, *tables = nullptr, *Eout = nullptr;
+           *coef = nullptr, *tables = nullptr, *Eout = nullptr;
     int *chl = nullptr;
     float *coef32 = nullptr, *tables32 = nullptr;
     double *lgrho = nullptr;
     uint32_t *Eid = nullptr;
+    Seg *seg = nullptr;
     Ctl *ctl = nullptr;
+    uint32_t *tile_member = nullptr, *chunk_member = nullptr;
     Tables tb{};
+    Map map{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int64_t step_host = 0;      // absolute step after all enqueued work
-    int64_t start_step = 0;
     bool failed = false;
+    size_t shared_bytes = 0, member_total = 0;
     std::vector<void *> mem;
-    std::vector<std::pair<uint32_t, int64_t>> id_index;  // (uid, creation index), sorted
+    std::vector<Member> members;
+    Ranges tiles, chunks, buckets;
 };
 
 namespace {
@@ -1175,7 +1396,7 @@ size_t tables32_len(int L) { return nf4_32_offset(L) + 4 * (size_t)(L + 1); }
 void plan_alloc(sim *h, Alloc &al)
 {
     const Layout &lo = h->lo;
-    const size_t n = (size_t)lo.n;
+    const size_t n = (size_t)lo.n_tiles * kWave;
     for (State *s : {&h->A, &h->B}) {
         al.add(&s->x, n); al.add(&s->y, n); al.add(&s->z, n);
         al.add(&s->vx, n); al.add(&s->vy, n); al.add(&s->vz, n);
@@ -1208,16 +1429,16 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->tables32, tables32_len(lo.L));
     al.add(&h->chunkS, (size_t)lo.n_chunks * lo.C2);
     al.add(&h->chunkC, (size_t)lo.n_chunks * lo.C2);
-    al.add(&h->T, (size_t)lo.C);
-    al.add(&h->Kc, (size_t)lo.C);
-    al.add(&h->u_asy, (size_t)std::max<int64_t>(lo.n_steps, 1));
-    al.add(&h->qdiff, (size_t)std::max<int64_t>(lo.n_steps, 1));
-    const int L = lo.L;
-    al.add(&h->tables, tables_len(L));
+    al.add(&h->T, (size_t)lo.n_members * std::max(lo.C, 1));
+    al.add(&h->Kc, (size_t)lo.n_members * std::max(lo.C, 1));
+    al.add(&h->tables, tables_len(lo.L));
     al.add(&h->chl, (size_t)std::max(lo.C, 1));
     al.add(&h->Eout, 3 * n);
     al.add(&h->Eid, n);
-    al.add(&h->ctl, 1);
+    al.add(&h->seg, (size_t)lo.n_members);
+    al.add(&h->ctl, (size_t)lo.n_members);
+    al.add(&h->tile_member, (size_t)lo.n_tiles);
+    al.add(&h->chunk_member, (size_t)lo.n_chunks);
 }
 
 // Host-side coefficient tables.  f_l and b^P_l are the closed forms of App. A
@@ -1245,9 +1466,9 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
                           ((l + 1.0) * (eps - 1.0) * a2l1 + l * eps + l + 1.0);
         const double c = (l % 2 == 1) ? 0.5 * (p0[l - 1] - p0[l + 1]) : 0.0;
         ftil[l] = (l == 0) ? 0.0 : f;
-        wl[l] = 1.0 / ((2.0 * l + 1.0) * p.ntilde);
+        wl[l] = 1.0 / (2.0 * l + 1.0);
         drive[l] = c * bP * std::sqrt(4.0 * kPi / (2.0 * l + 1.0));
-        selfw[l] = (l == 0) ? 0.0 : f / (4.0 * kPi * p.ntilde);
+        selfw[l] = (l == 0) ? 0.0 : f / (4.0 * kPi);
         nfA[l] = (2.0 * l + 1.0) / (l + 1.0);
         nfB[l] = (double)l / (l + 1.0);
         lval[l] = (double)l;
@@ -1279,11 +1500,14 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
 int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
 {
     const Layout &lo = h->lo;
-    const KParams &kp = h->kp;
-    const unsigned n = (unsigned)lo.n;
+    KParams kp = h->kp;
+    kp.field_only = field_only ? 1 : 0;
+    const Map &mp = h->map;
+    const unsigned n = (unsigned)lo.n_tiles * kWave;
     const unsigned gN = (n + kBlock - 1) / kBlock;
     const unsigned gT = (unsigned)((lo.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     const unsigned gC = (unsigned)((lo.C2 + kBlock - 1) / kBlock);
+    const unsigned gM = (unsigned)((lo.n_members + kBlock - 1) / kBlock);
     int e = 0;
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], s);
@@ -1291,37 +1515,40 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     mark(KN_SORT_CLEAR);
     k_sort_clear<<<(lo.nb + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(h->hist, lo.nb);
     mark(KN_SORT_KEY);
-    k_sort_key<<<gN, kBlock, 0, s>>>(h->ctl, h->A, h->dead, h->key, h->bkt, h->sub, h->hist, kp);
+    k_sort_key<<<gN, kBlock, 0, s>>>(mp, h->A, h->dead, h->key, h->bkt, h->sub, h->hist, kp);
     mark(KN_SCAN_A);
     k_scan_a<<<lo.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, lo.nb);
     mark(KN_SCAN_B);
-    k_scan_b<<<1, kBlock, 0, s>>>(h->bsum, lo.nb_blocks, h->ctl);
+    k_scan_b<<<1, kBlock, 0, s>>>(h->bsum, lo.nb_blocks);
     mark(KN_SCAN_C);
     k_scan_c<<<lo.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, lo.nb);
+    mark(KN_MEMBER_LIVE);
+    k_member_live<<<gM, kBlock, 0, s>>>(mp, h->off, kp);
     mark(KN_SORT_SCATTER);
-    k_sort_scatter<<<gN, kBlock, 0, s>>>(h->ctl, h->key, h->A.uid, h->bkt, h->sub, h->off, h->tkey,
-                                         h->tuid, h->tidx, h->tbkt);
+    k_sort_scatter<<<gN, kBlock, 0, s>>>(h->key, h->A.uid, h->bkt, h->sub, h->off, h->tkey,
+                                         h->tuid, h->tidx, h->tbkt, kp);
     mark(KN_SORT_RANK);
-    k_sort_rank_move<<<gN, kBlock, 0, s>>>(h->ctl, h->tkey, h->tuid, h->tidx, h->tbkt, h->off, h->A,
-                                           h->B);
+    k_sort_rank_move<<<gN, kBlock, 0, s>>>(mp, h->tkey, h->tuid, h->tidx, h->tbkt, h->off, h->A,
+                                           h->B, kp);
     mark(KN_MOMENTS);
     if (lo.C > 0) {
-        if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S, h->lgrho);
-        else k_moments<false><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->tb, kp, h->S, h->lgrho);
+        if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
+        else k_moments<false><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
     }
     mark(KN_CHUNK_SUMS);
-    if (lo.C > 0) k_chunk_sums<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkS, kp);
+    if (lo.C > 0) k_chunk_sums<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkS, kp);
     mark(KN_CHUNK_SCAN);
-    k_chunk_scan<<<std::max(gC, 1u), kBlock, 0, s>>>(h->chunkS, h->chunkC, h->T, h->ctl, kp);
+    if (lo.C > 0)
+        k_chunk_scan<<<dim3(gC, lo.n_members), kBlock, 0, s>>>(mp, h->chunkS, h->chunkC, h->T, kp);
     mark(KN_COEF_PREP);
-    k_coef_prep<<<1, kBlock, 0, s>>>(h->T, h->ctl, h->u_asy, h->qdiff, h->tb, kp, h->Kc);
+    k_coef_prep<<<lo.n_members, kBlock, 0, s>>>(mp, h->T, h->tb, kp, h->Kc);
     mark(KN_CHUNK_APPLY);
     if (lo.C > 0)
-        k_chunk_apply<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(h->S, h->chunkC, h->Kc, h->tb, kp,
-                                                               h->lgrho, h->coef, h->coef32);
+        k_chunk_apply<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkC, h->Kc, h->tb,
+                                                               kp, h->lgrho, h->coef, h->coef32);
     mark(KN_FIELD_PUSH);
 #define MRP_FIELD(FULLV, FO, F32)                                                              \
-    k_field_push<FULLV, FO, F32><<<gT, kBlock, 0, s>>>(h->ctl, h->B, h->A, h->dead, h->G, h->coef, \
+    k_field_push<FULLV, FO, F32><<<gT, kBlock, 0, s>>>(mp, h->B, h->A, h->dead, h->G, h->coef, \
                                                        h->coef32, h->tb, kp, h->Eout, h->Eid)
 #define MRP_FIELD_P(FULLV, FO) \
     do { if (lo.fp32) MRP_FIELD(FULLV, FO, true); else MRP_FIELD(FULLV, FO, false); } while (0)
@@ -1332,12 +1559,20 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
         if (lo.full) MRP_FIELD_P(true, false);
         else MRP_FIELD_P(false, false);
         mark(KN_STEP_FINISH);
-        k_step_finish<<<1, 1, 0, s>>>(h->ctl);
+        k_step_finish<<<gM, kBlock, 0, s>>>(mp, kp);
     }
     if (ev) (void)hipEventRecord(ev[KN_COUNT], s);
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) e = fail(SIM_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
     return e;
+}
+
+void free_member_arrays(Member &m)
+{
+    if (m.seg.u_asy) (void)hipFree((void *)m.seg.u_asy);
+    if (m.seg.qdiff) (void)hipFree(m.seg.qdiff);
+    m.seg.u_asy = nullptr;
+    m.seg.qdiff = nullptr;
 }
 
 void release(sim *h)
@@ -1346,6 +1581,7 @@ void release(sim *h)
     if (h->exec) (void)hipGraphExecDestroy(h->exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (Member &m : h->members) free_member_arrays(m);
     for (void *p : h->mem) (void)hipFree(p);
     h->mem.clear();
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -1365,98 +1601,28 @@ int mark_failed(sim *h, int code)
     return code;
 }
 
-}  // namespace
-
-extern "C" {
-
-void sim_params_default(sim_params *p)
+int check_member_index(sim *h, int32_t index)
 {
-    if (!p) return;
-    std::memset(p, 0, sizeof(*p));
-    p->struct_size = sizeof(sim_params);
-    p->d = 0.25;
-    p->eps_r = 4.0;
-    p->r_out = 5.0;
-    p->dt = 0.05;
-    p->ntilde = 1.0;
-    p->ion_density = 1.0;
-    p->q_surface0 = 0.0;
-    p->l_max = 8;
-    p->m_mode = SIM_M_FULL;
-    p->probe_bc = SIM_BC_ABSORB;
-    p->wall_bc = SIM_BC_SPECULAR;
-    p->precision = SIM_FP64;
-    p->tile = 0;
-    p->seed = 0;
-    p->mem_limit_bytes = 0;
+    if (index < 0 || index >= (int32_t)h->members.size() || !h->members[index].used)
+        return fail(SIM_ERANGE, "no member at index " + std::to_string(index));
+    return SIM_OK;
 }
 
-int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps)
+// Allocate the shared arrays, upload the tables, capture one step.
+int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
 {
-    Layout lo;
-    std::string why;
-    if (!make_layout(p, n, n_steps, &lo, &why)) return fail(SIM_EINVAL, why);
-    sim tmp;
-    tmp.lo = lo;
-    Alloc al;
-    plan_alloc(&tmp, al);
-    return (int64_t)al.total();
-}
-
-int sim_create(const sim_params *p, int64_t n, const double *pos, const double *vel,
-               const uint32_t *ids, const double *u_asy, int64_t n_steps, int64_t start_step,
-               void *hip_stream, sim_t **out)
-{
-    if (!out) return fail(SIM_EINVAL, "out is NULL");
-    *out = nullptr;
-    Layout lo;
-    std::string why;
-    if (!make_layout(p, n, n_steps, &lo, &why)) return fail(SIM_EINVAL, why);
-    if (!pos || !vel) return fail(SIM_EINVAL, "pos and vel are required");
-    if (n_steps > 0 && !u_asy) return fail(SIM_EINVAL, "u_asy is required when n_steps > 0");
-    if (start_step < 0 || start_step > n_steps) return fail(SIM_EINVAL, "start_step outside [0, n_steps]");
-    for (int64_t i = 0; i < n; ++i) {
-        const double *x = pos + 3 * i, *v = vel + 3 * i;
-        for (int j = 0; j < 3; ++j)
-            if (!std::isfinite(x[j]) || !std::isfinite(v[j]))
-                return fail(SIM_EINVAL, "non-finite particle state at index " + std::to_string(i));
-        const double r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-        if (!(r > 1.0 && r < p->r_out))
-            return fail(SIM_EINVAL, "particle " + std::to_string(i) + " not inside 1 < r < r_out");
-    }
-    for (int64_t s = 0; s < n_steps; ++s)
-        if (!std::isfinite(u_asy[s])) return fail(SIM_EINVAL, "non-finite u_asy");
-    std::vector<uint32_t> uid((size_t)n);
-    for (int64_t i = 0; i < n; ++i) uid[i] = ids ? ids[i] : (uint32_t)i;
-    std::vector<std::pair<uint32_t, int64_t>> idx((size_t)n);
-    for (int64_t i = 0; i < n; ++i) idx[i] = {uid[i], i};
-    std::sort(idx.begin(), idx.end());
-    for (int64_t i = 1; i < n; ++i)
-        if (idx[i].first == idx[i - 1].first) return fail(SIM_EINVAL, "ids are not distinct");
-
-    sim *h = new (std::nothrow) sim();
-    if (!h) return fail(SIM_ENOMEM, "host allocation failed");
     h->prm = *p;
     h->lo = lo;
-    h->id_index = std::move(idx);
     Alloc al;
     plan_alloc(h, al);
-    if (p->mem_limit_bytes && al.total() > p->mem_limit_bytes) {
-        delete h;
-        return fail(SIM_ENOMEM, "footprint " + std::to_string(al.total()) + " B exceeds mem_limit_bytes");
-    }
-    auto bail = [&](int code) {
-        release(h);
-        delete h;
-        return code;
-    };
+    h->shared_bytes = al.total();
+    if (p->mem_limit_bytes && h->shared_bytes > p->mem_limit_bytes)
+        return fail(SIM_ENOMEM, "footprint " + std::to_string(h->shared_bytes) +
+                                    " B exceeds mem_limit_bytes");
     for (auto &it : al.items) {
         void *ptr = nullptr;
         hipError_t e = hipMalloc(&ptr, std::max<size_t>(it.second, 1));
-        if (e != hipSuccess) {
-            fail(SIM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-            return bail(SIM_ENOMEM);
-        }
+        if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         h->mem.push_back(ptr);
         *it.first = ptr;
     }
@@ -1464,13 +1630,12 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
         h->stream = (hipStream_t)hip_stream;
     } else {
         if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
-            return bail(fail(SIM_EDEVICE, "hipStreamCreate failed"));
+            return fail(SIM_EDEVICE, "hipStreamCreate failed");
         h->own_stream = true;
     }
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
-        return bail(fail(SIM_EDEVICE, "hipStreamCreate failed"));
+        return fail(SIM_EDEVICE, "hipStreamCreate failed");
 
-    // tables
     std::vector<double> tab = build_tables(*p, lo);
     const int L = lo.L;
     double *tb = h->tables;
@@ -1506,7 +1671,7 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
     for (int m = 0; m <= (lo.full ? L : 0); ++m)
         for (int l = std::max(m, 1); l <= L; ++l)
             for (int sc = 0; sc < (m > 0 ? 2 : 1); ++sc) chl.push_back(l);
-    if ((int)chl.size() != lo.C) return bail(fail(SIM_EDEVICE, "channel count mismatch"));
+    if ((int)chl.size() != lo.C) return fail(SIM_EDEVICE, "channel count mismatch");
     if (chl.empty()) chl.push_back(0);
 
     KParams &kp = h->kp;
@@ -1516,66 +1681,211 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
     kp.n_tiles = lo.n_tiles;
     kp.n_chunks = lo.n_chunks;
     kp.nb = lo.nb;
-    kp.probe_bc = p->probe_bc;
-    kp.wall_bc = p->wall_bc;
-    kp.dt = p->dt;
-    kp.r_out = p->r_out;
-    kp.ntilde = p->ntilde;
-    kp.ion_density = p->ion_density;
-    kp.q_surface0 = p->q_surface0;
-    kp.inv_vol = 1.0 / (p->r_out * p->r_out * p->r_out - 1.0);
-    kp.seed = p->seed;
-    kp.n_steps = n_steps;
+    kp.n_members = lo.n_members;
     kp.fp32 = lo.fp32 ? 1 : 0;
+    kp.field_only = 0;
+    h->map.seg = h->seg;
+    h->map.ctl = h->ctl;
+    h->map.tile_member = h->tile_member;
+    h->map.chunk_member = h->chunk_member;
+    h->tiles.reset((uint32_t)lo.n_tiles);
+    h->chunks.reset((uint32_t)lo.n_chunks);
+    h->buckets.reset((uint32_t)lo.nb);
+    h->members.assign((size_t)lo.n_members, Member());
 
-    // upload the initial state (A, creation order) and the drive
-    std::vector<double> col((size_t)n);
-    auto up = [&](double *dst, const double *src, int j) -> hipError_t {
-        for (int64_t i = 0; i < n; ++i) col[i] = src[3 * i + j];
-        return hipMemcpy(dst, col.data(), sizeof(double) * n, hipMemcpyHostToDevice);
-    };
-    Ctl ctl{};
-    ctl.step = start_step;
-    ctl.n_cur = (uint32_t)n;
-    ctl.n_live = (uint32_t)n;
-    ctl.n_dead = 0;
-    ctl.q_surface = p->q_surface0;
-    std::vector<double> zeros((size_t)std::max<int64_t>(n_steps, 1), 0.0);
-    if (up(h->A.x, pos, 0) || up(h->A.y, pos, 1) || up(h->A.z, pos, 2) || up(h->A.vx, vel, 0) ||
-        up(h->A.vy, vel, 1) || up(h->A.vz, vel, 2) ||
-        hipMemcpy(h->A.uid, uid.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice) ||
-        hipMemset(h->dead, 0, (size_t)n) ||
-        hipMemcpy(h->tables, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) ||
+    std::vector<Seg> segs((size_t)lo.n_members);   // used = 0
+    std::vector<Ctl> ctls((size_t)lo.n_members);
+    std::vector<uint32_t> none_t((size_t)lo.n_tiles, kNone), none_c((size_t)lo.n_chunks, kNone);
+    if (hipMemcpy(h->tables, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->chl, chl.data(), sizeof(int) * chl.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->tables32, tab32.data(), sizeof(float) * tab32.size(), hipMemcpyHostToDevice) ||
-        hipMemcpy(h->ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice) ||
-        hipMemcpy(h->qdiff, zeros.data(), sizeof(double) * zeros.size(), hipMemcpyHostToDevice) ||
-        (n_steps > 0 &&
-         hipMemcpy(h->u_asy, u_asy, sizeof(double) * n_steps, hipMemcpyHostToDevice))) {
-        return bail(fail(SIM_EDEVICE, "upload failed"));
-    }
+        hipMemcpy(h->seg, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->ctl, ctls.data(), sizeof(Ctl) * ctls.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->tile_member, none_t.data(), 4 * none_t.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->chunk_member, none_c.data(), 4 * none_c.size(), hipMemcpyHostToDevice) ||
+        hipMemset(h->dead, 0, (size_t)lo.n_tiles * kWave))
+        return fail(SIM_EDEVICE, "upload failed");
+
     // capture one step into a graph
     if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return bail(fail(SIM_EDEVICE, "hipStreamBeginCapture failed"));
+        return fail(SIM_EDEVICE, "hipStreamBeginCapture failed");
     int le = launch_step(h, h->cap_stream, false, nullptr);
     hipError_t ce = hipStreamEndCapture(h->cap_stream, &h->graph);
-    if (le != SIM_OK) return bail(le);
-    if (ce != hipSuccess) return bail(fail(SIM_EDEVICE, std::string("capture: ") + hipGetErrorString(ce)));
+    if (le != SIM_OK) return le;
+    if (ce != hipSuccess) return fail(SIM_EDEVICE, std::string("capture: ") + hipGetErrorString(ce));
     if (hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0) != hipSuccess)
-        return bail(fail(SIM_EDEVICE, "hipGraphInstantiate failed"));
-    if (hipDeviceSynchronize() != hipSuccess) return bail(fail(SIM_EDEVICE, "device sync failed"));
-    h->step_host = start_step;
-    h->start_step = start_step;
-    *out = h;
+        return fail(SIM_EDEVICE, "hipGraphInstantiate failed");
+    if (hipDeviceSynchronize() != hipSuccess) return fail(SIM_EDEVICE, "device sync failed");
     return SIM_OK;
 }
 
-int sim_step(sim_t *h, int64_t k)
+// A member's host-side data after validation: ids and the id -> creation
+// index map.
+struct Prepared {
+    std::vector<uint32_t> uid;
+    std::vector<std::pair<uint32_t, int64_t>> idx;
+};
+
+// Validate a member completely (no device work).
+int prepare_member(const sim_member *m, Prepared *pr)
 {
-    int rc = check_handle(h);
+    std::string why;
+    if (!check_member_scalars(m, &why)) return fail(SIM_EINVAL, why);
+    const int64_t n = m->n;
+    if (!m->pos || !m->vel) return fail(SIM_EINVAL, "pos and vel are required");
+    if (m->n_steps > 0 && !m->u_asy) return fail(SIM_EINVAL, "u_asy is required when n_steps > 0");
+    for (int64_t i = 0; i < n; ++i) {
+        const double *x = m->pos + 3 * i, *v = m->vel + 3 * i;
+        for (int j = 0; j < 3; ++j)
+            if (!std::isfinite(x[j]) || !std::isfinite(v[j]))
+                return fail(SIM_EINVAL, "non-finite particle state at index " + std::to_string(i));
+        const double r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        if (!(r > 1.0 && r < m->r_out))
+            return fail(SIM_EINVAL, "particle " + std::to_string(i) + " not inside 1 < r < r_out");
+    }
+    for (int64_t s = 0; s < m->n_steps; ++s)
+        if (!std::isfinite(m->u_asy[s])) return fail(SIM_EINVAL, "non-finite u_asy");
+    pr->uid.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) pr->uid[i] = m->ids ? m->ids[i] : (uint32_t)i;
+    pr->idx.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) pr->idx[i] = {pr->uid[i], i};
+    std::sort(pr->idx.begin(), pr->idx.end());
+    for (int64_t i = 1; i < n; ++i)
+        if (pr->idx[i].first == pr->idx[i - 1].first) return fail(SIM_EINVAL, "ids are not distinct");
+    return SIM_OK;
+}
+
+// Place and upload one validated member.  On failure the handle is unchanged
+// (apart from the device contents of free ranges).
+int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
+{
+    const int64_t n = m->n;
+    std::vector<uint32_t> &uid = pr.uid;
+    int32_t slot = -1;
+    for (int32_t k = 0; k < (int32_t)h->members.size(); ++k)
+        if (!h->members[k].used) { slot = k; break; }
+    if (slot < 0) return fail(SIM_ENOMEM, "member table is full");
+    const size_t mbytes = member_bytes(m->n_steps);
+    if (h->prm.mem_limit_bytes && h->shared_bytes + h->member_total + mbytes > h->prm.mem_limit_bytes)
+        return fail(SIM_ENOMEM, "member arrays would exceed mem_limit_bytes");
+    const MemberShape sh = member_shape(n);
+    uint32_t t0 = 0, c0 = 0, b0 = 0;
+    if (!h->tiles.take(sh.nt, &t0)) return fail(SIM_ENOMEM, "no free tile range for the member");
+    if (!h->chunks.take(sh.nc, &c0)) {
+        h->tiles.give(t0, sh.nt);
+        return fail(SIM_ENOMEM, "no free chunk range for the member");
+    }
+    if (!h->buckets.take(sh.nb, &b0)) {
+        h->tiles.give(t0, sh.nt);
+        h->chunks.give(c0, sh.nc);
+        return fail(SIM_ENOMEM, "no free bucket range for the member");
+    }
+    Member mb;
+    mb.used = true;
+    mb.n = n;
+    mb.step_host = m->start_step;
+    mb.start_step = m->start_step;
+    mb.q_surface0 = m->q_surface0;
+    mb.id_index = std::move(pr.idx);
+    Seg &sg = mb.seg;
+    sg.p0 = t0 * kWave;
+    sg.cap = sh.nt * kWave;
+    sg.t0 = t0;
+    sg.nt = sh.nt;
+    sg.c0 = c0;
+    sg.nc = sh.nc;
+    sg.b0 = b0;
+    sg.nb = sh.nb;
+    sg.inv_vol = 1.0 / (m->r_out * m->r_out * m->r_out - 1.0);
+    sg.ntilde = m->ntilde;
+    sg.inv_ntilde = 1.0 / m->ntilde;
+    sg.ion_density = m->ion_density;
+    sg.q_surface0 = m->q_surface0;
+    sg.dt = m->dt;
+    sg.r_out = m->r_out;
+    sg.seed = m->seed;
+    sg.probe_bc = m->probe_bc;
+    sg.wall_bc = m->wall_bc;
+    sg.n_steps = m->n_steps;
+    sg.used = 1;
+    auto undo = [&](int code) {
+        free_member_arrays(mb);
+        h->tiles.give(t0, sh.nt);
+        h->chunks.give(c0, sh.nc);
+        h->buckets.give(b0, sh.nb);
+        return code;
+    };
+    const size_t ns = (size_t)std::max<int64_t>(m->n_steps, 1);
+    double *u_dev = nullptr, *q_dev = nullptr;
+    if (hipMalloc(&u_dev, 8 * ns) != hipSuccess) return undo(fail(SIM_ENOMEM, "hipMalloc of the drive failed"));
+    sg.u_asy = u_dev;
+    if (hipMalloc(&q_dev, 8 * ns) != hipSuccess) return undo(fail(SIM_ENOMEM, "hipMalloc of the response failed"));
+    sg.qdiff = q_dev;
+
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        h->failed = true;
+        return undo(fail(SIM_EDEVICE, "stream synchronisation failed"));
+    }
+    std::vector<double> col((size_t)n);
+    auto up = [&](double *dst, const double *src, int j) -> hipError_t {
+        for (int64_t i = 0; i < n; ++i) col[i] = src[3 * i + j];
+        return hipMemcpy(dst + sg.p0, col.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+    };
+    Ctl ctl{};
+    ctl.step = m->start_step;
+    ctl.n_cur = (uint32_t)n;
+    ctl.n_live = (uint32_t)n;
+    ctl.n_dead = 0;
+    ctl.q_surface = m->q_surface0;
+    std::vector<double> zeros(ns, 0.0);
+    std::vector<uint32_t> tm(sh.nt, (uint32_t)slot), cm(sh.nc, (uint32_t)slot);
+    if (up(h->A.x, m->pos, 0) || up(h->A.y, m->pos, 1) || up(h->A.z, m->pos, 2) ||
+        up(h->A.vx, m->vel, 0) || up(h->A.vy, m->vel, 1) || up(h->A.vz, m->vel, 2) ||
+        hipMemcpy(h->A.uid + sg.p0, uid.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice) ||
+        hipMemset(h->dead + sg.p0, 0, sg.cap) ||
+        hipMemcpy(q_dev, zeros.data(), 8 * ns, hipMemcpyHostToDevice) ||
+        (m->n_steps > 0 && hipMemcpy(u_dev, m->u_asy, 8 * m->n_steps, hipMemcpyHostToDevice)) ||
+        hipMemcpy(h->ctl + slot, &ctl, sizeof(Ctl), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->tile_member + t0, tm.data(), 4 * tm.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->chunk_member + c0, cm.data(), 4 * cm.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->seg + slot, &sg, sizeof(Seg), hipMemcpyHostToDevice)) {
+        h->failed = true;
+        return undo(fail(SIM_EDEVICE, "member upload failed"));
+    }
+    h->members[slot] = std::move(mb);
+    h->member_total += mbytes;
+    *index = slot;
+    return SIM_OK;
+}
+
+int engine_remove(sim *h, int32_t index)
+{
+    int rc = check_member_index(h, index);
     if (rc) return rc;
-    if (k < 0) return fail(SIM_EINVAL, "k < 0");
-    if (h->step_host + k > h->lo.n_steps) return fail(SIM_ERANGE, "steps beyond n_steps");
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        h->failed = true;
+        return fail(SIM_EDEVICE, "stream synchronisation failed");
+    }
+    Member &mb = h->members[index];
+    Seg off{};   // used = 0
+    std::vector<uint32_t> tm(mb.seg.nt, kNone), cm(mb.seg.nc, kNone);
+    if (hipMemcpy(h->seg + index, &off, sizeof(Seg), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->tile_member + mb.seg.t0, tm.data(), 4 * tm.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->chunk_member + mb.seg.c0, cm.data(), 4 * cm.size(), hipMemcpyHostToDevice)) {
+        h->failed = true;
+        return fail(SIM_EDEVICE, "member table update failed");
+    }
+    free_member_arrays(mb);
+    h->tiles.give(mb.seg.t0, mb.seg.nt);
+    h->chunks.give(mb.seg.c0, mb.seg.nc);
+    h->buckets.give(mb.seg.b0, mb.seg.nb);
+    h->member_total -= member_bytes(mb.seg.n_steps);
+    mb = Member();
+    return SIM_OK;
+}
+
+int enqueue_steps(sim *h, int64_t k)
+{
     for (int64_t i = 0; i < k; ++i) {
         hipError_t e = hipGraphLaunch(h->exec, h->stream);
         if (e != hipSuccess) {
@@ -1583,8 +1893,194 @@ int sim_step(sim_t *h, int64_t k)
             return fail(SIM_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         }
     }
-    h->step_host += k;
+    for (Member &m : h->members)
+        if (m.used) m.step_host = std::min(m.step_host + k, m.seg.n_steps);
     return SIM_OK;
+}
+
+sim_member member_from_params(const sim_params *p, int64_t n, const double *pos, const double *vel,
+                              const uint32_t *ids, const double *u_asy, int64_t n_steps,
+                              int64_t start_step)
+{
+    sim_member m;
+    std::memset(&m, 0, sizeof(m));
+    m.struct_size = sizeof(sim_member);
+    m.n = n;
+    m.pos = pos;
+    m.vel = vel;
+    m.ids = ids;
+    m.u_asy = u_asy;
+    m.n_steps = n_steps;
+    m.start_step = start_step;
+    m.ntilde = p->ntilde;
+    m.ion_density = p->ion_density;
+    m.q_surface0 = p->q_surface0;
+    m.r_out = p->r_out;
+    m.dt = p->dt;
+    m.seed = p->seed;
+    m.probe_bc = p->probe_bc;
+    m.wall_bc = p->wall_bc;
+    return m;
+}
+
+int64_t slots_for(int64_t n) { return (int64_t)member_shape(n).nt * kWave; }
+
+}  // namespace
+
+extern "C" {
+
+void sim_params_default(sim_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(sim_params);
+    p->d = 0.25;
+    p->eps_r = 4.0;
+    p->r_out = 5.0;
+    p->dt = 0.05;
+    p->ntilde = 1.0;
+    p->ion_density = 1.0;
+    p->q_surface0 = 0.0;
+    p->l_max = 8;
+    p->m_mode = SIM_M_FULL;
+    p->probe_bc = SIM_BC_ABSORB;
+    p->wall_bc = SIM_BC_SPECULAR;
+    p->precision = SIM_FP64;
+    p->tile = 0;
+    p->seed = 0;
+    p->mem_limit_bytes = 0;
+}
+
+void sim_member_default(sim_member *m)
+{
+    if (!m) return;
+    sim_params p;
+    sim_params_default(&p);
+    *m = member_from_params(&p, 0, nullptr, nullptr, nullptr, nullptr, 0, 0);
+}
+
+int64_t sim_batch_footprint_bytes(const sim_params *common, int64_t slot_capacity,
+                                  int32_t max_members)
+{
+    Layout lo;
+    std::string why;
+    if (!make_layout(common, slot_capacity, max_members, &lo, &why)) return fail(SIM_EINVAL, why);
+    sim tmp;
+    tmp.lo = lo;
+    Alloc al;
+    plan_alloc(&tmp, al);
+    return (int64_t)al.total();
+}
+
+int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps)
+{
+    std::string why;
+    if (!check_common(p, &why)) return fail(SIM_EINVAL, why);
+    sim_member m = member_from_params(p, n, nullptr, nullptr, nullptr, nullptr, n_steps, 0);
+    if (!check_member_scalars(&m, &why)) return fail(SIM_EINVAL, why);
+    const int64_t shared = sim_batch_footprint_bytes(p, slots_for(n), 1);
+    if (shared < 0) return shared;
+    return shared + (int64_t)member_bytes(n_steps);
+}
+
+int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t max_members,
+                     int32_t n_members, const sim_member *members, void *hip_stream, sim_t **out)
+{
+    if (!out) return fail(SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_members < 0 || (n_members > 0 && !members)) return fail(SIM_EINVAL, "bad member list");
+    std::string why;
+    if (!check_common(common, &why)) return fail(SIM_EINVAL, why);
+    int64_t need = 0;
+    std::vector<Prepared> prep((size_t)n_members);
+    for (int32_t i = 0; i < n_members; ++i) {
+        if (prepare_member(&members[i], &prep[i]))
+            return fail(SIM_EINVAL, "member " + std::to_string(i) + ": " + g_last_error);
+        need += slots_for(members[i].n);
+    }
+    if (max_members == 0) max_members = n_members;
+    if (max_members < n_members) return fail(SIM_EINVAL, "max_members < n_members");
+    if (slot_capacity == 0) slot_capacity = need;
+    if (slot_capacity < need) return fail(SIM_ENOMEM, "members need more slots than slot_capacity");
+    Layout lo;
+    if (!make_layout(common, slot_capacity, max_members, &lo, &why)) return fail(SIM_EINVAL, why);
+    sim *h = new (std::nothrow) sim();
+    if (!h) return fail(SIM_ENOMEM, "host allocation failed");
+    auto bail = [&](int code) {
+        release(h);
+        delete h;
+        return code;
+    };
+    int rc = engine_init(h, common, lo, hip_stream);
+    if (rc) return bail(rc);
+    for (int32_t i = 0; i < n_members; ++i) {
+        int32_t idx = -1;
+        rc = engine_add(h, &members[i], prep[i], &idx);
+        if (rc) {
+            const std::string msg = "member " + std::to_string(i) + ": " + g_last_error;
+            bail(rc);
+            return fail(rc, msg);
+        }
+    }
+    *out = h;
+    return SIM_OK;
+}
+
+int sim_create(const sim_params *p, int64_t n, const double *pos, const double *vel,
+               const uint32_t *ids, const double *u_asy, int64_t n_steps, int64_t start_step,
+               void *hip_stream, sim_t **out)
+{
+    if (!out) return fail(SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!check_common(p, &why)) return fail(SIM_EINVAL, why);
+    sim_member m = member_from_params(p, n, pos, vel, ids, u_asy, n_steps, start_step);
+    if (!check_member_scalars(&m, &why)) return fail(SIM_EINVAL, why);
+    if (p->mem_limit_bytes) {
+        const int64_t fp = sim_footprint_bytes(p, n, n_steps);
+        if (fp > (int64_t)p->mem_limit_bytes)
+            return fail(SIM_ENOMEM, "footprint " + std::to_string(fp) + " B exceeds mem_limit_bytes");
+    }
+    return sim_batch_create(p, 0, 1, 1, &m, hip_stream, out);
+}
+
+int sim_batch_add(sim_t *h, const sim_member *m, int32_t *index)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!index) return fail(SIM_EINVAL, "index is NULL");
+    Prepared pr;
+    rc = prepare_member(m, &pr);
+    if (rc) return rc;
+    return engine_add(h, m, pr, index);
+}
+
+int sim_batch_remove(sim_t *h, int32_t index)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    return engine_remove(h, index);
+}
+
+int sim_step(sim_t *h, int64_t k)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (k < 0) return fail(SIM_EINVAL, "k < 0");
+    for (const Member &m : h->members)
+        if (m.used && m.step_host + k > m.seg.n_steps) return fail(SIM_ERANGE, "steps beyond n_steps");
+    return enqueue_steps(h, k);
+}
+
+int sim_batch_step(sim_t *h, int64_t k)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (k < 0) return fail(SIM_EINVAL, "k < 0");
+    int64_t left = 0;
+    for (const Member &m : h->members)
+        if (m.used) left = std::max(left, m.seg.n_steps - m.step_host);
+    return enqueue_steps(h, std::min(k, left));
 }
 
 int sim_sync(sim_t *h)
@@ -1599,31 +2095,56 @@ int sim_sync(sim_t *h)
     return SIM_OK;
 }
 
-int sim_read_response(sim_t *h, int64_t first, int64_t count, double *q_diff)
+int sim_member_info(sim_t *h, int32_t index, int64_t *n, int64_t *step, int64_t *n_steps)
 {
     int rc = check_handle(h);
     if (rc) return rc;
+    rc = check_member_index(h, index);
+    if (rc) return rc;
+    const Member &m = h->members[index];
+    if (n) *n = m.n;
+    if (step) *step = m.step_host;
+    if (n_steps) *n_steps = m.seg.n_steps;
+    return SIM_OK;
+}
+
+int sim_member_read_response(sim_t *h, int32_t index, int64_t first, int64_t count, double *q_diff)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    rc = check_member_index(h, index);
+    if (rc) return rc;
+    const Member &m = h->members[index];
     if (count == 0) return SIM_OK;
-    if (!q_diff || count < 0 || first < h->start_step || first + count > h->step_host)
+    if (!q_diff || count < 0 || first < m.start_step || first + count > m.step_host)
         return fail(SIM_ERANGE, "response range not computed");
     rc = sim_sync(h);
     if (rc) return rc;
-    hipError_t e = hipMemcpy(q_diff, h->qdiff + first, sizeof(double) * count, hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(q_diff, m.seg.qdiff + first, sizeof(double) * count, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return mark_failed(h, fail(SIM_EDEVICE, "copy of Q_diff failed"));
     return SIM_OK;
 }
 
-int sim_read_state(sim_t *h, double *pos, double *vel, uint8_t *alive, double *q_surface,
-                   int64_t *step)
+int sim_read_response(sim_t *h, int64_t first, int64_t count, double *q_diff)
+{
+    return sim_member_read_response(h, 0, first, count, q_diff);
+}
+
+int sim_member_read_state(sim_t *h, int32_t index, double *pos, double *vel, uint8_t *alive,
+                          double *q_surface, int64_t *step)
 {
     int rc = check_handle(h);
     if (rc) return rc;
+    rc = check_member_index(h, index);
+    if (rc) return rc;
     rc = sim_sync(h);
     if (rc) return rc;
+    const Member &mb = h->members[index];
     Ctl ctl;
-    if (hipMemcpy(&ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(&ctl, h->ctl + index, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess)
         return mark_failed(h, fail(SIM_EDEVICE, "copy of control block failed"));
-    const int64_t n = h->lo.n;
+    const int64_t n = mb.n;
+    const size_t p0 = mb.seg.p0;
     const size_t na = ctl.n_cur, ng = ctl.n_dead;
     std::vector<double> a[6], g[6];
     std::vector<uint32_t> au(na), gu(ng);
@@ -1633,18 +2154,18 @@ int sim_read_state(sim_t *h, double *pos, double *vel, uint8_t *alive, double *q
     for (int j = 0; j < 6; ++j) {
         a[j].resize(na);
         g[j].resize(ng);
-        if ((na && hipMemcpy(a[j].data(), srcA[j], 8 * na, hipMemcpyDeviceToHost)) ||
-            (ng && hipMemcpy(g[j].data(), srcG[j], 8 * ng, hipMemcpyDeviceToHost)))
+        if ((na && hipMemcpy(a[j].data(), srcA[j] + p0, 8 * na, hipMemcpyDeviceToHost)) ||
+            (ng && hipMemcpy(g[j].data(), srcG[j] + p0, 8 * ng, hipMemcpyDeviceToHost)))
             return mark_failed(h, fail(SIM_EDEVICE, "state copy failed"));
     }
-    if ((na && (hipMemcpy(au.data(), h->A.uid, 4 * na, hipMemcpyDeviceToHost) ||
-                hipMemcpy(ad.data(), h->dead, na, hipMemcpyDeviceToHost))) ||
-        (ng && hipMemcpy(gu.data(), h->G.uid, 4 * ng, hipMemcpyDeviceToHost)))
+    if ((na && (hipMemcpy(au.data(), h->A.uid + p0, 4 * na, hipMemcpyDeviceToHost) ||
+                hipMemcpy(ad.data(), h->dead + p0, na, hipMemcpyDeviceToHost))) ||
+        (ng && hipMemcpy(gu.data(), h->G.uid + p0, 4 * ng, hipMemcpyDeviceToHost)))
         return mark_failed(h, fail(SIM_EDEVICE, "state copy failed"));
     auto find = [&](uint32_t u) -> int64_t {
-        auto it = std::lower_bound(h->id_index.begin(), h->id_index.end(),
+        auto it = std::lower_bound(mb.id_index.begin(), mb.id_index.end(),
                                    std::make_pair(u, (int64_t)-1));
-        if (it == h->id_index.end() || it->first != u) return -1;
+        if (it == mb.id_index.end() || it->first != u) return -1;
         return it->second;
     };
     if (alive) std::memset(alive, 0, (size_t)n);
@@ -1664,45 +2185,57 @@ int sim_read_state(sim_t *h, double *pos, double *vel, uint8_t *alive, double *q
         put(k, a, i);
         if (alive) alive[k] = 1;
     }
-    if (q_surface) *q_surface = h->prm.q_surface0 + kQ * (double)ctl.n_dead;
+    if (q_surface) *q_surface = mb.q_surface0 + kQ * (double)ctl.n_dead;
     if (step) *step = ctl.step;
     return SIM_OK;
 }
 
-int sim_eval_field(sim_t *h, double *E)
+int sim_read_state(sim_t *h, double *pos, double *vel, uint8_t *alive, double *q_surface,
+                   int64_t *step)
+{
+    return sim_member_read_state(h, 0, pos, vel, alive, q_surface, step);
+}
+
+int sim_member_eval_field(sim_t *h, int32_t index, double *E)
 {
     int rc = check_handle(h);
+    if (rc) return rc;
+    rc = check_member_index(h, index);
     if (rc) return rc;
     if (!E) return fail(SIM_EINVAL, "E is NULL");
     rc = launch_step(h, h->stream, true, nullptr);
     if (rc) return mark_failed(h, rc);
     rc = sim_sync(h);
     if (rc) return rc;
+    const Member &mb = h->members[index];
     Ctl ctl;
-    if (hipMemcpy(&ctl, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(&ctl, h->ctl + index, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess)
         return mark_failed(h, fail(SIM_EDEVICE, "copy of control block failed"));
-    const size_t nl = ctl.n_live;
+    const size_t nl = ctl.n_live, p0 = mb.seg.p0;
     std::vector<double> e(3 * nl);
     std::vector<uint32_t> u(nl);
-    if (nl && (hipMemcpy(e.data(), h->Eout, 8 * 3 * nl, hipMemcpyDeviceToHost) ||
-               hipMemcpy(u.data(), h->Eid, 4 * nl, hipMemcpyDeviceToHost)))
+    if (nl && (hipMemcpy(e.data(), h->Eout + 3 * p0, 8 * 3 * nl, hipMemcpyDeviceToHost) ||
+               hipMemcpy(u.data(), h->Eid + p0, 4 * nl, hipMemcpyDeviceToHost)))
         return mark_failed(h, fail(SIM_EDEVICE, "field copy failed"));
-    std::memset(E, 0, sizeof(double) * 3 * (size_t)h->lo.n);
+    std::memset(E, 0, sizeof(double) * 3 * (size_t)mb.n);
     for (size_t i = 0; i < nl; ++i) {
-        auto it = std::lower_bound(h->id_index.begin(), h->id_index.end(),
+        auto it = std::lower_bound(mb.id_index.begin(), mb.id_index.end(),
                                    std::make_pair(u[i], (int64_t)-1));
-        if (it == h->id_index.end() || it->first != u[i]) return fail(SIM_EDEVICE, "unknown id");
+        if (it == mb.id_index.end() || it->first != u[i]) return fail(SIM_EDEVICE, "unknown id");
         for (int j = 0; j < 3; ++j) E[3 * it->second + j] = e[3 * i + j];
     }
     return SIM_OK;
 }
+
+int sim_eval_field(sim_t *h, double *E) { return sim_member_eval_field(h, 0, E); }
 
 int sim_profile(sim_t *h, int64_t k, double *kernel_ms, int32_t n_kernels)
 {
     int rc = check_handle(h);
     if (rc) return rc;
     if (k <= 0 || !kernel_ms) return fail(SIM_EINVAL, "k must be > 0 and kernel_ms non-NULL");
-    if (h->step_host + k > h->lo.n_steps) return fail(SIM_ERANGE, "steps beyond n_steps");
+    for (const Member &m : h->members)
+        if (m.used && m.step_host + k > m.seg.n_steps) return fail(SIM_ERANGE, "steps beyond n_steps");
     hipEvent_t ev[KN_COUNT + 1];
     for (int i = 0; i <= KN_COUNT; ++i)
         if (hipEventCreate(&ev[i]) != hipSuccess) return fail(SIM_EDEVICE, "hipEventCreate failed");
@@ -1715,7 +2248,9 @@ int sim_profile(sim_t *h, int64_t k, double *kernel_ms, int32_t n_kernels)
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) acc[i] += ms;
         }
-        if (rc == SIM_OK) h->step_host += 1;
+        if (rc == SIM_OK)
+            for (Member &m : h->members)
+                if (m.used) m.step_host += 1;
     }
     for (int i = 0; i <= KN_COUNT; ++i) (void)hipEventDestroy(ev[i]);
     if (rc) return mark_failed(h, rc);
@@ -1735,7 +2270,7 @@ int sim_info(sim_t *h, int64_t *n, int32_t *tile, int32_t *channels)
 {
     int rc = check_handle(h);
     if (rc) return rc;
-    if (n) *n = h->lo.n;
+    if (n) *n = h->members.empty() || !h->members[0].used ? 0 : h->members[0].n;
     if (tile) *tile = kWave;
     if (channels) *channels = h->lo.C;
     return SIM_OK;

@@ -23,7 +23,10 @@ SIM_FP64, SIM_FP32_COMP = 0, 1
 EXPORTED = ("sim_params_default", "sim_create", "sim_step", "sim_sync", "sim_read_response",
             "sim_read_state", "sim_eval_field", "sim_profile", "sim_num_kernels",
             "sim_kernel_name", "sim_footprint_bytes", "sim_info", "sim_destroy",
-            "sim_strerror", "sim_last_error")
+            "sim_strerror", "sim_last_error", "sim_member_default", "sim_batch_create",
+            "sim_batch_footprint_bytes", "sim_batch_add", "sim_batch_remove", "sim_batch_step",
+            "sim_member_info", "sim_member_read_response", "sim_member_read_state",
+            "sim_member_eval_field")
 
 
 class sim_params(C.Structure):
@@ -34,6 +37,18 @@ class sim_params(C.Structure):
         ("l_max", C.c_int32), ("m_mode", C.c_int32), ("probe_bc", C.c_int32),
         ("wall_bc", C.c_int32), ("precision", C.c_int32), ("tile", C.c_int32),
         ("seed", C.c_uint64), ("mem_limit_bytes", C.c_uint64),
+    ]
+
+
+class sim_member(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("reserved0", C.c_uint32), ("n", C.c_int64),
+        ("pos", C.POINTER(C.c_double)), ("vel", C.POINTER(C.c_double)),
+        ("ids", C.POINTER(C.c_uint32)), ("u_asy", C.POINTER(C.c_double)),
+        ("n_steps", C.c_int64), ("start_step", C.c_int64),
+        ("ntilde", C.c_double), ("ion_density", C.c_double), ("q_surface0", C.c_double),
+        ("r_out", C.c_double), ("dt", C.c_double), ("seed", C.c_uint64),
+        ("probe_bc", C.c_int32), ("wall_bc", C.c_int32),
     ]
 
 
@@ -87,9 +102,25 @@ def lib():
     L.sim_strerror.restype = C.c_char_p
     L.sim_last_error.argtypes = []
     L.sim_last_error.restype = C.c_char_p
+    M = C.POINTER(sim_member)
+    i32p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    L.sim_member_default.argtypes = [M]
+    L.sim_member_default.restype = None
+    L.sim_batch_create.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, M, C.c_void_p,
+                                   C.POINTER(C.c_void_p)]
+    L.sim_batch_footprint_bytes.argtypes = [P, C.c_int64, C.c_int32]
+    L.sim_batch_footprint_bytes.restype = C.c_int64
+    L.sim_batch_add.argtypes = [H, M, i32p]
+    L.sim_batch_remove.argtypes = [H, C.c_int32]
+    L.sim_batch_step.argtypes = [H, C.c_int64]
+    L.sim_member_info.argtypes = [H, C.c_int32, i64p, i64p, i64p]
+    L.sim_member_read_response.argtypes = [H, C.c_int32, C.c_int64, C.c_int64, dp]
+    L.sim_member_read_state.argtypes = [H, C.c_int32, dp, dp, C.POINTER(C.c_uint8), dp, i64p]
+    L.sim_member_eval_field.argtypes = [H, C.c_int32, dp]
     for name in EXPORTED:
         if name not in ("sim_params_default", "sim_num_kernels", "sim_kernel_name",
-                        "sim_footprint_bytes", "sim_destroy", "sim_strerror", "sim_last_error"):
+                        "sim_footprint_bytes", "sim_destroy", "sim_strerror", "sim_last_error",
+                        "sim_member_default", "sim_batch_footprint_bytes"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -241,3 +272,163 @@ class Sim:
         c = C.c_int32()
         _check(lib().sim_info(self._handle(), C.byref(n), C.byref(t), C.byref(c)))
         return dict(n=n.value, tile=t.value, channels=c.value)
+
+
+@dataclass
+class Member:
+    """One simulation of a batch: its particles, drive and per-run parameters
+    (everything but the probe geometry, l_max, m_mode and precision, which the
+    batch's common SimParams fix)."""
+    pos: np.ndarray
+    vel: np.ndarray
+    u_asy: np.ndarray
+    ntilde: float
+    ids: np.ndarray | None = None
+    start_step: int = 0
+    ion_density: float = 1.0
+    q_surface0: float = 0.0
+    r_out: float = 5.0
+    dt: float = 0.05
+    seed: int = 0
+    probe_bc: int = SIM_BC_ABSORB
+    wall_bc: int = SIM_BC_SPECULAR
+
+    @staticmethod
+    def from_params(params: SimParams, pos, vel, u_asy, ids=None, start_step: int = 0) -> "Member":
+        return Member(pos=pos, vel=vel, u_asy=u_asy, ntilde=params.ntilde, ids=ids,
+                      start_step=start_step, ion_density=params.ion_density,
+                      q_surface0=params.q_surface0, r_out=params.r_out, dt=params.dt,
+                      seed=params.seed, probe_bc=params.probe_bc, wall_bc=params.wall_bc)
+
+    def to_c(self):
+        """(sim_member, arrays kept alive for the duration of the call)."""
+        pos = np.ascontiguousarray(self.pos, dtype=np.float64)
+        vel = np.ascontiguousarray(self.vel, dtype=np.float64)
+        u = np.ascontiguousarray(self.u_asy, dtype=np.float64)
+        n = pos.shape[0]
+        if pos.shape != (n, 3) or vel.shape != (n, 3):
+            raise ValueError("pos and vel must have shape [n, 3]")
+        ids = None if self.ids is None else np.ascontiguousarray(self.ids, dtype=np.uint32)
+        m = sim_member()
+        lib().sim_member_default(C.byref(m))
+        m.n = n
+        m.pos = _dp(pos)
+        m.vel = _dp(vel)
+        m.ids = None if ids is None else ids.ctypes.data_as(C.POINTER(C.c_uint32))
+        m.u_asy = _dp(u) if u.size else None
+        m.n_steps = u.shape[0]
+        m.start_step = self.start_step
+        for f in ("ntilde", "ion_density", "q_surface0", "r_out", "dt", "seed", "probe_bc",
+                  "wall_bc"):
+            setattr(m, f, getattr(self, f))
+        return m, (pos, vel, u, ids)
+
+
+def batch_footprint_bytes(params: SimParams, slot_capacity: int, max_members: int) -> int:
+    p = params.to_c()
+    v = lib().sim_batch_footprint_bytes(C.byref(p), slot_capacity, max_members)
+    if v < 0:
+        _check(int(v))
+    return int(v)
+
+
+class Batch:
+    """Many independent simulations stepped by the same kernel launches
+    (sim_batch_create ... sim_destroy).  Members may be admitted and retired
+    between steps; each member's results equal those of the member run alone."""
+
+    def __init__(self, common: SimParams, members=(), slot_capacity: int = 0,
+                 max_members: int = 0, stream=None, use_torch_stream: bool = True):
+        L = lib()
+        self._p = common.to_c()
+        cs, keep = [], []
+        for mb in members:
+            c, k = mb.to_c()
+            cs.append(c)
+            keep.append(k)
+        arr = (sim_member * max(len(cs), 1))(*cs)
+        if stream is None and use_torch_stream:
+            stream = _current_torch_stream()
+        h = C.c_void_p()
+        _check(L.sim_batch_create(C.byref(self._p), slot_capacity, max_members, len(cs),
+                                  arr if cs else None, stream, C.byref(h)))
+        self._h = h
+        self._n = {i: mb.to_c()[0].n for i, mb in enumerate(members)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sim_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _handle(self):
+        if not getattr(self, "_h", None):
+            raise SimError(SIM_ESTATE, "batch is closed")
+        return self._h
+
+    def add(self, member: Member) -> int:
+        c, keep = member.to_c()
+        idx = C.c_int32()
+        _check(lib().sim_batch_add(self._handle(), C.byref(c), C.byref(idx)))
+        self._n[idx.value] = c.n
+        del keep
+        return idx.value
+
+    def remove(self, index: int):
+        _check(lib().sim_batch_remove(self._handle(), index))
+        self._n.pop(index, None)
+
+    def step(self, k: int = 1):
+        _check(lib().sim_batch_step(self._handle(), k))
+
+    def step_strict(self, k: int = 1):
+        _check(lib().sim_step(self._handle(), k))
+
+    def sync(self):
+        _check(lib().sim_sync(self._handle()))
+
+    def info(self, index: int) -> dict:
+        n, st, ns = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().sim_member_info(self._handle(), index, C.byref(n), C.byref(st), C.byref(ns)))
+        return dict(n=n.value, step=st.value, n_steps=ns.value)
+
+    def read_response(self, index: int, first: int, count: int) -> np.ndarray:
+        out = np.zeros(count)
+        _check(lib().sim_member_read_response(self._handle(), index, first, count, _dp(out)))
+        return out
+
+    def read_state(self, index: int) -> dict:
+        n = self.info(index)["n"]
+        pos = np.zeros((n, 3))
+        vel = np.zeros((n, 3))
+        alive = np.zeros(n, dtype=np.uint8)
+        qs = C.c_double()
+        st = C.c_int64()
+        _check(lib().sim_member_read_state(self._handle(), index, _dp(pos), _dp(vel),
+                                           alive.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                           C.byref(qs), C.byref(st)))
+        return dict(pos=pos, vel=vel, alive=alive, q_surface=qs.value, step=st.value)
+
+    def eval_field(self, index: int) -> np.ndarray:
+        n = self.info(index)["n"]
+        E = np.zeros((n, 3))
+        _check(lib().sim_member_eval_field(self._handle(), index, _dp(E)))
+        return E
+
+    def profile(self, k: int) -> dict:
+        L = lib()
+        nk = L.sim_num_kernels()
+        ms = np.zeros(nk)
+        _check(L.sim_profile(self._handle(), k, _dp(ms), nk))
+        return {L.sim_kernel_name(i).decode(): float(ms[i]) for i in range(nk)}

@@ -40,7 +40,7 @@ def impulse_twins_small():
     for name, pos, u in runs:
         t0 = time.time()
         r = O.run(p, pos, st.vel, u, IMPULSE_STEPS)
-        print(f"oracle {name}: {time.time() - t0:.0f} s, absorbed {int(np.sum(~r.alive))}",
+        print(f"oracle {name}: {time.time() - t0:.0f} s, absorbed {r.absorbed}",
               flush=True)
         cols.append(r.qdiff)
     header = ("Q_diff(t_n), n = 0..%d, from the oracle.  Workload shell-1e4-L8: N = 1e4 uniform "
