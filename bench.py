@@ -194,13 +194,91 @@ def calibrate_copy(nbytes: int, reps: int = 3):
     torch.cuda.synchronize()
 
 
+def _alive(b, k):
+    return int(b.read_state(k)["alive"].sum())
+
+
+def bench_batch(args):
+    """64 independent runs of a parameter scan (N from 1e4 to 1e6, T_e 1-5 eV,
+    n_e 1e14-1e16), l_max = 16, in one batch: aggregate particle-steps/s of
+    the batched launch, and of the same runs one after another."""
+    import torch
+
+    from paper_2111_13072_amd import sim as S
+    from paper_2111_13072_amd import workload as W
+
+    wls = W.batch_workloads()
+    fp32 = args.precision == "fp32c"
+    cp = S.SimParams(l_max=wls[0].l_max, precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64)
+    n_steps = max(wls[0].n_steps, args.warmup + args.steps + args.profile_steps + 1)
+    members = []
+    for wl in wls:
+        st = wl.particles()
+        members.append(S.Member(pos=st.pos, vel=st.vel, u_asy=wl.drive(n_steps), ntilde=wl.ntilde,
+                                r_out=wl.r_out, dt=wl.dt))
+    n_all = sum(wl.n for wl in wls)
+    print(f"[bench] batch of {len(wls)} runs, {n_all} particles, l_max={cp.l_max} "
+          f"{args.precision}", file=sys.stderr, flush=True)
+    b = S.Batch(cp, members)
+    b.step(args.warmup)
+    b.sync()
+    alive0 = [_alive(b, k) for k in range(len(wls))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    b.sync()
+    t1 = time.perf_counter()
+    alive1 = [_alive(b, k) for k in range(len(wls))]
+    elapsed = t1 - t0
+    live = 0.5 * (sum(alive0) + sum(alive1))
+    value = live * args.steps / elapsed
+    print(f"[bench] batch: {args.steps} steps in {elapsed:.3f} s: {value:.4e} particle-steps/s",
+          file=sys.stderr, flush=True)
+    kms = b.profile(args.profile_steps)
+    b.close()
+
+    # the same runs one after another (each its own handle and graph)
+    seq_time = 0.0
+    for k, mb in enumerate(members):
+        with S.Batch(cp, [mb]) as one:
+            one.step(args.warmup)
+            one.sync()
+            ta = time.perf_counter()
+            one.step(args.seq_steps)
+            one.sync()
+            seq_time += (time.perf_counter() - ta) / args.seq_steps
+        if k % 16 == 15:
+            print(f"[bench] sequential: {k + 1} runs timed", file=sys.stderr, flush=True)
+    seq_value = live / seq_time
+    dom = "field_push"
+    flops = algorithmic_flops_per_particle(cp.l_max) * live
+    achieved = flops / (kms[dom] * 1e-3) / 1e12
+    peak = FP32_VECTOR_PEAK_TFLOPS if fp32 else FP64_VECTOR_PEAK_TFLOPS
+    line = {"metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64" if fp32 else "f64", "data": "synthetic",
+            "config": {"workload": f"batch{len(wls)}-L{cp.l_max}", "members": len(wls),
+                       "n_particles": n_all, "l_max": cp.l_max, "precision": args.precision,
+                       "parallelism": "single-gpu"},
+            "sequential_value": seq_value, "batch_speedup": value / seq_value,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved / peak, "traffic": None, "kernel": dom,
+                         "kernel_ms": kms[dom],
+                         "per_kernel_ms": {k: round(v, 5) for k, v in kms.items()}}}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large", "small"])
+    ap.add_argument("--workload", default="large", choices=["large", "small", "batch64"])
+    ap.add_argument("--seq-steps", type=int, default=20,
+                    help="batch64: timed steps of each member run alone, for comparison")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
@@ -234,6 +312,8 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "batch64":
+        return bench_batch(args)
     wl = W.LARGE if args.workload == "large" else W.SMALL_FP64
     st = wl.particles()
     n_total = args.warmup + args.steps + args.profile_steps + 1

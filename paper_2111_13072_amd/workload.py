@@ -171,3 +171,18 @@ LARGE = Workload("shell-2e6-L16", n=2_000_000, seed=2, l_max=16, n_steps=20_000)
 def sweep_workload(l_max: int, n_e: float, t_e_ev: float) -> Workload:
     return Workload(f"shell-1.6e7-L{l_max}-n{n_e:.0e}-T{t_e_ev:g}", n=16_000_000, seed=3,
                     l_max=l_max, n_steps=10_000, n_e=n_e, t_e_ev=t_e_ev)
+
+
+def batch_workloads(count: int = 64, seed: int = 4, l_max: int = 16,
+                    n_steps: int = 5000) -> list[Workload]:
+    """Independent runs of a parameter scan, drawn in this order from one
+    generator: log10 N ~ U(4, 6), T_e ~ U(1, 5) eV, log10 n_e ~ U(14, 16)
+    m^-3.  Member k's particles come from seed 1000 * seed + k."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    log_n = rng.uniform(4.0, 6.0, count)
+    t_e = rng.uniform(1.0, 5.0, count)
+    log_ne = rng.uniform(14.0, 16.0, count)
+    return [Workload(f"batch{seed}-{k}", n=int(round(10.0 ** log_n[k])), seed=1000 * seed + k,
+                     l_max=l_max, n_steps=n_steps, n_e=float(10.0 ** log_ne[k]),
+                     t_e_ev=float(t_e[k]))
+            for k in range(count)]
