@@ -270,13 +270,52 @@ def bench_batch(args):
     return 0
 
 
+def bench_serve(args):
+    """Continuous batching of Poisson arrivals (N log-uniform in [1e4, 4e6],
+    l_max in {8, 16, 32}, 200-2000 steps, T_e 1-5 eV, n_e 1e14-1e16) at 80%
+    offered load: latency percentiles from arrival to completion, and the
+    aggregate particle-steps/s over the whole service."""
+    from paper_2111_13072_amd import serve as SV
+    from paper_2111_13072_amd import sim as S
+
+    fp32 = args.precision == "fp32c"
+    reqs = SV.request_stream(seed=5, duration_s=args.serve_seconds, load=0.8)
+    print(f"[bench] serving {len(reqs)} requests over {args.serve_seconds:.0f} s, budget "
+          f"{args.serve_budget_gib:g} GiB", file=sys.stderr, flush=True)
+    srv = SV.Server(int(args.serve_budget_gib * 2**30),
+                    precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64, tick_steps=50)
+    t0 = time.perf_counter()
+    try:
+        done = srv.run(reqs, log=lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True))
+    finally:
+        srv.close()
+    wall = time.perf_counter() - t0
+    work = sum(d.n * d.n_steps for d in done)
+    lat = SV.latency_summary(done)
+    line = {"metric": METRIC, "value": work / wall, "unit": "particle-steps/s", "n_gpus": 1,
+            "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if fp32 else "f64",
+            "data": "synthetic",
+            "config": {"workload": "served-poisson", "requests": len(reqs),
+                       "arrival_window_s": args.serve_seconds, "offered_load": 0.8,
+                       "l_max": [8, 16, 32], "n_range": [1e4, 4e6], "steps_range": [200, 2000],
+                       "budget_gib": args.serve_budget_gib, "tick_steps": 50,
+                       "precision": args.precision, "parallelism": "single-gpu"},
+            "latency_s": lat, "rejected": len(srv.rejected), "wall_s": wall}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large", "small", "batch64"])
+    ap.add_argument("--workload", default="large", choices=["large", "small", "batch64", "serve"])
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="serve: length of the Poisson arrival window")
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--seq-steps", type=int, default=20,
                     help="batch64: timed steps of each member run alone, for comparison")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
@@ -314,6 +353,8 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     wl = W.LARGE if args.workload == "large" else W.SMALL_FP64
     st = wl.particles()
     n_total = args.warmup + args.steps + args.profile_steps + 1

@@ -1189,6 +1189,19 @@ struct Layout {
     int n_members;
 };
 
+// The part of the capacities in use: every member's tiles, chunks, buckets
+// and table index lie below these (at least 1 each).  Launch grids cover the
+// extent, not the capacity, so a large, sparsely filled handle steps at the
+// cost of what it holds.
+struct Extent {
+    int n_tiles = 1, n_chunks = 1, nb = 1, nb_blocks = 1, n_members = 1;
+    bool operator==(const Extent &o) const
+    {
+        return n_tiles == o.n_tiles && n_chunks == o.n_chunks && nb == o.nb &&
+               n_members == o.n_members;
+    }
+};
+
 // Per-member sizes.
 struct MemberShape {
     uint32_t nt, nc, nb;
@@ -1329,6 +1342,7 @@ struct Member {
 struct sim {
     sim_params prm;
     Layout lo;
+    Extent ext;
     KParams kp;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -1500,28 +1514,33 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
 int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
 {
     const Layout &lo = h->lo;
+    const Extent &ex = h->ext;
     KParams kp = h->kp;
     kp.field_only = field_only ? 1 : 0;
+    kp.n_tiles = ex.n_tiles;
+    kp.n_chunks = ex.n_chunks;
+    kp.nb = ex.nb;
+    kp.n_members = ex.n_members;
     const Map &mp = h->map;
-    const unsigned n = (unsigned)lo.n_tiles * kWave;
+    const unsigned n = (unsigned)ex.n_tiles * kWave;
     const unsigned gN = (n + kBlock - 1) / kBlock;
-    const unsigned gT = (unsigned)((lo.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    const unsigned gT = (unsigned)((ex.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     const unsigned gC = (unsigned)((lo.C2 + kBlock - 1) / kBlock);
-    const unsigned gM = (unsigned)((lo.n_members + kBlock - 1) / kBlock);
+    const unsigned gM = (unsigned)((ex.n_members + kBlock - 1) / kBlock);
     int e = 0;
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], s);
     };
     mark(KN_SORT_CLEAR);
-    k_sort_clear<<<(lo.nb + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(h->hist, lo.nb);
+    k_sort_clear<<<(ex.nb + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(h->hist, ex.nb);
     mark(KN_SORT_KEY);
     k_sort_key<<<gN, kBlock, 0, s>>>(mp, h->A, h->dead, h->key, h->bkt, h->sub, h->hist, kp);
     mark(KN_SCAN_A);
-    k_scan_a<<<lo.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, lo.nb);
+    k_scan_a<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, ex.nb);
     mark(KN_SCAN_B);
-    k_scan_b<<<1, kBlock, 0, s>>>(h->bsum, lo.nb_blocks);
+    k_scan_b<<<1, kBlock, 0, s>>>(h->bsum, ex.nb_blocks);
     mark(KN_SCAN_C);
-    k_scan_c<<<lo.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, lo.nb);
+    k_scan_c<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, ex.nb);
     mark(KN_MEMBER_LIVE);
     k_member_live<<<gM, kBlock, 0, s>>>(mp, h->off, kp);
     mark(KN_SORT_SCATTER);
@@ -1536,15 +1555,15 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
         else k_moments<false><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
     }
     mark(KN_CHUNK_SUMS);
-    if (lo.C > 0) k_chunk_sums<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkS, kp);
+    if (lo.C > 0) k_chunk_sums<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkS, kp);
     mark(KN_CHUNK_SCAN);
     if (lo.C > 0)
-        k_chunk_scan<<<dim3(gC, lo.n_members), kBlock, 0, s>>>(mp, h->chunkS, h->chunkC, h->T, kp);
+        k_chunk_scan<<<dim3(gC, ex.n_members), kBlock, 0, s>>>(mp, h->chunkS, h->chunkC, h->T, kp);
     mark(KN_COEF_PREP);
-    k_coef_prep<<<lo.n_members, kBlock, 0, s>>>(mp, h->T, h->tb, kp, h->Kc);
+    k_coef_prep<<<ex.n_members, kBlock, 0, s>>>(mp, h->T, h->tb, kp, h->Kc);
     mark(KN_CHUNK_APPLY);
     if (lo.C > 0)
-        k_chunk_apply<<<dim3(lo.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkC, h->Kc, h->tb,
+        k_chunk_apply<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkC, h->Kc, h->tb,
                                                                kp, h->lgrho, h->coef, h->coef32);
     mark(KN_FIELD_PUSH);
 #define MRP_FIELD(FULLV, FO, F32)                                                              \
@@ -1706,16 +1725,39 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
         hipMemset(h->dead, 0, (size_t)lo.n_tiles * kWave))
         return fail(SIM_EDEVICE, "upload failed");
 
-    // capture one step into a graph
+    if (hipDeviceSynchronize() != hipSuccess) return fail(SIM_EDEVICE, "device sync failed");
+    return SIM_OK;
+}
+
+// Recompute the extent in use and, when it changed (or no graph exists yet),
+// capture one step into a new graph.  The handle's stream is idle here.
+int update_graph(sim *h)
+{
+    Extent ex;
+    for (int32_t k = 0; k < (int32_t)h->members.size(); ++k) {
+        const Member &m = h->members[k];
+        if (!m.used) continue;
+        ex.n_tiles = std::max(ex.n_tiles, (int)(m.seg.t0 + m.seg.nt));
+        ex.n_chunks = std::max(ex.n_chunks, (int)(m.seg.c0 + m.seg.nc));
+        ex.nb = std::max(ex.nb, (int)(m.seg.b0 + m.seg.nb));
+        ex.n_members = std::max(ex.n_members, k + 1);
+    }
+    ex.nb_blocks = (ex.nb + kScanPerBlock - 1) / kScanPerBlock;
+    if (h->exec && ex == h->ext) return SIM_OK;
+    if (h->exec) (void)hipGraphExecDestroy(h->exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->exec = nullptr;
+    h->graph = nullptr;
+    h->ext = ex;
     if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(SIM_EDEVICE, "hipStreamBeginCapture failed");
+        return mark_failed(h, fail(SIM_EDEVICE, "hipStreamBeginCapture failed"));
     int le = launch_step(h, h->cap_stream, false, nullptr);
     hipError_t ce = hipStreamEndCapture(h->cap_stream, &h->graph);
-    if (le != SIM_OK) return le;
-    if (ce != hipSuccess) return fail(SIM_EDEVICE, std::string("capture: ") + hipGetErrorString(ce));
+    if (le != SIM_OK) return mark_failed(h, le);
+    if (ce != hipSuccess)
+        return mark_failed(h, fail(SIM_EDEVICE, std::string("capture: ") + hipGetErrorString(ce)));
     if (hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0) != hipSuccess)
-        return fail(SIM_EDEVICE, "hipGraphInstantiate failed");
-    if (hipDeviceSynchronize() != hipSuccess) return fail(SIM_EDEVICE, "device sync failed");
+        return mark_failed(h, fail(SIM_EDEVICE, "hipGraphInstantiate failed"));
     return SIM_OK;
 }
 
@@ -2022,6 +2064,8 @@ int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t ma
             return fail(rc, msg);
         }
     }
+    rc = update_graph(h);
+    if (rc) return bail(rc);
     *out = h;
     return SIM_OK;
 }
@@ -2052,14 +2096,18 @@ int sim_batch_add(sim_t *h, const sim_member *m, int32_t *index)
     Prepared pr;
     rc = prepare_member(m, &pr);
     if (rc) return rc;
-    return engine_add(h, m, pr, index);
+    rc = engine_add(h, m, pr, index);
+    if (rc) return rc;
+    return update_graph(h);
 }
 
 int sim_batch_remove(sim_t *h, int32_t index)
 {
     int rc = check_handle(h);
     if (rc) return rc;
-    return engine_remove(h, index);
+    rc = engine_remove(h, index);
+    if (rc) return rc;
+    return update_graph(h);
 }
 
 int sim_step(sim_t *h, int64_t k)

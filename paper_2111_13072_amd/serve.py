@@ -1,0 +1,198 @@
+"""Continuous-batching service of independent simulations.
+
+Requests (a plasma, a particle count, an l_max and a number of steps) arrive
+over time.  The server keeps one resident batch ("pool") per l_max class on
+its own HIP stream, admits waiting requests into a pool between steps when
+its tiles, chunks, buckets and memory allow (first come, first served within
+a class), steps every non-empty pool by a fixed tick, and retires finished
+requests after reading their response.  A request's response equals, bit for
+bit, that of the same request run alone (members never interact).
+
+The particles of newly arrived requests are generated on worker threads
+while the device steps the pools.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import sim as S
+from . import workload as W
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float      # seconds after the start of the service
+    n: int
+    l_max: int
+    n_steps: int
+    t_e_ev: float
+    n_e: float
+    seed: int
+
+    def workload(self) -> W.Workload:
+        return W.Workload(f"req{self.rid}", n=self.n, seed=self.seed, l_max=self.l_max,
+                          n_steps=self.n_steps, n_e=self.n_e, t_e_ev=self.t_e_ev)
+
+    def member(self) -> S.Member:
+        wl = self.workload()
+        st = wl.particles()
+        return S.Member(pos=st.pos, vel=st.vel, u_asy=wl.drive(self.n_steps), ntilde=wl.ntilde,
+                        r_out=wl.r_out, dt=wl.dt)
+
+
+def gpu_seconds_estimate(n: int, l_max: int, n_steps: int,
+                         s_per_particle_step_per_channel: float = 2.9e-12) -> float:
+    """Device time of a request at the measured cost of the batched path,
+    proportional to (l_max + 1)^2 per particle-step."""
+    return n * n_steps * (l_max + 1) ** 2 * s_per_particle_step_per_channel
+
+
+def request_stream(seed: int = 5, duration_s: float = 60.0, load: float = 0.8,
+                   n_range=(1e4, 4e6), l_choices=(8, 16, 32), steps_range=(200, 2000)) -> list:
+    """Poisson arrivals over duration_s.  N is log-uniform in n_range, l_max
+    uniform over l_choices, steps uniform in steps_range, T_e ~ U(1, 5) eV,
+    log10 n_e ~ U(14, 16).  The rate is set so that the offered device work
+    is `load` times one GPU (Little's law with the mean work per request)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    # mean device seconds per request, by sampling the same distributions
+    m = rng.uniform(np.log10(n_range[0]), np.log10(n_range[1]), 4096)
+    ls = rng.choice(l_choices, 4096)
+    ss = rng.integers(steps_range[0], steps_range[1] + 1, 4096)
+    mean_work = float(np.mean([gpu_seconds_estimate(10 ** a, b, c) for a, b, c in zip(m, ls, ss)]))
+    rate = load / mean_work
+    out = []
+    t = 0.0
+    rid = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration_s:
+            break
+        n = int(round(10 ** rng.uniform(np.log10(n_range[0]), np.log10(n_range[1]))))
+        out.append(Request(rid, t, n, int(rng.choice(l_choices)),
+                           int(rng.integers(steps_range[0], steps_range[1] + 1)),
+                           float(rng.uniform(1.0, 5.0)), float(10 ** rng.uniform(14.0, 16.0)),
+                           5000 + rid))
+        rid += 1
+    return out
+
+
+@dataclass
+class Done:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    n: int
+    l_max: int
+    n_steps: int
+    q_diff: np.ndarray = field(repr=False)
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    """Pools per l_max with the same particle capacity each; budget_bytes of
+    device memory is split over the classes in proportion to their
+    per-particle footprint."""
+
+    def __init__(self, budget_bytes: int, l_classes=(8, 16, 32), precision: int = S.SIM_FP64,
+                 tick_steps: int = 50, max_members: int = 256):
+        self.tick = tick_steps
+        self.pools = {}
+        per_particle = {}
+        for L in l_classes:
+            cp = S.SimParams(l_max=L, precision=precision)
+            probe = 1 << 20
+            per_particle[L] = S.batch_footprint_bytes(cp, probe, max_members) / probe
+        total = sum(per_particle.values())
+        for L in l_classes:
+            cp = S.SimParams(l_max=L, precision=precision)
+            # equal particle capacity per class: bytes in proportion to footprint
+            slots = int(budget_bytes / total) // 64 * 64
+            self.pools[L] = S.Batch(cp, [], slot_capacity=max(slots, 64),
+                                    max_members=max_members, use_torch_stream=False)
+        self.running = {L: {} for L in l_classes}    # member index -> (request, admitted)
+        self.rejected = []                            # requests larger than their pool
+
+    def close(self):
+        for b in self.pools.values():
+            b.close()
+
+    def _admit(self, L, req, member, now):
+        try:
+            idx = self.pools[L].add(member)
+        except S.SimError as e:
+            if e.code == S.SIM_ENOMEM:
+                return False
+            raise
+        self.running[L][idx] = (req, now)
+        return True
+
+    def run(self, requests, clock=time.perf_counter, log=None, workers: int = 4) -> list:
+        """Serve the requests (sorted by arrival) in real time; returns Done
+        records in completion order."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting = {L: deque() for L in self.pools}   # (request, future of its member)
+        done = []
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            t0 = clock()
+            while pending or any(waiting.values()) or any(self.running.values()):
+                now = clock() - t0
+                while pending and pending[0].arrival <= now:
+                    r = pending.popleft()
+                    if r.l_max not in self.pools:
+                        raise ValueError(f"no pool for l_max {r.l_max}")
+                    waiting[r.l_max].append((r, ex.submit(r.member)))
+                # one tick on every non-empty pool (asynchronous, own streams)
+                active = [L for L in self.pools if self.running[L]]
+                for L in active:
+                    self.pools[L].step(self.tick)
+                for L in active:
+                    self.pools[L].sync()
+                now = clock() - t0
+                # completions
+                for L in active:
+                    for idx, (r, adm) in list(self.running[L].items()):
+                        info = self.pools[L].info(idx)
+                        if info["step"] >= info["n_steps"]:
+                            q = self.pools[L].read_response(idx, 0, info["n_steps"])
+                            self.pools[L].remove(idx)
+                            del self.running[L][idx]
+                            done.append(Done(r.rid, r.arrival, adm, now, r.n, r.l_max, r.n_steps,
+                                             q))
+                            if log:
+                                log(f"done {r.rid} L{r.l_max} n={r.n} steps={r.n_steps} "
+                                    f"latency {now - r.arrival:.2f} s")
+                # admissions, first come first served within a class; a request
+                # that does not fit an empty pool never will
+                for L in self.pools:
+                    while waiting[L]:
+                        r, fut = waiting[L][0]
+                        if not fut.done() and self.running[L]:
+                            break
+                        mb = fut.result()
+                        if not self._admit(L, r, mb, clock() - t0):
+                            if not self.running[L]:
+                                self.rejected.append(r)
+                                waiting[L].popleft()
+                                continue
+                            break
+                        waiting[L].popleft()
+                if not any(self.running.values()) and not any(waiting.values()) and pending:
+                    time.sleep(max(0.0, pending[0].arrival - (clock() - t0)))
+        return done
+
+
+def latency_summary(done) -> dict:
+    lat = np.array([d.latency for d in done])
+    return {"requests": len(done), "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
+            "max_s": float(lat.max())}

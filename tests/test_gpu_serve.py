@@ -1,0 +1,68 @@
+"""Continuous batching: requests arriving over time, admitted into resident
+pools between steps, each answered exactly as if it had run alone."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2111_13072_amd import serve as SV
+from paper_2111_13072_amd import sim as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def small_requests():
+    rng = np.random.default_rng(17)
+    reqs = []
+    t = 0.0
+    for rid in range(10):
+        t += float(rng.exponential(0.05))
+        reqs.append(SV.Request(rid, t, int(rng.integers(300, 3000)), int(rng.choice([4, 6])),
+                               int(rng.integers(20, 80)), float(rng.uniform(1, 5)),
+                               float(10 ** rng.uniform(14, 16)), 900 + rid))
+    return reqs
+
+
+def test_served_results_equal_runs_alone():
+    reqs = small_requests()
+    # room for about two requests per class at a time: admission has to wait
+    cp = S.SimParams(l_max=6)
+    per = S.batch_footprint_bytes(cp, 1 << 16, 16) / (1 << 16)
+    srv = SV.Server(int(2 * 6000 * per), l_classes=(4, 6), tick_steps=8, max_members=16)
+    _say(f"[gpu] serving {len(reqs)} requests")
+    try:
+        done = srv.run(reqs)
+    finally:
+        srv.close()
+    assert not srv.rejected
+    assert sorted(d.rid for d in done) == list(range(len(reqs)))
+    waited = [d for d in done if d.admitted > d.arrival + 1e-3]
+    _say(f"[gpu] {len(waited)} requests waited for admission")
+    for d in done:
+        r = reqs[d.rid]
+        assert d.q_diff.shape == (r.n_steps,)
+        assert d.finished >= d.admitted >= d.arrival - 1e-9
+        with S.Batch(S.SimParams(l_max=r.l_max), [r.member()]) as b:
+            b.step(r.n_steps)
+            q = b.read_response(0, 0, r.n_steps)
+        assert np.array_equal(q, d.q_diff), d.rid
+    s = SV.latency_summary(done)
+    assert s["requests"] == len(reqs) and 0 < s["p50_s"] <= s["p99_s"] <= s["max_s"]
+
+
+def test_oversized_request_is_rejected_not_stuck():
+    srv = SV.Server(1, l_classes=(4,), tick_steps=4, max_members=4)   # one tile of capacity
+    reqs = [SV.Request(0, 0.0, 5000, 4, 10, 2.0, 1e15, 1),
+            SV.Request(1, 0.0, 50, 4, 10, 2.0, 1e15, 2)]
+    try:
+        done = srv.run(reqs)
+    finally:
+        srv.close()
+    assert [r.rid for r in srv.rejected] == [0]
+    assert [d.rid for d in done] == [1]
