@@ -177,7 +177,8 @@ void sim_destroy(sim_t *h);
  *
  * Each member occupies ceil(n/64) tiles of 64 particle slots, ceil(tiles/64)
  * carry chunks and max(1, n/8) sort buckets of the handle's capacity, plus
- * 16 bytes per step for its drive and response.
+ * 16 bytes per step for its drive and response and 16 bytes per node of an
+ * ion profile.
  */
 typedef struct {
     uint32_t struct_size;  /* sizeof(sim_member) */
@@ -197,6 +198,12 @@ typedef struct {
     uint64_t seed;
     int32_t probe_bc;
     int32_t wall_bc;
+    /* Optional immobile ion density (units of n_inf) at ion_profile_len >= 2
+     * equally spaced radii from 1 to r_out, linear in between, e.g. the ion
+     * profile of the floating equilibrium of App. D; replaces the uniform
+     * ion_density when non-NULL.  Copied. */
+    const double *ion_profile;
+    int64_t ion_profile_len;
 } sim_member;
 
 /* Fill *m with the per-member defaults of sim_params_default (arrays NULL). */

@@ -24,6 +24,7 @@ class _Params(C.Structure):
         ("ntilde", C.c_double), ("ion_density", C.c_double),
         ("l_max", C.c_int32), ("m_mode", C.c_int32), ("probe_bc", C.c_int32),
         ("wall_bc", C.c_int32), ("seed", C.c_uint64),
+        ("ion_prof", C.POINTER(C.c_double)), ("ion_prof_len", C.c_int64),
     ]
 
 
@@ -40,10 +41,17 @@ class Params:
     probe_bc: int = BC_ABSORB
     wall_bc: int = BC_SPECULAR
     seed: int = 0
+    ion_profile: np.ndarray | None = None   # density at equally spaced radii 1..r_out
 
     def _c(self) -> _Params:
+        prof, plen = None, 0
+        if self.ion_profile is not None:
+            self._prof = np.ascontiguousarray(self.ion_profile, dtype=np.float64)
+            if self._prof.ndim != 1 or self._prof.size < 2:
+                raise ValueError("ion_profile needs at least 2 nodes")
+            prof, plen = self._prof.ctypes.data_as(C.POINTER(C.c_double)), self._prof.size
         return _Params(self.d, self.eps_r, self.r_out, self.dt, self.ntilde, self.ion_density,
-                       self.l_max, self.m_mode, self.probe_bc, self.wall_bc, self.seed)
+                       self.l_max, self.m_mode, self.probe_bc, self.wall_bc, self.seed, prof, plen)
 
 
 _lib = None
@@ -58,6 +66,8 @@ def lib():
         dp = C.POINTER(C.c_double)
         P = C.POINTER(_Params)
         L.orc_coeffs.argtypes = [C.c_double, C.c_double, C.c_int, dp, dp, dp]
+        L.orc_ion_field.argtypes = [P, C.c_double, dp]
+        L.orc_ion_field.restype = C.c_double
         L.orc_greens.argtypes = [P, dp, dp, C.c_int, dp, dp]
         L.orc_psi_anti.argtypes = [P, dp, dp, dp]
         L.orc_field.argtypes = [P, C.c_int64, dp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint8),
@@ -147,6 +157,14 @@ def field(p: Params, pos, ids=None, alive=None, q_surface: float = 0.0, u_asy: f
     if rc != 0:
         raise ValueError("oracle: l_max out of range")
     return E, phi
+
+
+def ion_field(p: Params, r: float) -> tuple:
+    """(E_r, Phi) of the immobile ion background at radius r."""
+    phi = C.c_double()
+    pc = p._c()
+    e = lib().orc_ion_field(C.byref(pc), float(r), C.byref(phi))
+    return e, phi.value
 
 
 def qdiff(p: Params, pos, alive=None) -> float:

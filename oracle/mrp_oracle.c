@@ -58,6 +58,11 @@ typedef struct {
     int32_t probe_bc;
     int32_t wall_bc;
     uint64_t seed;       /* diffuse reflection only */
+    /* Optional immobile ion profile (replaces ion_density when non-NULL):
+     * density at ion_prof_len >= 2 equally spaced radii from 1 to r_out,
+     * linear in between. */
+    const double *ion_prof;
+    int64_t ion_prof_len;
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -247,16 +252,50 @@ static void psi_anti(const orc_params *p, const double *bP, const double *c, con
     }
 }
 
-/* Potential and field of the immobile uniform ion background of density
- * n_i filling 1 < r < r_out, through the l = 0 part of G~ (1/(4 pi r_>)). */
+/* int_a^b n(s) s^k ds over the profile, segment by segment with 3-point
+ * Gauss-Legendre quadrature (exact: the integrand is a polynomial of degree
+ * at most 3 on each segment). */
+static double prof_moment(const orc_params *p, double a, double b, int k)
+{
+    static const double xg[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};
+    static const double wg[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+    if (!(b > a)) return 0.0;
+    const int64_t K = p->ion_prof_len - 1;
+    const double h = (p->r_out - 1.0) / (double)K;
+    long double acc = 0.0L;
+    double lo = a;
+    while (lo < b) {
+        int64_t j = (int64_t)floor((lo - 1.0) / h);
+        if (j < 0) j = 0;
+        if (j > K - 1) j = K - 1;
+        double hi = 1.0 + (double)(j + 1) * h;
+        if (j == K - 1 || hi > b) hi = b;
+        if (!(hi > lo)) hi = b;   /* guard against a node rounding onto lo */
+        const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+        for (int g = 0; g < 3; ++g) {
+            const double s = mid + half * xg[g];
+            const double t = (s - (1.0 + (double)j * h)) / h;
+            const double n = p->ion_prof[j] * (1.0 - t) + p->ion_prof[j + 1] * t;
+            acc += (long double)(wg[g] * half * n * (k == 2 ? s * s : s));
+        }
+        lo = hi;
+    }
+    return (double)acc;
+}
+
+/* Potential and field of the immobile ion background through the l = 0 part
+ * of G~ (1/(4 pi r_>)): uniform density n_i on 1 < r < r_out, or the profile. */
 static double phi_ion(const orc_params *p, double r)
 {
+    if (p->ion_prof)
+        return prof_moment(p, 1.0, r, 2) / r + prof_moment(p, r, p->r_out, 1);
     double ni = p->ion_density, ro = p->r_out;
     return ni * ((r * r * r - 1.0) / (3.0 * r) + (ro * ro - r * r) / 2.0);
 }
 
 static double eion_r(const orc_params *p, double r)
 {
+    if (p->ion_prof) return prof_moment(p, 1.0, r, 2) / (r * r);
     return p->ion_density * (r * r * r - 1.0) / (3.0 * r * r);
 }
 
@@ -272,6 +311,13 @@ int orc_greens(const orc_params *p, const double *x, const double *y, int x_oute
     orc_coeffs(p->eps_r, p->d, p->l_max, f, bP, c);
     greens(p, f, x, y, x_outer, G, grad);
     return 0;
+}
+
+/* Radial field and potential of the ion background at radius r. */
+double orc_ion_field(const orc_params *p, double r, double *phi)
+{
+    if (phi) *phi = phi_ion(p, r);
+    return eion_r(p, r);
 }
 
 int orc_psi_anti(const orc_params *p, const double *x, double *psi, double *grad)

@@ -174,6 +174,22 @@ def admittance(q_response, u_asy, dt: float, pad: int = 16, w_max: float = 2.0) 
     return Spectrum(w[keep], Y)
 
 
+def admittance_from_fit(fit: DampedSine, omega, u_area: float = 1.0) -> Spectrum:
+    """Admittance of the fitted response (Sec. 4 takes the Fourier transform
+    of the fit).  The fit, a exp(-b (t - t0)) sin(c (t - t0) + phi) for
+    t >= t0, is continued back to the impulse at t = 0 as
+    a' exp(-b t) sin(c t + phi') with a' = a exp(b t0), phi' = phi - c t0;
+    its transform is Q^(w) = a' [c cos phi' + (b + i w) sin phi'] /
+    ((b + i w)^2 + c^2), and Y = i w Q^ / u^ with u^ = u_area for an impulse.
+    The fit's constant offset, a static shift, is left out."""
+    w = np.asarray(omega, dtype=np.float64)
+    amp = fit.amplitude * np.exp(fit.damping * fit.t0)
+    ph = fit.phase - fit.frequency * fit.t0
+    s = fit.damping + 1j * w
+    qh = amp * (fit.frequency * np.cos(ph) + s * np.sin(ph)) / (s * s + fit.frequency ** 2)
+    return Spectrum(w, 1j * w * qh / u_area)
+
+
 def lorentzian_from_fit(fit: DampedSine, omega) -> np.ndarray:
     """Spectrum of the fitted damped sine (Sec. 4: the transform of the fit)."""
     w = np.asarray(omega, dtype=np.float64)

@@ -92,7 +92,12 @@ struct Seg {
     int64_t n_steps;
     const double *u_asy;
     double *qdiff;
-    int32_t used, pad;
+    // optional ion profile: densities at ion_k + 1 equally spaced radii from 1
+    // to r_out, then the enclosed ion charge at those radii (super-particle units)
+    const double *ion_tab;
+    double ion_h, ion_inv_h;
+    int32_t ion_k;
+    int32_t used;
 };
 
 constexpr uint32_t kNone = 0xffffffffu;
@@ -140,6 +145,27 @@ struct Map {
     const uint32_t *tile_member;   // [n_tiles], kNone for free tiles
     const uint32_t *chunk_member;  // [n_chunks], kNone for free chunks
 };
+
+// Charge of the immobile ions inside radius r, in super-particle units: the
+// uniform background n_i (4 pi / 3)(r^3 - 1) ntilde, or the profile, linear
+// in r on each segment [r_j, r_j + h], integrated in closed form in the
+// offset dd = r - r_j.
+__device__ inline double ion_enclosed(const Seg &sg, double r, double r2)
+{
+    constexpr double kFourPi = 4.0 * 3.14159265358979323846;
+    if (!sg.ion_tab) return sg.ntilde * sg.ion_density * (kFourPi / 3.0) * (r2 * r - 1.0);
+    const int K = sg.ion_k;
+    int j = (int)((r - 1.0) * sg.ion_inv_h);
+    j = max(0, min(j, K - 1));
+    const double rj = 1.0 + (double)j * sg.ion_h;
+    const double dd = r - rj;
+    const double nj = sg.ion_tab[j];
+    const double beta = (sg.ion_tab[j + 1] - nj) * sg.ion_inv_h;
+    const double d2 = dd * dd;
+    const double seg = nj * (rj * rj * dd + rj * d2 + d2 * dd / 3.0) +
+                       beta * (rj * rj * d2 / 2.0 + 2.0 * rj * d2 * dd / 3.0 + d2 * d2 / 4.0);
+    return sg.ion_tab[K + 1 + j] + kFourPi * sg.ntilde * seg;
+}
 
 // A member takes part in this launch: it is in use and has steps left (or
 // the launch only evaluates the field).
@@ -1065,7 +1091,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
     // radial order (p is the sorted position) and the ion background
     // nt n_i (4 pi / 3)(r^3 - 1), all in super-particle units. ----
     {
-        const double ions = ntilde * sg.ion_density * (4.0 * kPi / 3.0) * (r2 * r - 1.0);
+        const double ions = ion_enclosed(sg, r, r2);
         const double enclosed = (ct.q_surface + kQ * (double)pl) + ions;
         const double e = enclosed / (4.0 * kPi * ntilde * r2);
         Ex += e * xh;
@@ -1248,6 +1274,10 @@ bool check_member_scalars(const sim_member *m, std::string *why)
         return false;
     }
     if (!std::isfinite(m->q_surface0)) { *why = "q_surface0 must be finite"; return false; }
+    if (m->ion_profile && (m->ion_profile_len < 2 || m->ion_profile_len > (1 << 24))) {
+        *why = "ion_profile_len must be in [2, 2^24]";
+        return false;
+    }
     if (m->probe_bc < SIM_BC_ABSORB || m->probe_bc > SIM_BC_DIFFUSE) { *why = "bad probe_bc"; return false; }
     if (m->wall_bc != SIM_BC_SPECULAR && m->wall_bc != SIM_BC_DIFFUSE) { *why = "bad wall_bc"; return false; }
     return true;
@@ -1283,7 +1313,12 @@ struct Alloc {
     }
 };
 
-size_t member_bytes(int64_t n_steps) { return 2 * (((size_t)std::max<int64_t>(n_steps, 1) * 8 + 255) & ~size_t(255)); }
+size_t member_bytes(int64_t n_steps, int64_t prof_len)
+{
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return 2 * al((size_t)std::max<int64_t>(n_steps, 1) * 8) +
+           (prof_len > 0 ? al((size_t)prof_len * 16) : 0);
+}
 
 // First-fit allocator of ranges [start, start + len) of a capacity.
 class Ranges {
@@ -1590,8 +1625,10 @@ void free_member_arrays(Member &m)
 {
     if (m.seg.u_asy) (void)hipFree((void *)m.seg.u_asy);
     if (m.seg.qdiff) (void)hipFree(m.seg.qdiff);
+    if (m.seg.ion_tab) (void)hipFree((void *)m.seg.ion_tab);
     m.seg.u_asy = nullptr;
     m.seg.qdiff = nullptr;
+    m.seg.ion_tab = nullptr;
 }
 
 void release(sim *h)
@@ -1787,6 +1824,10 @@ int prepare_member(const sim_member *m, Prepared *pr)
     }
     for (int64_t s = 0; s < m->n_steps; ++s)
         if (!std::isfinite(m->u_asy[s])) return fail(SIM_EINVAL, "non-finite u_asy");
+    if (m->ion_profile)
+        for (int64_t j = 0; j < m->ion_profile_len; ++j)
+            if (!std::isfinite(m->ion_profile[j]) || m->ion_profile[j] < 0.0)
+                return fail(SIM_EINVAL, "ion_profile values must be finite and >= 0");
     pr->uid.resize((size_t)n);
     for (int64_t i = 0; i < n; ++i) pr->uid[i] = m->ids ? m->ids[i] : (uint32_t)i;
     pr->idx.resize((size_t)n);
@@ -1807,7 +1848,7 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     for (int32_t k = 0; k < (int32_t)h->members.size(); ++k)
         if (!h->members[k].used) { slot = k; break; }
     if (slot < 0) return fail(SIM_ENOMEM, "member table is full");
-    const size_t mbytes = member_bytes(m->n_steps);
+    const size_t mbytes = member_bytes(m->n_steps, m->ion_profile ? m->ion_profile_len : 0);
     if (h->prm.mem_limit_bytes && h->shared_bytes + h->member_total + mbytes > h->prm.mem_limit_bytes)
         return fail(SIM_ENOMEM, "member arrays would exceed mem_limit_bytes");
     const MemberShape sh = member_shape(n);
@@ -1863,6 +1904,33 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     sg.u_asy = u_dev;
     if (hipMalloc(&q_dev, 8 * ns) != hipSuccess) return undo(fail(SIM_ENOMEM, "hipMalloc of the response failed"));
     sg.qdiff = q_dev;
+    std::vector<double> ion_tab;
+    if (m->ion_profile) {
+        // node densities, then the enclosed charge at every node, segment by
+        // segment in closed form (the same expression as the field kernel at
+        // dd = h)
+        const int64_t K = m->ion_profile_len - 1;
+        const double h = (m->r_out - 1.0) / (double)K;
+        ion_tab.assign(2 * (size_t)(K + 1), 0.0);
+        for (int64_t j = 0; j <= K; ++j) ion_tab[j] = m->ion_profile[j];
+        double q = 0.0;
+        for (int64_t j = 0; j < K; ++j) {
+            ion_tab[K + 1 + j] = q;
+            const double rj = 1.0 + (double)j * h, dd = h, d2 = dd * dd;
+            const double nj = m->ion_profile[j], beta = (m->ion_profile[j + 1] - nj) / h;
+            const double seg = nj * (rj * rj * dd + rj * d2 + d2 * dd / 3.0) +
+                               beta * (rj * rj * d2 / 2.0 + 2.0 * rj * d2 * dd / 3.0 + d2 * d2 / 4.0);
+            q += 4.0 * kPi * m->ntilde * seg;
+        }
+        ion_tab[2 * K + 1] = q;
+        double *t_dev = nullptr;
+        if (hipMalloc(&t_dev, 8 * ion_tab.size()) != hipSuccess)
+            return undo(fail(SIM_ENOMEM, "hipMalloc of the ion profile failed"));
+        sg.ion_tab = t_dev;
+        sg.ion_k = (int32_t)K;
+        sg.ion_h = h;
+        sg.ion_inv_h = (double)K / (m->r_out - 1.0);
+    }
 
     if (hipStreamSynchronize(h->stream) != hipSuccess) {
         h->failed = true;
@@ -1887,6 +1955,8 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
         hipMemset(h->dead + sg.p0, 0, sg.cap) ||
         hipMemcpy(q_dev, zeros.data(), 8 * ns, hipMemcpyHostToDevice) ||
         (m->n_steps > 0 && hipMemcpy(u_dev, m->u_asy, 8 * m->n_steps, hipMemcpyHostToDevice)) ||
+        (!ion_tab.empty() && hipMemcpy((void *)sg.ion_tab, ion_tab.data(), 8 * ion_tab.size(),
+                                       hipMemcpyHostToDevice)) ||
         hipMemcpy(h->ctl + slot, &ctl, sizeof(Ctl), hipMemcpyHostToDevice) ||
         hipMemcpy(h->tile_member + t0, tm.data(), 4 * tm.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->chunk_member + c0, cm.data(), 4 * cm.size(), hipMemcpyHostToDevice) ||
@@ -1921,7 +1991,7 @@ int engine_remove(sim *h, int32_t index)
     h->tiles.give(mb.seg.t0, mb.seg.nt);
     h->chunks.give(mb.seg.c0, mb.seg.nc);
     h->buckets.give(mb.seg.b0, mb.seg.nb);
-    h->member_total -= member_bytes(mb.seg.n_steps);
+    h->member_total -= member_bytes(mb.seg.n_steps, mb.seg.ion_tab ? mb.seg.ion_k + 1 : 0);
     mb = Member();
     return SIM_OK;
 }
@@ -2022,7 +2092,7 @@ int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps)
     if (!check_member_scalars(&m, &why)) return fail(SIM_EINVAL, why);
     const int64_t shared = sim_batch_footprint_bytes(p, slots_for(n), 1);
     if (shared < 0) return shared;
-    return shared + (int64_t)member_bytes(n_steps);
+    return shared + (int64_t)member_bytes(n_steps, 0);
 }
 
 int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t max_members,

@@ -1,0 +1,85 @@
+"""The paper's probe experiment (Sec. 4 with App. D), end to end on the GPU.
+
+For each electron temperature: the floating equilibrium (App. D) between the
+probe and r_out = 10, a driven run (impulse u_asy = 1 at the first step) and
+an undriven twin from the same state, the damped-sine fit of their Q_diff
+difference, the admittance of the fit, the least-squares Drude match
+(sheath delta, collision rate nu_eff) and K = nu_eff / (lambda_D / R).
+
+    python -m paper_2111_13072_amd.experiments [--steps 10000] [--l-max 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+from dataclasses import asdict, dataclass
+
+import numpy as np
+
+from . import analysis as A
+from . import equilibrium as EQ
+from . import sim as S
+from . import workload as W
+
+
+@dataclass
+class ProbeResponse:
+    t_e_ev: float
+    r_hat: float
+    psi_probe: float
+    fit_amplitude: float
+    fit_damping: float
+    fit_frequency: float
+    sheath: float
+    nu_eff: float
+    k: float
+
+
+def probe_response(t_e_ev: float, steps: int = 10000, l_max: int = 1, n: int = 500_000,
+                   seed: int = 6, fit_window: float = 30.0, precision: int = S.SIM_FP64):
+    """Returns (ProbeResponse, t, Q_diff driven - undriven)."""
+    ps = EQ.PaperSetup(n=n, seed=seed, t_e_ev=t_e_ev)
+    eq, st, ntilde, q_s, prof = ps.build()
+    mode = S.SIM_M_AXISYM if l_max == 1 else S.SIM_M_FULL
+    out = []
+    for drive in (True, False):
+        u = W.impulse_drive(steps, 1.0) if drive else np.zeros(steps)
+        mb = S.Member(pos=st.pos, vel=st.vel, u_asy=u, ntilde=ntilde, r_out=ps.r_out, dt=ps.dt,
+                      q_surface0=q_s, probe_bc=S.SIM_BC_DIFFUSE, wall_bc=S.SIM_BC_DIFFUSE,
+                      seed=seed, ion_profile=prof)
+        with S.Batch(S.SimParams(l_max=l_max, m_mode=mode, precision=precision), [mb]) as b:
+            b.step(steps)
+            out.append(b.read_response(0, 0, steps))
+    t = np.arange(steps) * ps.dt
+    diff = A.twin_difference(*out)
+    m = t <= fit_window
+    fit = A.fit_damped_sine(t[m], diff[m], 0.5)
+    w = np.linspace(0.005, 1.0, 400)
+    # the impulse u_asy = 1 lasts one step: its transform is dt
+    y_kin = A.admittance_from_fit(fit, w, u_area=ps.dt)
+    match = A.match_drude(w, y_kin.admittance, l_max=l_max, start=(0.5, 0.1))
+    res = ProbeResponse(t_e_ev, eq.r_hat, eq.psi_probe, fit.amplitude, fit.damping,
+                        fit.frequency, match.delta, match.nu,
+                        A.k_coefficient(match.nu, eq.debye))
+    return res, t, diff
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--l-max", type=int, default=1)
+    ap.add_argument("--temperatures", default="2,3,5")
+    args = ap.parse_args(argv)
+    rows = []
+    for te in [float(x) for x in args.temperatures.split(",")]:
+        res, _, _ = probe_response(te, args.steps, args.l_max)
+        rows.append(asdict(res))
+        print(json.dumps(rows[-1]), flush=True)
+    ks = [r["k"] for r in rows]
+    print(json.dumps({"K_mean": float(np.mean(ks))}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

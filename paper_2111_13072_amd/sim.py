@@ -49,6 +49,7 @@ class sim_member(C.Structure):
         ("ntilde", C.c_double), ("ion_density", C.c_double), ("q_surface0", C.c_double),
         ("r_out", C.c_double), ("dt", C.c_double), ("seed", C.c_uint64),
         ("probe_bc", C.c_int32), ("wall_bc", C.c_int32),
+        ("ion_profile", C.POINTER(C.c_double)), ("ion_profile_len", C.c_int64),
     ]
 
 
@@ -292,6 +293,7 @@ class Member:
     seed: int = 0
     probe_bc: int = SIM_BC_ABSORB
     wall_bc: int = SIM_BC_SPECULAR
+    ion_profile: np.ndarray | None = None   # densities at equally spaced radii 1..r_out
 
     @staticmethod
     def from_params(params: SimParams, pos, vel, u_asy, ids=None, start_step: int = 0) -> "Member":
@@ -321,7 +323,12 @@ class Member:
         for f in ("ntilde", "ion_density", "q_surface0", "r_out", "dt", "seed", "probe_bc",
                   "wall_bc"):
             setattr(m, f, getattr(self, f))
-        return m, (pos, vel, u, ids)
+        prof = None
+        if self.ion_profile is not None:
+            prof = np.ascontiguousarray(self.ion_profile, dtype=np.float64)
+            m.ion_profile = _dp(prof)
+            m.ion_profile_len = prof.size
+        return m, (pos, vel, u, ids, prof)
 
 
 def batch_footprint_bytes(params: SimParams, slot_capacity: int, max_members: int) -> int:

@@ -177,3 +177,31 @@ def test_k_coefficient_reproduces_paper_value():
     ks = [A.k_coefficient(nu, W.PlasmaScales(1e15, te, 0.004).v_th) for te, nu in rows]
     assert np.mean(ks) == pytest.approx(1.264, abs=1e-3)
     assert max(ks) - min(ks) < 0.02
+
+
+def test_admittance_from_fit_matches_transform_of_the_fit():
+    """Closed-form transform of the fitted damped sine against the FFT
+    estimator applied to the same function sampled finely."""
+    f = A.DampedSine(0.7, 0.05, 0.55, 0.8, 0.0, 0.0)
+    dt = 0.01
+    t = np.arange(0, 800, dt)
+    q = f(t)
+    u = np.zeros_like(t)
+    u[0] = 1.0 / dt
+    num = A.admittance(q, u, dt, pad=2, w_max=1.2)
+    ana = A.admittance_from_fit(f, num.omega)
+    # the sampled signal starts at q(0) = a sin(phi) != 0: the FFT of samples
+    # is the integral to first order in dt
+    assert np.max(np.abs(num.admittance - ana.admittance)) < 2e-3 * np.max(np.abs(ana.admittance))
+
+
+def test_admittance_from_fit_is_independent_of_the_fit_origin():
+    """The same function fitted from a later start t0 gives the same Y."""
+    t = np.arange(0, 200, 0.02)
+    q = damped(t, 0.5, 0.04, 0.6, 0.3)
+    w = np.linspace(0.05, 1.2, 50)
+    f0 = A.fit_damped_sine(t, q, 0.0, 0.6)
+    f1 = A.fit_damped_sine(t, q, 2.5, 0.6)
+    y0 = A.admittance_from_fit(f0, w).admittance
+    y1 = A.admittance_from_fit(f1, w).admittance
+    assert np.max(np.abs(y0 - y1)) < 1e-6 * np.max(np.abs(y0))
