@@ -444,8 +444,20 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const uint64_
 //   R_lm^c = Q_l^m C_m,  R_lm^s = Q_l^m S_m,  I_lm = r^-(2l+1) R_lm,
 // normalised so that sum_m Y_lm(a) Y_lm(b) = (2l+1)/(4 pi) P_l(a.b).
 
-constexpr int kBatch = 16;       // channels per LDS batch of the tile reduction
+constexpr int kBatch = 8;        // channels per LDS batch of the tile reduction
 constexpr int kBatchPad = kWave + 1;
+constexpr int kParts = kWave / (2 * kBatch);   // lanes sharing one (channel, kind) sum
+
+// Orders this wave's LDS accesses at this point: LDS instructions of one wave
+// complete in issue order, so rows a wave wrote are visible to its later
+// reads without a block barrier; the fences keep the compiler from moving
+// LDS accesses across.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Exchange the upper 32 lanes of a with the lower 32 lanes of b.
 __device__ inline void swap_wave_halves(double &a, double &b)
@@ -465,8 +477,9 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     // Per wave (one tile of 64 particles): for each channel, q R (interior)
     // and q I (exterior) are first folded across the two wave halves with a
     // lane swap (lanes 0-31 then hold R over particle pairs, lanes 32-63 I),
-    // written to an LDS row, and every 16 channels each lane (channel, kind,
-    // quarter) sums 16 rows; the quarters are combined across the wave.
+    // written to an LDS row, and every kBatch channels each lane (channel,
+    // kind, part) sums kBatch entries of a row; the parts are combined across
+    // the wave.  Each wave uses its own rows only.
     __shared__ double buf[kWavesPerBlock][kBatch][kBatchPad];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -508,22 +521,27 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         lgrho[tile] = log2(rho);
     }
 
-    const int cc = lane & (kBatch - 1);
-    const int kind = (lane >> 4) & 1;   // 0: interior (R), 1: exterior (I)
-    const int half = lane >> 5;
+    const int cc = lane % kBatch;
+    const int kind = (lane / kBatch) & 1;   // 0: interior (R), 1: exterior (I)
+    const int part = lane / (2 * kBatch);
+    const double *row_base = &buf[w][cc][kind * 32 + part * (32 / kParts)];
+    auto row_sum = [&]() {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < 32 / kParts; ++r) acc += row_base[r];
+#pragma unroll
+        for (int o = 2 * kBatch; o < kWave; o <<= 1) acc += __shfl_xor(acc, o);
+        return acc;
+    };
     int slot = 0, base = 0;
     auto put = [&](double rv, double iv) {
         swap_wave_halves(rv, iv);
         buf[w][slot][lane] = rv + iv;
         if (++slot == kBatch) {
-            __syncthreads();
-            double acc = 0.0;
-            const double *row = &buf[w][cc][kind * 32 + half * 16];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc += row[r];
-            acc += __shfl_xor(acc, 32);
-            if (tile_ok && half == 0) St[(kind ? C : 0) + base + cc] = acc;
-            __syncthreads();
+            wave_lds_sync();
+            const double acc = row_sum();
+            if (tile_ok && part == 0) St[(kind ? C : 0) + base + cc] = acc;
+            wave_lds_sync();
             base += kBatch;
             slot = 0;
         }
@@ -558,17 +576,10 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
             sl *= inv_r2;
         }
     }
-    if (slot > 0) {   // last, partial batch
-        const int count = slot;
-        __syncthreads();
-        double acc = 0.0;
-        const double *row = &buf[w][cc][kind * 32 + half * 16];
-        if (cc < count) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc += row[r];
-        }
-        acc += __shfl_xor(acc, 32);
-        if (tile_ok && half == 0 && cc < count) St[(kind ? C : 0) + base + cc] = acc;
+    if (slot > 0) {   // last, partial batch: rows >= slot hold stale values
+        wave_lds_sync();
+        const double acc = row_sum();
+        if (tile_ok && part == 0 && cc < slot) St[(kind ? C : 0) + base + cc] = acc;
     }
 }
 
@@ -999,7 +1010,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
     sh_ir[w][lane] = (R)inv_r;
     sh_r2[w][lane] = r2;
     sh_uid[w][lane] = uid;
-    __syncthreads();
+    wave_lds_sync();   // the rows are this wave's own
     if (!tile_live) return;
 
     const int L = kp.L;
