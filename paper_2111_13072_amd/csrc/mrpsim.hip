@@ -201,6 +201,17 @@ __device__ inline float rcp_r(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ inline double rsq_r(double v) { return 1.0 / sqrt(v); }
 __device__ inline float rsq_r(float v) { return __builtin_amdgcn_rsqf(v); }
 
+// Read of a table that no kernel writes while it runs, through the constant
+// address space: a wave-uniform index then becomes a scalar load through the
+// scalar cache even where the kernel stores to global memory in between
+// (which keeps the compiler from proving the read invariant).
+template <typename T>
+__device__ inline T ld_const(const T *p, int i)
+{
+    return reinterpret_cast<const __attribute__((address_space(4))) T *>(
+        reinterpret_cast<uintptr_t>(p))[i];
+}
+
 // r^2 as (x*x + y*y) + z*z without contraction: the exact radial sort key.
 __device__ inline double key_r2(double x, double y, double z)
 {
@@ -559,10 +570,15 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         }
         double Qp = 0.0, Qpp = 0.0;
         double sl = s_mm;
+        // recurrence constants read one l ahead (clamped index)
+        double na = ld_const(tb.alm, tri(m, m)), nb = ld_const(tb.blm, tri(m, m));
         for (int l = m; l <= L; ++l) {
+            const double a = na, b = nb;
+            na = ld_const(tb.alm, tri(min(l + 1, L), m));
+            nb = ld_const(tb.blm, tri(min(l + 1, L), m));
             double Qv;
-            if (l == m) Qv = tb.qmm[m];
-            else Qv = tb.alm[tri(l, m)] * z * Qp - tb.blm[tri(l, m)] * r2 * Qpp;
+            if (l == m) Qv = ld_const(tb.qmm, m);
+            else Qv = a * z * Qp - b * r2 * Qpp;
             Qpp = Qp;
             Qp = Qv;
             if (l > 0) {
