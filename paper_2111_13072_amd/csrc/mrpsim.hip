@@ -118,9 +118,13 @@ struct Tables {
     const double *alm;      // Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m
     const double *blm;
     const int *chl;         // degree l of each channel in stream order
+    // (Q_m^m or a_lm, 0 or b_lm) in stream order of (m, l): m = 0..m_top
+    // outer, l = m..L inner, so a loop over (m, l) reads consecutive entries
+    const double2 *ab;
     // FP32 copies for the FP32-compensated mode
     const float *qmm32, *alm32, *blm32;
     const float4 *nf4_32;
+    const float2 *ab32;
 };
 
 // Channels are kept in "stream order": m = 0..m_top outer, l = max(m,1)..L
@@ -210,6 +214,12 @@ __device__ inline T ld_const(const T *p, int i)
 {
     return reinterpret_cast<const __attribute__((address_space(4))) T *>(
         reinterpret_cast<uintptr_t>(p))[i];
+}
+
+__device__ inline double2 ld_const(const double2 *p, int i)
+{
+    const double *q = reinterpret_cast<const double *>(p);
+    return make_double2(ld_const(q, 2 * i), ld_const(q, 2 * i + 1));
 }
 
 // r^2 as (x*x + y*y) + z*z without contraction: the exact radial sort key.
@@ -560,6 +570,9 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
 
     double Cm = 1.0, Sm = 0.0;
     double s_mm = inv_r;  // r^-(2m+1)
+    int j = 0;   // (m, l) position in stream order
+    const int jmax = (m_top + 1) * (2 * L - m_top + 2) / 2 - 1;
+    double2 nab = ld_const(tb.ab, 0);
     for (int m = 0; m <= m_top; ++m) {
         if (m > 0) {
             const double nc = x * Cm - y * Sm;
@@ -570,15 +583,13 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         }
         double Qp = 0.0, Qpp = 0.0;
         double sl = s_mm;
-        // recurrence constants read one l ahead (clamped index)
-        double na = ld_const(tb.alm, tri(m, m)), nb = ld_const(tb.blm, tri(m, m));
-        for (int l = m; l <= L; ++l) {
-            const double a = na, b = nb;
-            na = ld_const(tb.alm, tri(min(l + 1, L), m));
-            nb = ld_const(tb.blm, tri(min(l + 1, L), m));
+        for (int l = m; l <= L; ++l, ++j) {
+            // (Q_m^m, 0) at l = m, else the recurrence constants (a_lm, b_lm)
+            const double2 ab = nab;
+            nab = ld_const(tb.ab, min(j + 1, jmax));   // read one step ahead
             double Qv;
-            if (l == m) Qv = ld_const(tb.qmm, m);
-            else Qv = a * z * Qp - b * r2 * Qpp;
+            if (l == m) Qv = ab.x;
+            else Qv = ab.x * z * Qp - ab.y * r2 * Qpp;
             Qpp = Qp;
             Qp = Qv;
             if (l > 0) {
@@ -630,45 +641,43 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(Map mp, const double *S, 
     chunkS[(size_t)j * kp.C2 + c] = s;
 }
 
-// Per member (blockIdx.y) and channel: exclusive prefix of the interior chunk
-// sums, exclusive suffix of the exterior ones, and the totals T_lm.
+// Per member (blockIdx.y) and channel (one wave each): exclusive prefix of the
+// interior chunk sums, exclusive suffix of the exterior ones, and the totals
+// T_lm.  The member's chunks, in scan order, are cut into 64 consecutive runs,
+// one per lane: each lane sums its run, the wave scans the run sums, and each
+// lane then writes its run's carries.
 __global__ __launch_bounds__(kBlock) void k_chunk_scan(Map mp, const double *chunkS,
                                                        double *chunkC, double *T, KParams kp)
 {
-    const int c = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int c = (int)uniform_u32(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
     const int s = blockIdx.y;
     if (c >= kp.C2) return;
     const Seg &sg = mp.seg[s];
     if (!member_runs(sg, mp.ctl[s], kp)) return;
-    constexpr int U = 16;   // loads kept in flight along the serial chain
     const int nc = (int)sg.nc;
-    const double *cS = chunkS + (size_t)sg.c0 * kp.C2;
-    double *cC = chunkC + (size_t)sg.c0 * kp.C2;
-    double run = 0.0;
-    if (c < kp.C) {
-        for (int j0 = 0; j0 < nc; j0 += U) {
-            double v[U];
+    const bool interior = c < kp.C;
+    const double *cS = chunkS + (size_t)sg.c0 * kp.C2 + c;
+    double *cC = chunkC + (size_t)sg.c0 * kp.C2 + c;
+    const int per = (nc + kWave - 1) / kWave;
+    const int q0 = lane * per, q1 = min(q0 + per, nc);   // this lane's run in scan order
+    auto chunk = [&](int q) { return interior ? q : nc - 1 - q; };
+    double part = 0.0;
+    for (int q = q0; q < q1; ++q) part += cS[(size_t)chunk(q) * kp.C2];
+    double incl = part;
 #pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = (j0 + u < nc) ? cS[(size_t)(j0 + u) * kp.C2 + c] : 0.0;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (j0 + u < nc) cC[(size_t)(j0 + u) * kp.C2 + c] = run;
-                run += v[u];
-            }
-        }
-    } else {
-        for (int j0 = nc - 1; j0 >= 0; j0 -= U) {
-            double v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = (j0 - u >= 0) ? cS[(size_t)(j0 - u) * kp.C2 + c] : 0.0;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (j0 - u >= 0) cC[(size_t)(j0 - u) * kp.C2 + c] = run;
-                run += v[u];
-            }
-        }
-        T[(size_t)s * kp.C + (c - kp.C)] = run;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
     }
+    double run = __shfl_up(incl, 1);
+    if (lane == 0) run = 0.0;
+    for (int q = q0; q < q1; ++q) {
+        const size_t at = (size_t)chunk(q) * kp.C2;
+        cC[at] = run;
+        run += cS[at];
+    }
+    if (!interior && lane == kWave - 1) T[(size_t)s * kp.C + (c - kp.C)] = incl;
 }
 
 // Per member (blockIdx.x): constant part of the interior coefficient, the
@@ -807,8 +816,10 @@ struct Grave {
 // (Assembling the radial part from the two partial derivatives of Q instead
 // loses a factor ~l to cancellation.)
 template <bool FULL, typename R>
-__device__ inline void far_field(const R *cf, int C, int L, const R *qmm, const R *alm,
-                                 const R *blm, R x, R y, R z, R &gx, R &gy, R &gz)
+__device__ inline void far_field(const R *cf, int C, int L,
+                                 const typename std::conditional<std::is_same<R, float>::value,
+                                                                 float2, double2>::type *abt,
+                                 R x, R y, R z, R &gx, R &gy, R &gz)
 {
     const R r2 = x * x + y * y + z * z;
     const R inv_r2 = rcp_r(r2);
@@ -818,6 +829,7 @@ __device__ inline void far_field(const R *cf, int C, int L, const R *qmm, const 
     R Cm = 1, Sm = 0, Cm1 = 0, Sm1 = 0;
     R s_mm = inv_r;
     int k = 0;   // stream position of the channel
+    int j = 0;
     for (int m = 0; m <= m_top; ++m) {
         if (m > 0) {
             Cm1 = Cm;
@@ -831,11 +843,12 @@ __device__ inline void far_field(const R *cf, int C, int L, const R *qmm, const 
         const R dm = (R)m;
         for (int l = m; l <= L; ++l) {
             R Qv, Dz;
+            const auto abv = abt[j++];   // (Q_m^m, 0) at l = m, else (a_lm, b_lm)
             if (l == m) {
-                Qv = qmm[m];
+                Qv = abv.x;
                 Dz = 0;
             } else {
-                const R a = alm[tri(l, m)], b = blm[tri(l, m)];
+                const R a = abv.x, b = abv.y;
                 const R az = a * z, br2 = b * r2;
                 Qv = az * Q1 - br2 * Q2;
                 Dz = a * Q1 + az * Dz1 - br2 * Dz2;
@@ -1047,11 +1060,11 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
         const double inv_rho = 1.0 / rho;
         R gx, gy, gz;
         if constexpr (FP32) {
-            far_field<FULL, float>(coef32 + (size_t)tile * kp.C2, kp.C, L, tb.qmm32, tb.alm32,
-                                   tb.blm32, (float)(x * inv_rho), (float)(y * inv_rho),
+            far_field<FULL, float>(coef32 + (size_t)tile * kp.C2, kp.C, L, tb.ab32,
+                                   (float)(x * inv_rho), (float)(y * inv_rho),
                                    (float)(z * inv_rho), gx, gy, gz);
         } else {
-            far_field<FULL, double>(coef + (size_t)tile * kp.C2, kp.C, L, tb.qmm, tb.alm, tb.blm, x,
+            far_field<FULL, double>(coef + (size_t)tile * kp.C2, kp.C, L, tb.ab, x,
                                     y, z, gx, gy, gz);
         }
         Ex = -(double)gx * inv_rho;
@@ -1457,7 +1470,9 @@ size_t nf4_offset(int L)
     return (base + 3) & ~size_t(3);
 }
 
-size_t tables_len(int L) { return nf4_offset(L) + 4 * (size_t)(L + 1); }
+size_t ab_offset(int L) { return nf4_offset(L) + 4 * (size_t)(L + 1); }   // 32-byte aligned
+
+size_t tables_len(int L) { return ab_offset(L) + 2 * (size_t)((L + 1) * (L + 2) / 2); }
 
 // FP32 copies: qmm, the two (l, m) triangles, then the near-field constants
 // at a 16-byte aligned offset.
@@ -1467,7 +1482,9 @@ size_t nf4_32_offset(int L)
     return (base + 3) & ~size_t(3);
 }
 
-size_t tables32_len(int L) { return nf4_32_offset(L) + 4 * (size_t)(L + 1); }
+size_t ab32_offset(int L) { return nf4_32_offset(L) + 4 * (size_t)(L + 1); }   // 16-byte aligned
+
+size_t tables32_len(int L) { return ab32_offset(L) + 2 * (size_t)((L + 1) * (L + 2) / 2); }
 
 void plan_alloc(sim *h, Alloc &al)
 {
@@ -1570,6 +1587,13 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
                 : 0.0;
         }
     }
+    double *ab = t.data() + ab_offset(L);
+    for (int m = 0, j = 0; m <= L; ++m) {
+        for (int l = m; l <= L; ++l, ++j) {
+            ab[2 * j] = (l == m) ? qmm[m] : alm[tri(l, m)];
+            ab[2 * j + 1] = (l == m) ? 0.0 : blm[tri(l, m)];
+        }
+    }
     return t;
 }
 
@@ -1620,7 +1644,8 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     if (lo.C > 0) k_chunk_sums<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkS, kp);
     mark(KN_CHUNK_SCAN);
     if (lo.C > 0)
-        k_chunk_scan<<<dim3(gC, ex.n_members), kBlock, 0, s>>>(mp, h->chunkS, h->chunkC, h->T, kp);
+        k_chunk_scan<<<dim3((lo.C2 + kWavesPerBlock - 1) / kWavesPerBlock, ex.n_members), kBlock, 0, s>>>(
+            mp, h->chunkS, h->chunkC, h->T, kp);
     mark(KN_COEF_PREP);
     k_coef_prep<<<ex.n_members, kBlock, 0, s>>>(mp, h->T, h->tb, kp, h->Kc);
     mark(KN_CHUNK_APPLY);
@@ -1734,6 +1759,7 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
     h->tb.alm = tb + (kQmmArray + 1) * (L + 1);
     h->tb.blm = tb + (kQmmArray + 1) * (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.nf4 = reinterpret_cast<const double4 *>(tb + nf4_offset(L));
+    h->tb.ab = reinterpret_cast<const double2 *>(tb + ab_offset(L));
     h->tb.chl = h->chl;
     std::vector<float> tab32(tables32_len(L), 0.f);
     {
@@ -1744,11 +1770,14 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
         for (size_t i = 0; i < 2 * ntri; ++i) tab32[(L + 1) + i] = (float)alm[i];
         const double *nf4 = tab.data() + nf4_offset(L);
         for (int i = 0; i < 4 * (L + 1); ++i) tab32[nf4_32_offset(L) + i] = (float)nf4[i];
+        const double *ab = tab.data() + ab_offset(L);
+        for (size_t i = 0; i < 2 * ntri; ++i) tab32[ab32_offset(L) + i] = (float)ab[i];
     }
     h->tb.qmm32 = h->tables32;
     h->tb.alm32 = h->tables32 + (L + 1);
     h->tb.blm32 = h->tables32 + (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.nf4_32 = reinterpret_cast<const float4 *>(h->tables32 + nf4_32_offset(L));
+    h->tb.ab32 = reinterpret_cast<const float2 *>(h->tables32 + ab32_offset(L));
     // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
     std::vector<int> chl;
     for (int m = 0; m <= (lo.full ? L : 0); ++m)
