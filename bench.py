@@ -306,13 +306,52 @@ def bench_serve(args):
     return 0
 
 
+def bench_sweep(args):
+    """Scale and accuracy sweep: 1.6e7 particles at l_max 8, 16, 32 for
+    n_e in {1e15, 1e16} m^-3 and T_e in {1, 3, 5} eV (FP32-compensated by
+    default): one JSON line per run with its particle-steps/s and kernel
+    times, each timed over --steps steps after --warmup."""
+    from paper_2111_13072_amd import sim as S
+    from paper_2111_13072_amd import workload as W
+
+    fp32 = args.precision == "fp32c"
+    for L in (8, 16, 32):
+        for n_e in (1e15, 1e16):
+            for te in (1.0, 3.0, 5.0):
+                wl = W.sweep_workload(L, n_e, te)
+                st = wl.particles()
+                n_total = args.warmup + args.steps + args.profile_steps + 1
+                prm = S.SimParams(d=wl.d, eps_r=wl.eps_r, r_out=wl.r_out, dt=wl.dt,
+                                  ntilde=wl.ntilde, l_max=L,
+                                  precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64)
+                with S.Sim(prm, st.pos, st.vel, wl.drive(n_total)) as sim:
+                    sim.step(args.warmup)
+                    sim.sync()
+                    t0 = time.perf_counter()
+                    sim.step(args.steps)
+                    sim.sync()
+                    el = time.perf_counter() - t0
+                    kms = sim.profile(args.profile_steps)
+                flops = algorithmic_flops_per_particle(L) * wl.n / (kms["field_push"] * 1e-3) / 1e12
+                peak = FP32_VECTOR_PEAK_TFLOPS if fp32 else FP64_VECTOR_PEAK_TFLOPS
+                print(json.dumps({"workload": wl.name, "precision": args.precision,
+                                  "value": wl.n * args.steps / el, "unit": "particle-steps/s",
+                                  "ms_per_step": 1e3 * el / args.steps,
+                                  "field_push_frac": flops / peak,
+                                  "per_kernel_ms": {k: round(v, 4) for k, v in kms.items()}}),
+                      flush=True)
+                del st
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large", "small", "batch64", "serve"])
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "small", "batch64", "serve", "sweep"])
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="serve: length of the Poisson arrival window")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
@@ -355,6 +394,8 @@ def main(argv=None):
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
     wl = W.LARGE if args.workload == "large" else W.SMALL_FP64
     st = wl.particles()
     n_total = args.warmup + args.steps + args.profile_steps + 1
