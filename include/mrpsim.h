@@ -100,6 +100,8 @@ void sim_params_default(sim_params *p);
  *              must satisfy 1 < r < r_out.  Copied; the caller keeps them.
  *   ids        host array [n] of distinct ids, or NULL for 0..n-1.  Ids break
  *              ties of equal radius in the radial order (key (r^2, id)).
+ *              sim_create simulates electrons only: ids must have bit 31
+ *              clear (batch members may carry mobile ions, see sim_member).
  *   u_asy      host array [n_steps]: antisymmetric electrode voltage
  *              u_1 - u_2 at t_s = s dt (Sec. 3); copied.
  *   start_step first step to run (checkpoint resume); 0 <= start_step <= n_steps.
@@ -204,6 +206,10 @@ typedef struct {
      * ion_density when non-NULL.  Copied. */
     const double *ion_profile;
     int64_t ion_profile_len;
+    /* m_i / m_e of mobile ions: a particle whose id has bit 31 set is an ion
+     * (charge +1, this mass); others are electrons.  Must be > 0 when any id
+     * has bit 31 set; ignored otherwise. */
+    double ion_mass;
 } sim_member;
 
 /* Fill *m with the per-member defaults of sim_params_default (arrays NULL). */

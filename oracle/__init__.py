@@ -25,6 +25,7 @@ class _Params(C.Structure):
         ("l_max", C.c_int32), ("m_mode", C.c_int32), ("probe_bc", C.c_int32),
         ("wall_bc", C.c_int32), ("seed", C.c_uint64),
         ("ion_prof", C.POINTER(C.c_double)), ("ion_prof_len", C.c_int64),
+        ("ion_mass", C.c_double),
     ]
 
 
@@ -42,6 +43,7 @@ class Params:
     wall_bc: int = BC_SPECULAR
     seed: int = 0
     ion_profile: np.ndarray | None = None   # density at equally spaced radii 1..r_out
+    ion_mass: float = 0.0                   # m_i / m_e of ids with bit 31 set (ions)
 
     def _c(self) -> _Params:
         prof, plen = None, 0
@@ -51,7 +53,8 @@ class Params:
                 raise ValueError("ion_profile needs at least 2 nodes")
             prof, plen = self._prof.ctypes.data_as(C.POINTER(C.c_double)), self._prof.size
         return _Params(self.d, self.eps_r, self.r_out, self.dt, self.ntilde, self.ion_density,
-                       self.l_max, self.m_mode, self.probe_bc, self.wall_bc, self.seed, prof, plen)
+                       self.l_max, self.m_mode, self.probe_bc, self.wall_bc, self.seed, prof, plen,
+                       self.ion_mass)
 
 
 _lib = None
@@ -72,7 +75,7 @@ def lib():
         L.orc_psi_anti.argtypes = [P, dp, dp, dp]
         L.orc_field.argtypes = [P, C.c_int64, dp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint8),
                                 C.c_double, C.c_double, C.c_int64, C.POINTER(C.c_int64), dp, dp]
-        L.orc_qdiff.argtypes = [P, C.c_int64, dp, C.POINTER(C.c_uint8)]
+        L.orc_qdiff.argtypes = [P, C.c_int64, dp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint8)]
         L.orc_qdiff.restype = C.c_double
         L.orc_run.argtypes = [P, C.c_int64, dp, dp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint8),
                               dp, dp, C.c_int64, C.c_int64, dp]
@@ -167,11 +170,15 @@ def ion_field(p: Params, r: float) -> tuple:
     return e, phi.value
 
 
-def qdiff(p: Params, pos, alive=None) -> float:
+def qdiff(p: Params, pos, alive=None, ids=None) -> float:
     pos = _f64(pos)
     al = _alive_arr(alive, pos.shape[0])
+    idp = None
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, np.uint32)
+        idp = ids.ctypes.data_as(C.POINTER(C.c_uint32))
     pc = p._c()
-    return lib().orc_qdiff(C.byref(pc), pos.shape[0], _dp(pos),
+    return lib().orc_qdiff(C.byref(pc), pos.shape[0], _dp(pos), idp,
                            al.ctypes.data_as(C.POINTER(C.c_uint8)))
 
 

@@ -39,9 +39,11 @@
 
 #define ORC_PI 3.14159265358979323846
 
-/* Electrons: charge -1 (units of e), mass 1 (units of m_e), Sec. 4. */
+/* Electrons: charge -1 (units of e), mass 1 (units of m_e), Sec. 4.  A
+ * particle whose id has bit 31 set is an ion: charge +1, mass ion_mass. */
 #define ORC_Q (-1.0)
 #define ORC_M (1.0)
+#define ORC_ION_BIT 0x80000000u
 
 enum { ORC_M_FULL = 0, ORC_M_AXISYM = 1 };
 enum { ORC_BC_ABSORB = 0, ORC_BC_SPECULAR = 1, ORC_BC_DIFFUSE = 2 };
@@ -63,7 +65,15 @@ typedef struct {
      * linear in between. */
     const double *ion_prof;
     int64_t ion_prof_len;
+    double ion_mass;     /* m_i / m_e of particles whose id has bit 31 set */
 } orc_params;
+
+static double charge_of(uint32_t id) { return (id & ORC_ION_BIT) ? 1.0 : ORC_Q; }
+
+static double mass_of(const orc_params *p, uint32_t id)
+{
+    return (id & ORC_ION_BIT) ? p->ion_mass : ORC_M;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Coefficients                                                              */
@@ -367,8 +377,9 @@ int orc_field(const orc_params *p, int64_t n, const double *pos, const uint32_t 
             int k_outer = key_less(key_r2(xi), ids[i], r2k, ids[k]);
             double G, g[3];
             greens(p, f, xk, xi, k_outer, &G, g);
-            phi += ORC_Q * G;
-            for (int j = 0; j < 3; ++j) gsum[j] += ORC_Q * g[j];
+            const double qi = charge_of(ids[i]);
+            phi += qi * G;
+            for (int j = 0; j < 3; ++j) gsum[j] += qi * g[j];
         }
         double rk = sqrt(r2k);
         double xh[3] = {xk[0] / rk, xk[1] / rk, xk[2] / rk};
@@ -389,7 +400,8 @@ int orc_field(const orc_params *p, int64_t n, const double *pos, const uint32_t 
 }
 
 /* Q_diff = -(1/nt) sum_i q_i Psi_anti,L(x_i)  (Sec. 4, truncated to odd l <= L). */
-double orc_qdiff(const orc_params *p, int64_t n, const double *pos, const uint8_t *alive)
+double orc_qdiff(const orc_params *p, int64_t n, const double *pos, const uint32_t *ids,
+                 const uint8_t *alive)
 {
     double f[ORC_LMAX_CAP + 1], bP[ORC_LMAX_CAP + 1], c[ORC_LMAX_CAP + 1];
     orc_coeffs(p->eps_r, p->d, p->l_max, f, bP, c);
@@ -398,7 +410,7 @@ double orc_qdiff(const orc_params *p, int64_t n, const double *pos, const uint8_
         if (alive && !alive[i]) continue;
         double psi;
         psi_anti(p, bP, c, pos + 3 * i, &psi, NULL);
-        s += ORC_Q * psi;
+        s += (ids ? charge_of(ids[i]) : ORC_Q) * psi;
     }
     return -s / p->ntilde;
 }
@@ -480,20 +492,21 @@ int64_t orc_step(const orc_params *p, int64_t n, double *pos, double *vel, const
                  uint8_t *alive, double *q_surface, double u_asy, int64_t step,
                  double *qdiff_out, double *E_scratch)
 {
-    *qdiff_out = orc_qdiff(p, n, pos, alive);
+    *qdiff_out = orc_qdiff(p, n, pos, ids, alive);
     orc_field(p, n, pos, ids, alive, *q_surface, u_asy, 0, NULL, E_scratch, NULL);
     int64_t absorbed = 0;
     for (int64_t k = 0; k < n; ++k) {
         if (alive && !alive[k]) continue;
         double *x = pos + 3 * k, *v = vel + 3 * k;
         const double *E = E_scratch + 3 * k;
-        for (int j = 0; j < 3; ++j) v[j] = v[j] + (ORC_Q / ORC_M) * E[j] * p->dt;
+        const double qk = charge_of(ids[k]), qm = qk / mass_of(p, ids[k]);
+        for (int j = 0; j < 3; ++j) v[j] = v[j] + qm * E[j] * p->dt;
         for (int j = 0; j < 3; ++j) x[j] = x[j] + v[j] * p->dt;
         double r = sqrt(key_r2(x));
         if (r <= 1.0) {
             if (p->probe_bc == ORC_BC_ABSORB) {
                 alive[k] = 0;
-                *q_surface += ORC_Q;
+                *q_surface += qk;
                 ++absorbed;
             } else {
                 double s = (2.0 - r) / r;
@@ -566,9 +579,10 @@ double orc_energy(const orc_params *p, int64_t n, const double *pos, const doubl
         double pair = phi[k] - phi_ion(p, r);   /* phi was built with Q_S = u = 0 */
         double psi;
         psi_anti(p, bP, c, pos + 3 * k, &psi, NULL);
-        ke += 0.5 * ORC_M * v2[k];
-        pe += 0.5 * ORC_Q * pair +
-              ORC_Q * (q_surface / (p->ntilde * 4.0 * ORC_PI * r) + phi_ion(p, r) + u_asy * psi);
+        const double qk = charge_of(ids[k]);
+        ke += 0.5 * mass_of(p, ids[k]) * v2[k];
+        pe += 0.5 * qk * pair +
+              qk * (q_surface / (p->ntilde * 4.0 * ORC_PI * r) + phi_ion(p, r) + u_asy * psi);
     }
     free(phi);
     free(E);

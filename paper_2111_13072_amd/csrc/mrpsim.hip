@@ -43,6 +43,8 @@ namespace {
 
 constexpr double kQ = -1.0;   // electron charge, units of e (Sec. 4)
 constexpr double kM = 1.0;    // electron mass, units of m_e
+// A particle whose id has this bit set is an ion: charge +1, mass ion_mass.
+constexpr uint32_t kIonBit = 0x80000000u;
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
@@ -75,7 +77,7 @@ struct Ctl {
     uint32_t n_cur;     // records in A (some may be flagged absorbed)
     uint32_t n_live;    // alive particles sorted into B this step
     uint32_t n_dead;    // particles absorbed so far (graveyard fill)
-    uint32_t pad;
+    uint32_t n_dead_ion;  // of which ions
     double q_surface;   // Q_S used by this step's field
 };
 
@@ -96,6 +98,7 @@ struct Seg {
     // to r_out, then the enclosed ion charge at those radii (super-particle units)
     const double *ion_tab;
     double ion_h, ion_inv_h;
+    double ion_qm;      // charge / mass of ion particles (+1 / ion_mass)
     int32_t ion_k;
     int32_t used;
 };
@@ -134,6 +137,7 @@ struct KParams {
     int L;          // l_max
     int C;          // channels: (L+1)^2 - 1 (full) or L (axisymmetric)
     int C2;         // 2C: interior then exterior
+    int SW;         // C2 + 1: tile sums also carry the tile's total charge
     int n_tiles;    // tile capacity (particle slots / 64)
     int n_chunks;   // chunk capacity
     int nb;         // bucket capacity
@@ -371,8 +375,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(const uint32_t *in, const uin
 }
 
 // Per member: alive count (its buckets' share of the global offsets) and the
-// surface charge Q_S = q_surface0 + q * (absorbed so far), which enters the
-// field as an interior l = 0 charge (Q_S / (4 pi r), Sec. 3).
+// surface charge Q_S = q_surface0 + the charge absorbed so far, which enters
+// the field as an interior l = 0 charge (Q_S / (4 pi r), Sec. 3).
 __global__ void k_member_live(Map mp, const uint32_t *off, KParams kp)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -381,7 +385,7 @@ __global__ void k_member_live(Map mp, const uint32_t *off, KParams kp)
     Ctl &c = mp.ctl[s];
     if (!member_runs(sg, c, kp)) return;
     c.n_live = off[sg.b0 + sg.nb] - off[sg.b0];
-    c.q_surface = sg.q_surface0 + kQ * (double)c.n_dead;
+    c.q_surface = (sg.q_surface0 + kQ * (double)(c.n_dead - c.n_dead_ion)) + (double)c.n_dead_ion;
 }
 
 // Bucket order (arbitrary inside a bucket): key, id and source index.
@@ -519,19 +523,26 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     const uint32_t p = tile * kWave + lane;
     const bool valid = tile_ok && lt * kWave + lane < n;
     double x = 0.0, y = 0.0, z = 2.0;
+    bool ion = false;
     if (valid) {
         x = B.x[p];
         y = B.y[p];
         z = B.z[p];
+        ion = (B.uid[p] & kIonBit) != 0;
     }
-    const double q = valid ? kQ : 0.0;
+    const double q = valid ? (ion ? 1.0 : kQ) : 0.0;
     const double r2 = x * x + y * y + z * z;
     const double inv_r2 = 1.0 / r2;
     const double inv_r = 1.0 / sqrt(r2);
     const int L = kp.L;
     const int C = kp.C;
     const int m_top = FULL ? L : 0;
-    double *St = S + (size_t)tile * kp.C2;
+    double *St = S + (size_t)tile * kp.SW;
+    {
+        // the tile's total charge (exact: a count of ions and electrons)
+        const int n_val = __popcll(__ballot(valid)), n_ion = __popcll(__ballot(valid && ion));
+        if (tile_ok && lane == 0) St[kp.C2] = (double)n_ion + kQ * (double)(n_val - n_ion);
+    }
     if (kp.fp32 && tile_ok && lane == 0) {
         // reference radius of the tile for the FP32 field: its first particle
         double rho = 1.0;
@@ -631,19 +642,19 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(Map mp, const double *S, 
                                                        KParams kp)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
-    if (c >= kp.C2) return;
+    if (c >= kp.SW) return;
     const int j = blockIdx.x;
     uint32_t mb;
     int t0, t1;
     if (!chunk_tiles(mp, kp, j, &mb, &t0, &t1)) return;
     double s = 0.0;
-    for (int t = t0; t < t1; ++t) s += S[(size_t)t * kp.C2 + c];
-    chunkS[(size_t)j * kp.C2 + c] = s;
+    for (int t = t0; t < t1; ++t) s += S[(size_t)t * kp.SW + c];
+    chunkS[(size_t)j * kp.SW + c] = s;
 }
 
 // Per member (blockIdx.y) and channel (one wave each): exclusive prefix of the
-// interior chunk sums, exclusive suffix of the exterior ones, and the totals
-// T_lm.  The member's chunks, in scan order, are cut into 64 consecutive runs,
+// interior chunk sums and of the charge column, exclusive suffix of the
+// exterior ones, and the totals T_lm.  The member's chunks, in scan order, are cut into 64 consecutive runs,
 // one per lane: each lane sums its run, the wave scans the run sums, and each
 // lane then writes its run's carries.
 __global__ __launch_bounds__(kBlock) void k_chunk_scan(Map mp, const double *chunkS,
@@ -652,18 +663,18 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(Map mp, const double *chu
     const int lane = threadIdx.x & 63;
     const int c = (int)uniform_u32(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
     const int s = blockIdx.y;
-    if (c >= kp.C2) return;
+    if (c >= kp.SW) return;
     const Seg &sg = mp.seg[s];
     if (!member_runs(sg, mp.ctl[s], kp)) return;
     const int nc = (int)sg.nc;
-    const bool interior = c < kp.C;
-    const double *cS = chunkS + (size_t)sg.c0 * kp.C2 + c;
-    double *cC = chunkC + (size_t)sg.c0 * kp.C2 + c;
+    const bool interior = c < kp.C || c == kp.C2;
+    const double *cS = chunkS + (size_t)sg.c0 * kp.SW + c;
+    double *cC = chunkC + (size_t)sg.c0 * kp.SW + c;
     const int per = (nc + kWave - 1) / kWave;
     const int q0 = lane * per, q1 = min(q0 + per, nc);   // this lane's run in scan order
     auto chunk = [&](int q) { return interior ? q : nc - 1 - q; };
     double part = 0.0;
-    for (int q = q0; q < q1; ++q) part += cS[(size_t)chunk(q) * kp.C2];
+    for (int q = q0; q < q1; ++q) part += cS[(size_t)chunk(q) * kp.SW];
     double incl = part;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -673,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(Map mp, const double *chu
     double run = __shfl_up(incl, 1);
     if (lane == 0) run = 0.0;
     for (int q = q0; q < q1; ++q) {
-        const size_t at = (size_t)chunk(q) * kp.C2;
+        const size_t at = (size_t)chunk(q) * kp.SW;
         cC[at] = run;
         run += cS[at];
     }
@@ -713,17 +724,22 @@ __global__ __launch_bounds__(kBlock) void k_coef_prep(Map mp, const double *T, T
 __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *S,
                                                         const double *chunkC, const double *Kc,
                                                         Tables tb, KParams kp, const double *lgrho,
-                                                        double *coef, float *coef32)
+                                                        double *coef, float *coef32, double *qpre)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
-    if (c >= kp.C2) return;
+    if (c >= kp.SW) return;
     const int j = blockIdx.x;
     uint32_t mb;
     int t0, t1;
     if (!chunk_tiles(mp, kp, j, &mb, &t0, &t1)) return;
     const double inv_nt = mp.seg[mb].inv_ntilde;
-    double run = chunkC[(size_t)j * kp.C2 + c];
-    if (c < kp.C) {
+    double run = chunkC[(size_t)j * kp.SW + c];
+    if (c == kp.C2) {   // charge of the member's particles before each tile
+        for (int t = t0; t < t1; ++t) {
+            qpre[t] = run;
+            run += S[(size_t)t * kp.SW + c];
+        }
+    } else if (c < kp.C) {
         const int l = tb.chl[c];
         const double w = tb.wl[l] * inv_nt;
         const double k = Kc[(size_t)mb * kp.C + c];
@@ -731,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *S,
             const double v = run * w + k;
             if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2(-(l + 1.0) * lgrho[t]));
             else coef[(size_t)t * kp.C2 + c] = v;
-            run += S[(size_t)t * kp.C2 + c];
+            run += S[(size_t)t * kp.SW + c];
         }
     } else {
         const int l = tb.chl[c - kp.C];
@@ -740,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *S,
             const double v = run * w;
             if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2((double)l * lgrho[t]));
             else coef[(size_t)t * kp.C2 + c] = v;
-            run += S[(size_t)t * kp.C2 + c];
+            run += S[(size_t)t * kp.SW + c];
         }
     }
 }
@@ -898,12 +914,14 @@ __device__ inline void far_field(const R *cf, int C, int L,
 // where v = xh_other - u xh (full) or e_z - cos(th) xh (axisymmetric).  The
 // three sums are symmetric in (k, j), so each pair is evaluated once: at step
 // s lane k takes partner (k + s) mod 64 and hands the partner's gradient to it
-// through a lane rotation.  Pair terms in R, accumulated in FP64.
+// through a lane rotation.  Each term carries the charge of its source (the
+// other particle of the pair).  Pair terms in R, accumulated in FP64.
 template <bool FULL, typename R, typename NF>
 __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R *sxh, const R *syh,
                                   const R *szh, const R *sr, const R *sir, const double *sr2,
-                                  const uint32_t *suid, R xh, R yh, R zh, R r, R inv_r, double r2,
-                                  uint32_t uid, double &ax, double &ay, double &az)
+                                  const uint32_t *suid, const R *sq, R xh, R yh, R zh, R r,
+                                  R inv_r, double r2, uint32_t uid, R qk, double &ax, double &ay,
+                                  double &az)
 {
     const R inv_r2 = inv_r * inv_r;
     for (int sft = 1; sft <= kWave / 2; ++sft) {
@@ -913,6 +931,7 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
         const R rj = sr[j], irj = sir[j];
         const double r2j = sr2[j];
         const uint32_t uj = suid[j];
+        const R qj = sq[j];
         const bool k_outer = (r2 > r2j) || (r2 == r2j && uid > uj);
         const R rho = k_outer ? rj * inv_r : r * irj;
         const R sc_out = k_outer ? inv_r2 : irj * irj;   // 1 / r_>^2
@@ -954,8 +973,8 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
         }
         if (FULL) SBj = SBk;
         const R S_out = -(Sl + S1), S_in = Sl;
-        const R SAk = k_outer ? S_out : S_in, sck = k_outer ? sc_out : sc_in;
-        const R SAj = k_outer ? S_in : S_out, scj = k_outer ? sc_in : sc_out;
+        const R SAk = k_outer ? S_out : S_in, sck = qj * (k_outer ? sc_out : sc_in);
+        const R SAj = k_outer ? S_in : S_out, scj = qk * (k_outer ? sc_in : sc_out);
         R vkx, vky, vkz, vjx, vjy, vjz;
         if (FULL) {
             vkx = xj - u * xh; vky = yj - u * yh; vkz = zj - u * zh;
@@ -986,8 +1005,9 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
 template <bool FULL, bool FIELD_ONLY, bool FP32>
 __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A, uint8_t *dead,
                                                        Grave G, const double *coef,
-                                                       const float *coef32, Tables tb, KParams kp,
-                                                       double *Eout, uint32_t *Eid)
+                                                       const float *coef32, const double *qpre,
+                                                       Tables tb, KParams kp, double *Eout,
+                                                       uint32_t *Eid)
 {
     using R = typename std::conditional<FP32, float, double>::type;
     using NF = typename std::conditional<FP32, float4, double4>::type;
@@ -995,6 +1015,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
         sh_zh[kWavesPerBlock][kWave], sh_r[kWavesPerBlock][kWave], sh_ir[kWavesPerBlock][kWave];
     __shared__ double sh_r2[kWavesPerBlock][kWave];
     __shared__ uint32_t sh_uid[kWavesPerBlock][kWave];
+    __shared__ R sh_q[kWavesPerBlock][kWave];
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -1039,6 +1060,9 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
     sh_ir[w][lane] = (R)inv_r;
     sh_r2[w][lane] = r2;
     sh_uid[w][lane] = uid;
+    const bool ion = valid && (uid & kIonBit);
+    const double qk = ion ? 1.0 : kQ;   // this particle's charge
+    sh_q[w][lane] = valid ? (R)qk : (R)0;
     wave_lds_sync();   // the rows are this wave's own
     if (!tile_live) return;
 
@@ -1072,16 +1096,16 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
         Ez = -(double)gz * inv_rho;
     }
 
-    // ---- near field (own tile); E += -(q / (4 pi nt)) grad D ----
+    // ---- near field (own tile); E += -(1 / (4 pi nt)) sum_j q_j grad D ----
     {
         double ax = 0.0, ay = 0.0, az = 0.0;
         const NF *nf;
         if constexpr (FP32) nf = tb.nf4_32;
         else nf = tb.nf4;
         near_field<FULL, R, NF>(lane, jn, L, nf, sh_xh[w], sh_yh[w], sh_zh[w], sh_r[w], sh_ir[w],
-                                sh_r2[w], sh_uid[w], (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
-                                ax, ay, az);
-        const double cn = -kQ / (4.0 * kPi * ntilde);
+                                sh_r2[w], sh_uid[w], sh_q[w], (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r,
+                                r2, uid, (R)qk, ax, ay, az);
+        const double cn = -1.0 / (4.0 * kPi * ntilde);
         Ex += cn * ax;
         Ey += cn * ay;
         Ez += cn * az;
@@ -1098,7 +1122,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
                 rl *= inv_r2;
             }
             // grad Phi_self = -q sum f_l (l+1)/(4 pi nt) r^-(2l+3) xh; E = -grad
-            const double e = kQ * inv_nt * sr;
+            const double e = qk * inv_nt * sr;
             Ex += e * xh;
             Ey += e * yh;
             Ez += e * zh;
@@ -1116,7 +1140,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
                 rl *= inv_r2;
             }
             // grad Phi_selfcorr = q sum (f_l/(4 pi nt)) r^-(2l+3) P_l [-(l+1) P_l xh + P'_l (e_z - c xh)]
-            const double qn = kQ * inv_nt;
+            const double qn = qk * inv_nt;
             const double gx = qn * (sr * xh + sz * (-zh * xh));
             const double gy = qn * (sr * yh + sz * (-zh * yh));
             const double gz = qn * (sr * zh + sz * (1.0 - zh * zh));
@@ -1127,12 +1151,17 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
     }
 
     // ---- l = 0: Gauss's law.  The l = 0 part of G~ is 1/(4 pi r_>), so only
-    // the charge enclosed by r_k pushes: Q_S, the p particles before k in the
-    // radial order (p is the sorted position) and the ion background
-    // nt n_i (4 pi / 3)(r^3 - 1), all in super-particle units. ----
+    // the charge enclosed by r_k pushes: Q_S, the particles before k in the
+    // radial order (those of earlier tiles, carried by the scan, and the
+    // lanes below in this tile) and the immobile ion background, all exact
+    // counts in super-particle units. ----
     {
+        const uint64_t below = (1ull << lane) - 1ull;
+        const int n_below = __popcll(__ballot(valid) & below);
+        const int i_below = __popcll(__ballot(ion) & below);
+        const double before = qpre[tile] + ((double)i_below + kQ * (double)(n_below - i_below));
         const double ions = ion_enclosed(sg, r, r2);
-        const double enclosed = (ct.q_surface + kQ * (double)pl) + ions;
+        const double enclosed = (ct.q_surface + before) + ions;
         const double e = enclosed / (4.0 * kPi * ntilde * r2);
         Ex += e * xh;
         Ey += e * yh;
@@ -1151,7 +1180,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
     if (!valid) return;
 
     // ---- leapfrog (Sec. 4 equations of motion) ----
-    const double qm = kQ / kM;
+    const double qm = ion ? sg.ion_qm : kQ / kM;
     const double dt = sg.dt;
     vx = __dadd_rn(vx, __dmul_rn(qm * Ex, dt));
     vy = __dadd_rn(vy, __dmul_rn(qm * Ey, dt));
@@ -1209,6 +1238,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
     A.uid[p] = uid;
     dead[p] = absorbed;
     if (absorbed) {
+        if (ion) atomicAdd(&ct.n_dead_ion, 1u);
         const uint32_t slot = sg.p0 + atomicAdd(&ct.n_dead, 1u);
         G.x[slot] = x;
         G.y[slot] = y;
@@ -1314,6 +1344,7 @@ bool check_member_scalars(const sim_member *m, std::string *why)
         return false;
     }
     if (!std::isfinite(m->q_surface0)) { *why = "q_surface0 must be finite"; return false; }
+    if (!(m->ion_mass >= 0.0) || !std::isfinite(m->ion_mass)) { *why = "ion_mass must be >= 0"; return false; }
     if (m->ion_profile && (m->ion_profile_len < 2 || m->ion_profile_len > (1 << 24))) {
         *why = "ion_profile_len must be in [2, 2^24]";
         return false;
@@ -1430,7 +1461,7 @@ struct sim {
     uint32_t *bkt = nullptr, *sub = nullptr, *tuid = nullptr, *tidx = nullptr, *tbkt = nullptr,
              *hist = nullptr, *off = nullptr, *bsum = nullptr;
     double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr, *Kc = nullptr,
-           *coef = nullptr, *tables = nullptr, *Eout = nullptr;
+           *coef = nullptr, *tables = nullptr, *Eout = nullptr, *qpre = nullptr;
     int *chl = nullptr;
     float *coef32 = nullptr, *tables32 = nullptr;
     double *lgrho = nullptr;
@@ -1509,7 +1540,8 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->hist, (size_t)lo.nb + 1);
     al.add(&h->off, (size_t)lo.nb + 1);
     al.add(&h->bsum, (size_t)lo.nb_blocks + 1);
-    al.add(&h->S, (size_t)lo.n_tiles * lo.C2);
+    al.add(&h->S, (size_t)lo.n_tiles * (lo.C2 + 1));
+    al.add(&h->qpre, (size_t)lo.n_tiles);
     if (lo.fp32) {
         al.add(&h->coef32, (size_t)lo.n_tiles * lo.C2);
         al.add(&h->lgrho, (size_t)lo.n_tiles);
@@ -1520,8 +1552,8 @@ void plan_alloc(sim *h, Alloc &al)
         al.add(&h->lgrho, 1);
     }
     al.add(&h->tables32, tables32_len(lo.L));
-    al.add(&h->chunkS, (size_t)lo.n_chunks * lo.C2);
-    al.add(&h->chunkC, (size_t)lo.n_chunks * lo.C2);
+    al.add(&h->chunkS, (size_t)lo.n_chunks * (lo.C2 + 1));
+    al.add(&h->chunkC, (size_t)lo.n_chunks * (lo.C2 + 1));
     al.add(&h->T, (size_t)lo.n_members * std::max(lo.C, 1));
     al.add(&h->Kc, (size_t)lo.n_members * std::max(lo.C, 1));
     al.add(&h->tables, tables_len(lo.L));
@@ -1611,7 +1643,7 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     const unsigned n = (unsigned)ex.n_tiles * kWave;
     const unsigned gN = (n + kBlock - 1) / kBlock;
     const unsigned gT = (unsigned)((ex.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
-    const unsigned gC = (unsigned)((lo.C2 + kBlock - 1) / kBlock);
+    const unsigned gC = (unsigned)((lo.C2 + 1 + kBlock - 1) / kBlock);   // tile-sum columns
     const unsigned gM = (unsigned)((ex.n_members + kBlock - 1) / kBlock);
     int e = 0;
     auto mark = [&](int k) {
@@ -1636,26 +1668,23 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     k_sort_rank_move<<<gN, kBlock, 0, s>>>(mp, h->tkey, h->tuid, h->tidx, h->tbkt, h->off, h->A,
                                            h->B, kp);
     mark(KN_MOMENTS);
-    if (lo.C > 0) {
-        if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
-        else k_moments<false><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
-    }
+    if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
+    else k_moments<false><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
     mark(KN_CHUNK_SUMS);
-    if (lo.C > 0) k_chunk_sums<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkS, kp);
+    k_chunk_sums<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkS, kp);
     mark(KN_CHUNK_SCAN);
-    if (lo.C > 0)
-        k_chunk_scan<<<dim3((lo.C2 + kWavesPerBlock - 1) / kWavesPerBlock, ex.n_members), kBlock, 0, s>>>(
-            mp, h->chunkS, h->chunkC, h->T, kp);
+    k_chunk_scan<<<dim3((lo.C2 + 1 + kWavesPerBlock - 1) / kWavesPerBlock, ex.n_members), kBlock, 0,
+                   s>>>(mp, h->chunkS, h->chunkC, h->T, kp);
     mark(KN_COEF_PREP);
     k_coef_prep<<<ex.n_members, kBlock, 0, s>>>(mp, h->T, h->tb, kp, h->Kc);
     mark(KN_CHUNK_APPLY);
-    if (lo.C > 0)
-        k_chunk_apply<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkC, h->Kc, h->tb,
-                                                               kp, h->lgrho, h->coef, h->coef32);
+    k_chunk_apply<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkC, h->Kc, h->tb, kp,
+                                                           h->lgrho, h->coef, h->coef32, h->qpre);
     mark(KN_FIELD_PUSH);
 #define MRP_FIELD(FULLV, FO, F32)                                                              \
     k_field_push<FULLV, FO, F32><<<gT, kBlock, 0, s>>>(mp, h->B, h->A, h->dead, h->G, h->coef, \
-                                                       h->coef32, h->tb, kp, h->Eout, h->Eid)
+                                                       h->coef32, h->qpre, h->tb, kp, h->Eout,  \
+                                                       h->Eid)
 #define MRP_FIELD_P(FULLV, FO) \
     do { if (lo.fp32) MRP_FIELD(FULLV, FO, true); else MRP_FIELD(FULLV, FO, false); } while (0)
     if (field_only) {
@@ -1790,6 +1819,7 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
     kp.L = lo.L;
     kp.C = lo.C;
     kp.C2 = lo.C2;
+    kp.SW = lo.C2 + 1;
     kp.n_tiles = lo.n_tiles;
     kp.n_chunks = lo.n_chunks;
     kp.nb = lo.nb;
@@ -1886,6 +1916,9 @@ int prepare_member(const sim_member *m, Prepared *pr)
                 return fail(SIM_EINVAL, "ion_profile values must be finite and >= 0");
     pr->uid.resize((size_t)n);
     for (int64_t i = 0; i < n; ++i) pr->uid[i] = m->ids ? m->ids[i] : (uint32_t)i;
+    if (!(m->ion_mass > 0.0))
+        for (int64_t i = 0; i < n; ++i)
+            if (pr->uid[i] & kIonBit) return fail(SIM_EINVAL, "ion ids (bit 31) need ion_mass > 0");
     pr->idx.resize((size_t)n);
     for (int64_t i = 0; i < n; ++i) pr->idx[i] = {pr->uid[i], i};
     std::sort(pr->idx.begin(), pr->idx.end());
@@ -1946,6 +1979,7 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     sg.probe_bc = m->probe_bc;
     sg.wall_bc = m->wall_bc;
     sg.n_steps = m->n_steps;
+    sg.ion_qm = m->ion_mass > 0.0 ? 1.0 / m->ion_mass : 0.0;
     sg.used = 1;
     auto undo = [&](int code) {
         free_member_arrays(mb);
@@ -2359,7 +2393,9 @@ int sim_member_read_state(sim_t *h, int32_t index, double *pos, double *vel, uin
         put(k, a, i);
         if (alive) alive[k] = 1;
     }
-    if (q_surface) *q_surface = mb.q_surface0 + kQ * (double)ctl.n_dead;
+    if (q_surface)
+        *q_surface = (mb.q_surface0 + kQ * (double)(ctl.n_dead - ctl.n_dead_ion)) +
+                     (double)ctl.n_dead_ion;
     if (step) *step = ctl.step;
     return SIM_OK;
 }

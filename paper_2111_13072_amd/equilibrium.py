@@ -153,31 +153,82 @@ def sample_electrons(eq: Equilibrium, n: int, seed: int, r_out: float, v_th: flo
     return ParticleState(pos=pos, vel=vel, ids=np.arange(n, dtype=np.uint32))
 
 
+def _radial_cdf(density, r_out: float, grid: int):
+    rg = np.linspace(1.0, r_out, grid)
+    w = density(rg) * rg ** 2
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (w[1:] + w[:-1]) * np.diff(rg))])
+    return rg, cdf
+
+
 def electron_count_density(eq: Equilibrium, r_out: float, grid: int = 200001) -> float:
     """4 pi int_1^r_out n_e r^2 dr: electrons (in n_inf R^3) between the walls."""
-    rg = np.linspace(1.0, r_out, grid)
-    w = eq.n_e(rg) * rg ** 2
-    return float(4.0 * np.pi * np.sum(0.5 * (w[1:] + w[:-1]) * np.diff(rg)))
+    _, cdf = _radial_cdf(eq.n_e, r_out, grid)
+    return float(4.0 * np.pi * cdf[-1])
+
+
+def ion_count_density(eq: Equilibrium, r_out: float, grid: int = 200001) -> float:
+    """4 pi int_1^r_out n_i r^2 dr: ions (in n_inf R^3) between the walls."""
+    _, cdf = _radial_cdf(eq.n_i, r_out, grid)
+    return float(4.0 * np.pi * cdf[-1])
+
+
+ION_ID_BIT = np.uint32(0x80000000)
+
+
+def sample_ions(eq: Equilibrium, n: int, seed: int, r_out: float, id_offset: int = 0,
+                grid: int = 200001) -> ParticleState:
+    """n ions with radial density n_i(r) 4 pi r^2 on (1, r_out), isotropic
+    directions and the cold radial inflow of App. D: speed
+    sqrt(-2 psi) c_s toward the probe, c_s = Lambda sqrt(m_e/m_i) in units of
+    R omega_pe.  Ids id_offset.. with bit 31 set (the ion marker).  Draw
+    order: U_r, U_c, U_phi [n]."""
+    rg, cdf = _radial_cdf(eq.n_i, r_out, grid)
+    cdf /= cdf[-1]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ur, uc, uphi = rng.random(n), rng.random(n), rng.random(n)
+    r = np.clip(np.interp(ur, cdf, rg), np.nextafter(1.0, 2.0), np.nextafter(r_out, 0.0))
+    ct = 2.0 * uc - 1.0
+    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+    ph = 2.0 * np.pi * uphi
+    rhat = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=1)
+    c_s = eq.debye / math.sqrt(eq.mass_ratio)
+    speed = np.sqrt(-2.0 * eq.psi(r)) * c_s
+    ids = (np.arange(n, dtype=np.uint32) + np.uint32(id_offset)) | ION_ID_BIT
+    return ParticleState(pos=r[:, None] * rhat, vel=-speed[:, None] * rhat, ids=ids)
 
 
 @dataclass
 class PaperSetup:
     """The paper's own workload (Sec. 4 with App. D): the floating
     equilibrium between the probe and r_out = 10 at n_inf = 1e15 m^-3,
-    T_e = 3 eV, diffuse walls, dt = 0.01, impulse drive."""
-    n: int = 500_000          # electrons (the paper's 1e6 super-particles count ions too)
+    T_e = 3 eV, diffuse walls, dt = 0.01, impulse drive; n super-particles
+    in total, electrons and mobile ions in the equilibrium's proportion
+    (or, with mobile_ions False, n electrons over an immobile ion profile)."""
+    n: int = 1_000_000
     seed: int = 6
     n_e: float = 1e15
     t_e_ev: float = 3.0
     r_out: float = 10.0
     dt: float = 0.01
     probe_radius_m: float = 4e-3
+    mobile_ions: bool = True
 
     def build(self):
         """(equilibrium, particles, ntilde, q_surface0 in super-particle units,
-        ion profile)."""
+        ion profile or None)."""
         sc = PlasmaScales(self.n_e, self.t_e_ev, self.probe_radius_m)
         eq = solve_floating_equilibrium(sc.v_th)
-        st = sample_electrons(eq, self.n, self.seed, self.r_out, sc.v_th)
-        ntilde = self.n / electron_count_density(eq, self.r_out)
-        return eq, st, ntilde, eq.surface_charge * ntilde, eq.ion_profile(self.r_out)
+        ne = electron_count_density(eq, self.r_out)
+        if not self.mobile_ions:
+            st = sample_electrons(eq, self.n, self.seed, self.r_out, sc.v_th)
+            ntilde = self.n / ne
+            return eq, st, ntilde, eq.surface_charge * ntilde, eq.ion_profile(self.r_out)
+        ni = ion_count_density(eq, self.r_out)
+        ntilde = self.n / (ne + ni)
+        n_el = int(round(ntilde * ne))
+        el = sample_electrons(eq, n_el, self.seed, self.r_out, sc.v_th)
+        io = sample_ions(eq, self.n - n_el, self.seed + 1, self.r_out, id_offset=n_el)
+        st = ParticleState(pos=np.concatenate([el.pos, io.pos]),
+                           vel=np.concatenate([el.vel, io.vel]),
+                           ids=np.concatenate([el.ids, io.ids]))
+        return eq, st, ntilde, eq.surface_charge * ntilde, None

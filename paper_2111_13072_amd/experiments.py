@@ -36,18 +36,21 @@ class ProbeResponse:
     k: float
 
 
-def probe_response(t_e_ev: float, steps: int = 10000, l_max: int = 1, n: int = 500_000,
-                   seed: int = 6, fit_window: float = 30.0, precision: int = S.SIM_FP64):
+def probe_response(t_e_ev: float, steps: int = 10000, l_max: int = 1, n: int = 1_000_000,
+                   seed: int = 6, fit_window: float = 30.0, precision: int = S.SIM_FP64,
+                   mobile_ions: bool = True):
     """Returns (ProbeResponse, t, Q_diff driven - undriven)."""
-    ps = EQ.PaperSetup(n=n, seed=seed, t_e_ev=t_e_ev)
+    ps = EQ.PaperSetup(n=n, seed=seed, t_e_ev=t_e_ev, mobile_ions=mobile_ions)
     eq, st, ntilde, q_s, prof = ps.build()
     mode = S.SIM_M_AXISYM if l_max == 1 else S.SIM_M_FULL
     out = []
     for drive in (True, False):
         u = W.impulse_drive(steps, 1.0) if drive else np.zeros(steps)
-        mb = S.Member(pos=st.pos, vel=st.vel, u_asy=u, ntilde=ntilde, r_out=ps.r_out, dt=ps.dt,
-                      q_surface0=q_s, probe_bc=S.SIM_BC_DIFFUSE, wall_bc=S.SIM_BC_DIFFUSE,
-                      seed=seed, ion_profile=prof)
+        mb = S.Member(pos=st.pos, vel=st.vel, u_asy=u, ntilde=ntilde, ids=st.ids, r_out=ps.r_out,
+                      dt=ps.dt, q_surface0=q_s, probe_bc=S.SIM_BC_DIFFUSE,
+                      wall_bc=S.SIM_BC_DIFFUSE, seed=seed, ion_profile=prof,
+                      ion_density=0.0 if mobile_ions else 1.0,
+                      ion_mass=eq.mass_ratio if mobile_ions else 0.0)
         with S.Batch(S.SimParams(l_max=l_max, m_mode=mode, precision=precision), [mb]) as b:
             b.step(steps)
             out.append(b.read_response(0, 0, steps))
@@ -70,10 +73,13 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--l-max", type=int, default=1)
     ap.add_argument("--temperatures", default="2,3,5")
+    ap.add_argument("--immobile-ions", action="store_true",
+                    help="electrons over the equilibrium's ion profile instead of mobile ions")
     args = ap.parse_args(argv)
     rows = []
     for te in [float(x) for x in args.temperatures.split(",")]:
-        res, _, _ = probe_response(te, args.steps, args.l_max)
+        res, _, _ = probe_response(te, args.steps, args.l_max,
+                                   mobile_ions=not args.immobile_ions)
         rows.append(asdict(res))
         print(json.dumps(rows[-1]), flush=True)
     ks = [r["k"] for r in rows]

@@ -50,6 +50,7 @@ class sim_member(C.Structure):
         ("r_out", C.c_double), ("dt", C.c_double), ("seed", C.c_uint64),
         ("probe_bc", C.c_int32), ("wall_bc", C.c_int32),
         ("ion_profile", C.POINTER(C.c_double)), ("ion_profile_len", C.c_int64),
+        ("ion_mass", C.c_double),
     ]
 
 
@@ -294,6 +295,7 @@ class Member:
     probe_bc: int = SIM_BC_ABSORB
     wall_bc: int = SIM_BC_SPECULAR
     ion_profile: np.ndarray | None = None   # densities at equally spaced radii 1..r_out
+    ion_mass: float = 0.0                   # m_i / m_e of ids with bit 31 set (mobile ions)
 
     @staticmethod
     def from_params(params: SimParams, pos, vel, u_asy, ids=None, start_step: int = 0) -> "Member":
@@ -321,7 +323,7 @@ class Member:
         m.n_steps = u.shape[0]
         m.start_step = self.start_step
         for f in ("ntilde", "ion_density", "q_surface0", "r_out", "dt", "seed", "probe_bc",
-                  "wall_bc"):
+                  "wall_bc", "ion_mass"):
             setattr(m, f, getattr(self, f))
         prof = None
         if self.ion_profile is not None:

@@ -104,3 +104,39 @@ def test_oracle_ion_field_of_a_profile(eq):
     for r in (1.5, 4.0, 9.0):
         assert O.ion_field(c, r)[0] == pytest.approx(O.ion_field(u, r)[0], rel=1e-14)
         assert O.ion_field(c, r)[1] == pytest.approx(O.ion_field(u, r)[1], rel=1e-14)
+
+
+def test_sampled_ions_follow_the_density_and_inflow(eq):
+    st = EQ.sample_ions(eq, 100_000, 4, 10.0, id_offset=7)
+    r = np.linalg.norm(st.pos, axis=1)
+    assert np.all((r > 1.0) & (r < 10.0))
+    assert np.all(st.ids & np.uint32(0x80000000)) and st.ids[0] & np.uint32(0x7fffffff) == 7
+    # radial inflow at sqrt(-2 psi) c_s: energy conservation of App. D
+    vr = np.sum(st.vel * st.pos, axis=1) / r
+    c_s = eq.debye / math.sqrt(eq.mass_ratio)
+    assert np.allclose(0.5 * vr ** 2 / c_s ** 2 + eq.psi(r), 0.0, atol=1e-12)
+    assert np.all(vr < 0)
+    tang = st.vel - vr[:, None] * st.pos / r[:, None]
+    assert np.max(np.abs(tang)) < 1e-12 * np.max(np.abs(st.vel))
+    edges = np.linspace(1.0, 10.0, 10)
+    hist, _ = np.histogram(r, edges)
+    rg = np.linspace(1.0, 10.0, 90001)
+    w = eq.n_i(rg) * rg ** 2
+    expect = np.array([np.trapezoid(w[(rg >= a) & (rg <= b)], rg[(rg >= a) & (rg <= b)])
+                       for a, b in zip(edges[:-1], edges[1:])])
+    expect *= len(r) / expect.sum()
+    assert np.all(np.abs(hist - expect) < 5 * np.sqrt(expect) + 5)
+
+
+def test_paper_setup_counts_both_species():
+    ps = EQ.PaperSetup(n=20_000)
+    eq, st, nt, qs, prof = ps.build()
+    ions = (st.ids & np.uint32(0x80000000)) != 0
+    assert prof is None and st.pos.shape == (20_000, 3)
+    ne, ni = EQ.electron_count_density(eq, 10.0), EQ.ion_count_density(eq, 10.0)
+    assert ions.sum() == pytest.approx(20_000 * ni / (ne + ni), abs=1)
+    assert nt == pytest.approx(20_000 / (ne + ni))
+    assert len(np.unique(st.ids)) == 20_000
+    # net charge of the probe plus the plasma between the walls ~ 0 (the
+    # quasi-neutral tail beyond r_out carries the rest)
+    assert abs(qs + (ions.sum() - (~ions).sum())) < 0.01 * ions.sum()

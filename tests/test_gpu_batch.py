@@ -51,6 +51,11 @@ MIXED = [
     (777, 43, 7, {"probe_bc": S.SIM_BC_SPECULAR, "wall_bc": S.SIM_BC_DIFFUSE, "seed": 9}),
     (1, 44, 12, {}),
     (3000, 45, 10, {"ion_density": 0.5, "q_surface0": -3.0}),
+    # mobile ions: the upper half of the ids carry the ion marker
+    (900, 46, 9, {"ion_density": 0.0, "ion_mass": 100.0,
+                  "ids": np.arange(900, dtype=np.uint32) | np.where(np.arange(900) % 2 == 1,
+                                                                     np.uint32(0x80000000),
+                                                                     np.uint32(0))}),
 ]
 
 

@@ -29,46 +29,69 @@ def equilibrium():
     return EQ.solve_floating_equilibrium(W.PlasmaScales(1e15, 3.0, 4e-3).v_th)
 
 
-def _member_and_oracle(eq, n, L, seed, n_steps, bc=S.SIM_BC_DIFFUSE, nodes=513):
+def _member_and_oracle(eq, n, L, seed, n_steps, bc=S.SIM_BC_DIFFUSE, nodes=513, mobile=False,
+                       probe_bc=None):
+    """The App. D state between the probe and r_out = 10: n electrons over
+    the immobile ion profile, or (mobile) n particles of both species."""
     r_out, dt = 10.0, 0.01
     v_th = eq.debye
-    st = EQ.sample_electrons(eq, n, seed, r_out, v_th)
-    ntilde = n / EQ.electron_count_density(eq, r_out)
-    prof = eq.ion_profile(r_out, nodes)
+    ne = EQ.electron_count_density(eq, r_out)
+    if mobile:
+        ni = EQ.ion_count_density(eq, r_out)
+        ntilde = n / (ne + ni)
+        n_el = int(round(ntilde * ne))
+        el = EQ.sample_electrons(eq, n_el, seed, r_out, v_th)
+        io = EQ.sample_ions(eq, n - n_el, seed + 1, r_out, id_offset=n_el)
+        pos, vel = np.concatenate([el.pos, io.pos]), np.concatenate([el.vel, io.vel])
+        ids = np.concatenate([el.ids, io.ids])
+        prof, mass = None, eq.mass_ratio
+    else:
+        st = EQ.sample_electrons(eq, n, seed, r_out, v_th)
+        pos, vel, ids = st.pos, st.vel, st.ids
+        ntilde = n / ne
+        prof, mass = eq.ion_profile(r_out, nodes), 0.0
     q_s = eq.surface_charge * ntilde
     u = W.impulse_drive(n_steps, 1.0)
-    mb = S.Member(pos=st.pos, vel=st.vel, u_asy=u, ntilde=ntilde, r_out=r_out, dt=dt,
-                  q_surface0=q_s, probe_bc=bc, wall_bc=bc, seed=77, ion_profile=prof)
-    op = O.Params(r_out=r_out, dt=dt, ntilde=ntilde, l_max=L, probe_bc=bc, wall_bc=bc, seed=77,
-                  ion_profile=prof)
-    return st, mb, op, u, q_s
+    pbc = bc if probe_bc is None else probe_bc
+    mb = S.Member(pos=pos, vel=vel, u_asy=u, ntilde=ntilde, ids=ids, r_out=r_out, dt=dt,
+                  q_surface0=q_s, probe_bc=pbc, wall_bc=bc, seed=77, ion_profile=prof,
+                  ion_density=0.0 if mobile else 1.0, ion_mass=mass)
+    op = O.Params(r_out=r_out, dt=dt, ntilde=ntilde, l_max=L, probe_bc=pbc, wall_bc=bc, seed=77,
+                  ion_profile=prof, ion_density=0.0 if mobile else 1.0, ion_mass=mass)
+    return pos, vel, ids, mb, op, u, q_s
 
 
+@pytest.mark.parametrize("mobile", [False, True], ids=["ion-profile", "mobile-ions"])
 @pytest.mark.parametrize("precision,tol", [(S.SIM_FP64, 1e-12), (S.SIM_FP32_COMP, 1e-5)],
                          ids=["fp64", "fp32c"])
-def test_ion_profile_field_matches_oracle(equilibrium, precision, tol):
+def test_app_d_field_matches_oracle(equilibrium, precision, tol, mobile):
     n, L = 3000, 8
-    _say(f"[gpu] App. D field: n={n} L={L} precision={precision}")
-    st, mb, op, u, q_s = _member_and_oracle(equilibrium, n, L, 31, 4)
+    _say(f"[gpu] App. D field: n={n} L={L} precision={precision} mobile ions={mobile}")
+    pos, vel, ids, mb, op, u, q_s = _member_and_oracle(equilibrium, n, L, 31, 4, mobile=mobile)
     with S.Batch(S.SimParams(l_max=L, precision=precision), [mb]) as b:
         E = b.eval_field(0)
-    Eo, _ = O.field(op, st.pos, q_surface=q_s, u_asy=u[0])
+    Eo, _ = O.field(op, pos, ids=ids, q_surface=q_s, u_asy=u[0])
     rms = np.sqrt(np.mean(np.sum(Eo * Eo, axis=1)))
     err = np.max(np.abs(E - Eo)) / rms
     _say(f"[gpu]   rel err {err:.3e}")
     assert err < tol
 
 
-def test_ion_profile_steps_match_oracle(equilibrium):
+@pytest.mark.parametrize("mobile,probe_bc", [(False, S.SIM_BC_DIFFUSE), (True, S.SIM_BC_DIFFUSE),
+                                             (True, S.SIM_BC_ABSORB)],
+                         ids=["ion-profile", "mobile-ions", "mobile-ions-absorbing"])
+def test_app_d_steps_match_oracle(equilibrium, mobile, probe_bc):
     n, L, steps = 2000, 6, 6
-    _say(f"[gpu] App. D steps: n={n} L={L} steps={steps} diffuse walls")
-    st, mb, op, u, q_s = _member_and_oracle(equilibrium, n, L, 32, steps)
+    _say(f"[gpu] App. D steps: n={n} L={L} steps={steps} mobile ions={mobile} probe_bc={probe_bc}")
+    pos, vel, ids, mb, op, u, q_s = _member_and_oracle(equilibrium, n, L, 32, steps,
+                                                       mobile=mobile, probe_bc=probe_bc)
     with S.Batch(S.SimParams(l_max=L), [mb]) as b:
         b.step(steps)
         gs = b.read_state(0)
         gq = b.read_response(0, 0, steps)
-    r = O.run(op, st.pos, st.vel, u, steps, q_surface=q_s)
+    r = O.run(op, pos, vel, u, steps, ids=ids, q_surface=q_s)
     assert np.array_equal(gs["alive"].astype(bool), r.alive.astype(bool))
+    assert gs["q_surface"] == r.q_surface
     assert np.max(np.abs(gs["pos"] - r.pos)) < 1e-11
     assert np.max(np.abs(gs["vel"] - r.vel)) < 1e-10
     assert np.max(np.abs(gq - r.qdiff)) < 1e-11 * np.max(np.abs(r.qdiff))

@@ -517,3 +517,105 @@ def test_philox4x64_10_matches_numpy(key, ctr):
     v = sum(int(w) << (64 * i) for i, w in enumerate(ctr)) + 1
     c = [(v >> (64 * i)) & (2**64 - 1) for i in range(4)]
     np.testing.assert_array_equal(O.philox4x64_10(c, key), raw)
+
+
+# --------------------------------------------------------------------------
+# Mobile ions (ids with bit 31 set: charge +1, mass ion_mass)
+# --------------------------------------------------------------------------
+
+ION = np.uint32(0x80000000)
+
+
+def _cloud(n, seed, r_out=5.0):
+    rng = np.random.default_rng(seed)
+    r = (1 + rng.random(n) * (r_out ** 3 - 1)) ** (1 / 3)
+    ct = 2 * rng.random(n) - 1
+    ph = 2 * np.pi * rng.random(n)
+    st = np.sqrt(1 - ct * ct)
+    return np.stack([r * st * np.cos(ph), r * st * np.sin(ph), r * ct], axis=1)
+
+
+def test_ion_charge_reverses_the_particle_field():
+    """With no surface charge, ion background or drive, the field at every
+    particle comes from the other particles only: making all of them ions
+    flips its sign."""
+    pos = _cloud(40, 61)
+    p = O.Params(ntilde=3.0, l_max=5, ion_density=0.0, ion_mass=100.0)
+    ids = np.arange(40, dtype=np.uint32)
+    Ee, _ = O.field(p, pos, ids=ids)
+    Ei, _ = O.field(p, pos, ids=ids | ION)
+    assert np.max(np.abs(Ei + Ee)) < 1e-14 * np.max(np.abs(Ee))
+
+
+def test_mixed_species_field_is_the_sum_over_species():
+    """E at particle k in a mixed cloud = field of the electrons at k + field
+    of the ions at k (each evaluated with k added as a target; its own
+    charge does not act on itself)."""
+    n = 30
+    pos = _cloud(n, 62)
+    rng = np.random.default_rng(63)
+    is_ion = rng.random(n) < 0.5
+    ids = np.arange(n, dtype=np.uint32) | np.where(is_ion, ION, np.uint32(0))
+    p = O.Params(ntilde=2.0, l_max=4, ion_density=0.4, ion_mass=50.0)
+    q = O.Params(ntilde=2.0, l_max=4, ion_density=0.0, ion_mass=50.0)
+    E, _ = O.field(p, pos, ids=ids, q_surface=-2.0, u_asy=0.3)
+    for k in range(n):
+        parts = []
+        for sel in (~is_ion, is_ion):
+            idx = np.flatnonzero(sel | (np.arange(n) == k))
+            kk = int(np.flatnonzero(idx == k)[0])
+            Ek, _ = O.field(q, pos[idx], ids=ids[idx], targets=[kk])
+            parts.append(Ek[0])
+        # background terms (Q_S, ions, drive) do not depend on the particles
+        e0, _ = O.field(p, pos[[k]], ids=ids[[k]], q_surface=-2.0, u_asy=0.3)
+        assert np.allclose(E[k], parts[0] + parts[1] + e0[0], rtol=1e-12, atol=1e-14)
+
+
+def test_ion_kick_is_the_electron_kick_over_minus_the_mass_ratio():
+    """A lone particle feels only the background fields: the velocity change
+    of an ion is -1/m_i times that of an electron at the same place."""
+    m_i = 1836.0
+    p = O.Params(ntilde=1.0, l_max=3, ion_density=0.7, ion_mass=m_i, dt=0.05)
+    x = np.array([[1.7, -0.4, 2.1]])
+    v = np.zeros((1, 3))
+    u = np.array([0.8])
+    re = O.run(p, x, v, u, 1, ids=np.array([5], np.uint32), q_surface=-1.5)
+    ri = O.run(p, x, v, u, 1, ids=np.array([5], np.uint32) | ION, q_surface=-1.5)
+    assert np.allclose(ri.vel, -re.vel / m_i, rtol=1e-14, atol=0)
+
+
+def test_absorbed_ion_adds_its_charge_to_the_probe():
+    p = O.Params(ntilde=1e30, l_max=0, ion_density=0.0, dt=0.1, ion_mass=4.0)
+    x = np.array([[1.05, 0.0, 0.0], [3.0, 0.0, 0.0]])
+    v = np.array([[-1.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    ids = np.array([0, 1], dtype=np.uint32) | ION
+    r = O.run(p, x, v, np.zeros(1), 1, ids=ids, q_surface=-3.0)
+    assert list(r.alive.astype(bool)) == [False, True]
+    assert r.q_surface == -2.0
+
+
+def test_energy_error_is_second_order_with_ions():
+    """The Hamiltonian test with a mixed cloud (two ions of mass 4; radii
+    spread so that the attraction does not reorder them)."""
+    pos = np.array([[1.6, 0.0, 0.3], [0.2, -2.5, 0.5], [2.2, 2.0, -1.5], [-1.0, 3.9, 0.5]])
+    vel = np.array([[0.05, 0.1, 0.0], [-0.1, 0.0, 0.05], [0.0, 0.1, 0.1], [0.1, 0.0, -0.1]])
+    ids = np.array([0, 1, 2, 3], dtype=np.uint32) | np.array([0, ION, 0, ION], dtype=np.uint32)
+    order0 = np.argsort(np.linalg.norm(pos, axis=1))
+    errs = []
+    for dt in (0.04, 0.02, 0.01):
+        p = O.Params(ntilde=2.0, l_max=3, ion_density=0.3, dt=dt, ion_mass=4.0,
+                     probe_bc=O.BC_SPECULAR, wall_bc=O.BC_SPECULAR)
+        nsteps = int(round(2.0 / dt))
+        u = np.full(nsteps, 0.5)
+        x, v = pos.copy(), vel.copy()
+        hs = []
+        for s in range(nsteps):
+            res = O.run(p, x, v, u, 1, ids=ids, start_step=s, q_surface=-1.0)
+            v2 = 0.5 * (np.sum(v * v, axis=1) + np.sum(res.vel * res.vel, axis=1))
+            hs.append(O.energy(p, x, v2, ids=ids, q_surface=-1.0, u_asy=0.5)[0])
+            x, v = res.pos, res.vel
+            r = np.linalg.norm(x, axis=1)
+            assert np.all(np.argsort(r) == order0) and r.min() > 1.0 and r.max() < p.r_out
+        errs.append(np.max(np.abs(np.array(hs) - hs[0])))
+    assert 3.6 < errs[0] / errs[1] < 4.4
+    assert 3.6 < errs[1] / errs[2] < 4.4
