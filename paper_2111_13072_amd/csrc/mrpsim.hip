@@ -121,13 +121,14 @@ struct Tables {
     const double *alm;      // Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m
     const double *blm;
     const int *chl;         // degree l of each channel in stream order
-    // (Q_m^m or a_lm, 0 or b_lm) in stream order of (m, l): m = 0..m_top
-    // outer, l = m..L inner, so a loop over (m, l) reads consecutive entries
-    const double2 *ab;
+    // (Q_m^m or a_lm, 0 or b_lm, l - m, 2l + 1) in stream order of (m, l):
+    // m = 0..m_top outer, l = m..L inner, so a loop over (m, l) reads
+    // consecutive entries, and the integer factors need no conversion
+    const double4 *abw;
     // FP32 copies for the FP32-compensated mode
     const float *qmm32, *alm32, *blm32;
     const float4 *nf4_32;
-    const float2 *ab32;
+    const float4 *abw32;
 };
 
 // Channels are kept in "stream order": m = 0..m_top outer, l = max(m,1)..L
@@ -220,10 +221,11 @@ __device__ inline T ld_const(const T *p, int i)
         reinterpret_cast<uintptr_t>(p))[i];
 }
 
-__device__ inline double2 ld_const(const double2 *p, int i)
+// The first two components of entry i of a table of double4.
+__device__ inline double2 ld_const_xy(const double4 *p, int i)
 {
     const double *q = reinterpret_cast<const double *>(p);
-    return make_double2(ld_const(q, 2 * i), ld_const(q, 2 * i + 1));
+    return make_double2(ld_const(q, 4 * i), ld_const(q, 4 * i + 1));
 }
 
 // r^2 as (x*x + y*y) + z*z without contraction: the exact radial sort key.
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     double s_mm = inv_r;  // r^-(2m+1)
     int j = 0;   // (m, l) position in stream order
     const int jmax = (m_top + 1) * (2 * L - m_top + 2) / 2 - 1;
-    double2 nab = ld_const(tb.ab, 0);
+    double2 nab = ld_const_xy(tb.abw, 0);
     for (int m = 0; m <= m_top; ++m) {
         if (m > 0) {
             const double nc = x * Cm - y * Sm;
@@ -597,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         for (int l = m; l <= L; ++l, ++j) {
             // (Q_m^m, 0) at l = m, else the recurrence constants (a_lm, b_lm)
             const double2 ab = nab;
-            nab = ld_const(tb.ab, min(j + 1, jmax));   // read one step ahead
+            nab = ld_const_xy(tb.abw, min(j + 1, jmax));   // read one step ahead
             double Qv;
             if (l == m) Qv = ab.x;
             else Qv = ab.x * z * Qp - ab.y * r2 * Qpp;
@@ -831,73 +833,77 @@ struct Grave {
 //              + (e_z - cos th rhat) sum U D_z Q + (sum Q dU/dx, sum Q dU/dy, 0).
 // (Assembling the radial part from the two partial derivatives of Q instead
 // loses a factor ~l to cancellation.)
-template <bool FULL, typename R>
-__device__ inline void far_field(const R *cf, int C, int L,
-                                 const typename std::conditional<std::is_same<R, float>::value,
-                                                                 float2, double2>::type *abt,
-                                 R x, R y, R z, R &gx, R &gy, R &gz)
+template <bool FULL, typename R, typename R4>
+__device__ inline void far_field(const R *cf, int C, int L, const R4 *ab, R x, R y, R z, R &gx,
+                                 R &gy, R &gz)
 {
     const R r2 = x * x + y * y + z * z;
     const R inv_r2 = rcp_r(r2);
     const R inv_r = rsq_r(r2);
     R Ga = 0, Gz = 0, Gx = 0, Gy = 0;
-    const int m_top = FULL ? L : 0;
-    R Cm = 1, Sm = 0, Cm1 = 0, Sm1 = 0;
-    R s_mm = inv_r;
-    int k = 0;   // stream position of the channel
-    int j = 0;
-    for (int m = 0; m <= m_top; ++m) {
-        if (m > 0) {
+    // m = 0: cos channels only, stream position k = l - 1; l = 0 (Q_0^0) only
+    // seeds the recurrence, its field is Gauss's law in the caller
+    {
+        R Q1 = ab[0].x, Q2 = 0, Dz1 = 0, Dz2 = 0;
+        R sl = inv_r * inv_r2;   // r^-(2l+1) at l = 1
+        for (int l = 1; l <= L; ++l) {
+            const R4 e = ab[l];
+            const R az = e.x * z, br2 = e.y * r2;
+            const R Qv = az * Q1 - br2 * Q2;
+            const R Dz = e.x * Q1 + az * Dz1 - br2 * Dz2;
+            Q2 = Q1;
+            Q1 = Qv;
+            Dz2 = Dz1;
+            Dz1 = Dz;
+            const R ac = cf[l - 1], bc = cf[C + l - 1];
+            const R tc = bc + sl * ac;
+            Ga += Qv * (e.z * tc - (e.w * sl) * ac);
+            Gz += tc * Dz;
+            sl *= inv_r2;
+        }
+    }
+    if (FULL) {
+        R Cm = 1, Sm = 0, Cm1 = 0, Sm1 = 0;
+        R s_mm = inv_r;
+        int j = L + 1;   // stream index of (m, l = m)
+        int k = L;       // channel position of (m, l = m), cos then sin
+        for (int m = 1; m <= L; ++m) {
             Cm1 = Cm;
             Sm1 = Sm;
             Cm = x * Cm1 - y * Sm1;
             Sm = x * Sm1 + y * Cm1;
             s_mm *= inv_r2;
-        }
-        R Q1 = 0, Q2 = 0, Dz1 = 0, Dz2 = 0;
-        R sl = s_mm;
-        const R dm = (R)m;
-        for (int l = m; l <= L; ++l) {
-            R Qv, Dz;
-            const auto abv = abt[j++];   // (Q_m^m, 0) at l = m, else (a_lm, b_lm)
-            if (l == m) {
-                Qv = abv.x;
-                Dz = 0;
-            } else {
-                const R a = abv.x, b = abv.y;
-                const R az = a * z, br2 = b * r2;
-                Qv = az * Q1 - br2 * Q2;
-                Dz = a * Q1 + az * Dz1 - br2 * Dz2;
-            }
-            Q2 = Q1;
-            Q1 = Qv;
-            Dz2 = Dz1;
-            Dz1 = Dz;
-            if (l == 0) {   // l = 0 is Gauss's law in the caller
-                sl *= inv_r2;
-                continue;
-            }
-            const R lm = (R)(l - m);
-            const R w1 = (R)(2 * l + 1) * sl;
-            const R ac = cf[k], bc = cf[C + k];
-            const R tc = bc + sl * ac;
-            if (!FULL || m == 0) {
-                Ga += Qv * (lm * tc - w1 * ac);
-                Gz += tc * Dz;
-                k += 1;
-            } else {
-                const R as = cf[k + 1], bs = cf[C + k + 1];
-                k += 2;
+            const R dm = (R)m;
+            R sl = s_mm;
+            // one (l, m) pair of channels with Q = Q_l^m and D_z Q = Dz
+            auto pair = [&](const R4 &e, R Qv, R Dz, bool first) {
+                const R ac = cf[k], bc = cf[C + k], as = cf[k + 1], bs = cf[C + k + 1];
+                const R tc = bc + sl * ac;
                 const R ts = bs + sl * as;
                 const R U = tc * Cm + ts * Sm;
                 const R V = ac * Cm + as * Sm;
-                Ga += Qv * (lm * U - w1 * V);
-                Gz += U * Dz;
+                Ga += Qv * (e.z * U - (e.w * sl) * V);
+                if (!first) Gz += U * Dz;   // D_z Q_m^m = 0
                 const R mq = dm * Qv;
                 Gx += mq * (tc * Cm1 + ts * Sm1);
                 Gy += mq * (ts * Cm1 - tc * Sm1);
+                k += 2;
+                sl *= inv_r2;
+            };
+            R Q1 = ab[j].x, Q2 = 0, Dz1 = 0, Dz2 = 0;
+            pair(ab[j], Q1, (R)0, true);
+            ++j;
+            for (int l = m + 1; l <= L; ++l, ++j) {
+                const R4 e = ab[j];
+                const R az = e.x * z, br2 = e.y * r2;
+                const R Qv = az * Q1 - br2 * Q2;
+                const R Dz = e.x * Q1 + az * Dz1 - br2 * Dz2;
+                Q2 = Q1;
+                Q1 = Qv;
+                Dz2 = Dz1;
+                Dz1 = Dz;
+                pair(e, Qv, Dz, false);
             }
-            sl *= inv_r2;
         }
     }
     const R xh = x * inv_r, yh = y * inv_r, c = z * inv_r;
@@ -1084,11 +1090,11 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
         const double inv_rho = 1.0 / rho;
         R gx, gy, gz;
         if constexpr (FP32) {
-            far_field<FULL, float>(coef32 + (size_t)tile * kp.C2, kp.C, L, tb.ab32,
+            far_field<FULL, float>(coef32 + (size_t)tile * kp.C2, kp.C, L, tb.abw32,
                                    (float)(x * inv_rho), (float)(y * inv_rho),
                                    (float)(z * inv_rho), gx, gy, gz);
         } else {
-            far_field<FULL, double>(coef + (size_t)tile * kp.C2, kp.C, L, tb.ab, x,
+            far_field<FULL, double>(coef + (size_t)tile * kp.C2, kp.C, L, tb.abw, x,
                                     y, z, gx, gy, gz);
         }
         Ex = -(double)gx * inv_rho;
@@ -1503,7 +1509,7 @@ size_t nf4_offset(int L)
 
 size_t ab_offset(int L) { return nf4_offset(L) + 4 * (size_t)(L + 1); }   // 32-byte aligned
 
-size_t tables_len(int L) { return ab_offset(L) + 2 * (size_t)((L + 1) * (L + 2) / 2); }
+size_t tables_len(int L) { return ab_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
 
 // FP32 copies: qmm, the two (l, m) triangles, then the near-field constants
 // at a 16-byte aligned offset.
@@ -1515,7 +1521,7 @@ size_t nf4_32_offset(int L)
 
 size_t ab32_offset(int L) { return nf4_32_offset(L) + 4 * (size_t)(L + 1); }   // 16-byte aligned
 
-size_t tables32_len(int L) { return ab32_offset(L) + 2 * (size_t)((L + 1) * (L + 2) / 2); }
+size_t tables32_len(int L) { return ab32_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
 
 void plan_alloc(sim *h, Alloc &al)
 {
@@ -1622,8 +1628,10 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
     double *ab = t.data() + ab_offset(L);
     for (int m = 0, j = 0; m <= L; ++m) {
         for (int l = m; l <= L; ++l, ++j) {
-            ab[2 * j] = (l == m) ? qmm[m] : alm[tri(l, m)];
-            ab[2 * j + 1] = (l == m) ? 0.0 : blm[tri(l, m)];
+            ab[4 * j] = (l == m) ? qmm[m] : alm[tri(l, m)];
+            ab[4 * j + 1] = (l == m) ? 0.0 : blm[tri(l, m)];
+            ab[4 * j + 2] = (double)(l - m);
+            ab[4 * j + 3] = 2.0 * l + 1.0;
         }
     }
     return t;
@@ -1788,7 +1796,7 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
     h->tb.alm = tb + (kQmmArray + 1) * (L + 1);
     h->tb.blm = tb + (kQmmArray + 1) * (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.nf4 = reinterpret_cast<const double4 *>(tb + nf4_offset(L));
-    h->tb.ab = reinterpret_cast<const double2 *>(tb + ab_offset(L));
+    h->tb.abw = reinterpret_cast<const double4 *>(tb + ab_offset(L));
     h->tb.chl = h->chl;
     std::vector<float> tab32(tables32_len(L), 0.f);
     {
@@ -1800,13 +1808,13 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
         const double *nf4 = tab.data() + nf4_offset(L);
         for (int i = 0; i < 4 * (L + 1); ++i) tab32[nf4_32_offset(L) + i] = (float)nf4[i];
         const double *ab = tab.data() + ab_offset(L);
-        for (size_t i = 0; i < 2 * ntri; ++i) tab32[ab32_offset(L) + i] = (float)ab[i];
+        for (size_t i = 0; i < 4 * ntri; ++i) tab32[ab32_offset(L) + i] = (float)ab[i];
     }
     h->tb.qmm32 = h->tables32;
     h->tb.alm32 = h->tables32 + (L + 1);
     h->tb.blm32 = h->tables32 + (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.nf4_32 = reinterpret_cast<const float4 *>(h->tables32 + nf4_32_offset(L));
-    h->tb.ab32 = reinterpret_cast<const float2 *>(h->tables32 + ab32_offset(L));
+    h->tb.abw32 = reinterpret_cast<const float4 *>(h->tables32 + ab32_offset(L));
     // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
     std::vector<int> chl;
     for (int m = 0; m <= (lo.full ? L : 0); ++m)
