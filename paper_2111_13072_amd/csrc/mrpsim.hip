@@ -581,39 +581,60 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         }
     };
 
-    double Cm = 1.0, Sm = 0.0;
-    double s_mm = inv_r;  // r^-(2m+1)
-    int j = 0;   // (m, l) position in stream order
+    // (Q_m^m or a_lm, 0 or b_lm) of the stream-order table, read one entry
+    // ahead of its use (clamped index)
     const int jmax = (m_top + 1) * (2 * L - m_top + 2) / 2 - 1;
-    double2 nab = ld_const_xy(tb.abw, 0);
-    for (int m = 0; m <= m_top; ++m) {
-        if (m > 0) {
+    int j = 0;                               // next entry to use
+    double2 nab = ld_const_xy(tb.abw, 0);    // holds entry j
+    auto next_entry = [&]() {
+        const double2 e = nab;
+        ++j;
+        nab = ld_const_xy(tb.abw, min(j, jmax));
+        return e;
+    };
+    // m = 0: channels l = 1..L (Q_0^0 only seeds the recurrence; l = 0 is
+    // Gauss's law in the field kernel)
+    {
+        double Qpp = 0.0, Qp = next_entry().x;
+        double sl = inv_r * inv_r2;   // r^-(2l+1) at l = 1
+        for (int l = 1; l <= L; ++l) {
+            const double2 ab = next_entry();
+            const double Qv = ab.x * z * Qp - ab.y * r2 * Qpp;
+            Qpp = Qp;
+            Qp = Qv;
+            const double rc = q * Qv;
+            put(rc, rc * sl);
+            sl *= inv_r2;
+        }
+    }
+    if (FULL) {
+        double Cm = 1.0, Sm = 0.0;
+        double s_mm = inv_r;  // r^-(2m+1)
+        for (int m = 1; m <= L; ++m) {
             const double nc = x * Cm - y * Sm;
             const double ns = x * Sm + y * Cm;
             Cm = nc;
             Sm = ns;
             s_mm *= inv_r2;
-        }
-        double Qp = 0.0, Qpp = 0.0;
-        double sl = s_mm;
-        for (int l = m; l <= L; ++l, ++j) {
-            // (Q_m^m, 0) at l = m, else the recurrence constants (a_lm, b_lm)
-            const double2 ab = nab;
-            nab = ld_const_xy(tb.abw, min(j + 1, jmax));   // read one step ahead
-            double Qv;
-            if (l == m) Qv = ab.x;
-            else Qv = ab.x * z * Qp - ab.y * r2 * Qpp;
-            Qpp = Qp;
-            Qp = Qv;
-            if (l > 0) {
-                const double rc = q * Qv * Cm;
+            const double qc = q * Cm, qs = q * Sm;
+            double sl = s_mm;
+            double Qpp = 0.0, Qp = next_entry().x;   // l = m: Q_m^m
+            {
+                const double rc = Qp * qc, rs = Qp * qs;
                 put(rc, rc * sl);
-                if (FULL && m > 0) {
-                    const double rs = q * Qv * Sm;
-                    put(rs, rs * sl);
-                }
+                put(rs, rs * sl);
+                sl *= inv_r2;
             }
-            sl *= inv_r2;
+            for (int l = m + 1; l <= L; ++l) {
+                const double2 ab = next_entry();
+                const double Qv = ab.x * z * Qp - ab.y * r2 * Qpp;
+                Qpp = Qp;
+                Qp = Qv;
+                const double rc = Qv * qc, rs = Qv * qs;
+                put(rc, rc * sl);
+                put(rs, rs * sl);
+                sl *= inv_r2;
+            }
         }
     }
     if (slot > 0) {   // last, partial batch: rows >= slot hold stale values
