@@ -50,7 +50,10 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxL = 64;
-constexpr int kChunk = 64;        // tiles per chunk of the carry scan
+// Tiles per chunk of the carry scan, per member: a power of two in
+// [kChunkMin, kChunkMax], about a member's tiles / kChunkTarget, so that small
+// members get short serial chains and large ones few chunks.
+constexpr int kChunkMin = 8, kChunkMax = 64, kChunkTarget = 256;
 constexpr int kScanPerBlock = 1024;  // histogram entries per block of the bucket scan
 constexpr int kBucketOccupancy = 8;  // mean particles per sort bucket
 
@@ -86,6 +89,7 @@ struct Seg {
     uint32_t p0, cap;   // particle slots [p0, p0 + cap); p0 is a multiple of 64
     uint32_t t0, nt;    // tiles [t0, t0 + nt), t0 = p0 / 64
     uint32_t c0, nc;    // carry chunks [c0, c0 + nc)
+    uint32_t cl;        // tiles per chunk
     uint32_t b0, nb;    // sort buckets [b0, b0 + nb)
     double inv_vol;     // 1 / (r_out^3 - 1)
     double ntilde, inv_ntilde, ion_density, q_surface0, dt, r_out;
@@ -238,12 +242,6 @@ __device__ inline double key_r2(double x, double y, double z)
 // Sort: exact order by (r^2, id) through volume-uniform buckets
 // ---------------------------------------------------------------------------
 
-__global__ void k_sort_clear(uint32_t *hist, int nb)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i <= nb) hist[i] = 0;
-}
-
 // Key, bucket and slot inside the bucket, over all particle slots.  A wave
 // is one tile and so lies in one member.  Lanes of a wave that fall into the
 // same bucket (particles arrive nearly sorted, so a wave touches few buckets)
@@ -354,7 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_b(uint32_t *bsum, int nblocks)
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_c(const uint32_t *in, const uint32_t *bsum,
+// The histogram's last reader: it leaves the histogram zeroed for the next
+// step (the handle zeroes it once at creation).
+__global__ __launch_bounds__(kBlock) void k_scan_c(uint32_t *in, const uint32_t *bsum,
                                                    uint32_t *out, int n)
 {
     constexpr int per = kScanPerBlock / kBlock;
@@ -366,6 +366,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(const uint32_t *in, const uin
         v[k] = (base + k < n) ? in[base + k] : 0u;
         s += v[k];
     }
+#pragma unroll
+    for (int k = 0; k < per; ++k)
+        if (base + k < n) in[base + k] = 0u;
     uint32_t tot;
     uint32_t run = bsum[blockIdx.x] + block_exclusive_scan(s, &tot);
 #pragma unroll
@@ -378,16 +381,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(const uint32_t *in, const uin
 
 // Per member: alive count (its buckets' share of the global offsets) and the
 // surface charge Q_S = q_surface0 + the charge absorbed so far, which enters
-// the field as an interior l = 0 charge (Q_S / (4 pi r), Sec. 3).
-__global__ void k_member_live(Map mp, const uint32_t *off, KParams kp)
+// the field as an interior l = 0 charge (Q_S / (4 pi r), Sec. 3).  Done by
+// the first block of the rank kernel (after the offsets, before the moments).
+__device__ inline void member_live(const Map &mp, const uint32_t *off, const KParams &kp)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= kp.n_members) return;
-    const Seg &sg = mp.seg[s];
-    Ctl &c = mp.ctl[s];
-    if (!member_runs(sg, c, kp)) return;
-    c.n_live = off[sg.b0 + sg.nb] - off[sg.b0];
-    c.q_surface = (sg.q_surface0 + kQ * (double)(c.n_dead - c.n_dead_ion)) + (double)c.n_dead_ion;
+    for (int s = threadIdx.x; s < kp.n_members; s += blockDim.x) {
+        const Seg &sg = mp.seg[s];
+        Ctl &c = mp.ctl[s];
+        if (!member_runs(sg, c, kp)) continue;
+        c.n_live = off[sg.b0 + sg.nb] - off[sg.b0];
+        c.q_surface =
+            (sg.q_surface0 + kQ * (double)(c.n_dead - c.n_dead_ion)) + (double)c.n_dead_ion;
+    }
 }
 
 // Bucket order (arbitrary inside a bucket): key, id and source index.
@@ -419,6 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const uint64_
 {
     __shared__ uint64_t wkey[kRankWindow];
     __shared__ uint32_t wuid[kRankWindow];
+    if (blockIdx.x == 0) member_live(mp, off, kp);
     const uint32_t n = off[kp.nb];   // alive particles of all running members
     const uint32_t p0 = xcd_block(blockIdx.x, gridDim.x) * kBlock;
     if (p0 >= n) return;
@@ -656,8 +662,8 @@ __device__ inline bool chunk_tiles(const Map &mp, const KParams &kp, int j, uint
     if (m == kNone || !member_runs(mp.seg[m], mp.ctl[m], kp)) return false;
     const Seg &sg = mp.seg[m];
     *mb = m;
-    *t0 = (int)(sg.t0 + (uint32_t)(j - (int)sg.c0) * kChunk);
-    *t1 = min(*t0 + kChunk, (int)(sg.t0 + sg.nt));
+    *t0 = (int)(sg.t0 + (uint32_t)(j - (int)sg.c0) * sg.cl);
+    *t1 = min(*t0 + (int)sg.cl, (int)(sg.t0 + sg.nt));
     return true;
 }
 
@@ -714,48 +720,35 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(Map mp, const double *chu
     if (!interior && lane == kWave - 1) T[(size_t)s * kp.C + (c - kp.C)] = incl;
 }
 
-// Per member (blockIdx.x): constant part of the interior coefficient, the
-// image response -f_l T_lm and the hemisphere drive (odd l, m = 0; stream
-// positions 0..L-1 hold m = 0, l = 1..L); and the probe response Q_diff(t_step).
-__global__ __launch_bounds__(kBlock) void k_coef_prep(Map mp, const double *T, Tables tb,
-                                                      KParams kp, double *Kc)
-{
-    const int s = blockIdx.x;
-    const Seg &sg = mp.seg[s];
-    const Ctl &ct = mp.ctl[s];
-    if (!member_runs(sg, ct, kp)) return;
-    const int64_t step = ct.step;
-    const bool in_run = step >= 0 && step < sg.n_steps;
-    const double u = in_run ? sg.u_asy[step] : 0.0;
-    const double *Ts = T + (size_t)s * kp.C;
-    for (int c = threadIdx.x; c < kp.C; c += kBlock) {
-        const int l = tb.chl[c];
-        double k = -tb.ftil[l] * Ts[c] * (tb.wl[l] * sg.inv_ntilde);
-        if (c < kp.L) k += u * tb.drive_w[l];
-        Kc[(size_t)s * kp.C + c] = k;
-    }
-    if (threadIdx.x == 0) {
-        double acc = 0.0;
-        for (int l = 1; l <= kp.L; l += 2) acc += tb.drive_w[l] * Ts[l - 1];
-        if (in_run) sg.qdiff[step] = -acc / sg.ntilde;
-    }
-}
-
-// Per-tile coefficients of the field kernel.  FP64 mode: absolute FP64
-// values.  FP32 mode: values pre-scaled to the tile's coordinates x / rho
-// (interior rho^-(l+1), exterior rho^l), stored as FP32.
+// Per-tile coefficients of the field kernel.  Interior coefficient of tile
+// t: the carry of the tiles before it, plus the constant part: the image
+// response -f_l T_lm and the hemisphere drive (odd l, m = 0; stream positions
+// 0..L-1 hold m = 0, l = 1..L).  Exterior: the carry of the tiles after it.
+// FP64 mode: absolute FP64 values.  FP32 mode: values pre-scaled to the
+// tile's coordinates x / rho (interior rho^-(l+1), exterior rho^l), stored
+// as FP32.  The block of the member's first chunk also records the probe
+// response Q_diff(t_step) from the totals.
 __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *S,
-                                                        const double *chunkC, const double *Kc,
+                                                        const double *chunkC, const double *T,
                                                         Tables tb, KParams kp, const double *lgrho,
                                                         double *coef, float *coef32, double *qpre)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
-    if (c >= kp.SW) return;
     const int j = blockIdx.x;
     uint32_t mb;
     int t0, t1;
     if (!chunk_tiles(mp, kp, j, &mb, &t0, &t1)) return;
-    const double inv_nt = mp.seg[mb].inv_ntilde;
+    const Seg &sg = mp.seg[mb];
+    const int64_t step = mp.ctl[mb].step;
+    const bool in_run = step >= 0 && step < sg.n_steps;
+    const double *Ts = T + (size_t)mb * kp.C;
+    if (c == 0 && blockIdx.y == 0 && j == (int)sg.c0 && in_run) {
+        double acc = 0.0;
+        for (int l = 1; l <= kp.L; l += 2) acc += tb.drive_w[l] * Ts[l - 1];
+        sg.qdiff[step] = -acc / sg.ntilde;
+    }
+    if (c >= kp.SW) return;
+    const double inv_nt = sg.inv_ntilde;
     double run = chunkC[(size_t)j * kp.SW + c];
     if (c == kp.C2) {   // charge of the member's particles before each tile
         for (int t = t0; t < t1; ++t) {
@@ -765,7 +758,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *S,
     } else if (c < kp.C) {
         const int l = tb.chl[c];
         const double w = tb.wl[l] * inv_nt;
-        const double k = Kc[(size_t)mb * kp.C + c];
+        double k = -tb.ftil[l] * Ts[c] * w;
+        if (c < kp.L && in_run) k += sg.u_asy[step] * tb.drive_w[l];
         for (int t = t0; t < t1; ++t) {
             const double v = run * w + k;
             if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2(-(l + 1.0) * lgrho[t]));
@@ -1292,15 +1286,14 @@ __global__ void k_step_finish(Map mp, KParams kp)
 // ---------------------------------------------------------------------------
 
 enum KernelId {
-    KN_SORT_CLEAR, KN_SORT_KEY, KN_SCAN_A, KN_SCAN_B, KN_SCAN_C, KN_MEMBER_LIVE, KN_SORT_SCATTER,
-    KN_SORT_RANK, KN_MOMENTS, KN_CHUNK_SUMS, KN_CHUNK_SCAN, KN_COEF_PREP, KN_CHUNK_APPLY,
-    KN_FIELD_PUSH, KN_STEP_FINISH, KN_COUNT
+    KN_SORT_KEY, KN_SCAN_A, KN_SCAN_B, KN_SCAN_C, KN_SORT_SCATTER, KN_SORT_RANK, KN_MOMENTS,
+    KN_CHUNK_SUMS, KN_CHUNK_SCAN, KN_CHUNK_APPLY, KN_FIELD_PUSH, KN_STEP_FINISH, KN_COUNT
 };
 
 const char *kKernelNames[KN_COUNT] = {
-    "sort_clear", "sort_key", "bucket_scan_a", "bucket_scan_b", "bucket_scan_c", "member_live",
-    "sort_scatter", "sort_rank_move", "moments", "carry_chunk_sums", "carry_chunk_scan",
-    "coef_prep", "carry_apply", "field_push", "step_finish"};
+    "sort_key", "bucket_scan_a", "bucket_scan_b", "bucket_scan_c", "sort_scatter",
+    "sort_rank_move", "moments", "carry_chunk_sums", "carry_chunk_scan", "carry_apply",
+    "field_push", "step_finish"};
 
 // What all members of a handle share, and the handle's capacities.
 struct Layout {
@@ -1327,14 +1320,16 @@ struct Extent {
 
 // Per-member sizes.
 struct MemberShape {
-    uint32_t nt, nc, nb;
+    uint32_t nt, nc, nb, cl;
 };
 
 MemberShape member_shape(int64_t n)
 {
     MemberShape m;
     m.nt = (uint32_t)((n + kWave - 1) / kWave);
-    m.nc = (m.nt + kChunk - 1) / kChunk;
+    m.cl = kChunkMin;
+    while (m.cl < (uint32_t)kChunkMax && (uint64_t)m.cl * kChunkTarget < m.nt) m.cl *= 2;
+    m.nc = (m.nt + m.cl - 1) / m.cl;
     m.nb = (uint32_t)std::max<int64_t>(1, n / kBucketOccupancy);
     return m;
 }
@@ -1381,8 +1376,10 @@ bool check_member_scalars(const sim_member *m, std::string *why)
     return true;
 }
 
-bool make_layout(const sim_params *p, int64_t slots, int32_t max_members, Layout *lo,
-                 std::string *why)
+// chunks < 0: room for any mix of members (every tile in the shortest
+// chunks, plus one partial chunk per member); else exactly that many.
+bool make_layout(const sim_params *p, int64_t slots, int32_t max_members, int64_t chunks,
+                 Layout *lo, std::string *why)
 {
     if (!check_common(p, why)) return false;
     if (slots <= 0 || slots > 0x7fffffffLL - kWave) { *why = "slot capacity must be in [1, 2^31 - 64)"; return false; }
@@ -1395,7 +1392,8 @@ bool make_layout(const sim_params *p, int64_t slots, int32_t max_members, Layout
     lo->n_tiles = (int)((slots + kWave - 1) / kWave);
     lo->n_members = max_members;
     // every member rounds its chunks and buckets up by at most one
-    lo->n_chunks = (lo->n_tiles + kChunk - 1) / kChunk + (max_members > 1 ? max_members : 0);
+    lo->n_chunks = chunks >= 0 ? (int)std::max<int64_t>(1, chunks)
+                               : (lo->n_tiles + kChunkMin - 1) / kChunkMin + max_members;
     lo->nb = (int)std::max<int64_t>(1, slots / kBucketOccupancy) + (max_members > 1 ? max_members : 0);
     lo->nb_blocks = (lo->nb + kScanPerBlock - 1) / kScanPerBlock;
     return true;
@@ -1487,7 +1485,7 @@ struct sim {
     uint64_t *tkey = nullptr;
     uint32_t *bkt = nullptr, *sub = nullptr, *tuid = nullptr, *tidx = nullptr, *tbkt = nullptr,
              *hist = nullptr, *off = nullptr, *bsum = nullptr;
-    double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr, *Kc = nullptr,
+    double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr,
            *coef = nullptr, *tables = nullptr, *Eout = nullptr, *qpre = nullptr;
     int *chl = nullptr;
     float *coef32 = nullptr, *tables32 = nullptr;
@@ -1582,7 +1580,6 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->chunkS, (size_t)lo.n_chunks * (lo.C2 + 1));
     al.add(&h->chunkC, (size_t)lo.n_chunks * (lo.C2 + 1));
     al.add(&h->T, (size_t)lo.n_members * std::max(lo.C, 1));
-    al.add(&h->Kc, (size_t)lo.n_members * std::max(lo.C, 1));
     al.add(&h->tables, tables_len(lo.L));
     al.add(&h->chl, (size_t)std::max(lo.C, 1));
     al.add(&h->Eout, 3 * n);
@@ -1678,8 +1675,6 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], s);
     };
-    mark(KN_SORT_CLEAR);
-    k_sort_clear<<<(ex.nb + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(h->hist, ex.nb);
     mark(KN_SORT_KEY);
     k_sort_key<<<gN, kBlock, 0, s>>>(mp, h->A, h->dead, h->key, h->bkt, h->sub, h->hist, kp);
     mark(KN_SCAN_A);
@@ -1688,8 +1683,6 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     k_scan_b<<<1, kBlock, 0, s>>>(h->bsum, ex.nb_blocks);
     mark(KN_SCAN_C);
     k_scan_c<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, ex.nb);
-    mark(KN_MEMBER_LIVE);
-    k_member_live<<<gM, kBlock, 0, s>>>(mp, h->off, kp);
     mark(KN_SORT_SCATTER);
     k_sort_scatter<<<gN, kBlock, 0, s>>>(h->key, h->A.uid, h->bkt, h->sub, h->off, h->tkey,
                                          h->tuid, h->tidx, h->tbkt, kp);
@@ -1704,10 +1697,8 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     mark(KN_CHUNK_SCAN);
     k_chunk_scan<<<dim3((lo.C2 + 1 + kWavesPerBlock - 1) / kWavesPerBlock, ex.n_members), kBlock, 0,
                    s>>>(mp, h->chunkS, h->chunkC, h->T, kp);
-    mark(KN_COEF_PREP);
-    k_coef_prep<<<ex.n_members, kBlock, 0, s>>>(mp, h->T, h->tb, kp, h->Kc);
     mark(KN_CHUNK_APPLY);
-    k_chunk_apply<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkC, h->Kc, h->tb, kp,
+    k_chunk_apply<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkC, h->T, h->tb, kp,
                                                            h->lgrho, h->coef, h->coef32, h->qpre);
     mark(KN_FIELD_PUSH);
 #define MRP_FIELD(FULLV, FO, F32)                                                              \
@@ -1874,7 +1865,8 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
         hipMemcpy(h->ctl, ctls.data(), sizeof(Ctl) * ctls.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->tile_member, none_t.data(), 4 * none_t.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->chunk_member, none_c.data(), 4 * none_c.size(), hipMemcpyHostToDevice) ||
-        hipMemset(h->dead, 0, (size_t)lo.n_tiles * kWave))
+        hipMemset(h->dead, 0, (size_t)lo.n_tiles * kWave) ||
+        hipMemset(h->hist, 0, sizeof(uint32_t) * ((size_t)lo.nb + 1)))
         return fail(SIM_EDEVICE, "upload failed");
 
     if (hipDeviceSynchronize() != hipSuccess) return fail(SIM_EDEVICE, "device sync failed");
@@ -1995,6 +1987,7 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     sg.nt = sh.nt;
     sg.c0 = c0;
     sg.nc = sh.nc;
+    sg.cl = sh.cl;
     sg.b0 = b0;
     sg.nb = sh.nb;
     sg.inv_vol = 1.0 / (m->r_out * m->r_out * m->r_out - 1.0);
@@ -2190,17 +2183,30 @@ void sim_member_default(sim_member *m)
     *m = member_from_params(&p, 0, nullptr, nullptr, nullptr, nullptr, 0, 0);
 }
 
-int64_t sim_batch_footprint_bytes(const sim_params *common, int64_t slot_capacity,
-                                  int32_t max_members)
+}  // extern "C"
+
+namespace {
+
+int64_t footprint(const sim_params *common, int64_t slots, int32_t max_members, int64_t chunks)
 {
     Layout lo;
     std::string why;
-    if (!make_layout(common, slot_capacity, max_members, &lo, &why)) return fail(SIM_EINVAL, why);
+    if (!make_layout(common, slots, max_members, chunks, &lo, &why)) return fail(SIM_EINVAL, why);
     sim tmp;
     tmp.lo = lo;
     Alloc al;
     plan_alloc(&tmp, al);
     return (int64_t)al.total();
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sim_batch_footprint_bytes(const sim_params *common, int64_t slot_capacity,
+                                  int32_t max_members)
+{
+    return footprint(common, slot_capacity, max_members, -1);
 }
 
 int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps)
@@ -2209,7 +2215,7 @@ int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps)
     if (!check_common(p, &why)) return fail(SIM_EINVAL, why);
     sim_member m = member_from_params(p, n, nullptr, nullptr, nullptr, nullptr, n_steps, 0);
     if (!check_member_scalars(&m, &why)) return fail(SIM_EINVAL, why);
-    const int64_t shared = sim_batch_footprint_bytes(p, slots_for(n), 1);
+    const int64_t shared = footprint(p, slots_for(n), 1, member_shape(n).nc);
     if (shared < 0) return shared;
     return shared + (int64_t)member_bytes(n_steps, 0);
 }
@@ -2222,19 +2228,23 @@ int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t ma
     if (n_members < 0 || (n_members > 0 && !members)) return fail(SIM_EINVAL, "bad member list");
     std::string why;
     if (!check_common(common, &why)) return fail(SIM_EINVAL, why);
-    int64_t need = 0;
+    int64_t need = 0, chunks = 0;
     std::vector<Prepared> prep((size_t)n_members);
     for (int32_t i = 0; i < n_members; ++i) {
         if (prepare_member(&members[i], &prep[i]))
             return fail(SIM_EINVAL, "member " + std::to_string(i) + ": " + g_last_error);
         need += slots_for(members[i].n);
+        chunks += member_shape(members[i].n).nc;
     }
+    // exactly the initial members, or room for any later mix
+    const bool exact = slot_capacity == 0 && (max_members == 0 || max_members == n_members);
     if (max_members == 0) max_members = n_members;
     if (max_members < n_members) return fail(SIM_EINVAL, "max_members < n_members");
     if (slot_capacity == 0) slot_capacity = need;
     if (slot_capacity < need) return fail(SIM_ENOMEM, "members need more slots than slot_capacity");
     Layout lo;
-    if (!make_layout(common, slot_capacity, max_members, &lo, &why)) return fail(SIM_EINVAL, why);
+    if (!make_layout(common, slot_capacity, max_members, exact ? chunks : -1, &lo, &why))
+        return fail(SIM_EINVAL, why);
     sim *h = new (std::nothrow) sim();
     if (!h) return fail(SIM_ENOMEM, "host allocation failed");
     auto bail = [&](int code) {
