@@ -242,15 +242,37 @@ __device__ inline double key_r2(double x, double y, double z)
 // Sort: exact order by (r^2, id) through volume-uniform buckets
 // ---------------------------------------------------------------------------
 
-// Key, bucket and slot inside the bucket, over all particle slots.  A wave
-// is one tile and so lies in one member.  Lanes of a wave that fall into the
-// same bucket (particles arrive nearly sorted, so a wave touches few buckets)
-// take one atomic add together; its return value is the group's first slot.
-__global__ void k_sort_key(Map mp, State A, const uint8_t *dead, uint64_t *key, uint32_t *bkt,
-                           uint32_t *sub, uint32_t *hist, KParams kp)
+// Bucket of a key: a monotone non-decreasing map of r^2 to the member's
+// buckets [b0, b0 + nb) by enclosed shell volume.  The sort and the rank
+// kernels both use this one expression, so they agree bit for bit.
+__device__ inline uint32_t bucket_of(double r2, double inv_vol, uint32_t b0, uint32_t nb)
+{
+    const double t = (r2 * sqrt(r2) - 1.0) * inv_vol * (double)nb;
+    uint32_t lb;
+    if (!(t > 0.0)) lb = 0;
+    else if (!(t < (double)(nb - 1))) lb = nb - 1;
+    else lb = (uint32_t)t;
+    return b0 + lb;
+}
+
+// Sort records: (key, bucket, slot in the bucket) per particle slot, then
+// (key, id, source slot) per position in bucket order; one 16-byte access each.
+struct alignas(16) KeyRec {
+    uint64_t key;
+    uint32_t bkt, sub;
+};
+struct alignas(16) OrdRec {
+    uint64_t key;
+    uint32_t uid, idx;
+};
+
+// Key, bucket and slot inside the bucket, over all particle slots.  One
+// step moves a particle across ~10^2 buckets, so the lanes of a wave land in
+// almost distinct buckets: each takes its slot with its own atomic add.
+__global__ void k_sort_key(Map mp, State A, const uint8_t *dead, KeyRec *krec, uint32_t *hist,
+                           KParams kp)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
     const uint32_t tile = i >> 6;
     if ((int)tile >= kp.n_tiles) return;   // whole waves: i < 64 * n_tiles
     const uint32_t mb = uniform_u32(mp.tile_member[tile]);
@@ -267,40 +289,14 @@ __global__ void k_sort_key(Map mp, State A, const uint8_t *dead, uint64_t *key, 
             nb = sg.nb;
         }
     }
-    uint32_t b = kNone;
+    KeyRec rec{0ull, kNone, 0u};
     if (live) {
         const double r2 = key_r2(A.x[i], A.y[i], A.z[i]);
-        key[i] = (uint64_t)__double_as_longlong(r2);
-        // Monotone non-decreasing map of r^2 to [0, nb): enclosed shell volume.
-        const double t = (r2 * sqrt(r2) - 1.0) * inv_vol * (double)nb;
-        uint32_t lb;
-        if (!(t > 0.0)) lb = 0;
-        else if (!(t < (double)(nb - 1))) lb = nb - 1;
-        else lb = (uint32_t)t;
-        b = b0 + lb;
+        rec.key = (uint64_t)__double_as_longlong(r2);
+        rec.bkt = bucket_of(r2, inv_vol, b0, nb);
+        rec.sub = atomicAdd(&hist[rec.bkt], 1u);
     }
-    bkt[i] = b;
-    // Group the lanes by bucket (no memory traffic), then every group leader
-    // adds its group's count in one atomic instruction.
-    uint64_t todo = __ballot(live);
-    const uint64_t below = (1ull << lane) - 1ull;
-    int my_leader = lane;
-    uint32_t my_rank = 0, my_count = 0;
-    while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const uint32_t bl = (uint32_t)__builtin_amdgcn_readlane((int)b, leader);
-        const uint64_t grp = __ballot(live && b == bl) & todo;
-        if ((grp >> lane) & 1ull) {
-            my_leader = leader;
-            my_rank = (uint32_t)__popcll(grp & below);
-        }
-        if (lane == leader) my_count = (uint32_t)__popcll(grp);
-        todo &= ~grp;
-    }
-    uint32_t base = 0;
-    if (live && my_leader == lane) base = atomicAdd(&hist[b], my_count);
-    base = (uint32_t)__shfl((int)base, my_leader);
-    if (live) sub[i] = base + my_rank;
+    krec[i] = rec;
 }
 
 // Exclusive scan of a u32 array of length n into out[0..n], out[n] = total.
@@ -395,20 +391,15 @@ __device__ inline void member_live(const Map &mp, const uint32_t *off, const KPa
     }
 }
 
-// Bucket order (arbitrary inside a bucket): key, id and source index.
-__global__ void k_sort_scatter(const uint64_t *key, const uint32_t *uid, const uint32_t *bkt,
-                               const uint32_t *sub, const uint32_t *off, uint64_t *tkey,
-                               uint32_t *tuid, uint32_t *tidx, uint32_t *tbkt, KParams kp)
+// Bucket order (arbitrary inside a bucket): key, id and source slot.
+__global__ void k_sort_scatter(const KeyRec *krec, const uint32_t *uid, const uint32_t *off,
+                               OrdRec *orec, KParams kp)
 {
     const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= (uint32_t)kp.n_tiles * kWave) return;
-    const uint32_t b = bkt[i];
-    if (b == kNone) return;
-    const uint32_t pos = off[b] + sub[i];
-    tkey[pos] = key[i];
-    tuid[pos] = uid[i];
-    tidx[pos] = i;
-    tbkt[pos] = b;
+    const KeyRec r = krec[i];
+    if (r.bkt == kNone) return;
+    orec[off[r.bkt] + r.sub] = OrdRec{r.key, uid[i], i};
 }
 
 // Final position = bucket start + number of bucket mates with a smaller
@@ -417,10 +408,15 @@ __global__ void k_sort_scatter(const uint64_t *key, const uint32_t *uid, const u
 // cover a window of whole buckets, staged in LDS when it fits.
 constexpr int kRankWindow = 2048;
 
-__global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const uint64_t *tkey,
-                                                           const uint32_t *tuid, const uint32_t *tidx,
-                                                           const uint32_t *tbkt, const uint32_t *off,
-                                                           State A, State B, KParams kp)
+__device__ inline uint32_t bucket_of_rec(const Map &mp, const OrdRec &r)
+{
+    const Seg &sg = mp.seg[mp.tile_member[r.idx >> 6]];
+    return bucket_of(__longlong_as_double((long long)r.key), sg.inv_vol, sg.b0, sg.nb);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec *orec,
+                                                           const uint32_t *off, State A, State B,
+                                                           KParams kp)
 {
     __shared__ uint64_t wkey[kRankWindow];
     __shared__ uint32_t wuid[kRankWindow];
@@ -429,21 +425,24 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const uint64_
     const uint32_t p0 = xcd_block(blockIdx.x, gridDim.x) * kBlock;
     if (p0 >= n) return;
     const uint32_t p_last = min(p0 + kBlock, n) - 1;
-    const uint32_t w0 = off[tbkt[p0]], w1 = off[tbkt[p_last] + 1];
+    const uint32_t w0 = off[bucket_of_rec(mp, orec[p0])];
+    const uint32_t w1 = off[bucket_of_rec(mp, orec[p_last]) + 1];
     const bool staged = (w1 - w0) <= (uint32_t)kRankWindow;
     if (staged) {
         for (uint32_t j = w0 + threadIdx.x; j < w1; j += kBlock) {
-            wkey[j - w0] = tkey[j];
-            wuid[j - w0] = tuid[j];
+            const OrdRec r = orec[j];
+            wkey[j - w0] = r.key;
+            wuid[j - w0] = r.uid;
         }
     }
     __syncthreads();
     const uint32_t p = p0 + threadIdx.x;
     if (p >= n) return;
-    const uint32_t b = tbkt[p];
+    const OrdRec me = orec[p];
+    const uint32_t b = bucket_of_rec(mp, me);
     const uint32_t lo = off[b], hi = off[b + 1];
-    const uint64_t k = tkey[p];
-    const uint32_t u = tuid[p];
+    const uint64_t k = me.key;
+    const uint32_t u = me.uid;
     uint32_t rank = 0;
     if (staged) {
         for (uint32_t j = lo - w0; j < hi - w0; ++j) {
@@ -452,11 +451,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const uint64_
         }
     } else {
         for (uint32_t j = lo; j < hi; ++j) {
-            const uint64_t kj = tkey[j];
-            rank += (kj < k) || (kj == k && tuid[j] < u);
+            const OrdRec rj = orec[j];
+            rank += (rj.key < k) || (rj.key == k && rj.uid < u);
         }
     }
-    const uint32_t i = tidx[p];
+    const uint32_t i = me.idx;
     const Seg &sg = mp.seg[mp.tile_member[i >> 6]];
     const uint32_t d = sg.p0 + (lo + rank - off[sg.b0]);
     B.x[d] = A.x[i];
@@ -1481,10 +1480,9 @@ struct sim {
     State A{}, B{};
     Grave G{};
     uint8_t *dead = nullptr;
-    uint64_t *key = nullptr;
-    uint64_t *tkey = nullptr;
-    uint32_t *bkt = nullptr, *sub = nullptr, *tuid = nullptr, *tidx = nullptr, *tbkt = nullptr,
-             *hist = nullptr, *off = nullptr, *bsum = nullptr;
+    KeyRec *krec = nullptr;
+    OrdRec *orec = nullptr;
+    uint32_t *hist = nullptr, *off = nullptr, *bsum = nullptr;
     double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr,
            *coef = nullptr, *tables = nullptr, *Eout = nullptr, *qpre = nullptr;
     int *chl = nullptr;
@@ -1555,13 +1553,8 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->G.vx, n); al.add(&h->G.vy, n); al.add(&h->G.vz, n);
     al.add(&h->G.uid, n);
     al.add(&h->dead, n);
-    al.add(&h->key, n);
-    al.add(&h->bkt, n);
-    al.add(&h->sub, n);
-    al.add(&h->tkey, n);
-    al.add(&h->tuid, n);
-    al.add(&h->tidx, n);
-    al.add(&h->tbkt, n);
+    al.add(&h->krec, n);
+    al.add(&h->orec, n);
     al.add(&h->hist, (size_t)lo.nb + 1);
     al.add(&h->off, (size_t)lo.nb + 1);
     al.add(&h->bsum, (size_t)lo.nb_blocks + 1);
@@ -1676,7 +1669,7 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
         if (ev) (void)hipEventRecord(ev[k], s);
     };
     mark(KN_SORT_KEY);
-    k_sort_key<<<gN, kBlock, 0, s>>>(mp, h->A, h->dead, h->key, h->bkt, h->sub, h->hist, kp);
+    k_sort_key<<<gN, kBlock, 0, s>>>(mp, h->A, h->dead, h->krec, h->hist, kp);
     mark(KN_SCAN_A);
     k_scan_a<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, ex.nb);
     mark(KN_SCAN_B);
@@ -1684,11 +1677,9 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     mark(KN_SCAN_C);
     k_scan_c<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, ex.nb);
     mark(KN_SORT_SCATTER);
-    k_sort_scatter<<<gN, kBlock, 0, s>>>(h->key, h->A.uid, h->bkt, h->sub, h->off, h->tkey,
-                                         h->tuid, h->tidx, h->tbkt, kp);
+    k_sort_scatter<<<gN, kBlock, 0, s>>>(h->krec, h->A.uid, h->off, h->orec, kp);
     mark(KN_SORT_RANK);
-    k_sort_rank_move<<<gN, kBlock, 0, s>>>(mp, h->tkey, h->tuid, h->tidx, h->tbkt, h->off, h->A,
-                                           h->B, kp);
+    k_sort_rank_move<<<gN, kBlock, 0, s>>>(mp, h->orec, h->off, h->A, h->B, kp);
     mark(KN_MOMENTS);
     if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
     else k_moments<false><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
