@@ -69,9 +69,19 @@ int fail(int code, const std::string &msg)
 // Device-side structures
 // ---------------------------------------------------------------------------
 
+// Sorted state (this step's radial order), one array per component: the
+// moments and field kernels read it with unit stride.
 struct State {
     double *x, *y, *z, *vx, *vy, *vz;
     uint32_t *uid;
+};
+
+// Unsorted state (after the push, in the previous step's order): one 64-byte
+// record per particle, so the sort's gather of a particle from its scattered
+// source slot is a single cache line.
+struct alignas(64) PRec {
+    double x, y, z, vx, vy, vz;
+    uint32_t uid, pad[3];
 };
 
 // Per-member control block in device memory.
@@ -259,7 +269,7 @@ __device__ inline uint32_t bucket_of(double r2, double inv_vol, uint32_t b0, uin
 // (key, id, source slot) per position in bucket order; one 16-byte access each.
 struct alignas(16) KeyRec {
     uint64_t key;
-    uint32_t bkt, sub;
+    uint32_t uid, sub;   // sub = kNone: not sorted this step
 };
 struct alignas(16) OrdRec {
     uint64_t key;
@@ -269,8 +279,8 @@ struct alignas(16) OrdRec {
 // Key, bucket and slot inside the bucket, over all particle slots.  One
 // step moves a particle across ~10^2 buckets, so the lanes of a wave land in
 // almost distinct buckets: each takes its slot with its own atomic add.
-__global__ void k_sort_key(Map mp, State A, const uint8_t *dead, KeyRec *krec, uint32_t *hist,
-                           KParams kp)
+__global__ void k_sort_key(Map mp, const PRec *A, const uint8_t *dead, KeyRec *krec,
+                           uint32_t *hist, KParams kp)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t tile = i >> 6;
@@ -289,12 +299,12 @@ __global__ void k_sort_key(Map mp, State A, const uint8_t *dead, KeyRec *krec, u
             nb = sg.nb;
         }
     }
-    KeyRec rec{0ull, kNone, 0u};
+    KeyRec rec{0ull, 0u, kNone};
     if (live) {
-        const double r2 = key_r2(A.x[i], A.y[i], A.z[i]);
+        const double r2 = key_r2(A[i].x, A[i].y, A[i].z);
         rec.key = (uint64_t)__double_as_longlong(r2);
-        rec.bkt = bucket_of(r2, inv_vol, b0, nb);
-        rec.sub = atomicAdd(&hist[rec.bkt], 1u);
+        rec.uid = A[i].uid;
+        rec.sub = atomicAdd(&hist[bucket_of(r2, inv_vol, b0, nb)], 1u);
     }
     krec[i] = rec;
 }
@@ -392,14 +402,18 @@ __device__ inline void member_live(const Map &mp, const uint32_t *off, const KPa
 }
 
 // Bucket order (arbitrary inside a bucket): key, id and source slot.
-__global__ void k_sort_scatter(const KeyRec *krec, const uint32_t *uid, const uint32_t *off,
-                               OrdRec *orec, KParams kp)
+__global__ void k_sort_scatter(Map mp, const KeyRec *krec, const uint32_t *off, OrdRec *orec,
+                               KParams kp)
 {
     const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= (uint32_t)kp.n_tiles * kWave) return;
     const KeyRec r = krec[i];
-    if (r.bkt == kNone) return;
-    orec[off[r.bkt] + r.sub] = OrdRec{r.key, uid[i], i};
+    if (r.sub == kNone) return;
+    // the bucket again, from the key and the member of this slot's tile (the
+    // same arithmetic as in the key kernel, so the same bucket)
+    const Seg &sg = mp.seg[mp.tile_member[i >> 6]];
+    const uint32_t b = bucket_of(__longlong_as_double((long long)r.key), sg.inv_vol, sg.b0, sg.nb);
+    orec[off[b] + r.sub] = OrdRec{r.key, r.uid, i};
 }
 
 // Final position = bucket start + number of bucket mates with a smaller
@@ -415,7 +429,8 @@ __device__ inline uint32_t bucket_of_rec(const Map &mp, const OrdRec &r)
 }
 
 __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec *orec,
-                                                           const uint32_t *off, State A, State B,
+                                                           const uint32_t *off, const PRec *A,
+                                                           State B,
                                                            KParams kp)
 {
     __shared__ uint64_t wkey[kRankWindow];
@@ -458,12 +473,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec 
     const uint32_t i = me.idx;
     const Seg &sg = mp.seg[mp.tile_member[i >> 6]];
     const uint32_t d = sg.p0 + (lo + rank - off[sg.b0]);
-    B.x[d] = A.x[i];
-    B.y[d] = A.y[i];
-    B.z[d] = A.z[i];
-    B.vx[d] = A.vx[i];
-    B.vy[d] = A.vy[i];
-    B.vz[d] = A.vz[i];
+    const PRec a = A[i];
+    B.x[d] = a.x;
+    B.y[d] = a.y;
+    B.z[d] = a.z;
+    B.vx[d] = a.vx;
+    B.vy[d] = a.vy;
+    B.vz[d] = a.vz;
     B.uid[d] = u;
 }
 
@@ -1023,7 +1039,7 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
 }
 
 template <bool FULL, bool FIELD_ONLY, bool FP32>
-__global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A, uint8_t *dead,
+__global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, PRec *A, uint8_t *dead,
                                                        Grave G, const double *coef,
                                                        const float *coef32, const double *qpre,
                                                        Tables tb, KParams kp, double *Eout,
@@ -1249,13 +1265,16 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, State A,
             }
         }
     }
-    A.x[p] = x;
-    A.y[p] = y;
-    A.z[p] = z;
-    A.vx[p] = vx;
-    A.vy[p] = vy;
-    A.vz[p] = vz;
-    A.uid[p] = uid;
+    PRec out;
+    out.x = x;
+    out.y = y;
+    out.z = z;
+    out.vx = vx;
+    out.vy = vy;
+    out.vz = vz;
+    out.uid = uid;
+    out.pad[0] = out.pad[1] = out.pad[2] = 0u;
+    A[p] = out;
     dead[p] = absorbed;
     if (absorbed) {
         if (ion) atomicAdd(&ct.n_dead_ion, 1u);
@@ -1477,7 +1496,8 @@ struct sim {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
-    State A{}, B{};
+    PRec *A = nullptr;
+    State B{};
     Grave G{};
     uint8_t *dead = nullptr;
     KeyRec *krec = nullptr;
@@ -1544,11 +1564,10 @@ void plan_alloc(sim *h, Alloc &al)
 {
     const Layout &lo = h->lo;
     const size_t n = (size_t)lo.n_tiles * kWave;
-    for (State *s : {&h->A, &h->B}) {
-        al.add(&s->x, n); al.add(&s->y, n); al.add(&s->z, n);
-        al.add(&s->vx, n); al.add(&s->vy, n); al.add(&s->vz, n);
-        al.add(&s->uid, n);
-    }
+    al.add(&h->A, n);
+    al.add(&h->B.x, n); al.add(&h->B.y, n); al.add(&h->B.z, n);
+    al.add(&h->B.vx, n); al.add(&h->B.vy, n); al.add(&h->B.vz, n);
+    al.add(&h->B.uid, n);
     al.add(&h->G.x, n); al.add(&h->G.y, n); al.add(&h->G.z, n);
     al.add(&h->G.vx, n); al.add(&h->G.vy, n); al.add(&h->G.vz, n);
     al.add(&h->G.uid, n);
@@ -1677,7 +1696,7 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     mark(KN_SCAN_C);
     k_scan_c<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, ex.nb);
     mark(KN_SORT_SCATTER);
-    k_sort_scatter<<<gN, kBlock, 0, s>>>(h->krec, h->A.uid, h->off, h->orec, kp);
+    k_sort_scatter<<<gN, kBlock, 0, s>>>(mp, h->krec, h->off, h->orec, kp);
     mark(KN_SORT_RANK);
     k_sort_rank_move<<<gN, kBlock, 0, s>>>(mp, h->orec, h->off, h->A, h->B, kp);
     mark(KN_MOMENTS);
@@ -2039,11 +2058,18 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
         h->failed = true;
         return undo(fail(SIM_EDEVICE, "stream synchronisation failed"));
     }
-    std::vector<double> col((size_t)n);
-    auto up = [&](double *dst, const double *src, int j) -> hipError_t {
-        for (int64_t i = 0; i < n; ++i) col[i] = src[3 * i + j];
-        return hipMemcpy(dst + sg.p0, col.data(), sizeof(double) * n, hipMemcpyHostToDevice);
-    };
+    std::vector<PRec> recs((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        PRec &r = recs[i];
+        r.x = m->pos[3 * i];
+        r.y = m->pos[3 * i + 1];
+        r.z = m->pos[3 * i + 2];
+        r.vx = m->vel[3 * i];
+        r.vy = m->vel[3 * i + 1];
+        r.vz = m->vel[3 * i + 2];
+        r.uid = uid[i];
+        r.pad[0] = r.pad[1] = r.pad[2] = 0u;
+    }
     Ctl ctl{};
     ctl.step = m->start_step;
     ctl.n_cur = (uint32_t)n;
@@ -2052,9 +2078,7 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     ctl.q_surface = m->q_surface0;
     std::vector<double> zeros(ns, 0.0);
     std::vector<uint32_t> tm(sh.nt, (uint32_t)slot), cm(sh.nc, (uint32_t)slot);
-    if (up(h->A.x, m->pos, 0) || up(h->A.y, m->pos, 1) || up(h->A.z, m->pos, 2) ||
-        up(h->A.vx, m->vel, 0) || up(h->A.vy, m->vel, 1) || up(h->A.vz, m->vel, 2) ||
-        hipMemcpy(h->A.uid + sg.p0, uid.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice) ||
+    if (hipMemcpy(h->A + sg.p0, recs.data(), sizeof(PRec) * n, hipMemcpyHostToDevice) ||
         hipMemset(h->dead + sg.p0, 0, sg.cap) ||
         hipMemcpy(q_dev, zeros.data(), 8 * ns, hipMemcpyHostToDevice) ||
         (m->n_steps > 0 && hipMemcpy(u_dev, m->u_asy, 8 * m->n_steps, hipMemcpyHostToDevice)) ||
@@ -2387,19 +2411,24 @@ int sim_member_read_state(sim_t *h, int32_t index, double *pos, double *vel, uin
     std::vector<double> a[6], g[6];
     std::vector<uint32_t> au(na), gu(ng);
     std::vector<uint8_t> ad(na);
-    double *srcA[6] = {h->A.x, h->A.y, h->A.z, h->A.vx, h->A.vy, h->A.vz};
+    std::vector<PRec> ar(na);
     double *srcG[6] = {h->G.x, h->G.y, h->G.z, h->G.vx, h->G.vy, h->G.vz};
     for (int j = 0; j < 6; ++j) {
-        a[j].resize(na);
         g[j].resize(ng);
-        if ((na && hipMemcpy(a[j].data(), srcA[j] + p0, 8 * na, hipMemcpyDeviceToHost)) ||
-            (ng && hipMemcpy(g[j].data(), srcG[j] + p0, 8 * ng, hipMemcpyDeviceToHost)))
+        if (ng && hipMemcpy(g[j].data(), srcG[j] + p0, 8 * ng, hipMemcpyDeviceToHost))
             return mark_failed(h, fail(SIM_EDEVICE, "state copy failed"));
     }
-    if ((na && (hipMemcpy(au.data(), h->A.uid + p0, 4 * na, hipMemcpyDeviceToHost) ||
+    if ((na && (hipMemcpy(ar.data(), h->A + p0, sizeof(PRec) * na, hipMemcpyDeviceToHost) ||
                 hipMemcpy(ad.data(), h->dead + p0, na, hipMemcpyDeviceToHost))) ||
         (ng && hipMemcpy(gu.data(), h->G.uid + p0, 4 * ng, hipMemcpyDeviceToHost)))
         return mark_failed(h, fail(SIM_EDEVICE, "state copy failed"));
+    for (int j = 0; j < 6; ++j) a[j].resize(na);
+    for (size_t i = 0; i < na; ++i) {
+        const PRec &r = ar[i];
+        a[0][i] = r.x; a[1][i] = r.y; a[2][i] = r.z;
+        a[3][i] = r.vx; a[4][i] = r.vy; a[5][i] = r.vz;
+        au[i] = r.uid;
+    }
     auto find = [&](uint32_t u) -> int64_t {
         auto it = std::lower_bound(mb.id_index.begin(), mb.id_index.end(),
                                    std::make_pair(u, (int64_t)-1));
