@@ -139,10 +139,22 @@ struct Tables {
     // m = 0..m_top outer, l = m..L inner, so a loop over (m, l) reads
     // consecutive entries, and the integer factors need no conversion
     const double4 *abw;
+    // Legendre constants of the full near field, per l: {c_l, l c_l,
+    // gamma_{l+1}, (2l+1) c_l}, where P_l = c_l Ph_l and the rescaled
+    // polynomials obey Ph_{l+1} = u Ph_l - gamma_{l+1} Ph_{l-1}
+    const double4 *lg4;
+    // Far-field recurrence in stream order of (m, l): the field kernel uses
+    // Qh_l^m = Q_l^m / N_lm with Qh_m^m = 1, Qh_l^m = z Qh_{l-1}^m -
+    // gamma_lm r^2 Qh_{l-2}^m; entries {gamma_lm, l - m, l + m + 1, 0}.  The
+    // coefficients carry the factor N_lm instead (chn, per channel).
+    const double4 *fq4;
+    const double *chn;
     // FP32 copies for the FP32-compensated mode
     const float *qmm32, *alm32, *blm32;
     const float4 *nf4_32;
     const float4 *abw32;
+    const float4 *lg4_32;
+    const float4 *fq4_32;
 };
 
 // Channels are kept in "stream order": m = 0..m_top outer, l = max(m,1)..L
@@ -772,18 +784,19 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *S,
         }
     } else if (c < kp.C) {
         const int l = tb.chl[c];
+        const double nrm = tb.chn[c];
         const double w = tb.wl[l] * inv_nt;
         double k = -tb.ftil[l] * Ts[c] * w;
         if (c < kp.L && in_run) k += sg.u_asy[step] * tb.drive_w[l];
         for (int t = t0; t < t1; ++t) {
-            const double v = run * w + k;
+            const double v = (run * w + k) * nrm;
             if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2(-(l + 1.0) * lgrho[t]));
             else coef[(size_t)t * kp.C2 + c] = v;
             run += S[(size_t)t * kp.SW + c];
         }
     } else {
         const int l = tb.chl[c - kp.C];
-        const double w = tb.wl[l] * inv_nt;
+        const double w = tb.wl[l] * inv_nt * tb.chn[c - kp.C];
         for (int t = t1 - 1; t >= t0; --t) {
             const double v = run * w;
             if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2((double)l * lgrho[t]));
@@ -853,87 +866,116 @@ struct Grave {
 // Far field of all other tiles through this tile's coefficient vector
 // (interior alpha then exterior beta, stream order), evaluated at scaled
 // coordinates xi = x / rho in the working precision R; returns grad_xi Phi.
-//   Phi(xi) = sum_lm Q_l^m(z, r^2) U_lm,
+//   Phi(xi) = sum_lm Qh_l^m(z, r^2) U_lm,
 //   U_lm = (beta + s_l alpha)^c C_m + (beta + s_l alpha)^s S_m,  s_l = r^-(2l+1),
 //   V_lm = alpha^c C_m + alpha^s S_m,
-// with Q_l^m = a z Q_{l-1}^m - b r^2 Q_{l-2}^m and D_z Q its z-derivative at
-// fixed r^2.  Q_l^m C_m is homogeneous of degree l, so the radial derivative is
-// exact by Euler's relation and only D_z Q enters the tangential part:
-//   grad Phi = rhat (1/r) sum [(l - m) Q U - (2l+1) s_l Q V]
-//              + (e_z - cos th rhat) sum U D_z Q + (sum Q dU/dx, sum Q dU/dy, 0).
+// with the rescaled Qh_l^m = Q_l^m / N_lm (the coefficients carry N_lm):
+// Qh_m^m = 1, Qh_l^m = z Qh_{l-1}^m - gamma_lm r^2 Qh_{l-2}^m, and D_z Qh its
+// z-derivative at fixed r^2, D_z Qh_l = Qh_{l-1} + z D_z Qh_{l-1} - gamma r^2
+// D_z Qh_{l-2}.  Qh_l^m C_m is homogeneous of degree l, so the radial
+// derivative is exact by Euler's relation and only D_z Qh enters the
+// tangential part:
+//   grad Phi = rhat (1/r) sum [(l - m) Qh U - (2l+1) s_l Qh V]
+//              + (e_z - cos th rhat) sum U D_z Qh + (sum Qh dU/dx, sum Qh dU/dy, 0).
 // (Assembling the radial part from the two partial derivatives of Q instead
 // loses a factor ~l to cancellation.)
 template <bool FULL, typename R, typename R4>
-__device__ inline void far_field(const R *cf, int C, int L, const R4 *ab, R x, R y, R z, R &gx,
+__device__ inline void far_field(const R *cf, int C, int L, const R4 *fq, R x, R y, R z, R &gx,
                                  R &gy, R &gz)
 {
     const R r2 = x * x + y * y + z * z;
     const R inv_r2 = rcp_r(r2);
     const R inv_r = rsq_r(r2);
     R Ga = 0, Gz = 0, Gx = 0, Gy = 0;
-    // m = 0: cos channels only, stream position k = l - 1; l = 0 (Q_0^0) only
-    // seeds the recurrence, its field is Gauss's law in the caller
+    // With t_c = b_c + s_l a_c (s_l = r^-(2l+1)) each (l, m) adds to the radial
+    // sum Qh [(l - m) t - (2l+1) s_l a] = (l - m) Qh b - (l + m + 1) s_l Qh a,
+    // to the D_z sum Dz t and to the sum for d/dx, d/dy of C_m, S_m Qh t: each a
+    // b part and an a part, two FMAs with the coefficient as scalar operand.
+    // m = 0: cos channels only, stream position k = l - 1; l = 0 only seeds
+    // the recurrence, its field is Gauss's law in the caller
     {
-        R Q1 = ab[0].x, Q2 = 0, Dz1 = 0, Dz2 = 0;
-        R sl = inv_r * inv_r2;   // r^-(2l+1) at l = 1
+        R Q1 = 1, Q2 = 0, D1 = 0, D2 = 0;   // Qh_{l-1}, Qh_{l-2} and their D_z
+        R sl = inv_r * inv_r2;              // r^-(2l+1) at l = 1
+#pragma unroll 2
         for (int l = 1; l <= L; ++l) {
-            const R4 e = ab[l];
-            const R az = e.x * z, br2 = e.y * r2;
-            const R Qv = az * Q1 - br2 * Q2;
-            const R Dz = e.x * Q1 + az * Dz1 - br2 * Dz2;
+            const R4 e = fq[l];
+            const R gr2 = e.x * r2;
+            const R Qv = z * Q1 - gr2 * Q2;
+            const R Dz = (Q1 + z * D1) - gr2 * D2;
+            const R ac = cf[l - 1], bc = cf[C + l - 1];
+            const R Qs = Qv * sl, Qz = e.y * Qv, Qa = e.z * Qs, Ds = Dz * sl;
+            Ga = fma(Qz, bc, Ga);
+            Ga = fma(-Qa, ac, Ga);
+            Gz = fma(Dz, bc, Gz);
+            Gz = fma(Ds, ac, Gz);
             Q2 = Q1;
             Q1 = Qv;
-            Dz2 = Dz1;
-            Dz1 = Dz;
-            const R ac = cf[l - 1], bc = cf[C + l - 1];
-            const R tc = bc + sl * ac;
-            Ga += Qv * (e.z * tc - (e.w * sl) * ac);
-            Gz += tc * Dz;
+            D2 = D1;
+            D1 = Dz;
             sl *= inv_r2;
         }
     }
     if (FULL) {
-        R Cm = 1, Sm = 0, Cm1 = 0, Sm1 = 0;
+        // C_m, S_m and C_{m-1}, S_{m-1} are common to all l of one m: the l
+        // loop sums the cos and sin parts separately, combined once per m
+        R Cm = 1, Sm = 0;
         R s_mm = inv_r;
         int j = L + 1;   // stream index of (m, l = m)
         int k = L;       // channel position of (m, l = m), cos then sin
         for (int m = 1; m <= L; ++m) {
-            Cm1 = Cm;
-            Sm1 = Sm;
+            const R Cm1 = Cm, Sm1 = Sm;
             Cm = x * Cm1 - y * Sm1;
             Sm = x * Sm1 + y * Cm1;
             s_mm *= inv_r2;
-            const R dm = (R)m;
             R sl = s_mm;
-            // one (l, m) pair of channels with Q = Q_l^m and D_z Q = Dz
-            auto pair = [&](const R4 &e, R Qv, R Dz, bool first) {
+            // l = m: Qh = 1, D_z Qh = 0
+            R Ac, As, Tc, Ts, Zc = 0, Zs = 0;
+            {
+                const R4 e = fq[j];
                 const R ac = cf[k], bc = cf[C + k], as = cf[k + 1], bs = cf[C + k + 1];
-                const R tc = bc + sl * ac;
-                const R ts = bs + sl * as;
-                const R U = tc * Cm + ts * Sm;
-                const R V = ac * Cm + as * Sm;
-                Ga += Qv * (e.z * U - (e.w * sl) * V);
-                if (!first) Gz += U * Dz;   // D_z Q_m^m = 0
-                const R mq = dm * Qv;
-                Gx += mq * (tc * Cm1 + ts * Sm1);
-                Gy += mq * (ts * Cm1 - tc * Sm1);
+                const R Qa = e.z * sl;
+                Tc = sl * ac + bc;
+                Ts = sl * as + bs;
+                Ac = -Qa * ac;
+                As = -Qa * as;
+                ++j;
                 k += 2;
                 sl *= inv_r2;
-            };
-            R Q1 = ab[j].x, Q2 = 0, Dz1 = 0, Dz2 = 0;
-            pair(ab[j], Q1, (R)0, true);
-            ++j;
-            for (int l = m + 1; l <= L; ++l, ++j) {
-                const R4 e = ab[j];
-                const R az = e.x * z, br2 = e.y * r2;
-                const R Qv = az * Q1 - br2 * Q2;
-                const R Dz = e.x * Q1 + az * Dz1 - br2 * Dz2;
+            }
+            R Q1 = 1, Q2 = 0, D1 = 0, D2 = 0;
+#pragma unroll 2
+            for (int l = m + 1; l <= L; ++l) {
+                const R4 e = fq[j];
+                const R ac = cf[k], bc = cf[C + k], as = cf[k + 1], bs = cf[C + k + 1];
+                const R gr2 = e.x * r2;
+                const R Qv = z * Q1 - gr2 * Q2;
+                const R Dz = (Q1 + z * D1) - gr2 * D2;
+                const R Qs = Qv * sl, Qz = e.y * Qv, Qa = e.z * Qs, Ds = Dz * sl;
+                Tc = fma(Qv, bc, Tc);
+                Tc = fma(Qs, ac, Tc);
+                Ts = fma(Qv, bs, Ts);
+                Ts = fma(Qs, as, Ts);
+                Zc = fma(Dz, bc, Zc);
+                Zc = fma(Ds, ac, Zc);
+                Zs = fma(Dz, bs, Zs);
+                Zs = fma(Ds, as, Zs);
+                Ac = fma(Qz, bc, Ac);
+                Ac = fma(-Qa, ac, Ac);
+                As = fma(Qz, bs, As);
+                As = fma(-Qa, as, As);
                 Q2 = Q1;
                 Q1 = Qv;
-                Dz2 = Dz1;
-                Dz1 = Dz;
-                pair(e, Qv, Dz, false);
+                D2 = D1;
+                D1 = Dz;
+                ++j;
+                k += 2;
+                sl *= inv_r2;
             }
+            const R dm = (R)m;
+            Ga += Cm * Ac + Sm * As;
+            Gz += Cm * Zc + Sm * Zs;
+            Gx += dm * (Tc * Cm1 + Ts * Sm1);
+            Gy += dm * (Ts * Cm1 - Tc * Sm1);
         }
     }
     const R xh = x * inv_r, yh = y * inv_r, c = z * inv_r;
@@ -955,7 +997,7 @@ __device__ inline void far_field(const R *cf, int C, int L, const R4 *ab, R x, R
 template <bool FULL, typename R, typename NF>
 __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R *sxh, const R *syh,
                                   const R *szh, const R *sr, const R *sir, const double *sr2,
-                                  const uint32_t *suid, const R *sq, R xh, R yh, R zh, R r,
+                                  const uint64_t *suid, const R *sq, R xh, R yh, R zh, R r,
                                   R inv_r, double r2, uint32_t uid, R qk, double &ax, double &ay,
                                   double &az)
 {
@@ -966,7 +1008,7 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
         const R xj = sxh[j], yj = syh[j], zj = szh[j];
         const R rj = sr[j], irj = sir[j];
         const double r2j = sr2[j];
-        const uint32_t uj = suid[j];
+        const uint32_t uj = (uint32_t)suid[j];
         const R qj = sq[j];
         const bool k_outer = (r2 > r2j) || (r2 == r2j && uid > uj);
         const R rho = k_outer ? rj * inv_r : r * irj;
@@ -1038,6 +1080,136 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
     }
 }
 
+// One wave's particles for the near field, each row written twice (entries
+// i and i + 64), so that the partner k + s and the sender k - s + 64 of a
+// lane k are plain offsets from the lane's own entry for every shift s.
+template <typename R>
+struct NearRows {
+    R xh[2 * kWave], yh[2 * kWave], zh[2 * kWave], r[2 * kWave], ir[2 * kWave], q[2 * kWave];
+    double r2[2 * kWave];
+    uint64_t uid[2 * kWave];   // 8 bytes like r2: one index scale for all rows
+};
+
+__device__ inline double bpermute(int addr, double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ inline float bpermute(int addr, float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+
+// Full near field.  Per pair (k, j), with rho = r_< / r_> and u = xh_k . xh_j:
+//   S1 = sum_l rho^l P_l(u),  Sl = sum_l l rho^l P_l(u),  SB = sum_l rho^l P'_l(u)
+// (l = 1..L) and, as above, S_in = Sl, S_out = -(Sl + S1).  For either particle
+// the scale is 1 / (r_own r_>) whether it is the inner or the outer one, and
+// grad D = (SA - SB u) xh_own + SB xh_other: a multiple of the own direction
+// plus a multiple of the other's.  Each lane sums the multiples of its own
+// direction in one number and the rest in a vector; the partner's two
+// multiples go to it by a lane permutation, and it scales the sender's
+// direction (read from LDS) itself.  Lanes without a particle carry charge 0,
+// so their terms vanish without masks.  The Legendre sums use the rescaled
+// polynomials of the lg table (a two-operation recurrence); l = 1 is peeled.
+template <typename R, typename LG>
+__device__ inline void near_field_full(int lane, int L, const LG *lg, const NearRows<R> &nr, R xh,
+                                       R yh, R zh, R r, R ir, double r2, uint32_t uid, R qk,
+                                       double &ax, double &ay, double &az)
+{
+    double dck = 0.0, dbx = 0.0, dby = 0.0, dbz = 0.0;
+    R ck = 0, bx = 0, by = 0, bz = 0;
+    auto flush = [&]() {   // partial sums of a few shifts into FP64 (FP32 mode)
+        dck += (double)ck;
+        dbx += (double)bx;
+        dby += (double)by;
+        dbz += (double)bz;
+        ck = 0;
+        bx = 0;
+        by = 0;
+        bz = 0;
+    };
+    const LG c1 = lg[1];
+    const int lane4 = lane * 4;
+    auto shift = [&](const int sft, R qk_s, bool last) {
+        const int j = lane + sft;   // partner, in the doubled row
+        const R xj = nr.xh[j], yj = nr.yh[j], zj = nr.zh[j];
+        const R rj = nr.r[j], irj = nr.ir[j];
+        const double r2j = nr.r2[j];
+        const uint32_t uj = (uint32_t)nr.uid[j];
+        const R qj = last && lane >= kWave / 2 ? (R)0 : nr.q[j];
+        const bool k_outer = (r2 > r2j) | ((r2 == r2j) & (uid > uj));
+        const R irmx = k_outer ? ir : irj;   // 1 / r_>
+        const R rmin = k_outer ? rj : r;     // r_<
+        const R rho = rmin * irmx;
+        const R u = xh * xj + yh * yj + zh * zj;
+        // l = 1: P_1 = u, P'_1 = 1.  Then two degrees per pass with the
+        // registers of Ph_l and Ph_{l-1} (and of P'_l, P'_{l-1}) trading roles
+        R S1 = rho * u, Sl = S1, SB = rho;
+        R Pa = u * u - c1.z, Pb = u, dPa = c1.w * u, dPb = 1, rl = rho * rho;
+        int l = 2;
+        for (; l < L; l += 2) {
+            const LG ca = lg[l], cb = lg[l + 1];
+            R t = rl * Pa;   // degree l from Pa
+            S1 += ca.x * t;
+            Sl += ca.y * t;
+            SB += rl * dPa;
+            Pb = u * Pa - ca.z * Pb;   // Ph_{l+1}
+            dPb += ca.w * Pa;          // P'_{l+1}
+            rl *= rho;
+            t = rl * Pb;     // degree l + 1 from Pb
+            S1 += cb.x * t;
+            Sl += cb.y * t;
+            SB += rl * dPb;
+            Pa = u * Pb - cb.z * Pa;   // Ph_{l+2}
+            dPa += cb.w * Pb;          // P'_{l+2}
+            rl *= rho;
+        }
+        if (l == L) {
+            const LG ca = lg[l];
+            const R t = rl * Pa;
+            S1 += ca.x * t;
+            Sl += ca.y * t;
+            SB += rl * dPa;
+        }
+        const R S_out = -(Sl + S1), S_in = Sl;
+        const R SAk = k_outer ? S_out : S_in, SAj = k_outer ? S_in : S_out;
+        const R wk = qj * (ir * irmx), wj = qk_s * (irj * irmx);
+        const R bk = wk * SB, bj = wj * SB;
+        ck = fma(wk, SAk, ck);
+        ck = fma(-bk, u, ck);
+        bx = fma(bk, xj, bx);
+        by = fma(bk, yj, by);
+        bz = fma(bk, zj, bz);
+        const R cj = fma(-bj, u, wj * SAj);
+        // lane k's partner is k + sft, so lane k receives from k - sft
+        const int src_addr = (lane4 + 4 * (kWave - sft)) & (4 * kWave - 1);
+        const R cr = bpermute(src_addr, cj), br = bpermute(src_addr, bj);
+        const int src = lane + kWave - sft;   // in the doubled row
+        ck += cr;
+        bx = fma(br, nr.xh[src], bx);
+        by = fma(br, nr.yh[src], by);
+        bz = fma(br, nr.zh[src], bz);
+    };
+    if constexpr (sizeof(R) == 4) {
+        for (int s0 = 1; s0 < kWave / 2; s0 += 8) {
+#pragma unroll 1
+            for (int sft = s0; sft < min(s0 + 8, kWave / 2); ++sft) shift(sft, qk, false);
+            flush();
+        }
+    } else {
+#pragma unroll 1
+        for (int sft = 1; sft < kWave / 2; ++sft) shift(sft, qk, false);
+    }
+    // the pairs (k, k + 32) and (k + 32, k) are one pair: lanes 0-31 take it
+    shift(kWave / 2, lane >= kWave / 2 ? (R)0 : qk, true);
+    flush();
+    ax += dck * (double)xh + dbx;
+    ay += dck * (double)yh + dby;
+    az += dck * (double)zh + dbz;
+}
+
 template <bool FULL, bool FIELD_ONLY, bool FP32>
 __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, PRec *A, uint8_t *dead,
                                                        Grave G, const double *coef,
@@ -1047,11 +1219,7 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, PRec *A,
 {
     using R = typename std::conditional<FP32, float, double>::type;
     using NF = typename std::conditional<FP32, float4, double4>::type;
-    __shared__ R sh_xh[kWavesPerBlock][kWave], sh_yh[kWavesPerBlock][kWave],
-        sh_zh[kWavesPerBlock][kWave], sh_r[kWavesPerBlock][kWave], sh_ir[kWavesPerBlock][kWave];
-    __shared__ double sh_r2[kWavesPerBlock][kWave];
-    __shared__ uint32_t sh_uid[kWavesPerBlock][kWave];
-    __shared__ R sh_q[kWavesPerBlock][kWave];
+    __shared__ NearRows<R> rows[kWavesPerBlock];
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -1089,16 +1257,20 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, PRec *A,
     const double inv_r = 1.0 / r;
     const double inv_r2 = 1.0 / r2;
     const double xh = x * inv_r, yh = y * inv_r, zh = z * inv_r;
-    sh_xh[w][lane] = (R)xh;
-    sh_yh[w][lane] = (R)yh;
-    sh_zh[w][lane] = (R)zh;
-    sh_r[w][lane] = (R)r;
-    sh_ir[w][lane] = (R)inv_r;
-    sh_r2[w][lane] = r2;
-    sh_uid[w][lane] = uid;
     const bool ion = valid && (uid & kIonBit);
     const double qk = ion ? 1.0 : kQ;   // this particle's charge
-    sh_q[w][lane] = valid ? (R)qk : (R)0;
+    NearRows<R> &nr = rows[w];
+    for (int c = 0; c < 2; ++c) {
+        const int i = lane + c * kWave;
+        nr.xh[i] = (R)xh;
+        nr.yh[i] = (R)yh;
+        nr.zh[i] = (R)zh;
+        nr.r[i] = (R)r;
+        nr.ir[i] = (R)inv_r;
+        nr.q[i] = valid ? (R)qk : (R)0;
+        nr.r2[i] = r2;
+        nr.uid[i] = uid;
+    }
     wave_lds_sync();   // the rows are this wave's own
     if (!tile_live) return;
 
@@ -1120,11 +1292,11 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, PRec *A,
         const double inv_rho = 1.0 / rho;
         R gx, gy, gz;
         if constexpr (FP32) {
-            far_field<FULL, float>(coef32 + (size_t)tile * kp.C2, kp.C, L, tb.abw32,
+            far_field<FULL, float>(coef32 + (size_t)tile * kp.C2, kp.C, L, tb.fq4_32,
                                    (float)(x * inv_rho), (float)(y * inv_rho),
                                    (float)(z * inv_rho), gx, gy, gz);
         } else {
-            far_field<FULL, double>(coef + (size_t)tile * kp.C2, kp.C, L, tb.abw, x,
+            far_field<FULL, double>(coef + (size_t)tile * kp.C2, kp.C, L, tb.fq4, x,
                                     y, z, gx, gy, gz);
         }
         Ex = -(double)gx * inv_rho;
@@ -1135,12 +1307,22 @@ __global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, PRec *A,
     // ---- near field (own tile); E += -(1 / (4 pi nt)) sum_j q_j grad D ----
     {
         double ax = 0.0, ay = 0.0, az = 0.0;
-        const NF *nf;
-        if constexpr (FP32) nf = tb.nf4_32;
-        else nf = tb.nf4;
-        near_field<FULL, R, NF>(lane, jn, L, nf, sh_xh[w], sh_yh[w], sh_zh[w], sh_r[w], sh_ir[w],
-                                sh_r2[w], sh_uid[w], sh_q[w], (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r,
-                                r2, uid, (R)qk, ax, ay, az);
+        if (L < 1) {
+            // monopole only: Gauss's law below
+        } else if constexpr (FULL) {
+            const NF *lg;
+            if constexpr (FP32) lg = tb.lg4_32;
+            else lg = tb.lg4;
+            near_field_full<R, NF>(lane, L, lg, nr, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
+                                   valid ? (R)qk : (R)0, ax, ay, az);
+        } else {
+            const NF *nf;
+            if constexpr (FP32) nf = tb.nf4_32;
+            else nf = tb.nf4;
+            near_field<FULL, R, NF>(lane, jn, L, nf, nr.xh, nr.yh, nr.zh, nr.r, nr.ir, nr.r2,
+                                    nr.uid, nr.q, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
+                                    (R)qk, ax, ay, az);
+        }
         const double cn = -1.0 / (4.0 * kPi * ntilde);
         Ex += cn * ax;
         Ey += cn * ay;
@@ -1506,6 +1688,7 @@ struct sim {
     double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr,
            *coef = nullptr, *tables = nullptr, *Eout = nullptr, *qpre = nullptr;
     int *chl = nullptr;
+    double *chn = nullptr;
     float *coef32 = nullptr, *tables32 = nullptr;
     double *lgrho = nullptr;
     uint32_t *Eid = nullptr;
@@ -1546,7 +1729,11 @@ size_t nf4_offset(int L)
 
 size_t ab_offset(int L) { return nf4_offset(L) + 4 * (size_t)(L + 1); }   // 32-byte aligned
 
-size_t tables_len(int L) { return ab_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
+size_t lg4_offset(int L) { return ab_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
+
+size_t fq4_offset(int L) { return lg4_offset(L) + 4 * (size_t)(L + 1); }
+
+size_t tables_len(int L) { return fq4_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
 
 // FP32 copies: qmm, the two (l, m) triangles, then the near-field constants
 // at a 16-byte aligned offset.
@@ -1558,7 +1745,11 @@ size_t nf4_32_offset(int L)
 
 size_t ab32_offset(int L) { return nf4_32_offset(L) + 4 * (size_t)(L + 1); }   // 16-byte aligned
 
-size_t tables32_len(int L) { return ab32_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
+size_t lg4_32_offset(int L) { return ab32_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
+
+size_t fq4_32_offset(int L) { return lg4_32_offset(L) + 4 * (size_t)(L + 1); }
+
+size_t tables32_len(int L) { return fq4_32_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
 
 void plan_alloc(sim *h, Alloc &al)
 {
@@ -1594,6 +1785,7 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->T, (size_t)lo.n_members * std::max(lo.C, 1));
     al.add(&h->tables, tables_len(lo.L));
     al.add(&h->chl, (size_t)std::max(lo.C, 1));
+    al.add(&h->chn, (size_t)std::max(lo.C, 1));
     al.add(&h->Eout, 3 * n);
     al.add(&h->Eid, n);
     al.add(&h->seg, (size_t)lo.n_members);
@@ -1662,6 +1854,30 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
             ab[4 * j + 1] = (l == m) ? 0.0 : blm[tri(l, m)];
             ab[4 * j + 2] = (double)(l - m);
             ab[4 * j + 3] = 2.0 * l + 1.0;
+        }
+    }
+    // P_l = c_l Ph_l with c_0 = 1, c_l = c_{l-1} (2l-1)/l: the three-term
+    // recurrence l P_l = (2l-1) u P_{l-1} - (l-1) P_{l-2} becomes
+    // Ph_l = u Ph_{l-1} - gamma_l Ph_{l-2}, gamma_l = (l-1)^2 / ((2l-1)(2l-3));
+    // P'_{l+1} = P'_{l-1} + (2l+1) c_l Ph_l
+    double *lg = t.data() + lg4_offset(L);
+    for (int l = 0; l <= L; ++l) {
+        double c = 1.0;
+        for (int k = 1; k <= l; ++k) c *= (2.0 * k - 1.0) / k;
+        lg[4 * l + 0] = c;
+        lg[4 * l + 1] = l * c;
+        lg[4 * l + 2] = (double)l * l / ((2.0 * l + 1.0) * (2.0 * l - 1.0));
+        lg[4 * l + 3] = (2.0 * l + 1.0) * c;
+    }
+    // rescaled far-field recurrence: Q_l^m = N_lm Qh_l^m with N_mm = Q_m^m and
+    // N_lm = a_lm N_{l-1,m}, so gamma_lm = b_lm / (a_lm a_{l-1,m})
+    double *fq = t.data() + fq4_offset(L);
+    for (int m = 0, j = 0; m <= L; ++m) {
+        for (int l = m; l <= L; ++l, ++j) {
+            fq[4 * j] = (l >= m + 2) ? blm[tri(l, m)] / (alm[tri(l, m)] * alm[tri(l - 1, m)]) : 0.0;
+            fq[4 * j + 1] = (double)(l - m);
+            fq[4 * j + 2] = (double)(l + m + 1);
+            fq[4 * j + 3] = 0.0;
         }
     }
     return t;
@@ -1819,6 +2035,9 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
     h->tb.blm = tb + (kQmmArray + 1) * (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.nf4 = reinterpret_cast<const double4 *>(tb + nf4_offset(L));
     h->tb.abw = reinterpret_cast<const double4 *>(tb + ab_offset(L));
+    h->tb.lg4 = reinterpret_cast<const double4 *>(tb + lg4_offset(L));
+    h->tb.fq4 = reinterpret_cast<const double4 *>(tb + fq4_offset(L));
+    h->tb.chn = h->chn;
     h->tb.chl = h->chl;
     std::vector<float> tab32(tables32_len(L), 0.f);
     {
@@ -1831,19 +2050,42 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
         for (int i = 0; i < 4 * (L + 1); ++i) tab32[nf4_32_offset(L) + i] = (float)nf4[i];
         const double *ab = tab.data() + ab_offset(L);
         for (size_t i = 0; i < 4 * ntri; ++i) tab32[ab32_offset(L) + i] = (float)ab[i];
+        const double *lg = tab.data() + lg4_offset(L);
+        for (int i = 0; i < 4 * (L + 1); ++i) tab32[lg4_32_offset(L) + i] = (float)lg[i];
+        const double *fq = tab.data() + fq4_offset(L);
+        for (size_t i = 0; i < 4 * ntri; ++i) tab32[fq4_32_offset(L) + i] = (float)fq[i];
     }
     h->tb.qmm32 = h->tables32;
     h->tb.alm32 = h->tables32 + (L + 1);
     h->tb.blm32 = h->tables32 + (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.nf4_32 = reinterpret_cast<const float4 *>(h->tables32 + nf4_32_offset(L));
     h->tb.abw32 = reinterpret_cast<const float4 *>(h->tables32 + ab32_offset(L));
+    h->tb.lg4_32 = reinterpret_cast<const float4 *>(h->tables32 + lg4_32_offset(L));
+    h->tb.fq4_32 = reinterpret_cast<const float4 *>(h->tables32 + fq4_32_offset(L));
     // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
+    // and its far-field normalisation N_lm
     std::vector<int> chl;
-    for (int m = 0; m <= (lo.full ? L : 0); ++m)
-        for (int l = std::max(m, 1); l <= L; ++l)
-            for (int sc = 0; sc < (m > 0 ? 2 : 1); ++sc) chl.push_back(l);
+    std::vector<double> chn;
+    {
+        const double *qmm = tab.data() + kQmmArray * (L + 1);
+        const double *alm = qmm + (L + 1);
+        for (int m = 0; m <= (lo.full ? L : 0); ++m) {
+            double nlm = qmm[m];   // N_mm
+            for (int l = m; l <= L; ++l) {
+                if (l > m) nlm *= alm[tri(l, m)];
+                if (l == 0) continue;
+                for (int sc = 0; sc < (m > 0 ? 2 : 1); ++sc) {
+                    chl.push_back(l);
+                    chn.push_back(nlm);
+                }
+            }
+        }
+    }
     if ((int)chl.size() != lo.C) return fail(SIM_EDEVICE, "channel count mismatch");
-    if (chl.empty()) chl.push_back(0);
+    if (chl.empty()) {
+        chl.push_back(0);
+        chn.push_back(0.0);
+    }
 
     KParams &kp = h->kp;
     kp.L = lo.L;
@@ -1870,6 +2112,7 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
     std::vector<uint32_t> none_t((size_t)lo.n_tiles, kNone), none_c((size_t)lo.n_chunks, kNone);
     if (hipMemcpy(h->tables, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->chl, chl.data(), sizeof(int) * chl.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->chn, chn.data(), sizeof(double) * chn.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->tables32, tab32.data(), sizeof(float) * tab32.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->seg, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->ctl, ctls.data(), sizeof(Ctl) * ctls.size(), hipMemcpyHostToDevice) ||
