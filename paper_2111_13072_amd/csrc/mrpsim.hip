@@ -504,9 +504,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec 
 //   R_lm^c = Q_l^m C_m,  R_lm^s = Q_l^m S_m,  I_lm = r^-(2l+1) R_lm,
 // normalised so that sum_m Y_lm(a) Y_lm(b) = (2l+1)/(4 pi) P_l(a.b).
 
-constexpr int kBatch = 8;        // channels per LDS batch of the tile reduction
-constexpr int kBatchPad = kWave + 1;
-constexpr int kParts = kWave / (2 * kBatch);   // lanes sharing one (channel, kind) sum
+constexpr int kSlots = 8;       // LDS slots per batch; a slot holds two channels
+constexpr int kRowPad = 17;     // a 16-lane row of a slot, padded against bank conflicts
+constexpr int kSlotLen = 4 * kRowPad;
 
 // Orders this wave's LDS accesses at this point: LDS instructions of one wave
 // complete in issue order, so rows a wave wrote are visible to its later
@@ -530,17 +530,47 @@ __device__ inline void swap_wave_halves(double &a, double &b)
     b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | (uint64_t)lo[1]));
 }
 
+// Exchange the odd 16-lane rows of a with the even rows of b: afterwards
+// a = (a0, b0, a2, b2) and b = (a1, b1, a3, b3) by rows.
+__device__ inline void swap_odd_even_rows(double &a, double &b)
+{
+    const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    const auto hi =
+        __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+    a = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | (uint64_t)lo[0]));
+    b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | (uint64_t)lo[1]));
+}
+
+// The value of lane (this lane xor 1), through DPP.
+__device__ inline double dpp_xor1(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    constexpr int kQuadPerm1032 = 0xB1;   // quad_perm [1, 0, 3, 2]
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, kQuadPerm1032,
+                                                              0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32),
+                                                              kQuadPerm1032, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 template <bool FULL>
 __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, KParams kp,
                                                     double *S, double *lgrho)
 {
-    // Per wave (one tile of 64 particles): for each channel, q R (interior)
-    // and q I (exterior) are first folded across the two wave halves with a
-    // lane swap (lanes 0-31 then hold R over particle pairs, lanes 32-63 I),
-    // written to an LDS row, and every kBatch channels each lane (channel,
-    // kind, part) sums kBatch entries of a row; the parts are combined across
-    // the wave.  Each wave uses its own rows only.
-    __shared__ double buf[kWavesPerBlock][kBatch][kBatchPad];
+    // Per wave (one tile of 64 particles), the lane sums of q R (interior)
+    // and q I (exterior) of every channel, in a tree:
+    //  1. R and I of one channel are folded across the wave halves (lanes
+    //     0-31 then hold R over particle pairs, lanes 32-63 I);
+    //  2. two channels (cos and sin of one (l, m), or two degrees of m = 0)
+    //     are folded across 16-lane rows: rows 0-3 hold R of the first, R of
+    //     the second, I of the first, I of the second, each as 16 sums of 4
+    //     particles, written to one LDS slot;
+    //  3. every kSlots slots each lane pair sums the 16 entries of one row
+    //     (8 each, then a lane exchange) and one of the two stores it.
+    // The m = 0 block is padded to an even count with a zero channel, so a
+    // slot always holds two positions of the padded channel order.
+    __shared__ double buf[kWavesPerBlock][kSlots * kSlotLen];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + w);
@@ -588,30 +618,39 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         lgrho[tile] = log2(rho);
     }
 
-    const int cc = lane % kBatch;
-    const int kind = (lane / kBatch) & 1;   // 0: interior (R), 1: exterior (I)
-    const int part = lane / (2 * kBatch);
-    const double *row_base = &buf[w][cc][kind * 32 + part * (32 / kParts)];
-    auto row_sum = [&]() {
-        double acc = 0.0;
+    double *wb = buf[w];
+    // writer: lane -> (row lane / 16, entry lane % 16) of a slot
+    double *wr = wb + (lane >> 4) * kRowPad + (lane & 15);
+    // reader: lane pair v = lane / 2 sums row v % 4 of slot v / 4, half lane % 2
+    const int v = lane >> 1;
+    const double *rd = wb + v * kRowPad + (lane & 1) * 8;
+    const int pad0 = L & 1;             // zero channel after the m = 0 block
+    const int n_pos = C + pad0;         // padded channel positions
+    int slot = 0, base = 0;             // base: padded position of slot 0
+    auto flush = [&]() {
+        wave_lds_sync();
+        double acc = rd[0];
 #pragma unroll
-        for (int r = 0; r < 32 / kParts; ++r) acc += row_base[r];
-#pragma unroll
-        for (int o = 2 * kBatch; o < kWave; o <<= 1) acc += __shfl_xor(acc, o);
-        return acc;
+        for (int k = 1; k < 8; ++k) acc += rd[k];
+        acc += dpp_xor1(acc);
+        const int s = v >> 2, row = v & 3;
+        const int pos = base + 2 * s + (row & 1);   // padded position
+        // padded position -> channel: the m = 0 block is positions 0..L-1
+        const int ch = pos < L ? pos : pos - pad0;
+        if (tile_ok && (lane & 1) == 0 && s < slot && pos < n_pos && !(pad0 && pos == L))
+            St[(row >> 1) * C + ch] = acc;
+        wave_lds_sync();
+        base += 2 * kSlots;
+        slot = 0;
     };
-    int slot = 0, base = 0;
-    auto put = [&](double rv, double iv) {
-        swap_wave_halves(rv, iv);
-        buf[w][slot][lane] = rv + iv;
-        if (++slot == kBatch) {
-            wave_lds_sync();
-            const double acc = row_sum();
-            if (tile_ok && part == 0) St[(kind ? C : 0) + base + cc] = acc;
-            wave_lds_sync();
-            base += kBatch;
-            slot = 0;
-        }
+    // one slot from two channels (R, I each)
+    auto put2 = [&](double r0, double i0, double r1, double i1) {
+        swap_wave_halves(r0, i0);
+        swap_wave_halves(r1, i1);
+        double f0 = r0 + i0, f1 = r1 + i1;
+        swap_odd_even_rows(f0, f1);
+        wr[slot * kSlotLen] = f0 + f1;
+        if (++slot == kSlots) flush();
     };
 
     // (Q_m^m or a_lm, 0 or b_lm) of the stream-order table, read one entry
@@ -626,18 +665,28 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         return e;
     };
     // m = 0: channels l = 1..L (Q_0^0 only seeds the recurrence; l = 0 is
-    // Gauss's law in the field kernel)
+    // Gauss's law in the field kernel), two degrees per slot; the two Q
+    // registers trade roles instead of being copied
     {
-        double Qpp = 0.0, Qp = next_entry().x;
-        double sl = inv_r * inv_r2;   // r^-(2l+1) at l = 1
-        for (int l = 1; l <= L; ++l) {
-            const double2 ab = next_entry();
-            const double Qv = ab.x * z * Qp - ab.y * r2 * Qpp;
-            Qpp = Qp;
-            Qp = Qv;
-            const double rc = q * Qv;
-            put(rc, rc * sl);
+        double Qa = next_entry().x, Qb = 0.0;   // Q_{l-1}, Q_{l-2}
+        double sl = inv_r * inv_r2;             // r^-(2l+1) at l = 1
+        int l = 1;
+        for (; l < L; l += 2) {
+            double2 ab = next_entry();
+            Qb = ab.x * z * Qa - ab.y * r2 * Qb;   // Q_l
+            const double r0 = q * Qb, i0 = r0 * sl;
             sl *= inv_r2;
+            ab = next_entry();
+            Qa = ab.x * z * Qb - ab.y * r2 * Qa;   // Q_{l+1}
+            const double r1 = q * Qa, i1 = r1 * sl;
+            sl *= inv_r2;
+            put2(r0, i0, r1, i1);
+        }
+        if (l == L) {
+            const double2 ab = next_entry();
+            Qb = ab.x * z * Qa - ab.y * r2 * Qb;
+            const double r0 = q * Qb;
+            put2(r0, r0 * sl, 0.0, 0.0);
         }
     }
     if (FULL) {
@@ -651,30 +700,31 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
             s_mm *= inv_r2;
             const double qc = q * Cm, qs = q * Sm;
             double sl = s_mm;
-            double Qpp = 0.0, Qp = next_entry().x;   // l = m: Q_m^m
-            {
-                const double rc = Qp * qc, rs = Qp * qs;
-                put(rc, rc * sl);
-                put(rs, rs * sl);
-                sl *= inv_r2;
-            }
-            for (int l = m + 1; l <= L; ++l) {
-                const double2 ab = next_entry();
-                const double Qv = ab.x * z * Qp - ab.y * r2 * Qpp;
-                Qpp = Qp;
-                Qp = Qv;
+            // cos and sin of one (l, m) fill one slot
+            auto emit = [&](double Qv) {
                 const double rc = Qv * qc, rs = Qv * qs;
-                put(rc, rc * sl);
-                put(rs, rs * sl);
+                put2(rc, rc * sl, rs, rs * sl);
                 sl *= inv_r2;
+            };
+            double Qa = next_entry().x, Qb = 0.0;   // l = m: Q_m^m
+            emit(Qa);
+            int l = m + 1;
+            for (; l < L; l += 2) {
+                double2 ab = next_entry();
+                Qb = ab.x * z * Qa - ab.y * r2 * Qb;
+                emit(Qb);
+                ab = next_entry();
+                Qa = ab.x * z * Qb - ab.y * r2 * Qa;
+                emit(Qa);
+            }
+            if (l == L) {
+                const double2 ab = next_entry();
+                Qb = ab.x * z * Qa - ab.y * r2 * Qb;
+                emit(Qb);
             }
         }
     }
-    if (slot > 0) {   // last, partial batch: rows >= slot hold stale values
-        wave_lds_sync();
-        const double acc = row_sum();
-        if (tile_ok && part == 0 && cc < slot) St[(kind ? C : 0) + base + cc] = acc;
-    }
+    if (slot > 0) flush();   // last, partial batch: slots >= slot hold stale values
 }
 
 // ---------------------------------------------------------------------------
@@ -1210,8 +1260,9 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
     az += dck * (double)zh + dbz;
 }
 
+// FP32 (half the LDS rows, fewer registers) runs at six waves per SIMD
 template <bool FULL, bool FIELD_ONLY, bool FP32>
-__global__ __launch_bounds__(kBlock) void k_field_push(Map mp, State B, PRec *A, uint8_t *dead,
+__global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, State B, PRec *A, uint8_t *dead,
                                                        Grave G, const double *coef,
                                                        const float *coef32, const double *qpre,
                                                        Tables tb, KParams kp, double *Eout,
