@@ -744,8 +744,13 @@ __device__ inline bool chunk_tiles(const Map &mp, const KParams &kp, int j, uint
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_chunk_sums(Map mp, const double *S, double *chunkS,
-                                                       KParams kp)
+// The tile loops of the carry kernels issue the loads of kCarryBatch tiles
+// before using them (a chunk is up to 64 tiles walked by one thread, and one
+// HBM round trip per tile would dominate); the sums keep the tile order.
+constexpr int kCarryBatch = 8;
+
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(Map mp, const double *__restrict__ S,
+                                                       double *__restrict__ chunkS, KParams kp)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
     if (c >= kp.SW) return;
@@ -753,8 +758,19 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(Map mp, const double *S, 
     uint32_t mb;
     int t0, t1;
     if (!chunk_tiles(mp, kp, j, &mb, &t0, &t1)) return;
+    const size_t sw = (size_t)kp.SW;
+    const double *src = S + (size_t)t0 * sw + c;
+    const int nt = t1 - t0;
     double s = 0.0;
-    for (int t = t0; t < t1; ++t) s += S[(size_t)t * kp.SW + c];
+    int t = 0;
+    for (; t + kCarryBatch <= nt; t += kCarryBatch) {
+        double v[kCarryBatch];
+#pragma unroll
+        for (int k = 0; k < kCarryBatch; ++k) v[k] = src[(size_t)(t + k) * sw];
+#pragma unroll
+        for (int k = 0; k < kCarryBatch; ++k) s += v[k];
+    }
+    for (; t < nt; ++t) s += src[(size_t)t * sw];
     chunkS[(size_t)j * kp.SW + c] = s;
 }
 
@@ -805,10 +821,14 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(Map mp, const double *chu
 // tile's coordinates x / rho (interior rho^-(l+1), exterior rho^l), stored
 // as FP32.  The block of the member's first chunk also records the probe
 // response Q_diff(t_step) from the totals.
-__global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *S,
-                                                        const double *chunkC, const double *T,
-                                                        Tables tb, KParams kp, const double *lgrho,
-                                                        double *coef, float *coef32, double *qpre)
+__global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *__restrict__ S,
+                                                        const double *__restrict__ chunkC,
+                                                        const double *__restrict__ T, Tables tb,
+                                                        KParams kp,
+                                                        const double *__restrict__ lgrho,
+                                                        double *__restrict__ coef,
+                                                        float *__restrict__ coef32,
+                                                        double *__restrict__ qpre)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
     const int j = blockIdx.x;
@@ -826,32 +846,56 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *S,
     }
     if (c >= kp.SW) return;
     const double inv_nt = sg.inv_ntilde;
+    const size_t sw = (size_t)kp.SW;
     double run = chunkC[(size_t)j * kp.SW + c];
-    if (c == kp.C2) {   // charge of the member's particles before each tile
-        for (int t = t0; t < t1; ++t) {
-            qpre[t] = run;
-            run += S[(size_t)t * kp.SW + c];
+    // Walks the chunk's tiles in scan order (dir +1 from t0, -1 from t1 - 1),
+    // calling f(t, carry before t) with the loads of kCarryBatch tiles issued
+    // ahead; the carry accumulates in tile order.
+    auto walk = [&](int dir, auto f) {
+        const int nt = t1 - t0;
+        const int first = dir > 0 ? t0 : t1 - 1;
+        int i = 0;
+        for (; i + kCarryBatch <= nt; i += kCarryBatch) {
+            double v[kCarryBatch];
+#pragma unroll
+            for (int k = 0; k < kCarryBatch; ++k) v[k] = S[(size_t)(first + dir * (i + k)) * sw + c];
+#pragma unroll
+            for (int k = 0; k < kCarryBatch; ++k) {
+                f(first + dir * (i + k), run);
+                run += v[k];
+            }
         }
+        for (; i < nt; ++i) {
+            const int t = first + dir * i;
+            f(t, run);
+            run += S[(size_t)t * sw + c];
+        }
+    };
+    if (c == kp.C2) {   // charge of the member's particles before each tile
+        walk(1, [&](int t, double carry) { qpre[t] = carry; });
     } else if (c < kp.C) {
         const int l = tb.chl[c];
         const double nrm = tb.chn[c];
         const double w = tb.wl[l] * inv_nt;
         double k = -tb.ftil[l] * Ts[c] * w;
         if (c < kp.L && in_run) k += sg.u_asy[step] * tb.drive_w[l];
-        for (int t = t0; t < t1; ++t) {
-            const double v = (run * w + k) * nrm;
-            if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2(-(l + 1.0) * lgrho[t]));
-            else coef[(size_t)t * kp.C2 + c] = v;
-            run += S[(size_t)t * kp.SW + c];
+        if (kp.fp32) {
+            walk(1, [&](int t, double carry) {
+                const double v = (carry * w + k) * nrm;
+                coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2(-(l + 1.0) * lgrho[t]));
+            });
+        } else {
+            walk(1, [&](int t, double carry) { coef[(size_t)t * kp.C2 + c] = (carry * w + k) * nrm; });
         }
     } else {
         const int l = tb.chl[c - kp.C];
         const double w = tb.wl[l] * inv_nt * tb.chn[c - kp.C];
-        for (int t = t1 - 1; t >= t0; --t) {
-            const double v = run * w;
-            if (kp.fp32) coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2((double)l * lgrho[t]));
-            else coef[(size_t)t * kp.C2 + c] = v;
-            run += S[(size_t)t * kp.SW + c];
+        if (kp.fp32) {
+            walk(-1, [&](int t, double carry) {
+                coef32[(size_t)t * kp.C2 + c] = (float)(carry * w * exp2((double)l * lgrho[t]));
+            });
+        } else {
+            walk(-1, [&](int t, double carry) { coef[(size_t)t * kp.C2 + c] = carry * w; });
         }
     }
 }
