@@ -601,7 +601,6 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     const double inv_r = 1.0 / sqrt(r2);
     const int L = kp.L;
     const int C = kp.C;
-    const int m_top = FULL ? L : 0;
     double *St = S + (size_t)tile * kp.SW;
     {
         // the tile's total charge (exact: a count of ions and electrons)
@@ -654,14 +653,15 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     };
 
     // (Q_m^m or a_lm, 0 or b_lm) of the stream-order table, read one entry
-    // ahead of its use (clamped index)
-    const int jmax = (m_top + 1) * (2 * L - m_top + 2) / 2 - 1;
-    int j = 0;                               // next entry to use
-    double2 nab = ld_const_xy(tb.abw, 0);    // holds entry j
+    // ahead of its use through a running pointer.  The read after the last
+    // entry lands in the Legendre tables that follow the triangle in the
+    // same block (its value is never used).
+    const double4 *ahead = tb.abw + 1;       // entry after the one held
+    double2 nab = ld_const_xy(tb.abw, 0);    // holds the next entry to use
     auto next_entry = [&]() {
         const double2 e = nab;
-        ++j;
-        nab = ld_const_xy(tb.abw, min(j, jmax));
+        nab = ld_const_xy(ahead, 0);
+        ++ahead;
         return e;
     };
     // m = 0: channels l = 1..L (Q_0^0 only seeds the recurrence; l = 0 is
