@@ -219,6 +219,15 @@ def bench_batch(args):
     n_all = sum(wl.n for wl in wls)
     print(f"[bench] batch of {len(wls)} runs, {n_all} particles, l_max={cp.l_max} "
           f"{args.precision}", file=sys.stderr, flush=True)
+    tuning = None
+    if args.autotune:
+        from paper_2111_13072_amd import tune as T
+        tuned = T.autotune(T.batch_builder(members), cp, n_all, steps=5, warmup=2)
+        cp = tuned.apply(cp)
+        tuning = {"sort_bucket": tuned.sort_bucket, "carry_chunk": tuned.carry_chunk,
+                  "trial_ms_per_step": round(tuned.ms_per_step, 4),
+                  "default_trial_ms_per_step": round(tuned.default_ms_per_step, 4)}
+        print(f"[bench] autotune: {tuning}", file=sys.stderr, flush=True)
     b = S.Batch(cp, members)
     b.step(args.warmup)
     b.sync()
@@ -266,6 +275,8 @@ def bench_batch(args):
                          "frac": achieved / peak, "traffic": None, "kernel": dom,
                          "kernel_ms": kms[dom],
                          "per_kernel_ms": {k: round(v, 5) for k, v in kms.items()}}}
+    if tuning is not None:
+        line["tuning"] = tuning
     print(json.dumps(line), flush=True)
     return 0
 
@@ -359,6 +370,9 @@ def main(argv=None):
                     help="batch64: timed steps of each member run alone, for comparison")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="large/small: choose sort bucket and carry chunk sizes by short timed "
+                         "trials first (outside the timed region)")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, launch a plain copy of this size (counter calibration)")
@@ -406,6 +420,15 @@ def main(argv=None):
                       precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64)
     print(f"[bench] workload {wl.name}: n={wl.n} l_max={wl.l_max} {args.precision}, "
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    tuning = None
+    if args.autotune:
+        from paper_2111_13072_amd import tune as T
+        tuned = T.autotune(T.sim_builder(st.pos, st.vel), prm, wl.n)
+        prm = tuned.apply(prm)
+        tuning = {"sort_bucket": tuned.sort_bucket, "carry_chunk": tuned.carry_chunk,
+                  "trial_ms_per_step": round(tuned.ms_per_step, 4),
+                  "default_trial_ms_per_step": round(tuned.default_ms_per_step, 4)}
+        print(f"[bench] autotune: {tuning}", file=sys.stderr, flush=True)
 
     sim = S.Sim(prm, st.pos, st.vel, u)
     E_gpu = sim.eval_field() if not args.no_cpu_baseline else None
@@ -453,6 +476,8 @@ def main(argv=None):
                        "n_e_m3": wl.n_e, "T_e_eV": wl.t_e_ev, "r_out": wl.r_out, "dt": wl.dt,
                        "parallelism": "single-gpu"},
             "roofline": roof}
+    if tuning is not None:
+        line["tuning"] = tuning
     if not args.no_cpu_baseline:
         rec, err, ns = cpu_baseline(wl, st, prm, E_gpu, u_now, q_s0, args.cpu_budget_s)
         line["cpu_baseline"] = rec

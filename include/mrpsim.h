@@ -86,6 +86,13 @@ typedef struct {
     int32_t tile;
     uint64_t seed;
     uint64_t mem_limit_bytes;
+    /* Launch sizes that leave the results unchanged up to the rounding order
+     * of the radial carries (the autotuner's knobs; 0 = built-in choice):
+     * sort_bucket: mean particles per radial sort bucket, 1..256 (built-in 8);
+     * carry_chunk: tiles per carry chunk, 8..1024 (built-in: a power of two
+     * in [8, 64], about a member's tiles / 256). */
+    int32_t sort_bucket;
+    int32_t carry_chunk;
 } sim_params;
 
 /* Fill *p with the defaults (d = 0.25, eps_r = 4, r_out = 5, dt = 0.05,

@@ -1591,6 +1591,21 @@ const char *kKernelNames[KN_COUNT] = {
     "field_push", "step_finish"};
 
 // What all members of a handle share, and the handle's capacities.
+// The tunable launch sizes of sim_params, with 0 resolved to the built-in
+// choice (bucket) or kept as "automatic" (chunk).
+struct Tuning {
+    int bucket = kBucketOccupancy;   // mean particles per sort bucket
+    int chunk = 0;                   // tiles per carry chunk, 0: by member size
+};
+
+Tuning tuning_of(const sim_params *p)
+{
+    Tuning t;
+    if (p->sort_bucket > 0) t.bucket = p->sort_bucket;
+    if (p->carry_chunk > 0) t.chunk = p->carry_chunk;
+    return t;
+}
+
 struct Layout {
     int L, C, C2;
     bool full, fp32;
@@ -1598,6 +1613,7 @@ struct Layout {
     int n_chunks;
     int nb, nb_blocks;
     int n_members;
+    Tuning tu;
 };
 
 // The part of the capacities in use: every member's tiles, chunks, buckets
@@ -1618,14 +1634,20 @@ struct MemberShape {
     uint32_t nt, nc, nb, cl;
 };
 
-MemberShape member_shape(int64_t n)
+uint32_t tiles_for(int64_t n) { return (uint32_t)((n + kWave - 1) / kWave); }
+
+MemberShape member_shape(int64_t n, const Tuning &tu)
 {
     MemberShape m;
-    m.nt = (uint32_t)((n + kWave - 1) / kWave);
-    m.cl = kChunkMin;
-    while (m.cl < (uint32_t)kChunkMax && (uint64_t)m.cl * kChunkTarget < m.nt) m.cl *= 2;
+    m.nt = tiles_for(n);
+    if (tu.chunk > 0) {
+        m.cl = (uint32_t)tu.chunk;
+    } else {
+        m.cl = kChunkMin;
+        while (m.cl < (uint32_t)kChunkMax && (uint64_t)m.cl * kChunkTarget < m.nt) m.cl *= 2;
+    }
     m.nc = (m.nt + m.cl - 1) / m.cl;
-    m.nb = (uint32_t)std::max<int64_t>(1, n / kBucketOccupancy);
+    m.nb = (uint32_t)std::max<int64_t>(1, n / tu.bucket);
     return m;
 }
 
@@ -1639,6 +1661,11 @@ bool check_common(const sim_params *p, std::string *why)
     if (p->m_mode != SIM_M_FULL && p->m_mode != SIM_M_AXISYM) { *why = "bad m_mode"; return false; }
     if (p->precision != SIM_FP64 && p->precision != SIM_FP32_COMP) { *why = "bad precision"; return false; }
     if (p->tile != 0 && p->tile != kWave) { *why = "tile must be 0 or 64"; return false; }
+    if (p->sort_bucket < 0 || p->sort_bucket > 256) { *why = "sort_bucket must be 0 or in [1, 256]"; return false; }
+    if (p->carry_chunk != 0 && (p->carry_chunk < kChunkMin || p->carry_chunk > 1024)) {
+        *why = "carry_chunk must be 0 or in [8, 1024]";
+        return false;
+    }
     return true;
 }
 
@@ -1686,10 +1713,12 @@ bool make_layout(const sim_params *p, int64_t slots, int32_t max_members, int64_
     lo->C2 = 2 * lo->C;
     lo->n_tiles = (int)((slots + kWave - 1) / kWave);
     lo->n_members = max_members;
+    lo->tu = tuning_of(p);
     // every member rounds its chunks and buckets up by at most one
+    const int cl_min = lo->tu.chunk > 0 ? lo->tu.chunk : kChunkMin;
     lo->n_chunks = chunks >= 0 ? (int)std::max<int64_t>(1, chunks)
-                               : (lo->n_tiles + kChunkMin - 1) / kChunkMin + max_members;
-    lo->nb = (int)std::max<int64_t>(1, slots / kBucketOccupancy) + (max_members > 1 ? max_members : 0);
+                               : (lo->n_tiles + cl_min - 1) / cl_min + max_members;
+    lo->nb = (int)std::max<int64_t>(1, slots / lo->tu.bucket) + (max_members > 1 ? max_members : 0);
     lo->nb_blocks = (lo->nb + kScanPerBlock - 1) / kScanPerBlock;
     return true;
 }
@@ -2309,7 +2338,7 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     const size_t mbytes = member_bytes(m->n_steps, m->ion_profile ? m->ion_profile_len : 0);
     if (h->prm.mem_limit_bytes && h->shared_bytes + h->member_total + mbytes > h->prm.mem_limit_bytes)
         return fail(SIM_ENOMEM, "member arrays would exceed mem_limit_bytes");
-    const MemberShape sh = member_shape(n);
+    const MemberShape sh = member_shape(n, h->lo.tu);
     uint32_t t0 = 0, c0 = 0, b0 = 0;
     if (!h->tiles.take(sh.nt, &t0)) return fail(SIM_ENOMEM, "no free tile range for the member");
     if (!h->chunks.take(sh.nc, &c0)) {
@@ -2500,7 +2529,7 @@ sim_member member_from_params(const sim_params *p, int64_t n, const double *pos,
     return m;
 }
 
-int64_t slots_for(int64_t n) { return (int64_t)member_shape(n).nt * kWave; }
+int64_t slots_for(int64_t n) { return (int64_t)tiles_for(n) * kWave; }
 
 }  // namespace
 
@@ -2568,7 +2597,7 @@ int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps)
     if (!check_common(p, &why)) return fail(SIM_EINVAL, why);
     sim_member m = member_from_params(p, n, nullptr, nullptr, nullptr, nullptr, n_steps, 0);
     if (!check_member_scalars(&m, &why)) return fail(SIM_EINVAL, why);
-    const int64_t shared = footprint(p, slots_for(n), 1, member_shape(n).nc);
+    const int64_t shared = footprint(p, slots_for(n), 1, member_shape(n, tuning_of(p)).nc);
     if (shared < 0) return shared;
     return shared + (int64_t)member_bytes(n_steps, 0);
 }
@@ -2587,7 +2616,7 @@ int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t ma
         if (prepare_member(&members[i], &prep[i]))
             return fail(SIM_EINVAL, "member " + std::to_string(i) + ": " + g_last_error);
         need += slots_for(members[i].n);
-        chunks += member_shape(members[i].n).nc;
+        chunks += member_shape(members[i].n, tuning_of(common)).nc;
     }
     // exactly the initial members, or room for any later mix
     const bool exact = slot_capacity == 0 && (max_members == 0 || max_members == n_members);

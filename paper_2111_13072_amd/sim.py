@@ -37,6 +37,7 @@ class sim_params(C.Structure):
         ("l_max", C.c_int32), ("m_mode", C.c_int32), ("probe_bc", C.c_int32),
         ("wall_bc", C.c_int32), ("precision", C.c_int32), ("tile", C.c_int32),
         ("seed", C.c_uint64), ("mem_limit_bytes", C.c_uint64),
+        ("sort_bucket", C.c_int32), ("carry_chunk", C.c_int32),
     ]
 
 
@@ -151,6 +152,9 @@ class SimParams:
     tile: int = 0
     seed: int = 0
     mem_limit_bytes: int = 0
+    # launch sizes chosen by paper_2111_13072_amd.tune (0: built-in choice)
+    sort_bucket: int = 0
+    carry_chunk: int = 0
 
     def to_c(self) -> sim_params:
         p = sim_params()
