@@ -357,24 +357,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_a(const uint32_t *in, uint32_t 
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_b(uint32_t *bsum, int nblocks)
-{
-    uint32_t carry = 0;
-    for (int base = 0; base < nblocks; base += kBlock) {
-        int i = base + threadIdx.x;
-        uint32_t v = i < nblocks ? bsum[i] : 0u;
-        uint32_t tot;
-        uint32_t ex = block_exclusive_scan(v, &tot);
-        if (i < nblocks) bsum[i] = carry + ex;
-        carry += tot;
-    }
-}
-
+// Offsets of the buckets: each block adds the sums of the blocks before it
+// (at most a few thousand, read from L2) to the scan of its own entries.
 // The histogram's last reader: it leaves the histogram zeroed for the next
 // step (the handle zeroes it once at creation).
 __global__ __launch_bounds__(kBlock) void k_scan_c(uint32_t *in, const uint32_t *bsum,
                                                    uint32_t *out, int n)
 {
+    uint32_t before = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kBlock) before += bsum[k];
+    uint32_t carry;
+    block_exclusive_scan(before, &carry);
     constexpr int per = kScanPerBlock / kBlock;
     const int base = blockIdx.x * kScanPerBlock + threadIdx.x * per;
     uint32_t v[per];
@@ -388,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(uint32_t *in, const uint32_t 
     for (int k = 0; k < per; ++k)
         if (base + k < n) in[base + k] = 0u;
     uint32_t tot;
-    uint32_t run = bsum[blockIdx.x] + block_exclusive_scan(s, &tot);
+    uint32_t run = carry + block_exclusive_scan(s, &tot);
 #pragma unroll
     for (int k = 0; k < per; ++k) {
         if (base + k < n) out[base + k] = run;
@@ -1581,12 +1574,12 @@ __global__ void k_step_finish(Map mp, KParams kp)
 // ---------------------------------------------------------------------------
 
 enum KernelId {
-    KN_SORT_KEY, KN_SCAN_A, KN_SCAN_B, KN_SCAN_C, KN_SORT_SCATTER, KN_SORT_RANK, KN_MOMENTS,
+    KN_SORT_KEY, KN_SCAN_A, KN_SCAN_C, KN_SORT_SCATTER, KN_SORT_RANK, KN_MOMENTS,
     KN_CHUNK_SUMS, KN_CHUNK_SCAN, KN_CHUNK_APPLY, KN_FIELD_PUSH, KN_STEP_FINISH, KN_COUNT
 };
 
 const char *kKernelNames[KN_COUNT] = {
-    "sort_key", "bucket_scan_a", "bucket_scan_b", "bucket_scan_c", "sort_scatter",
+    "sort_key", "bucket_sums", "bucket_offsets", "sort_scatter",
     "sort_rank_move", "moments", "carry_chunk_sums", "carry_chunk_scan", "carry_apply",
     "field_push", "step_finish"};
 
@@ -2031,8 +2024,6 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     k_sort_key<<<gN, kBlock, 0, s>>>(mp, h->A, h->dead, h->krec, h->hist, kp);
     mark(KN_SCAN_A);
     k_scan_a<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, ex.nb);
-    mark(KN_SCAN_B);
-    k_scan_b<<<1, kBlock, 0, s>>>(h->bsum, ex.nb_blocks);
     mark(KN_SCAN_C);
     k_scan_c<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, ex.nb);
     mark(KN_SORT_SCATTER);
