@@ -128,16 +128,12 @@ struct Tables {
     const double *self_w;   // f_l / (4 pi)
     const double *nfA;      // (2l+1)/(l+1)
     const double *nfB;      // l/(l+1)
-    const double *lval;     // l
-    const double *tl1;      // 2l+1
     const double4 *nf4;     // {(2l+1)/(l+1), l/(l+1), 2l+1, l}, one wide load per l
-    const double *qmm;      // sectoral normalisation Q_m^m
-    const double *alm;      // Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m
-    const double *blm;
     const int *chl;         // degree l of each channel in stream order
-    // (Q_m^m or a_lm, 0 or b_lm, l - m, 2l + 1) in stream order of (m, l):
-    // m = 0..m_top outer, l = m..L inner, so a loop over (m, l) reads
-    // consecutive entries, and the integer factors need no conversion
+    // Moments recurrence Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m in
+    // stream order of (m, l) (m outer, l = m..L inner, so a loop over (m, l)
+    // reads consecutive entries): (Q_m^m or a_lm, 0 or b_lm, l - m, 2l + 1),
+    // of which the moments kernel reads the first two
     const double4 *abw;
     // Legendre constants of the full near field, per l: {c_l, l c_l,
     // gamma_{l+1}, (2l+1) c_l}, where P_l = c_l Ph_l and the rescaled
@@ -149,10 +145,8 @@ struct Tables {
     // coefficients carry the factor N_lm instead (chn, per channel).
     const double4 *fq4;
     const double *chn;
-    // FP32 copies for the FP32-compensated mode
-    const float *qmm32, *alm32, *blm32;
+    // FP32 copies of the field kernel's tables for the FP32-compensated mode
     const float4 *nf4_32;
-    const float4 *abw32;
     const float4 *lg4_32;
     const float4 *fq4_32;
 };
@@ -1852,17 +1846,12 @@ size_t fq4_offset(int L) { return lg4_offset(L) + 4 * (size_t)(L + 1); }
 
 size_t tables_len(int L) { return fq4_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
 
-// FP32 copies: qmm, the two (l, m) triangles, then the near-field constants
-// at a 16-byte aligned offset.
-size_t nf4_32_offset(int L)
-{
-    const size_t base = (size_t)(L + 1) + 2 * (size_t)((L + 1) * (L + 2) / 2);
-    return (base + 3) & ~size_t(3);
-}
+// FP32 copies of the field kernel's tables, each at a 16-byte aligned offset:
+// the axisymmetric near-field constants, the full near-field Legendre
+// constants, the far-field recurrence.
+size_t nf4_32_offset(int) { return 0; }
 
-size_t ab32_offset(int L) { return nf4_32_offset(L) + 4 * (size_t)(L + 1); }   // 16-byte aligned
-
-size_t lg4_32_offset(int L) { return ab32_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
+size_t lg4_32_offset(int L) { return nf4_32_offset(L) + 4 * (size_t)(L + 1); }
 
 size_t fq4_32_offset(int L) { return lg4_32_offset(L) + 4 * (size_t)(L + 1); }
 
@@ -2143,11 +2132,6 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
     h->tb.self_w = tb + 3 * (L + 1);
     h->tb.nfA = tb + 4 * (L + 1);
     h->tb.nfB = tb + 5 * (L + 1);
-    h->tb.lval = tb + 6 * (L + 1);
-    h->tb.tl1 = tb + 7 * (L + 1);
-    h->tb.qmm = tb + kQmmArray * (L + 1);
-    h->tb.alm = tb + (kQmmArray + 1) * (L + 1);
-    h->tb.blm = tb + (kQmmArray + 1) * (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.nf4 = reinterpret_cast<const double4 *>(tb + nf4_offset(L));
     h->tb.abw = reinterpret_cast<const double4 *>(tb + ab_offset(L));
     h->tb.lg4 = reinterpret_cast<const double4 *>(tb + lg4_offset(L));
@@ -2156,25 +2140,15 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
     h->tb.chl = h->chl;
     std::vector<float> tab32(tables32_len(L), 0.f);
     {
-        const double *qmm = tab.data() + kQmmArray * (L + 1);
-        const double *alm = qmm + (L + 1);
         const size_t ntri = (size_t)(L + 1) * (L + 2) / 2;
-        for (int m = 0; m <= L; ++m) tab32[m] = (float)qmm[m];
-        for (size_t i = 0; i < 2 * ntri; ++i) tab32[(L + 1) + i] = (float)alm[i];
         const double *nf4 = tab.data() + nf4_offset(L);
         for (int i = 0; i < 4 * (L + 1); ++i) tab32[nf4_32_offset(L) + i] = (float)nf4[i];
-        const double *ab = tab.data() + ab_offset(L);
-        for (size_t i = 0; i < 4 * ntri; ++i) tab32[ab32_offset(L) + i] = (float)ab[i];
         const double *lg = tab.data() + lg4_offset(L);
         for (int i = 0; i < 4 * (L + 1); ++i) tab32[lg4_32_offset(L) + i] = (float)lg[i];
         const double *fq = tab.data() + fq4_offset(L);
         for (size_t i = 0; i < 4 * ntri; ++i) tab32[fq4_32_offset(L) + i] = (float)fq[i];
     }
-    h->tb.qmm32 = h->tables32;
-    h->tb.alm32 = h->tables32 + (L + 1);
-    h->tb.blm32 = h->tables32 + (L + 1) + (L + 1) * (L + 2) / 2;
     h->tb.nf4_32 = reinterpret_cast<const float4 *>(h->tables32 + nf4_32_offset(L));
-    h->tb.abw32 = reinterpret_cast<const float4 *>(h->tables32 + ab32_offset(L));
     h->tb.lg4_32 = reinterpret_cast<const float4 *>(h->tables32 + lg4_32_offset(L));
     h->tb.fq4_32 = reinterpret_cast<const float4 *>(h->tables32 + fq4_32_offset(L));
     // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
