@@ -47,10 +47,13 @@ class Request:
 
 
 def gpu_seconds_estimate(n: int, l_max: int, n_steps: int,
-                         s_per_particle_step_per_channel: float = 2.9e-12) -> float:
-    """Device time of a request at the measured cost of the batched path,
-    proportional to (l_max + 1)^2 per particle-step."""
-    return n * n_steps * (l_max + 1) ** 2 * s_per_particle_step_per_channel
+                         s_per_particle_step: float = 1.8e-10,
+                         s_per_particle_step_per_channel: float = 1.3e-12) -> float:
+    """Device time of a request at the measured cost of the step: a part per
+    particle-step that does not depend on l_max (sort, push) plus a part
+    proportional to (l_max + 1)^2 (moments, carries, field); the two
+    constants fit the FP64 step times at 1.6e7 particles, l_max 8 and 32."""
+    return n * n_steps * (s_per_particle_step + (l_max + 1) ** 2 * s_per_particle_step_per_channel)
 
 
 def request_stream(seed: int = 5, duration_s: float = 60.0, load: float = 0.8,
