@@ -1301,7 +1301,13 @@ __global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, Sta
 {
     using R = typename std::conditional<FP32, float, double>::type;
     using NF = typename std::conditional<FP32, float4, double4>::type;
-    __shared__ NearRows<R> rows[kWavesPerBlock];
+    // Per wave: the tile's coefficients while the far field runs (when they
+    // fit), then the near field's rows.
+    union WaveLds {
+        NearRows<R> rows;
+        R cf[sizeof(NearRows<R>) / sizeof(R)];
+    };
+    __shared__ WaveLds lds[kWavesPerBlock];
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -1341,19 +1347,6 @@ __global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, Sta
     const double xh = x * inv_r, yh = y * inv_r, zh = z * inv_r;
     const bool ion = valid && (uid & kIonBit);
     const double qk = ion ? 1.0 : kQ;   // this particle's charge
-    NearRows<R> &nr = rows[w];
-    for (int c = 0; c < 2; ++c) {
-        const int i = lane + c * kWave;
-        nr.xh[i] = (R)xh;
-        nr.yh[i] = (R)yh;
-        nr.zh[i] = (R)zh;
-        nr.r[i] = (R)r;
-        nr.ir[i] = (R)inv_r;
-        nr.q[i] = valid ? (R)qk : (R)0;
-        nr.r2[i] = r2;
-        nr.uid[i] = uid;
-    }
-    wave_lds_sync();   // the rows are this wave's own
     if (!tile_live) return;
 
     const int L = kp.L;
@@ -1373,13 +1366,28 @@ __global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, Sta
         }
         const double inv_rho = 1.0 / rho;
         R gx, gy, gz;
+        const R *cfg;
+        const NF *fq;
         if constexpr (FP32) {
-            far_field<FULL, float>(coef32 + (size_t)tile * kp.C2, kp.C, L, tb.fq4_32,
-                                   (float)(x * inv_rho), (float)(y * inv_rho),
-                                   (float)(z * inv_rho), gx, gy, gz);
+            cfg = coef32 + (size_t)tile * kp.C2;
+            fq = tb.fq4_32;
         } else {
-            far_field<FULL, double>(coef + (size_t)tile * kp.C2, kp.C, L, tb.fq4, x,
-                                    y, z, gx, gy, gz);
+            cfg = coef + (size_t)tile * kp.C2;
+            fq = tb.fq4;
+        }
+        const R xs = (R)(x * inv_rho), ys = (R)(y * inv_rho), zs = (R)(z * inv_rho);
+        // the tile's coefficients are read by every pass of every lane: staged
+        // in LDS with coalesced loads (broadcast reads) when they fit, else
+        // read through the scalar cache
+        constexpr int kCfCap = (int)(sizeof(WaveLds) / sizeof(R));
+        if (kp.C2 <= kCfCap) {
+            R *cbuf = lds[w].cf;
+            for (int i = lane; i < kp.C2; i += kWave) cbuf[i] = cfg[i];
+            wave_lds_sync();
+            far_field<FULL, R>(cbuf, kp.C, L, fq, xs, ys, zs, gx, gy, gz);
+            wave_lds_sync();   // read before the rows below overwrite them
+        } else {
+            far_field<FULL, R>(cfg, kp.C, L, fq, xs, ys, zs, gx, gy, gz);
         }
         Ex = -(double)gx * inv_rho;
         Ey = -(double)gy * inv_rho;
@@ -1387,6 +1395,19 @@ __global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, Sta
     }
 
     // ---- near field (own tile); E += -(1 / (4 pi nt)) sum_j q_j grad D ----
+    NearRows<R> &nr = lds[w].rows;
+    for (int c = 0; c < 2; ++c) {
+        const int i = lane + c * kWave;
+        nr.xh[i] = (R)xh;
+        nr.yh[i] = (R)yh;
+        nr.zh[i] = (R)zh;
+        nr.r[i] = (R)r;
+        nr.ir[i] = (R)inv_r;
+        nr.q[i] = valid ? (R)qk : (R)0;
+        nr.r2[i] = r2;
+        nr.uid[i] = uid;
+    }
+    wave_lds_sync();   // the rows are this wave's own
     {
         double ax = 0.0, ay = 0.0, az = 0.0;
         if (L < 1) {
