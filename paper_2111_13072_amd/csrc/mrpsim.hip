@@ -960,8 +960,20 @@ struct Grave {
 //              + (e_z - cos th rhat) sum U D_z Qh + (sum Qh dU/dx, sum Qh dU/dy, 0).
 // (Assembling the radial part from the two partial derivatives of Q instead
 // loses a factor ~l to cancellation.)
-template <bool FULL, typename R, typename R4>
-__device__ inline void far_field(const R *cf, int C, int L, const R4 *fq, R x, R y, R z, R &gx,
+// Where the far field reads the coefficients of channel k: interior at
+// p[k - base], exterior at p[stride + k - base].
+template <typename R>
+struct CfView {
+    const R *p;
+    int base, stride;
+    __device__ R a(int k) const { return p[k - base]; }
+    __device__ R b(int k) const { return p[stride + k - base]; }
+};
+
+// stage(k0, k1) returns a view holding channels [k0, k1): the m = 0 block,
+// then one m block at a time, in stream order.
+template <bool FULL, typename R, typename R4, typename Stage>
+__device__ inline void far_field(Stage &&stage, int L, const R4 *fq, R x, R y, R z, R &gx,
                                  R &gy, R &gz)
 {
     const R r2 = x * x + y * y + z * z;
@@ -977,13 +989,14 @@ __device__ inline void far_field(const R *cf, int C, int L, const R4 *fq, R x, R
     {
         R Q1 = 1, Q2 = 0, D1 = 0, D2 = 0;   // Qh_{l-1}, Qh_{l-2} and their D_z
         R sl = inv_r * inv_r2;              // r^-(2l+1) at l = 1
+        const CfView<R> v = stage(0, L);
 #pragma unroll 2
         for (int l = 1; l <= L; ++l) {
             const R4 e = fq[l];
             const R gr2 = e.x * r2;
             const R Qv = z * Q1 - gr2 * Q2;
             const R Dz = (Q1 + z * D1) - gr2 * D2;
-            const R ac = cf[l - 1], bc = cf[C + l - 1];
+            const R ac = v.a(l - 1), bc = v.b(l - 1);
             const R Qs = Qv * sl, Qz = e.y * Qv, Qa = e.z * Qs, Ds = Dz * sl;
             Ga = fma(Qz, bc, Ga);
             Ga = fma(-Qa, ac, Ga);
@@ -1011,9 +1024,10 @@ __device__ inline void far_field(const R *cf, int C, int L, const R4 *fq, R x, R
             R sl = s_mm;
             // l = m: Qh = 1, D_z Qh = 0
             R Ac, As, Tc, Ts, Zc = 0, Zs = 0;
+            const CfView<R> v = stage(k, k + 2 * (L - m + 1));
             {
                 const R4 e = fq[j];
-                const R ac = cf[k], bc = cf[C + k], as = cf[k + 1], bs = cf[C + k + 1];
+                const R ac = v.a(k), bc = v.b(k), as = v.a(k + 1), bs = v.b(k + 1);
                 const R Qa = e.z * sl;
                 Tc = sl * ac + bc;
                 Ts = sl * as + bs;
@@ -1027,7 +1041,7 @@ __device__ inline void far_field(const R *cf, int C, int L, const R4 *fq, R x, R
 #pragma unroll 2
             for (int l = m + 1; l <= L; ++l) {
                 const R4 e = fq[j];
-                const R ac = cf[k], bc = cf[C + k], as = cf[k + 1], bs = cf[C + k + 1];
+                const R ac = v.a(k), bc = v.b(k), as = v.a(k + 1), bs = v.b(k + 1);
                 const R gr2 = e.x * r2;
                 const R Qv = z * Q1 - gr2 * Q2;
                 const R Dz = (Q1 + z * D1) - gr2 * D2;
@@ -1376,19 +1390,33 @@ __global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, Sta
             fq = tb.fq4;
         }
         const R xs = (R)(x * inv_rho), ys = (R)(y * inv_rho), zs = (R)(z * inv_rho);
-        // the tile's coefficients are read by every pass of every lane: staged
-        // in LDS with coalesced loads (broadcast reads) when they fit, else
-        // read through the scalar cache
-        constexpr int kCfCap = (int)(sizeof(WaveLds) / sizeof(R));
-        if (kp.C2 <= kCfCap) {
-            R *cbuf = lds[w].cf;
-            for (int i = lane; i < kp.C2; i += kWave) cbuf[i] = cfg[i];
-            wave_lds_sync();
-            far_field<FULL, R>(cbuf, kp.C, L, fq, xs, ys, zs, gx, gy, gz);
-            wave_lds_sync();   // read before the rows below overwrite them
-        } else {
-            far_field<FULL, R>(cfg, kp.C, L, fq, xs, ys, zs, gx, gy, gz);
-        }
+        // The tile's coefficients are read by every pass of every lane: they
+        // go to LDS with coalesced loads (the far field reads them as
+        // broadcasts), in windows of kWin channels (interior, then exterior)
+        // that hold whole m blocks; a window moves on when the next block
+        // does not fit (never at l_max <= 21 in FP64, 24 in FP32).  An m block
+        // has at most 2 l_max <= 128 channels.
+        constexpr int kWin = (int)(sizeof(WaveLds) / sizeof(R)) / 2;
+        static_assert(kWin >= 2 * kMaxL, "an m block must fit a window");
+        R *cbuf = lds[w].cf;
+        const int C = kp.C;
+        int win0 = 0, win_len = -1;   // resident channels [win0, win0 + win_len)
+        auto stage = [&](int k0, int k1) {
+            if (win_len < 0 || k1 > win0 + win_len) {
+                if (win_len >= 0) wave_lds_sync();   // the old window's reads are done
+                const int len = min(kWin, C - k0);
+                for (int i = lane; i < len; i += kWave) {
+                    cbuf[i] = cfg[k0 + i];
+                    cbuf[kWin + i] = cfg[C + k0 + i];
+                }
+                wave_lds_sync();
+                win0 = k0;
+                win_len = len;
+            }
+            return CfView<R>{cbuf, win0, kWin};
+        };
+        far_field<FULL, R>(stage, L, fq, xs, ys, zs, gx, gy, gz);
+        wave_lds_sync();   // read before the rows below overwrite them
         Ex = -(double)gx * inv_rho;
         Ey = -(double)gy * inv_rho;
         Ez = -(double)gz * inv_rho;
