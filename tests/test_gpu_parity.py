@@ -52,6 +52,8 @@ FIELD_CASES = [
     ("one-tile-64-L3", 64, 3, S.SIM_M_FULL, 28),
     ("two-tiles-65-L3", 65, 3, S.SIM_M_FULL, 29),
     ("shell-1000-L32", 1000, 32, S.SIM_M_FULL, 30),
+    # the largest l_max: the tile coefficients pass through LDS in nine windows
+    ("shell-700-L64", 700, 64, S.SIM_M_FULL, 31),
 ]
 
 
