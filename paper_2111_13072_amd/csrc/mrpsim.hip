@@ -732,7 +732,7 @@ __device__ inline bool chunk_tiles(const Map &mp, const KParams &kp, int j, uint
 }
 
 // The tile loops of the carry kernels issue the loads of kCarryBatch tiles
-// before using them (a chunk is up to 64 tiles walked by one thread, and one
+// before using them (a chunk is 8-64 tiles, or the tuned length, walked by one thread, and one
 // HBM round trip per tile would dominate); the sums keep the tile order.
 constexpr int kCarryBatch = 8;
 
