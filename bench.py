@@ -37,9 +37,19 @@ def algorithmic_flops_per_particle(l_max: int) -> float:
     return 20.0 * (l_max + 1) ** 2
 
 
+def _code_hash(text: str) -> str:
+    """Hash of HIP/C++ source with comments and whitespace removed (so an edit
+    of a comment does not retire a profile taken on the same code)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = re.sub(r"\s+", " ", text).strip()
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
 def _kernel_source_hash() -> str:
     p = os.path.join(ROOT, "paper_2111_13072_amd", "csrc", "mrpsim.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    return _code_hash(open(p).read())
 
 
 def _traffic_from_profiles(kernel: str, workload: str):
