@@ -130,19 +130,17 @@ struct Tables {
     const double *nfB;      // l/(l+1)
     const double4 *nf4;     // {(2l+1)/(l+1), l/(l+1), 2l+1, l}, one wide load per l
     const int *chl;         // degree l of each channel in stream order
-    // Moments recurrence Q_l^m = a_lm z Q_{l-1}^m - b_lm r^2 Q_{l-2}^m in
-    // stream order of (m, l) (m outer, l = m..L inner, so a loop over (m, l)
-    // reads consecutive entries): (Q_m^m or a_lm, 0 or b_lm, l - m, 2l + 1),
-    // of which the moments kernel reads the first two
-    const double4 *abw;
     // Legendre constants of the full near field, per l: {c_l, l c_l,
     // gamma_{l+1}, (2l+1) c_l}, where P_l = c_l Ph_l and the rescaled
     // polynomials obey Ph_{l+1} = u Ph_l - gamma_{l+1} Ph_{l-1}
     const double4 *lg4;
-    // Far-field recurrence in stream order of (m, l): the field kernel uses
-    // Qh_l^m = Q_l^m / N_lm with Qh_m^m = 1, Qh_l^m = z Qh_{l-1}^m -
-    // gamma_lm r^2 Qh_{l-2}^m; entries {gamma_lm, l - m, l + m + 1, 0}.  The
-    // coefficients carry the factor N_lm instead (chn, per channel).
+    // Rescaled harmonic recurrence in stream order of (m, l) (m outer,
+    // l = m..L inner, so a loop over (m, l) reads consecutive entries): the
+    // moments and the far field use Qh_l^m = Q_l^m / N_lm with Qh_m^m = 1,
+    // Qh_l^m = z Qh_{l-1}^m - gamma_lm r^2 Qh_{l-2}^m; entries {gamma_lm,
+    // l - m, l + m + 1, 0}, one zero entry after the triangle.  The tile sums
+    // are sums of Qh; the carries apply N_lm (chn, per channel) twice: once to
+    // turn the sums into true moments, once for the field's Qh.
     const double4 *fq4;
     const double *chn;
     // FP32 copies of the field kernel's tables for the FP32-compensated mode
@@ -241,12 +239,6 @@ __device__ inline T ld_const(const T *p, int i)
         reinterpret_cast<uintptr_t>(p))[i];
 }
 
-// The first two components of entry i of a table of double4.
-__device__ inline double2 ld_const_xy(const double4 *p, int i)
-{
-    const double *q = reinterpret_cast<const double *>(p);
-    return make_double2(ld_const(q, 4 * i), ld_const(q, 4 * i + 1));
-}
 
 // r^2 as (x*x + y*y) + z*z without contraction: the exact radial sort key.
 __device__ inline double key_r2(double x, double y, double z)
@@ -489,7 +481,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec 
 // Real solid harmonics through the polynomial Q_l^m(z, r^2) = r^l P~_l^m /
 // (r sin th)^m and (x + i y)^m = C_m + i S_m:
 //   R_lm^c = Q_l^m C_m,  R_lm^s = Q_l^m S_m,  I_lm = r^-(2l+1) R_lm,
-// normalised so that sum_m Y_lm(a) Y_lm(b) = (2l+1)/(4 pi) P_l(a.b).
+// normalised so that sum_m Y_lm(a) Y_lm(b) = (2l+1)/(4 pi) P_l(a.b).  The
+// kernel sums the rescaled Qh_l^m = Q_l^m / N_lm (a three-operation
+// recurrence); the carries restore N_lm.
 
 constexpr int kSlots = 8;       // LDS slots per batch; a slot holds two channels
 constexpr int kRowPad = 17;     // a 16-lane row of a slot, padded against bank conflicts
@@ -639,39 +633,36 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         if (++slot == kSlots) flush();
     };
 
-    // (Q_m^m or a_lm, 0 or b_lm) of the stream-order table, read one entry
-    // ahead of its use through a running pointer.  The read after the last
-    // entry lands in the Legendre tables that follow the triangle in the
-    // same block (its value is never used).
-    const double4 *ahead = tb.abw + 1;       // entry after the one held
-    double2 nab = ld_const_xy(tb.abw, 0);    // holds the next entry to use
-    auto next_entry = [&]() {
-        const double2 e = nab;
-        nab = ld_const_xy(ahead, 0);
-        ++ahead;
-        return e;
+    // gamma_lm of the stream-order table, read one entry ahead of its use
+    // through a running pointer (the read after the last entry lands on the
+    // table's zero entry after the triangle; its value is never used)
+    const double *ahead = reinterpret_cast<const double *>(tb.fq4 + 1);   // entry after the one held
+    double ng = ld_const(reinterpret_cast<const double *>(tb.fq4), 0);   // the next entry to use
+    auto next_gamma = [&]() {
+        const double g = ng;
+        ng = ld_const(ahead, 0);
+        ahead += 4;
+        return g;
     };
-    // m = 0: channels l = 1..L (Q_0^0 only seeds the recurrence; l = 0 is
-    // Gauss's law in the field kernel), two degrees per slot; the two Q
+    // m = 0: channels l = 1..L (Qh_0^0 = 1 only seeds the recurrence; l = 0
+    // is Gauss's law in the field kernel), two degrees per slot; the two Qh
     // registers trade roles instead of being copied
     {
-        double Qa = next_entry().x, Qb = 0.0;   // Q_{l-1}, Q_{l-2}
+        (void)next_gamma();                     // l = 0
+        double Qa = 1.0, Qb = 0.0;              // Qh_{l-1}, Qh_{l-2}
         double sl = inv_r * inv_r2;             // r^-(2l+1) at l = 1
         int l = 1;
         for (; l < L; l += 2) {
-            double2 ab = next_entry();
-            Qb = ab.x * z * Qa - ab.y * r2 * Qb;   // Q_l
+            Qb = z * Qa - next_gamma() * r2 * Qb;   // Qh_l
             const double r0 = q * Qb, i0 = r0 * sl;
             sl *= inv_r2;
-            ab = next_entry();
-            Qa = ab.x * z * Qb - ab.y * r2 * Qa;   // Q_{l+1}
+            Qa = z * Qb - next_gamma() * r2 * Qa;   // Qh_{l+1}
             const double r1 = q * Qa, i1 = r1 * sl;
             sl *= inv_r2;
             put2(r0, i0, r1, i1);
         }
         if (l == L) {
-            const double2 ab = next_entry();
-            Qb = ab.x * z * Qa - ab.y * r2 * Qb;
+            Qb = z * Qa - next_gamma() * r2 * Qb;
             const double r0 = q * Qb;
             put2(r0, r0 * sl, 0.0, 0.0);
         }
@@ -693,20 +684,18 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
                 put2(rc, rc * sl, rs, rs * sl);
                 sl *= inv_r2;
             };
-            double Qa = next_entry().x, Qb = 0.0;   // l = m: Q_m^m
+            (void)next_gamma();                     // l = m: Qh_m^m = 1
+            double Qa = 1.0, Qb = 0.0;
             emit(Qa);
             int l = m + 1;
             for (; l < L; l += 2) {
-                double2 ab = next_entry();
-                Qb = ab.x * z * Qa - ab.y * r2 * Qb;
+                Qb = z * Qa - next_gamma() * r2 * Qb;
                 emit(Qb);
-                ab = next_entry();
-                Qa = ab.x * z * Qb - ab.y * r2 * Qa;
+                Qa = z * Qb - next_gamma() * r2 * Qa;
                 emit(Qa);
             }
             if (l == L) {
-                const double2 ab = next_entry();
-                Qb = ab.x * z * Qa - ab.y * r2 * Qb;
+                Qb = z * Qa - next_gamma() * r2 * Qb;
                 emit(Qb);
             }
         }
@@ -828,7 +817,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *__
     const double *Ts = T + (size_t)mb * kp.C;
     if (c == 0 && blockIdx.y == 0 && j == (int)sg.c0 && in_run) {
         double acc = 0.0;
-        for (int l = 1; l <= kp.L; l += 2) acc += tb.drive_w[l] * Ts[l - 1];
+        // m = 0 channel l sits at stream position l - 1; its total is a sum of Qh
+        for (int l = 1; l <= kp.L; l += 2) acc += tb.drive_w[l] * tb.chn[l - 1] * Ts[l - 1];
         sg.qdiff[step] = -acc / sg.ntilde;
     }
     if (c >= kp.SW) return;
@@ -863,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *__
     } else if (c < kp.C) {
         const int l = tb.chl[c];
         const double nrm = tb.chn[c];
-        const double w = tb.wl[l] * inv_nt;
+        const double w = tb.wl[l] * inv_nt * nrm;   // the sums are of Qh = Q / N_lm
         double k = -tb.ftil[l] * Ts[c] * w;
         if (c < kp.L && in_run) k += sg.u_asy[step] * tb.drive_w[l];
         if (kp.fp32) {
@@ -876,7 +866,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *__
         }
     } else {
         const int l = tb.chl[c - kp.C];
-        const double w = tb.wl[l] * inv_nt * tb.chn[c - kp.C];
+        const double nrm = tb.chn[c - kp.C];
+        const double w = tb.wl[l] * inv_nt * nrm * nrm;   // sums of Qh; the field's Qh
         if (kp.fp32) {
             walk(-1, [&](int t, double carry) {
                 coef32[(size_t)t * kp.C2 + c] = (float)(carry * w * exp2((double)l * lgrho[t]));
@@ -1877,8 +1868,10 @@ namespace {
     } while (0)
 
 // Layout of the table block: 9 per-l arrays (ftil, wl, drive_w, self_w, nfA,
-// nfB, lval, tl1, qmm, in this order), the two (l, m) triangles, then the
-// interleaved near-field constants at a 32-byte aligned offset.
+// nfB, lval, tl1, qmm, in this order), the two (l, m) triangles a_lm, b_lm
+// (host side: N_lm and gamma_lm come from them), then at 32-byte aligned
+// offsets the near-field constants (nf4, lg4) and the rescaled recurrence
+// (fq4) with its zero entry.
 constexpr int kQmmArray = 8;   // index of qmm among the per-l arrays
 
 size_t nf4_offset(int L)
@@ -1887,13 +1880,12 @@ size_t nf4_offset(int L)
     return (base + 3) & ~size_t(3);
 }
 
-size_t ab_offset(int L) { return nf4_offset(L) + 4 * (size_t)(L + 1); }   // 32-byte aligned
-
-size_t lg4_offset(int L) { return ab_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
+size_t lg4_offset(int L) { return nf4_offset(L) + 4 * (size_t)(L + 1); }   // 32-byte aligned
 
 size_t fq4_offset(int L) { return lg4_offset(L) + 4 * (size_t)(L + 1); }
 
-size_t tables_len(int L) { return fq4_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
+// one zero entry after the fq4 triangle: the moments kernel reads one ahead
+size_t tables_len(int L) { return fq4_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2 + 1); }
 
 // FP32 copies of the field kernel's tables, each at a 16-byte aligned offset:
 // the axisymmetric near-field constants, the full near-field Legendre
@@ -2000,15 +1992,6 @@ std::vector<double> build_tables(const sim_params &p, const Layout &lo)
             blm[tri(l, m)] = (l >= m + 2)
                 ? std::sqrt(((l - 1.0) * (l - 1.0) - m2) * (2.0 * l + 1.0) / ((l2 - m2) * (2.0 * l - 3.0)))
                 : 0.0;
-        }
-    }
-    double *ab = t.data() + ab_offset(L);
-    for (int m = 0, j = 0; m <= L; ++m) {
-        for (int l = m; l <= L; ++l, ++j) {
-            ab[4 * j] = (l == m) ? qmm[m] : alm[tri(l, m)];
-            ab[4 * j + 1] = (l == m) ? 0.0 : blm[tri(l, m)];
-            ab[4 * j + 2] = (double)(l - m);
-            ab[4 * j + 3] = 2.0 * l + 1.0;
         }
     }
     // P_l = c_l Ph_l with c_0 = 1, c_l = c_{l-1} (2l-1)/l: the three-term
@@ -2182,7 +2165,6 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
     h->tb.nfA = tb + 4 * (L + 1);
     h->tb.nfB = tb + 5 * (L + 1);
     h->tb.nf4 = reinterpret_cast<const double4 *>(tb + nf4_offset(L));
-    h->tb.abw = reinterpret_cast<const double4 *>(tb + ab_offset(L));
     h->tb.lg4 = reinterpret_cast<const double4 *>(tb + lg4_offset(L));
     h->tb.fq4 = reinterpret_cast<const double4 *>(tb + fq4_offset(L));
     h->tb.chn = h->chn;
