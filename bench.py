@@ -194,6 +194,91 @@ def summarize_traffic(fetch_dir: str, write_dir: str, out_json: str, workload: s
     print(f"wrote {md}")
 
 
+HBM_PEAK_GBS = 8000.0
+N_SIMD = 1024             # 256 compute units x 4 SIMDs
+CLOCK_GHZ = 2.4           # peak engine clock
+VALU_CYCLES = 4           # a wave64 VALU instruction on a 16-lane SIMD
+
+
+def _short_kernel(name: str) -> str:
+    return name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+
+
+def summarize_util(trace_dir: str, valu_dir: str, fetch_dir: str, write_dir: str, out_md: str,
+                   copy_bytes: int, commands: list):
+    """Per kernel, against the MI355X peaks: achieved HBM GB/s (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy of copy_bytes in and out, over the
+    kernel's average duration in the trace), VALU busy (rocprof's VALUBusy
+    definition, one quad-cycle per VALU instruction: SQ_INSTS_VALU x 4 cycles
+    over 1024 SIMDs x duration x 2.4 GHz) and executed FP64/FP32 vector flop
+    rates (SQ_INSTS_VALU_FLOPS_* adds each VALU instruction's flops per lane,
+    so x 64 lanes)."""
+    dur = {}
+    for r in _read_csv(_find(trace_dir, "kernel_stats.csv")):
+        dur[_short_kernel(r["Name"])] = float(r["AverageNs"]) * 1e-9
+
+    def by_short(d):   # the counters of one kernel under its short name
+        out = {}
+        for k, v in d.items():
+            out.setdefault(_short_kernel(k), []).extend(v)
+        return out
+
+    f = by_short(_counter_by_kernel(fetch_dir, "FETCH_SIZE"))
+    w = by_short(_counter_by_kernel(write_dir, "WRITE_SIZE"))
+
+    def copy_kib(d):
+        c = [v for k, v in d.items() if "UnaryFunctor" in k or "MulFunctor" in k]
+        return float(np.median(c[0])) if c else None
+
+    cf, cw = copy_kib(f), copy_kib(w)
+    sf = copy_bytes / (cf * 1024.0) if cf else 1.0
+    sw = copy_bytes / (cw * 1024.0) if cw else 1.0
+    cnt = {c: by_short(_counter_by_kernel(valu_dir, c)) for c in
+           ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP32")}
+
+    def med(d, k):
+        v = d.get(k)
+        return float(np.median(v)) if v else None
+
+    lines = ["# Kernels against the MI355X peaks (HBM 8 TB/s, FP64 vector 78.6 TFLOP/s, "
+             "FP32 vector 157.3 TFLOP/s)", "",
+             f"Trace durations; FETCH_SIZE / WRITE_SIZE scaled by a plain copy of {copy_bytes} B "
+             f"in and out (fetch x{sf:.3f}, write x{sw:.3f}); VALU busy = SQ_INSTS_VALU x "
+             f"{VALU_CYCLES} cycles / ({N_SIMD} SIMDs x duration x {CLOCK_GHZ} GHz), rocprof's "
+             "VALUBusy at the peak clock (one quad-cycle per instruction: FP32 operations issue "
+             "faster on gfx950, so FP32 work can read above 100%); executed flops = 64 x "
+             "SQ_INSTS_VALU_FLOPS_FP64 (or _FP32) per dispatch over the duration.",
+             "", "Commands:", "", "```"] + commands + ["```", "",
+             "| kernel | us | HBM MB | GB/s | % of HBM peak | VALU instr / wave | VALU busy % "
+             "| FP64 TFLOP/s | % of FP64 peak | FP32 TFLOP/s |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    names = sorted(set(cnt["SQ_INSTS_VALU"]) | set(f) | set(w))
+    rows = []
+    for k in names:
+        if "at::native" in k or "rocclr" in k:
+            continue
+        s = k
+        t = dur.get(s)
+        if not t:
+            continue
+        hbm = ((med(f, k) or 0.0) * sf + (med(w, k) or 0.0) * sw) * 1024.0
+        gbs = hbm / t / 1e9
+        vi, wv = med(cnt["SQ_INSTS_VALU"], k), med(cnt["SQ_WAVES"], k)
+        f64, f32 = med(cnt["SQ_INSTS_VALU_FLOPS_FP64"], k), med(cnt["SQ_INSTS_VALU_FLOPS_FP32"], k)
+        issue = vi * VALU_CYCLES / (N_SIMD * t * CLOCK_GHZ * 1e9) if vi else None
+        tf64 = 64.0 * f64 / t / 1e12 if f64 else 0.0
+        tf32 = 64.0 * f32 / t / 1e12 if f32 else 0.0
+        rows.append((t, s, hbm, gbs, vi, wv, issue, tf64, tf32))
+    for t, s, hbm, gbs, vi, wv, issue, tf64, tf32 in sorted(rows, reverse=True):
+        per_wave = f"{vi / wv:.0f}" if vi and wv else "-"
+        lines.append(f"| {s} | {t * 1e6:.2f} | {hbm / 1e6:.1f} | {gbs:.0f} | "
+                     f"{100 * gbs / HBM_PEAK_GBS:.1f} | {per_wave} | "
+                     f"{'-' if issue is None else f'{100 * issue:.1f}'} | {tf64:.2f} | "
+                     f"{100 * tf64 / FP64_VECTOR_PEAK_TFLOPS:.1f} | {tf32:.2f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print(f"wrote {out_md}")
+
+
 def calibrate_copy(nbytes: int, reps: int = 3):
     """A plain elementwise copy of known size, for counter calibration."""
     import torch
@@ -388,6 +473,8 @@ def main(argv=None):
                     help="after the run, launch a plain copy of this size (counter calibration)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "OUT_MD"))
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
+    ap.add_argument("--summarize-util", nargs=5,
+                    metavar=("TRACE_DIR", "VALU_DIR", "FETCH_DIR", "WRITE_DIR", "OUT_MD"))
     ap.add_argument("--command", default="", help="command recorded in a summary")
     args = ap.parse_args(argv)
 
@@ -396,9 +483,15 @@ def main(argv=None):
         return 0
     if args.summarize_traffic:
         wl_name = "shell-2e6-L16" if args.workload == "large" else "shell-1e4-L8"
+        if args.precision == "fp32c":
+            wl_name += "-fp32c"
         summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1],
                           args.summarize_traffic[2], wl_name, "field_push",
                           args.calibrate_copy_mib * 2**20, args.command.split(" ;; "))
+        return 0
+    if args.summarize_util:
+        summarize_util(*args.summarize_util, args.calibrate_copy_mib * 2**20,
+                       args.command.split(" ;; "))
         return 0
 
     if args.gpus != 1:
