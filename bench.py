@@ -279,6 +279,48 @@ def summarize_util(trace_dir: str, valu_dir: str, fetch_dir: str, write_dir: str
     print(f"wrote {out_md}")
 
 
+def summarize_clock(pmc_dir: str, out_md: str, commands: list, n_xcd: int = 8):
+    """Engine clock and VALU occupancy per kernel from one counter run of
+    GRBM_GUI_ACTIVE (cycles, summed over the XCDs), SQ_INSTS_VALU,
+    SQ_ACTIVE_INST_VALU (quad-cycles) and SQ_WAVES, over each dispatch's own
+    start and end timestamps (first dispatch of each kernel)."""
+    first = {}
+    for r in _read_csv(_find(pmc_dir, "counter_collection.csv")):
+        k = _short_kernel(r["Kernel_Name"])
+        if "at::native" in k or "rocclr" in k:
+            continue
+        d = int(r["Dispatch_Id"])
+        if k in first and first[k][0] != d:
+            continue
+        rec = first.setdefault(k, (d, {}))[1]
+        rec[r["Counter_Name"]] = float(r["Counter_Value"])
+        rec["dur"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    lines = ["# Engine clock and VALU occupancy per kernel", "",
+             f"GRBM_GUI_ACTIVE / {n_xcd} XCDs over the dispatch's duration gives the clock; VALU "
+             f"busy = SQ_INSTS_VALU x {VALU_CYCLES} cycles / ({N_SIMD} SIMDs x those cycles); "
+             "SQ_ACTIVE_INST_VALU / SQ_INSTS_VALU > 1 where instructions take more than one "
+             "quad-cycle.  Kernels shorter than 100 us are left out: the counter window around a "
+             "dispatch adds several microseconds of cycles to it.", "", "Command:", "", "```"
+             ] + commands + ["```", "",
+             "| kernel | us | GHz | VALU busy % | ACTIVE_INST_VALU / INSTS_VALU | VALU pipe busy % |",
+             "|---|---|---|---|---|---|"]
+    rows = []
+    for k, (_, c) in first.items():
+        t = c.get("dur", 0.0)
+        cyc = c.get("GRBM_GUI_ACTIVE", 0.0) / n_xcd
+        vi = c.get("SQ_INSTS_VALU", 0.0)
+        if t < 100e-6 or cyc <= 0 or vi <= 0:
+            continue
+        busy = vi * VALU_CYCLES / (N_SIMD * cyc)
+        ratio = c.get("SQ_ACTIVE_INST_VALU", vi) / vi
+        rows.append((t, k, cyc / t / 1e9, busy, ratio))
+    for t, k, ghz, busy, ratio in sorted(rows, reverse=True):
+        lines.append(f"| {k} | {t * 1e6:.1f} | {ghz:.2f} | {100 * busy:.1f} | {ratio:.3f} | "
+                     f"{100 * busy * ratio:.1f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print(f"wrote {out_md}")
+
+
 def calibrate_copy(nbytes: int, reps: int = 3):
     """A plain elementwise copy of known size, for counter calibration."""
     import torch
@@ -475,6 +517,7 @@ def main(argv=None):
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
     ap.add_argument("--summarize-util", nargs=5,
                     metavar=("TRACE_DIR", "VALU_DIR", "FETCH_DIR", "WRITE_DIR", "OUT_MD"))
+    ap.add_argument("--summarize-clock", nargs=2, metavar=("PMC_DIR", "OUT_MD"))
     ap.add_argument("--command", default="", help="command recorded in a summary")
     args = ap.parse_args(argv)
 
@@ -488,6 +531,9 @@ def main(argv=None):
         summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1],
                           args.summarize_traffic[2], wl_name, "field_push",
                           args.calibrate_copy_mib * 2**20, args.command.split(" ;; "))
+        return 0
+    if args.summarize_clock:
+        summarize_clock(args.summarize_clock[0], args.summarize_clock[1], args.command.split(" ;; "))
         return 0
     if args.summarize_util:
         summarize_util(*args.summarize_util, args.calibrate_copy_mib * 2**20,
