@@ -338,7 +338,10 @@ def _alive(b, k):
 def bench_batch(args):
     """64 independent runs of a parameter scan (N from 1e4 to 1e6, T_e 1-5 eV,
     n_e 1e14-1e16), l_max = 16, in one batch: aggregate particle-steps/s of
-    the batched launch, and of the same runs one after another."""
+    the batched launch, and of the same runs one after another (in the same
+    precision and as plain FP64 runs)."""
+    from dataclasses import replace
+
     import torch
 
     from paper_2111_13072_amd import sim as S
@@ -383,19 +386,25 @@ def bench_batch(args):
     kms = b.profile(args.profile_steps)
     b.close()
 
-    # the same runs one after another (each its own handle and graph)
-    seq_time = 0.0
-    for k, mb in enumerate(members):
-        with S.Batch(cp, [mb]) as one:
-            one.step(args.warmup)
-            one.sync()
-            ta = time.perf_counter()
-            one.step(args.seq_steps)
-            one.sync()
-            seq_time += (time.perf_counter() - ta) / args.seq_steps
-        if k % 16 == 15:
-            print(f"[bench] sequential: {k + 1} runs timed", file=sys.stderr, flush=True)
-    seq_value = live / seq_time
+    # the same runs one after another (each its own handle and graph), in the
+    # batch's precision and, for FP32c, also as plain FP64 runs
+    def sequential(params, label):
+        total = 0.0
+        for k, mb in enumerate(members):
+            with S.Batch(params, [mb]) as one:
+                one.step(args.warmup)
+                one.sync()
+                ta = time.perf_counter()
+                one.step(args.seq_steps)
+                one.sync()
+                total += (time.perf_counter() - ta) / args.seq_steps
+            if k % 16 == 15:
+                print(f"[bench] sequential {label}: {k + 1} runs timed", file=sys.stderr,
+                      flush=True)
+        return live / total
+
+    seq_value = sequential(cp, args.precision)
+    seq_fp64 = sequential(replace(cp, precision=S.SIM_FP64), "fp64") if fp32 else seq_value
     dom = "field_push"
     flops = algorithmic_flops_per_particle(cp.l_max) * live
     achieved = flops / (kms[dom] * 1e-3) / 1e12
@@ -408,6 +417,7 @@ def bench_batch(args):
                        "n_particles": n_all, "l_max": cp.l_max, "precision": args.precision,
                        "parallelism": "single-gpu"},
             "sequential_value": seq_value, "batch_speedup": value / seq_value,
+            "sequential_fp64_value": seq_fp64, "speedup_vs_fp64_runs": value / seq_fp64,
             "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                          "frac": achieved / peak, "traffic": None, "kernel": dom,
                          "kernel_ms": kms[dom],
@@ -440,6 +450,7 @@ def bench_serve(args):
     wall = time.perf_counter() - t0
     work = sum(d.n * d.n_steps for d in done)
     lat = SV.latency_summary(done)
+    isolated = _isolated_fp64(done, reqs, args)
     line = {"metric": METRIC, "value": work / wall, "unit": "particle-steps/s", "n_gpus": 1,
             "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if fp32 else "f64",
@@ -449,9 +460,49 @@ def bench_serve(args):
                        "l_max": [8, 16, 32], "n_range": [1e4, 4e6], "steps_range": [200, 2000],
                        "budget_gib": args.serve_budget_gib, "tick_steps": 50,
                        "precision": args.precision, "parallelism": "single-gpu"},
-            "latency_s": lat, "rejected": len(srv.rejected), "wall_s": wall}
+            "latency_s": lat, "rejected": len(srv.rejected), "wall_s": wall,
+            "isolated_fp64": isolated}
     print(json.dumps(line), flush=True)
     return 0
+
+
+def _isolated_fp64(done, reqs, args, sample: int = 8, steps: int = 40):
+    """Plain per-request FP64 baseline on a sample of the served requests
+    (spread over the size range): each run alone as one simulation, `steps`
+    timed steps scaled to its step count; the served latency over that time."""
+    import torch
+
+    from paper_2111_13072_amd import sim as S
+
+    if not done:
+        return None
+    by_id = {r.rid: r for r in reqs}
+    ordered = sorted(done, key=lambda d: d.n * d.n_steps)
+    pick = [ordered[round(i * (len(ordered) - 1) / max(sample - 1, 1))] for i in range(sample)]
+    pick = list({d.rid: d for d in pick}.values())
+    ratios, iso_work, iso_time = [], 0.0, 0.0
+    for d in pick:
+        wl = by_id[d.rid].workload()
+        st = wl.particles()
+        prm = S.SimParams(ntilde=wl.ntilde, l_max=wl.l_max, r_out=wl.r_out, dt=wl.dt,
+                          precision=S.SIM_FP64)
+        with S.Sim(prm, st.pos, st.vel, wl.drive(steps + 5)) as sim:
+            sim.step(5)
+            sim.sync()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            sim.step(steps)
+            sim.sync()
+            per_step = (time.perf_counter() - ta) / steps
+        t_iso = per_step * d.n_steps
+        ratios.append(d.latency / t_iso)
+        iso_work += d.n * d.n_steps
+        iso_time += t_iso
+    print(f"[bench] isolated FP64 baseline on {len(pick)} requests", file=sys.stderr, flush=True)
+    return {"requests": len(pick), "steps_timed": steps,
+            "particle_steps_per_s": iso_work / iso_time,
+            "served_latency_over_isolated_p50": float(np.median(ratios)),
+            "served_latency_over_isolated_max": float(np.max(ratios))}
 
 
 def bench_sweep(args):
