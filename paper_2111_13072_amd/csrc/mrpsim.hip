@@ -485,9 +485,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec 
 // kernel sums the rescaled Qh_l^m = Q_l^m / N_lm (a three-operation
 // recurrence); the carries restore N_lm.
 
-constexpr int kSlots = 8;       // LDS slots per batch; a slot holds two channels
-constexpr int kRowPad = 17;     // a 16-lane row of a slot, padded against bank conflicts
-constexpr int kSlotLen = 4 * kRowPad;
+// A slot holds two channels, one LDS row each: the wave's 64 lanes after the
+// fold across wave halves, interior partial sums (lanes 0-31) at row offsets
+// 0-31 and exterior ones (lanes 32-63) at kHalfOff.  With kRowLen = 66 and
+// kHalfOff = 33 the rows' lanes fall on distinct banks both when a wave writes
+// a row and when it reads a batch back (each group of kLanesPerQ lanes one
+// half row).
+constexpr int kSlots = 4;                          // slots per batch
+constexpr int kRowLen = 66;
+constexpr int kHalfOff = 33;
+constexpr int kLanesPerQ = kWave / (4 * kSlots);   // lanes that sum one half row
+constexpr int kPartials = 32 / kLanesPerQ;         // entries each of them adds
+static_assert(kLanesPerQ == 2 || kLanesPerQ == 4, "a half row is summed by 2 or 4 lanes");
 
 // Orders this wave's LDS accesses at this point: LDS instructions of one wave
 // complete in issue order, so rows a wave wrote are visible to its later
@@ -511,27 +520,16 @@ __device__ inline void swap_wave_halves(double &a, double &b)
     b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | (uint64_t)lo[1]));
 }
 
-// Exchange the odd 16-lane rows of a with the even rows of b: afterwards
-// a = (a0, b0, a2, b2) and b = (a1, b1, a3, b3) by rows.
-__device__ inline void swap_odd_even_rows(double &a, double &b)
-{
-    const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
-    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
-    const auto hi =
-        __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
-    a = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | (uint64_t)lo[0]));
-    b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | (uint64_t)lo[1]));
-}
-
-// The value of lane (this lane xor 1), through DPP.
-__device__ inline double dpp_xor1(double v)
+// The value of another lane of this lane's quad, through DPP: kPerm is a
+// quad_perm control (0xB1: lane xor 1, 0x4E: lane xor 2).
+template <int kPerm>
+__device__ inline double dpp_quad(double v)
 {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
-    constexpr int kQuadPerm1032 = 0xB1;   // quad_perm [1, 0, 3, 2]
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, kQuadPerm1032,
-                                                              0xF, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32),
-                                                              kQuadPerm1032, 0xF, 0xF, false);
+    const uint32_t lo =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, kPerm, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), kPerm, 0xF, 0xF, false);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
@@ -542,16 +540,15 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     // Per wave (one tile of 64 particles), the lane sums of q R (interior)
     // and q I (exterior) of every channel, in a tree:
     //  1. R and I of one channel are folded across the wave halves (lanes
-    //     0-31 then hold R over particle pairs, lanes 32-63 I);
-    //  2. two channels (cos and sin of one (l, m), or two degrees of m = 0)
-    //     are folded across 16-lane rows: rows 0-3 hold R of the first, R of
-    //     the second, I of the first, I of the second, each as 16 sums of 4
-    //     particles, written to one LDS slot;
-    //  3. every kSlots slots each lane pair sums the 16 entries of one row
-    //     (8 each, then a lane exchange) and one of the two stores it.
+    //     0-31 then hold R over particle pairs, lanes 32-63 I), and the
+    //     result is one LDS row of a slot; a slot holds two channels (cos
+    //     and sin of one (l, m), or two degrees of m = 0);
+    //  2. every kSlots slots each group of kLanesPerQ lanes sums one half
+    //     row (kPartials entries each, then lane exchanges within the quad)
+    //     and the group's first lane stores it.
     // The m = 0 block is padded to an even count with a zero channel, so a
     // slot always holds two positions of the padded channel order.
-    __shared__ double buf[kWavesPerBlock][kSlots * kSlotLen];
+    __shared__ double buf[kWavesPerBlock][kSlots * 2 * kRowLen];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + w);
@@ -599,11 +596,13 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     }
 
     double *wb = buf[w];
-    // writer: lane -> (row lane / 16, entry lane % 16) of a slot
-    double *wr = wb + (lane >> 4) * kRowPad + (lane & 15);
-    // reader: lane pair v = lane / 2 sums row v % 4 of slot v / 4, half lane % 2
-    const int v = lane >> 1;
-    const double *rd = wb + v * kRowPad + (lane & 1) * 8;
+    // writer: lane -> its entry of a row
+    double *wr = wb + lane + (lane >= 32 ? kHalfOff - 32 : 0);
+    // reader: lane group v = 4 s + 2 j + h (slot s, its channel j, interior
+    // or exterior h) sums half row h of row (s, j); part t of it
+    const int v = lane / kLanesPerQ, t = lane % kLanesPerQ;
+    const int rs = v >> 2, rj = (v >> 1) & 1, rh = v & 1;
+    const double *rd = wb + (2 * rs + rj) * kRowLen + rh * kHalfOff + t * kPartials;
     const int pad0 = L & 1;             // zero channel after the m = 0 block
     const int n_pos = C + pad0;         // padded channel positions
     int slot = 0, base = 0;             // base: padded position of slot 0
@@ -611,14 +610,14 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         wave_lds_sync();
         double acc = rd[0];
 #pragma unroll
-        for (int k = 1; k < 8; ++k) acc += rd[k];
-        acc += dpp_xor1(acc);
-        const int s = v >> 2, row = v & 3;
-        const int pos = base + 2 * s + (row & 1);   // padded position
+        for (int k = 1; k < kPartials; ++k) acc += rd[k];
+        acc += dpp_quad<0xB1>(acc);
+        if (kLanesPerQ == 4) acc += dpp_quad<0x4E>(acc);
+        const int pos = base + 2 * rs + rj;   // padded position
         // padded position -> channel: the m = 0 block is positions 0..L-1
         const int ch = pos < L ? pos : pos - pad0;
-        if (tile_ok && (lane & 1) == 0 && s < slot && pos < n_pos && !(pad0 && pos == L))
-            St[(row >> 1) * C + ch] = acc;
+        if (tile_ok && t == 0 && rs < slot && pos < n_pos && !(pad0 && pos == L))
+            St[rh * C + ch] = acc;
         wave_lds_sync();
         base += 2 * kSlots;
         slot = 0;
@@ -627,9 +626,9 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     auto put2 = [&](double r0, double i0, double r1, double i1) {
         swap_wave_halves(r0, i0);
         swap_wave_halves(r1, i1);
-        double f0 = r0 + i0, f1 = r1 + i1;
-        swap_odd_even_rows(f0, f1);
-        wr[slot * kSlotLen] = f0 + f1;
+        double *row = wr + slot * 2 * kRowLen;
+        row[0] = r0 + i0;
+        row[kRowLen] = r1 + i1;
         if (++slot == kSlots) flush();
     };
 
