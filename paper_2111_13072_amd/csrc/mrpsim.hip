@@ -521,16 +521,16 @@ __device__ inline void swap_wave_halves(double &a, double &b)
 }
 
 // The value of another lane of this lane's quad, through DPP: kPerm is a
-// quad_perm control (0xB1: lane xor 1, 0x4E: lane xor 2).
+// quad_perm control (0xB1: lane xor 1, 0x4E: lane xor 2).  A quad
+// permutation has a source for every lane, so no "old" value is needed.
 template <int kPerm>
 __device__ inline double dpp_quad(double v)
 {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo =
-        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, kPerm, 0xF, 0xF, false);
-    const uint32_t hi =
-        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), kPerm, 0xF, 0xF, false);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    const uint32_t plo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, kPerm, 0xF, 0xF, true);
+    const uint32_t phi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), kPerm, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((uint64_t)phi << 32) | plo));
 }
 
 template <bool FULL>
