@@ -441,7 +441,8 @@ def bench_serve(args):
     print(f"[bench] serving {len(reqs)} requests over {args.serve_seconds:.0f} s, budget "
           f"{args.serve_budget_gib:g} GiB", file=sys.stderr, flush=True)
     srv = SV.Server(int(args.serve_budget_gib * 2**30),
-                    precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64, tick_steps=50)
+                    precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64, tick_steps=50,
+                    small_max=args.serve_small_max)
     t0 = time.perf_counter()
     try:
         done = srv.run(reqs, log=lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True))
@@ -459,6 +460,7 @@ def bench_serve(args):
                        "arrival_window_s": args.serve_seconds, "offered_load": 0.8,
                        "l_max": [8, 16, 32], "n_range": [1e4, 4e6], "steps_range": [200, 2000],
                        "budget_gib": args.serve_budget_gib, "tick_steps": 50,
+                       "small_max": args.serve_small_max,
                        "precision": args.precision, "parallelism": "single-gpu"},
             "latency_s": lat, "rejected": len(srv.rejected), "wall_s": wall,
             "isolated_fp64": isolated}
@@ -554,6 +556,9 @@ def main(argv=None):
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="serve: length of the Poisson arrival window")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-small-max", type=int, default=200000,
+                    help="serve: requests of at most this many particles get pools of their own "
+                         "(0: one pool per l_max)")
     ap.add_argument("--seq-steps", type=int, default=20,
                     help="batch64: timed steps of each member run alone, for comparison")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])

@@ -36,6 +36,7 @@ enum {
     SIM_ESTATE = -4,   /* NULL, destroyed or failed handle */
     SIM_EDEVICE = -5   /* a HIP runtime call failed */
 };
+enum { SIM_BUSY = 1 };   /* sim_query only: work still running */
 
 enum { SIM_M_FULL = 0, SIM_M_AXISYM = 1 };
 enum { SIM_BC_ABSORB = 0, SIM_BC_SPECULAR = 1, SIM_BC_DIFFUSE = 2 };
@@ -131,6 +132,16 @@ int sim_step(sim_t *h, int64_t k);
 
 /* Wait for all enqueued work of the handle. */
 int sim_sync(sim_t *h);
+
+/*
+ * Non-blocking check of the handle's enqueued work: SIM_OK when all of it has
+ * completed, SIM_BUSY (positive, not an error) while some still runs, a
+ * negative code if the device reported a failure (the handle then fails as
+ * after sim_sync).  Lets a host loop that drives several handles, such as a
+ * server with one resident batch per class, tend whichever finishes first
+ * without waiting on the others.
+ */
+int sim_query(sim_t *h);
 
 /*
  * Copy Q_diff[first .. first+count) to host (synchronises).  Q_diff(t_s) =

@@ -2719,6 +2719,17 @@ int sim_sync(sim_t *h)
     return SIM_OK;
 }
 
+int sim_query(sim_t *h)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    const hipError_t e = hipStreamQuery(h->stream);
+    if (e == hipSuccess) return SIM_OK;
+    if (e == hipErrorNotReady) return SIM_BUSY;
+    h->failed = true;
+    return fail(SIM_EDEVICE, std::string("hipStreamQuery: ") + hipGetErrorString(e));
+}
+
 int sim_member_info(sim_t *h, int32_t index, int64_t *n, int64_t *step, int64_t *n_steps)
 {
     int rc = check_handle(h);
@@ -2923,6 +2934,7 @@ const char *sim_strerror(int status)
     case SIM_ERANGE: return "index out of range";
     case SIM_ESTATE: return "invalid or failed handle";
     case SIM_EDEVICE: return "HIP runtime error";
+    case SIM_BUSY: return "work still running";
     default: return "unknown status";
     }
 }

@@ -1,12 +1,14 @@
 """Continuous-batching service of independent simulations.
 
 Requests (a plasma, a particle count, an l_max and a number of steps) arrive
-over time.  The server keeps one resident batch ("pool") per l_max class on
-its own HIP stream, admits waiting requests into a pool between steps when
-its tiles, chunks, buckets and memory allow (first come, first served within
-a class), steps every non-empty pool by a fixed tick, and retires finished
-requests after reading their response.  A request's response equals, bit for
-bit, that of the same request run alone (members never interact).
+over time.  The server keeps resident batches ("pools") per l_max class, and
+optionally per size class, each on its own HIP stream.  Whenever a pool's
+tick (a fixed number of steps of all its members) has completed, the server
+retires the members that reached their length after reading their response,
+admits waiting requests when its tiles, chunks, buckets and memory allow
+(first come, first served within the pool), and launches the next tick; it
+never waits on one pool to tend another.  A request's response equals, bit
+for bit, that of the same request run alone (members never interact).
 
 The particles of newly arrived requests are generated on worker threads
 while the device steps the pools.
@@ -101,14 +103,31 @@ class Done:
         return self.finished - self.arrival
 
 
+@dataclass
+class Pool:
+    """One resident batch: the requests it runs (member index -> [request,
+    admission time, steps done]) and whether a tick is in flight."""
+    key: tuple                      # (l_max, size class)
+    batch: S.Batch
+    running: dict = field(default_factory=dict)
+    busy: bool = False
+
+
 class Server:
-    """Pools per l_max with the same particle capacity each; budget_bytes of
-    device memory is split over the classes in proportion to their
-    per-particle footprint."""
+    """Pools per l_max class and, with small_max > 0, per size class: requests
+    of at most small_max particles go to the class's small pool (small_share
+    of its memory), larger ones to its large pool, so that a small request
+    does not advance at the pace of a pool holding multi-million-particle
+    runs.  budget_bytes of device memory is split over the l_max classes in
+    proportion to their per-particle footprint (equal particle capacity per
+    class).  Each pool steps on its own stream and is tended as soon as its
+    tick completes, whatever the other pools are doing."""
 
     def __init__(self, budget_bytes: int, l_classes=(8, 16, 32), precision: int = S.SIM_FP64,
-                 tick_steps: int = 50, max_members: int = 256):
+                 tick_steps: int = 50, max_members: int = 256, small_max: int = 0,
+                 small_share: float = 0.25):
         self.tick = tick_steps
+        self.small_max = small_max
         self.pools = {}
         per_particle = {}
         for L in l_classes:
@@ -120,77 +139,101 @@ class Server:
             cp = S.SimParams(l_max=L, precision=precision)
             # equal particle capacity per class: bytes in proportion to footprint
             slots = int(budget_bytes / total) // 64 * 64
-            self.pools[L] = S.Batch(cp, [], slot_capacity=max(slots, 64),
-                                    max_members=max_members, use_torch_stream=False)
-        self.running = {L: {} for L in l_classes}    # member index -> (request, admitted)
-        self.rejected = []                            # requests larger than their pool
+            if small_max > 0:
+                small = int(slots * small_share) // 64 * 64
+                shares = {0: small, 1: slots - small}
+            else:
+                shares = {0: slots}
+            for cls, n in shares.items():
+                self.pools[(L, cls)] = Pool((L, cls), S.Batch(
+                    cp, [], slot_capacity=max(n, 64), max_members=max_members,
+                    use_torch_stream=False))
+        self.rejected = []   # requests larger than their pool
+
+    def pool_key(self, req: Request) -> tuple:
+        if req.l_max not in {k[0] for k in self.pools}:
+            raise ValueError(f"no pool for l_max {req.l_max}")
+        return (req.l_max, 1 if 0 < self.small_max < req.n else 0)
 
     def close(self):
-        for b in self.pools.values():
-            b.close()
+        for p in self.pools.values():
+            p.batch.close()
 
-    def _admit(self, L, req, member, now):
+    @staticmethod
+    def _admit(pool: Pool, req, member, now) -> bool:
         try:
-            idx = self.pools[L].add(member)
+            idx = pool.batch.add(member)
         except S.SimError as e:
             if e.code == S.SIM_ENOMEM:
                 return False
             raise
-        self.running[L][idx] = (req, now)
+        pool.running[idx] = [req, now, 0]
         return True
 
-    def run(self, requests, clock=time.perf_counter, log=None, workers: int = 4) -> list:
+    def _retire(self, pool: Pool, now, done, log):
+        """After a tick: the members whose step count reached their length
+        (counted on the host, confirmed by the library) answer and leave."""
+        for idx, rec in list(pool.running.items()):
+            r, adm, steps = rec
+            rec[2] = steps = min(steps + self.tick, r.n_steps)
+            if steps < r.n_steps:
+                continue
+            info = pool.batch.info(idx)
+            if info["step"] < info["n_steps"]:
+                raise RuntimeError(f"request {r.rid}: host and device step counts disagree")
+            q = pool.batch.read_response(idx, 0, info["n_steps"])
+            pool.batch.remove(idx)
+            del pool.running[idx]
+            done.append(Done(r.rid, r.arrival, adm, now, r.n, r.l_max, r.n_steps, q))
+            if log:
+                log(f"done {r.rid} L{r.l_max} n={r.n} steps={r.n_steps} "
+                    f"latency {now - r.arrival:.2f} s")
+
+    def run(self, requests, clock=time.perf_counter, log=None, workers: int = 4,
+            poll_s: float = 2e-4) -> list:
         """Serve the requests (sorted by arrival) in real time; returns Done
         records in completion order."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
-        waiting = {L: deque() for L in self.pools}   # (request, future of its member)
+        waiting = {k: deque() for k in self.pools}   # (request, future of its member)
         done = []
+        pools = list(self.pools.values())
         with ThreadPoolExecutor(max_workers=workers) as ex:
             t0 = clock()
-            while pending or any(waiting.values()) or any(self.running.values()):
+            while pending or any(waiting.values()) or any(p.running for p in pools):
+                progressed = False
                 now = clock() - t0
                 while pending and pending[0].arrival <= now:
                     r = pending.popleft()
-                    if r.l_max not in self.pools:
-                        raise ValueError(f"no pool for l_max {r.l_max}")
-                    waiting[r.l_max].append((r, ex.submit(r.member)))
-                # one tick on every non-empty pool (asynchronous, own streams)
-                active = [L for L in self.pools if self.running[L]]
-                for L in active:
-                    self.pools[L].step(self.tick)
-                for L in active:
-                    self.pools[L].sync()
-                now = clock() - t0
-                # completions
-                for L in active:
-                    for idx, (r, adm) in list(self.running[L].items()):
-                        info = self.pools[L].info(idx)
-                        if info["step"] >= info["n_steps"]:
-                            q = self.pools[L].read_response(idx, 0, info["n_steps"])
-                            self.pools[L].remove(idx)
-                            del self.running[L][idx]
-                            done.append(Done(r.rid, r.arrival, adm, now, r.n, r.l_max, r.n_steps,
-                                             q))
-                            if log:
-                                log(f"done {r.rid} L{r.l_max} n={r.n} steps={r.n_steps} "
-                                    f"latency {now - r.arrival:.2f} s")
-                # admissions, first come first served within a class; a request
-                # that does not fit an empty pool never will
-                for L in self.pools:
-                    while waiting[L]:
-                        r, fut = waiting[L][0]
-                        if not fut.done() and self.running[L]:
-                            break
-                        mb = fut.result()
-                        if not self._admit(L, r, mb, clock() - t0):
-                            if not self.running[L]:
-                                self.rejected.append(r)
-                                waiting[L].popleft()
-                                continue
-                            break
-                        waiting[L].popleft()
-                if not any(self.running.values()) and not any(waiting.values()) and pending:
-                    time.sleep(max(0.0, pending[0].arrival - (clock() - t0)))
+                    waiting[self.pool_key(r)].append((r, ex.submit(r.member)))
+                    progressed = True
+                for pool in pools:
+                    if pool.busy:
+                        if not pool.batch.query():
+                            continue
+                        pool.busy = False
+                        self._retire(pool, clock() - t0, done, log)
+                        progressed = True
+                    # admissions, first come first served within the pool; a
+                    # request that does not fit an empty pool never will
+                    wq = waiting[pool.key]
+                    while wq and wq[0][1].done():
+                        r, fut = wq[0]
+                        if not self._admit(pool, r, fut.result(), clock() - t0):
+                            if pool.running:
+                                break
+                            self.rejected.append(r)
+                        wq.popleft()
+                        progressed = True
+                    if pool.running:
+                        pool.batch.step(self.tick)
+                        pool.busy = True
+                        progressed = True
+                if not progressed:
+                    idle = not any(p.busy for p in pools) and not any(waiting.values())
+                    if idle and pending:
+                        time.sleep(max(0.0, pending[0].arrival - (clock() - t0)))
+                    else:
+                        time.sleep(poll_s)
         return done
 
 

@@ -15,12 +15,14 @@ import numpy as np
 from .build import LIB
 
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_ERANGE, SIM_ESTATE, SIM_EDEVICE = 0, -1, -2, -3, -4, -5
+SIM_BUSY = 1   # sim_query: work still running
 SIM_M_FULL, SIM_M_AXISYM = 0, 1
 SIM_BC_ABSORB, SIM_BC_SPECULAR, SIM_BC_DIFFUSE = 0, 1, 2
 SIM_FP64, SIM_FP32_COMP = 0, 1
 
 # Every function include/mrpsim.h declares.
-EXPORTED = ("sim_params_default", "sim_create", "sim_step", "sim_sync", "sim_read_response",
+EXPORTED = ("sim_params_default", "sim_create", "sim_step", "sim_sync", "sim_query",
+            "sim_read_response",
             "sim_read_state", "sim_eval_field", "sim_profile", "sim_num_kernels",
             "sim_kernel_name", "sim_footprint_bytes", "sim_info", "sim_destroy",
             "sim_strerror", "sim_last_error", "sim_member_default", "sim_batch_create",
@@ -88,6 +90,7 @@ def lib():
                              C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]
     L.sim_step.argtypes = [H, C.c_int64]
     L.sim_sync.argtypes = [H]
+    L.sim_query.argtypes = [H]
     L.sim_read_response.argtypes = [H, C.c_int64, C.c_int64, dp]
     L.sim_read_state.argtypes = [H, dp, dp, C.POINTER(C.c_uint8), dp, C.POINTER(C.c_int64)]
     L.sim_eval_field.argtypes = [H, dp]
@@ -243,6 +246,14 @@ class Sim:
 
     def sync(self):
         _check(lib().sim_sync(self._handle()))
+
+    def query(self) -> bool:
+        """True when all enqueued work has completed (does not wait)."""
+        rc = lib().sim_query(self._handle())
+        if rc == SIM_BUSY:
+            return False
+        _check(rc)
+        return True
 
     def read_response(self, first: int, count: int) -> np.ndarray:
         out = np.zeros(count)
@@ -410,6 +421,14 @@ class Batch:
 
     def sync(self):
         _check(lib().sim_sync(self._handle()))
+
+    def query(self) -> bool:
+        """True when all enqueued work has completed (does not wait)."""
+        rc = lib().sim_query(self._handle())
+        if rc == SIM_BUSY:
+            return False
+        _check(rc)
+        return True
 
     def info(self, index: int) -> dict:
         n, st, ns = C.c_int64(), C.c_int64(), C.c_int64()

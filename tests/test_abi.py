@@ -41,8 +41,12 @@ def test_params_layout_matches_header():
 
 def test_strerror_covers_codes():
     L = S.lib()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, S.SIM_BUSY):
         assert L.sim_strerror(code).decode() not in ("", "unknown status")
+
+
+def test_query_rejects_a_null_handle():
+    assert S.lib().sim_query(None) == S.SIM_ESTATE
 
 
 def test_footprint_grows_with_size_and_rejects_bad_params():

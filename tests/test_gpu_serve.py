@@ -29,13 +29,17 @@ def small_requests():
     return reqs
 
 
-def test_served_results_equal_runs_alone():
+@pytest.mark.parametrize("small_max", [0, 1500])
+def test_served_results_equal_runs_alone(small_max):
     reqs = small_requests()
-    # room for about two requests per class at a time: admission has to wait
+    # room for about two requests per class at a time: admission has to wait;
+    # with small_max, requests of up to 1500 particles have pools of their own
     cp = S.SimParams(l_max=6)
     per = S.batch_footprint_bytes(cp, 1 << 16, 16) / (1 << 16)
-    srv = SV.Server(int(2 * 6000 * per), l_classes=(4, 6), tick_steps=8, max_members=16)
-    _say(f"[gpu] serving {len(reqs)} requests")
+    srv = SV.Server(int(2 * 6000 * per), l_classes=(4, 6), tick_steps=8, max_members=16,
+                    small_max=small_max)
+    assert len(srv.pools) == (4 if small_max else 2)
+    _say(f"[gpu] serving {len(reqs)} requests, small_max {small_max}")
     try:
         done = srv.run(reqs)
     finally:
