@@ -1295,16 +1295,20 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
     az += dck * (double)zh + dbz;
 }
 
-// FP32 (half the LDS rows, fewer registers) runs at six waves per SIMD
-template <bool FULL, bool FIELD_ONLY, bool FP32>
-__global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, State B, PRec *A, uint8_t *dead,
+// FP32 (half the LDS rows, fewer registers) runs at six waves per SIMD;
+// NEAR64: FP32 far field with the near field in FP64 (FP32 mode at high l_max)
+template <bool FULL, bool FIELD_ONLY, bool FP32, bool NEAR64>
+__global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(Map mp, State B, PRec *A, uint8_t *dead,
                                                        Grave G, const double *coef,
                                                        const float *coef32, const double *qpre,
                                                        Tables tb, KParams kp, double *Eout,
                                                        uint32_t *Eid)
 {
-    using R = typename std::conditional<FP32, float, double>::type;
-    using NF = typename std::conditional<FP32, float4, double4>::type;
+    // R, NF: the near field's precision; RF, NFF: the far field's
+    using R = typename std::conditional<FP32 && !NEAR64, float, double>::type;
+    using NF = typename std::conditional<FP32 && !NEAR64, float4, double4>::type;
+    using RF = typename std::conditional<FP32, float, double>::type;
+    using NFF = typename std::conditional<FP32, float4, double4>::type;
     // Per wave: the tile's coefficients while the far field runs (when they
     // fit), then the near field's rows.
     union WaveLds {
@@ -1369,9 +1373,9 @@ __global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, Sta
             rho = sqrt(key_r2(B.x[p0], B.y[p0], B.z[p0]));
         }
         const double inv_rho = 1.0 / rho;
-        R gx, gy, gz;
-        const R *cfg;
-        const NF *fq;
+        RF gx, gy, gz;
+        const RF *cfg;
+        const NFF *fq;
         if constexpr (FP32) {
             cfg = coef32 + (size_t)tile * kp.C2;
             fq = tb.fq4_32;
@@ -1379,16 +1383,16 @@ __global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, Sta
             cfg = coef + (size_t)tile * kp.C2;
             fq = tb.fq4;
         }
-        const R xs = (R)(x * inv_rho), ys = (R)(y * inv_rho), zs = (R)(z * inv_rho);
+        const RF xs = (RF)(x * inv_rho), ys = (RF)(y * inv_rho), zs = (RF)(z * inv_rho);
         // The tile's coefficients are read by every pass of every lane: they
         // go to LDS with coalesced loads (the far field reads them as
         // broadcasts), in windows of kWin channels (interior, then exterior)
         // that hold whole m blocks; a window moves on when the next block
         // does not fit (never at l_max <= 21 in FP64, 24 in FP32).  An m block
         // has at most 2 l_max <= 128 channels.
-        constexpr int kWin = (int)(sizeof(WaveLds) / sizeof(R)) / 2;
+        constexpr int kWin = (int)(sizeof(WaveLds) / sizeof(RF)) / 2;
         static_assert(kWin >= 2 * kMaxL, "an m block must fit a window");
-        R *cbuf = lds[w].cf;
+        RF *cbuf = reinterpret_cast<RF *>(lds[w].cf);
         const int C = kp.C;
         int win0 = 0, win_len = -1;   // resident channels [win0, win0 + win_len)
         auto stage = [&](int k0, int k1) {
@@ -1403,9 +1407,9 @@ __global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, Sta
                 win0 = k0;
                 win_len = len;
             }
-            return CfView<R>{cbuf, win0, kWin};
+            return CfView<RF>{cbuf, win0, kWin};
         };
-        far_field<FULL, R>(stage, L, fq, xs, ys, zs, gx, gy, gz);
+        far_field<FULL, RF>(stage, L, fq, xs, ys, zs, gx, gy, gz);
         wave_lds_sync();   // read before the rows below overwrite them
         Ex = -(double)gx * inv_rho;
         Ey = -(double)gy * inv_rho;
@@ -1432,13 +1436,13 @@ __global__ __launch_bounds__(kBlock, FP32 ? 6 : 4) void k_field_push(Map mp, Sta
             // monopole only: Gauss's law below
         } else if constexpr (FULL) {
             const NF *lg;
-            if constexpr (FP32) lg = tb.lg4_32;
+            if constexpr (std::is_same<R, float>::value) lg = tb.lg4_32;
             else lg = tb.lg4;
             near_field_full<R, NF>(lane, L, lg, nr, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
                                    valid ? (R)qk : (R)0, ax, ay, az);
         } else {
             const NF *nf;
-            if constexpr (FP32) nf = tb.nf4_32;
+            if constexpr (std::is_same<R, float>::value) nf = tb.nf4_32;
             else nf = tb.nf4;
             near_field<FULL, R, NF>(lane, jn, L, nf, nr.xh, nr.yh, nr.zh, nr.r, nr.ir, nr.r2,
                                     nr.uid, nr.q, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
@@ -1632,9 +1636,17 @@ Tuning tuning_of(const sim_params *p)
     return t;
 }
 
+// In the FP32 mode the near field's FP32 error grows with l_max (pairs at
+// nearly equal radius sum slowly decaying Legendre series and their
+// derivatives): measured 9e-6 of the RMS field at l_max 16, 2e-5 at 20, 5e-5
+// at 32.  From this degree on the near field runs in FP64 while the far field
+// stays FP32 (then 2e-6 to 1.2e-5 up to l_max 48, at a third more field time).
+constexpr int kNear64MinL = 17;
+
 struct Layout {
     int L, C, C2;
     bool full, fp32;
+    bool near64;     // FP32 mode with an FP64 near field (l_max >= kNear64MinL)
     int n_tiles;     // particle slots / 64
     int n_chunks;
     int nb, nb_blocks;
@@ -1735,6 +1747,7 @@ bool make_layout(const sim_params *p, int64_t slots, int32_t max_members, int64_
     lo->L = p->l_max;
     lo->full = p->m_mode == SIM_M_FULL;
     lo->fp32 = p->precision == SIM_FP32_COMP;
+    lo->near64 = lo->fp32 && p->l_max >= kNear64MinL;
     lo->C = lo->full ? (p->l_max + 1) * (p->l_max + 1) - 1 : p->l_max;
     lo->C2 = 2 * lo->C;
     lo->n_tiles = (int)((slots + kWave - 1) / kWave);
@@ -2062,12 +2075,16 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     k_chunk_apply<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkC, h->T, h->tb, kp,
                                                            h->lgrho, h->coef, h->coef32, h->qpre);
     mark(KN_FIELD_PUSH);
-#define MRP_FIELD(FULLV, FO, F32)                                                              \
-    k_field_push<FULLV, FO, F32><<<gT, kBlock, 0, s>>>(mp, h->B, h->A, h->dead, h->G, h->coef, \
-                                                       h->coef32, h->qpre, h->tb, kp, h->Eout,  \
-                                                       h->Eid)
-#define MRP_FIELD_P(FULLV, FO) \
-    do { if (lo.fp32) MRP_FIELD(FULLV, FO, true); else MRP_FIELD(FULLV, FO, false); } while (0)
+#define MRP_FIELD(FULLV, FO, F32, N64)                                                   \
+    k_field_push<FULLV, FO, F32, N64><<<gT, kBlock, 0, s>>>(mp, h->B, h->A, h->dead, h->G, \
+                                                            h->coef, h->coef32, h->qpre,   \
+                                                            h->tb, kp, h->Eout, h->Eid)
+#define MRP_FIELD_P(FULLV, FO)                                           \
+    do {                                                                 \
+        if (lo.near64) MRP_FIELD(FULLV, FO, true, true);                 \
+        else if (lo.fp32) MRP_FIELD(FULLV, FO, true, false);             \
+        else MRP_FIELD(FULLV, FO, false, false);                         \
+    } while (0)
     if (field_only) {
         if (lo.full) MRP_FIELD_P(true, true);
         else MRP_FIELD_P(false, true);

@@ -1,7 +1,8 @@
 """GPU (HIP) against the CPU oracle on identical seeded inputs.
 
 Field metric: max_k |E_gpu - E_oracle| / RMS_k |E_oracle|; bar 1e-12 in FP64,
-1e-5 in the FP32-compensated mode (l_max <= 16).
+1e-5 in the FP32-compensated mode (l_max <= 16; 2e-5 above, where its near
+field runs in FP64).
 Every case prints its name, size and seed before touching the GPU.
 """
 from __future__ import annotations
@@ -203,17 +204,21 @@ def test_deterministic_and_resumable():
 # --------------------------------------------------------------------------
 
 FP32_FIELD_TOL = 1e-5
-# The FP32 field evaluation carries ~l * 2^-24 error per harmonic term, and the
-# m-sums of a near pair cancel by ~l, so the bound grows like l_max^2 * 2^-24:
-# it meets 1e-5 up to l_max = 16; at l_max = 32 the measured error is 4.3e-5
-# and the stated bound is 1e-4 (FP64 mode meets 1e-12 there).
-FP32_FIELD_TOL_L32 = 1e-4
+# Above l_max 16 the FP32 mode evaluates the near field (the pairs inside a
+# tile, at nearly equal radius) in FP64: in FP32 its error grows with l_max
+# (2e-5 of the RMS field at l_max 20, 5e-5 at 32).  What remains is the FP32
+# far field's, measured 2e-6 to 1.2e-5 for l_max 20 to 48; the bound stated
+# there is 2e-5 (FP64 mode meets 1e-12).
+FP32_FIELD_TOL_HIGH_L = 2e-5
 
 FP32_CASES = [
     ("shell-3000-L8", 3000, 8, S.SIM_M_FULL, 61, FP32_FIELD_TOL),
     ("ragged-777-L5", 777, 5, S.SIM_M_FULL, 62, FP32_FIELD_TOL),
     ("shell-2000-L16", 2000, 16, S.SIM_M_FULL, 63, FP32_FIELD_TOL),
-    ("shell-1000-L32", 1000, 32, S.SIM_M_FULL, 64, FP32_FIELD_TOL_L32),
+    ("shell-1500-L20", 1500, 20, S.SIM_M_FULL, 70, FP32_FIELD_TOL_HIGH_L),
+    ("shell-1500-L24", 1500, 24, S.SIM_M_FULL, 71, FP32_FIELD_TOL_HIGH_L),
+    ("shell-1000-L32", 1000, 32, S.SIM_M_FULL, 64, FP32_FIELD_TOL_HIGH_L),
+    ("shell-700-L48", 700, 48, S.SIM_M_FULL, 72, FP32_FIELD_TOL_HIGH_L),
     ("axisym-640-L6", 640, 6, S.SIM_M_AXISYM, 65, FP32_FIELD_TOL),
     ("monopole-500-L0", 500, 0, S.SIM_M_FULL, 66, FP32_FIELD_TOL),
 ]
