@@ -129,6 +129,7 @@ class Server:
         self.tick = tick_steps
         self.small_max = small_max
         self.pools = {}
+        self.slots = {}   # particle slots of each pool
         per_particle = {}
         for L in l_classes:
             cp = S.SimParams(l_max=L, precision=precision)
@@ -145,15 +146,23 @@ class Server:
             else:
                 shares = {0: slots}
             for cls, n in shares.items():
+                self.slots[(L, cls)] = max(n, 64)
                 self.pools[(L, cls)] = Pool((L, cls), S.Batch(
                     cp, [], slot_capacity=max(n, 64), max_members=max_members,
                     use_torch_stream=False))
         self.rejected = []   # requests larger than their pool
 
     def pool_key(self, req: Request) -> tuple:
-        if req.l_max not in {k[0] for k in self.pools}:
+        """The request's pool: its l_max class, and the small pool when it has
+        at most small_max particles and fits that pool's slots (a request too
+        big for the small pool goes to the large one)."""
+        if (req.l_max, 0) not in self.pools:
             raise ValueError(f"no pool for l_max {req.l_max}")
-        return (req.l_max, 1 if 0 < self.small_max < req.n else 0)
+        if self.small_max <= 0:
+            return (req.l_max, 0)
+        tiles = -(-req.n // 64) * 64
+        small = req.n <= self.small_max and tiles <= self.slots[(req.l_max, 0)]
+        return (req.l_max, 0 if small else 1)
 
     def close(self):
         for p in self.pools.values():

@@ -1,0 +1,46 @@
+"""Host logic of the server: which pool a request goes to (no device)."""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_2111_13072_amd import serve as SV  # noqa: E402
+
+
+def _shell(small_max, small_slots=1472, large_slots=4480, classes=(4, 8)):
+    """A server's routing state without its device pools."""
+    srv = SV.Server.__new__(SV.Server)
+    srv.small_max = small_max
+    srv.pools = {}
+    srv.slots = {}
+    for L in classes:
+        for cls, n in ((0, small_slots), (1, large_slots)) if small_max > 0 else ((0, large_slots),):
+            srv.pools[(L, cls)] = None
+            srv.slots[(L, cls)] = n
+    return srv
+
+
+def _req(n, L=4):
+    return SV.Request(0, 0.0, n, L, 10, 2.0, 1e15, 1)
+
+
+def test_small_requests_go_to_the_small_pool_when_they_fit():
+    srv = _shell(1500)
+    assert srv.pool_key(_req(300)) == (4, 0)
+    assert srv.pool_key(_req(1472)) == (4, 0)       # 23 whole tiles: fits 1472 slots
+    assert srv.pool_key(_req(1473)) == (4, 1)       # 24 tiles: too big for the small pool
+    assert srv.pool_key(_req(1501)) == (4, 1)       # above small_max
+    assert srv.pool_key(_req(300, L=8)) == (8, 0)
+
+
+def test_one_pool_per_class_without_a_split():
+    srv = _shell(0)
+    assert srv.pool_key(_req(10)) == (4, 0)
+    assert srv.pool_key(_req(10 ** 6)) == (4, 0)
+
+
+def test_unknown_l_max_is_refused():
+    with pytest.raises(ValueError):
+        _shell(1500).pool_key(_req(100, L=6))
