@@ -154,3 +154,26 @@ def test_strict_step_and_lenient_batch_step():
         b.step(100)
         assert b.info(0)["step"] == 3 and b.info(1)["step"] == 5
         assert b.read_state(0)["step"] == 3 and b.read_state(1)["step"] == 5
+
+
+def test_query_reports_completion():
+    """sim_query answers without waiting: busy or done, and done after a sync."""
+    import time
+
+    _say("[gpu] sim_query on a stepping handle")
+    mb = make_member(30000, 7, 60)
+    with S.Batch(common(L=8), [mb], use_torch_stream=False) as b:
+        b.sync()
+        assert b.query()                  # nothing enqueued
+        b.step(40)
+        seen_done = False
+        t_end = time.perf_counter() + 60.0
+        while time.perf_counter() < t_end:
+            if b.query():
+                seen_done = True
+                break
+            time.sleep(1e-3)
+        assert seen_done
+        b.sync()
+        assert b.query()
+        assert b.info(0)["step"] == 40

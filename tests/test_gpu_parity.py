@@ -278,8 +278,9 @@ def test_fp32_large_workload_sampled_field():
     assert err <= FP32_FIELD_TOL
 
 
-def test_fp32_steps_track_oracle():
-    n, L, steps = 2000, 8, 5
+@pytest.mark.parametrize("L", [8, 20], ids=["L8", "L20-fp64-near"])
+def test_fp32_steps_track_oracle(L):
+    n, steps = 2000, 5
     _say(f"[gpu] fp32 stepping n={n} L={L} steps={steps}")
     sp, op = _params(n, L, q_surface0=-2.0, precision=S.SIM_FP32_COMP)
     st = W.uniform_shell(n, 41, 5.0, 0.3)
