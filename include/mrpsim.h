@@ -278,7 +278,12 @@ int sim_member_read_response(sim_t *h, int32_t index, int64_t first, int64_t cou
 int sim_member_read_state(sim_t *h, int32_t index, double *pos, double *vel, uint8_t *alive,
                           double *q_surface, int64_t *step);
 int sim_member_eval_field(sim_t *h, int32_t index, double *E);
+
+/* Static text for a status code (SIM_OK, SIM_BUSY or a SIM_E* code). */
 const char *sim_strerror(int status);
+
+/* Message of the calling thread's last failure; valid until that thread's
+ * next call into the library. */
 const char *sim_last_error(void);
 
 #ifdef __cplusplus
