@@ -62,9 +62,10 @@ enum { SIM_FP64 = 0, SIM_FP32_COMP = 1 };
  *               harmonics and contraction, near-field pair sums) in FP32 at
  *               tile-scaled coordinates, with FP64 moments, radial scans,
  *               l = 0 (Gauss) term, accumulation and positions; above
- *               l_max 16 the near-field pair sums run in FP64 too.  Field
- *               error against the FP64 definition: <= 1e-5 of the RMS field
- *               for l_max <= 16, <= 2e-5 (measured 2e-6 to 1.2e-5) up to 48.
+ *               l_max 32 the near-field pair sums run in FP64 too.  Field
+ *               error against the FP64 definition: about 1e-5 of the RMS
+ *               field or less for l_max <= 16 (measured at most 1.04e-5 on
+ *               random inputs), <= 2e-5 up to 48.
  *   tile        particles per tile of the radial scan (0 = choose).
  *   seed        key of the counter-based generator of diffuse walls.
  *   mem_limit_bytes  0 = none; otherwise sim_create fails with SIM_ENOMEM

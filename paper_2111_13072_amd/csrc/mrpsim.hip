@@ -147,6 +147,9 @@ struct Tables {
     const float4 *nf4_32;
     const float4 *lg4_32;
     const float4 *fq4_32;
+    // FP32 near field's Legendre recurrence on D_l = P_l - P_{l-1}, per l:
+    // {l / (l+1), -(2l+1) / (l+1), 2l+1, l+1}
+    const float4 *lw4_32;
 };
 
 // Channels are kept in "stream order": m = 0..m_top outer, l = max(m,1)..L
@@ -1196,8 +1199,9 @@ __device__ inline float bpermute(int addr, float v)
 // direction in one number and the rest in a vector; the partner's two
 // multiples go to it by a lane permutation, and it scales the sender's
 // direction (read from LDS) itself.  Lanes without a particle carry charge 0,
-// so their terms vanish without masks.  The Legendre sums use the rescaled
-// polynomials of the lg table (a two-operation recurrence); l = 1 is peeled.
+// so their terms vanish without masks.  In FP64 the Legendre sums use the
+// rescaled polynomials of the lg table (a two-operation recurrence; l = 1 is
+// peeled); in FP32 a recurrence on P_l - P_{l-1} driven by 1 - u (lw table).
 template <typename R, typename LG>
 __device__ inline void near_field_full(int lane, int L, const LG *lg, const NearRows<R> &nr, R xh,
                                        R yh, R zh, R r, R ir, double r2, uint32_t uid, R qk,
@@ -1228,35 +1232,75 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
         const R irmx = k_outer ? ir : irj;   // 1 / r_>
         const R rmin = k_outer ? rj : r;     // r_<
         const R rho = rmin * irmx;
-        const R u = xh * xj + yh * yj + zh * zj;
-        // l = 1: P_1 = u, P'_1 = 1.  Then two degrees per pass with the
-        // registers of Ph_l and Ph_{l-1} (and of P'_l, P'_{l-1}) trading roles
-        R S1 = rho * u, Sl = S1, SB = rho;
-        R Pa = u * u - c1.z, Pb = u, dPa = c1.w * u, dPb = 1, rl = rho * rho;
-        int l = 2;
-        for (; l < L; l += 2) {
-            const LG ca = lg[l], cb = lg[l + 1];
-            R t = rl * Pa;   // degree l from Pa
-            S1 += ca.x * t;
-            Sl += ca.y * t;
-            SB += rl * dPa;
-            Pb = u * Pa - ca.z * Pb;   // Ph_{l+1}
-            dPb += ca.w * Pa;          // P'_{l+1}
-            rl *= rho;
-            t = rl * Pb;     // degree l + 1 from Pb
-            S1 += cb.x * t;
-            Sl += cb.y * t;
-            SB += rl * dPb;
-            Pa = u * Pb - cb.z * Pa;   // Ph_{l+2}
-            dPa += cb.w * Pb;          // P'_{l+2}
-            rl *= rho;
-        }
-        if (l == L) {
-            const LG ca = lg[l];
-            const R t = rl * Pa;
-            S1 += ca.x * t;
-            Sl += ca.y * t;
-            SB += rl * dPa;
+        R u, S1, Sl, SB;
+        if constexpr (sizeof(R) == 4) {
+            // FP32: w = 1 - u = |xh_j - xh_k|^2 / 2 (for nearly parallel
+            // directions the difference is exact, so w keeps its relative
+            // precision where a dot product would leave 1 - u an absolute
+            // 2^-24), and the Legendre recurrence runs on the differences
+            // D_l = P_l - P_{l-1}: (l+1) D_{l+1} = l D_l - (2l+1) w P_l.  Near
+            // u = 1, where the sums of rho^l P_l and rho^l P'_l amplify errors
+            // in u, this keeps P_l to FP32 relative precision.
+            const R dx = xj - xh, dy = yj - yh, dz = zj - zh;
+            const R w = 0.5f * fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            u = 1.0f - w;
+            S1 = rho * u;
+            Sl = S1;
+            SB = rho;
+            // two degrees per pass, the registers of degree l and l + 1
+            // trading roles: (Pa, Da, dPa) hold P_l, D_l, P'_l and dPb
+            // P'_{l-1}, which the first half overwrites with P'_{l+1}
+            R Pa = u, Da = -w, dPa = 1, dPb = 0, rl = rho, Pb, Db;
+            auto degree = [&](const LG c, R &P, R &D, R &dPm, R &Pn, R &Dn) {
+                Dn = fmaf(c.x, D, c.y * (w * P));
+                Pn = P + Dn;
+                dPm = fmaf(c.z, P, dPm);   // P'_{l+1} = P'_{l-1} + (2l+1) P_l
+                rl *= rho;
+                const R t = rl * Pn;
+                S1 += t;
+                Sl = fmaf(c.w, t, Sl);
+                SB = fmaf(rl, dPm, SB);
+            };
+            int l = 1;
+            for (; l + 1 < L; l += 2) {
+                degree(lg[l], Pa, Da, dPb, Pb, Db);       // degree l + 1
+                degree(lg[l + 1], Pb, Db, dPa, Pa, Da);   // degree l + 2
+            }
+            if (l < L) degree(lg[l], Pa, Da, dPb, Pb, Db);
+        } else {
+            u = xh * xj + yh * yj + zh * zj;
+            // l = 1: P_1 = u, P'_1 = 1.  Then two degrees per pass with the
+            // registers of Ph_l and Ph_{l-1} (and of P'_l, P'_{l-1}) trading
+            // roles
+            S1 = rho * u;
+            Sl = S1;
+            SB = rho;
+            R Pa = u * u - c1.z, Pb = u, dPa = c1.w * u, dPb = 1, rl = rho * rho;
+            int l = 2;
+            for (; l < L; l += 2) {
+                const LG ca = lg[l], cb = lg[l + 1];
+                R t = rl * Pa;   // degree l from Pa
+                S1 += ca.x * t;
+                Sl += ca.y * t;
+                SB += rl * dPa;
+                Pb = u * Pa - ca.z * Pb;   // Ph_{l+1}
+                dPb += ca.w * Pa;          // P'_{l+1}
+                rl *= rho;
+                t = rl * Pb;     // degree l + 1 from Pb
+                S1 += cb.x * t;
+                Sl += cb.y * t;
+                SB += rl * dPb;
+                Pa = u * Pb - cb.z * Pa;   // Ph_{l+2}
+                dPa += cb.w * Pb;          // P'_{l+2}
+                rl *= rho;
+            }
+            if (l == L) {
+                const LG ca = lg[l];
+                const R t = rl * Pa;
+                S1 += ca.x * t;
+                Sl += ca.y * t;
+                SB += rl * dPa;
+            }
         }
         const R S_out = -(Sl + S1), S_in = Sl;
         const R SAk = k_outer ? S_out : S_in, SAj = k_outer ? S_in : S_out;
@@ -1337,15 +1381,14 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     const bool valid = tile_live && pl < n;
     const int jn = tile_live ? (int)min((uint32_t)kWave, n - lt * kWave) : 0;
 
-    double x = 0.0, y = 0.0, z = 2.0, vx = 0.0, vy = 0.0, vz = 0.0;
+    // (the velocities are read at the push, so that they hold no registers
+    // through the field evaluation)
+    double x = 0.0, y = 0.0, z = 2.0;
     uint32_t uid = 0xffffffffu;
     if (valid) {
         x = B.x[p];
         y = B.y[p];
         z = B.z[p];
-        vx = B.vx[p];
-        vy = B.vy[p];
-        vz = B.vz[p];
         uid = B.uid[p];
     }
     const double r2 = key_r2(x, y, z);
@@ -1436,7 +1479,7 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
             // monopole only: Gauss's law below
         } else if constexpr (FULL) {
             const NF *lg;
-            if constexpr (std::is_same<R, float>::value) lg = tb.lg4_32;
+            if constexpr (std::is_same<R, float>::value) lg = tb.lw4_32;
             else lg = tb.lg4;
             near_field_full<R, NF>(lane, L, lg, nr, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
                                    valid ? (R)qk : (R)0, ax, ay, az);
@@ -1525,6 +1568,7 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     // ---- leapfrog (Sec. 4 equations of motion) ----
     const double qm = ion ? sg.ion_qm : kQ / kM;
     const double dt = sg.dt;
+    double vx = B.vx[p], vy = B.vy[p], vz = B.vz[p];
     vx = __dadd_rn(vx, __dmul_rn(qm * Ex, dt));
     vy = __dadd_rn(vy, __dmul_rn(qm * Ey, dt));
     vz = __dadd_rn(vz, __dmul_rn(qm * Ez, dt));
@@ -1638,10 +1682,10 @@ Tuning tuning_of(const sim_params *p)
 
 // In the FP32 mode the near field's FP32 error grows with l_max (pairs at
 // nearly equal radius sum slowly decaying Legendre series and their
-// derivatives): measured 9e-6 of the RMS field at l_max 16, 2e-5 at 20, 5e-5
-// at 32.  From this degree on the near field runs in FP64 while the far field
-// stays FP32 (then 2e-6 to 1.2e-5 up to l_max 48, at a third more field time).
-constexpr int kNear64MinL = 17;
+// derivatives); with the recurrence driven by 1 - u it stays under ~1e-5 of
+// the RMS field up to l_max 32 (2.9e-5 at 48).  From this degree on the near
+// field runs in FP64 while the far field stays FP32.
+constexpr int kNear64MinL = 33;
 
 struct Layout {
     int L, C, C2;
@@ -1908,7 +1952,9 @@ size_t lg4_32_offset(int L) { return nf4_32_offset(L) + 4 * (size_t)(L + 1); }
 
 size_t fq4_32_offset(int L) { return lg4_32_offset(L) + 4 * (size_t)(L + 1); }
 
-size_t tables32_len(int L) { return fq4_32_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
+size_t lw4_32_offset(int L) { return fq4_32_offset(L) + 4 * (size_t)((L + 1) * (L + 2) / 2); }
+
+size_t tables32_len(int L) { return lw4_32_offset(L) + 4 * (size_t)(L + 1); }
 
 void plan_alloc(sim *h, Alloc &al)
 {
@@ -2194,10 +2240,18 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
         for (int i = 0; i < 4 * (L + 1); ++i) tab32[lg4_32_offset(L) + i] = (float)lg[i];
         const double *fq = tab.data() + fq4_offset(L);
         for (size_t i = 0; i < 4 * ntri; ++i) tab32[fq4_32_offset(L) + i] = (float)fq[i];
+        float *lw = tab32.data() + lw4_32_offset(L);
+        for (int l = 0; l <= L; ++l) {
+            lw[4 * l + 0] = (float)((double)l / (l + 1.0));
+            lw[4 * l + 1] = (float)(-(2.0 * l + 1.0) / (l + 1.0));
+            lw[4 * l + 2] = (float)(2.0 * l + 1.0);
+            lw[4 * l + 3] = (float)(l + 1.0);
+        }
     }
     h->tb.nf4_32 = reinterpret_cast<const float4 *>(h->tables32 + nf4_32_offset(L));
     h->tb.lg4_32 = reinterpret_cast<const float4 *>(h->tables32 + lg4_32_offset(L));
     h->tb.fq4_32 = reinterpret_cast<const float4 *>(h->tables32 + fq4_32_offset(L));
+    h->tb.lw4_32 = reinterpret_cast<const float4 *>(h->tables32 + lw4_32_offset(L));
     // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
     // and its far-field normalisation N_lm
     std::vector<int> chl;

@@ -1,8 +1,7 @@
 """GPU (HIP) against the CPU oracle on identical seeded inputs.
 
 Field metric: max_k |E_gpu - E_oracle| / RMS_k |E_oracle|; bar 1e-12 in FP64,
-1e-5 in the FP32-compensated mode (l_max <= 16; 2e-5 above, where its near
-field runs in FP64).
+1e-5 in the FP32-compensated mode (l_max <= 16; 2e-5 above).
 Every case prints its name, size and seed before touching the GPU.
 """
 from __future__ import annotations
@@ -204,11 +203,11 @@ def test_deterministic_and_resumable():
 # --------------------------------------------------------------------------
 
 FP32_FIELD_TOL = 1e-5
-# Above l_max 16 the FP32 mode evaluates the near field (the pairs inside a
-# tile, at nearly equal radius) in FP64: in FP32 its error grows with l_max
-# (2e-5 of the RMS field at l_max 20, 5e-5 at 32).  What remains is the FP32
-# far field's, measured 2e-6 to 1.2e-5 for l_max 20 to 48; the bound stated
-# there is 2e-5 (FP64 mode meets 1e-12).
+# The FP32 near field (pairs inside a tile, at nearly equal radius) runs its
+# Legendre recurrence on 1 - u, which keeps its error under ~1e-5 up to
+# l_max 32; above, it runs in FP64.  Measured for l_max 20 to 48: 2e-6 to
+# 1.2e-5, the largest set by the FP32 far field; the bound stated there is
+# 2e-5 (FP64 mode meets 1e-12).
 FP32_FIELD_TOL_HIGH_L = 2e-5
 
 FP32_CASES = [
@@ -278,7 +277,7 @@ def test_fp32_large_workload_sampled_field():
     assert err <= FP32_FIELD_TOL
 
 
-@pytest.mark.parametrize("L", [8, 20], ids=["L8", "L20-fp64-near"])
+@pytest.mark.parametrize("L", [8, 20, 34], ids=["L8", "L20", "L34-fp64-near"])
 def test_fp32_steps_track_oracle(L):
     n, steps = 2000, 5
     _say(f"[gpu] fp32 stepping n={n} L={L} steps={steps}")
@@ -291,6 +290,8 @@ def test_fp32_steps_track_oracle(L):
         out = sim.read_state()
     ref = O.run(op, st.pos, st.vel, u, steps, q_surface=-2.0)
     np.testing.assert_array_equal(out["alive"], ref.alive)
-    # a 1e-5 relative field error moves a particle by < 1e-5 |E| dt^2 per step
-    assert np.max(np.abs(out["pos"] - ref.pos)) <= 1e-7
-    assert np.max(np.abs(qd - ref.qdiff)) <= 1e-6 * np.max(np.abs(ref.qdiff))
+    # a relative field error e moves a particle by < e |E| dt^2 per step: 1e-7
+    # for the 1e-5 bound up to l_max 16, 2e-7 for the 2e-5 bound above
+    field_tol = FP32_FIELD_TOL if L <= 16 else FP32_FIELD_TOL_HIGH_L
+    assert np.max(np.abs(out["pos"] - ref.pos)) <= 1e-2 * field_tol
+    assert np.max(np.abs(qd - ref.qdiff)) <= 0.1 * field_tol * np.max(np.abs(ref.qdiff))
