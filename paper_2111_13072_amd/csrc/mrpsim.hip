@@ -92,6 +92,9 @@ struct Ctl {
     uint32_t n_dead;    // particles absorbed so far (graveyard fill)
     uint32_t n_dead_ion;  // of which ions
     double q_surface;   // Q_S used by this step's field
+    // the step whose sort keys, bucket slots and bucket counts the last push
+    // already produced (-1: none; the key kernel computes them)
+    int64_t keys_for = -1;
 };
 
 // Per-member description (device table, written by the host between steps).
@@ -280,6 +283,9 @@ struct alignas(16) OrdRec {
 // Key, bucket and slot inside the bucket, over all particle slots.  One
 // step moves a particle across ~10^2 buckets, so the lanes of a wave land in
 // almost distinct buckets: each takes its slot with its own atomic add.
+// Members whose last push already produced this step's records (keys_for)
+// are skipped: the push kernel's tail does the same work for the particles
+// it moves, where the field's arithmetic hides the atomics' latency.
 __global__ void k_sort_key(Map mp, const PRec *A, const uint8_t *dead, KeyRec *krec,
                            uint32_t *hist, KParams kp)
 {
@@ -294,6 +300,7 @@ __global__ void k_sort_key(Map mp, const PRec *A, const uint8_t *dead, KeyRec *k
         const Seg &sg = mp.seg[mb];
         const Ctl &c = mp.ctl[mb];
         if (member_runs(sg, c, kp)) {
+            if (c.keys_for == c.step) return;   // wave-uniform
             live = (i - sg.p0) < c.n_cur && !dead[i];
             inv_vol = sg.inv_vol;
             b0 = sg.b0;
@@ -389,23 +396,31 @@ __device__ inline void member_live(const Map &mp, const uint32_t *off, const KPa
         const Seg &sg = mp.seg[s];
         Ctl &c = mp.ctl[s];
         if (!member_runs(sg, c, kp)) continue;
+        c.keys_for = -1;   // this step's sort records are consumed
         c.n_live = off[sg.b0 + sg.nb] - off[sg.b0];
         c.q_surface =
             (sg.q_surface0 + kQ * (double)(c.n_dead - c.n_dead_ion)) + (double)c.n_dead_ion;
     }
 }
 
-// Bucket order (arbitrary inside a bucket): key, id and source slot.
+// Bucket order (arbitrary inside a bucket): key, id and source slot.  Only
+// the records of running members' first n_cur slots count (the push writes
+// records for the slots it moves, and slots past the alive count may hold
+// older ones).
 __global__ void k_sort_scatter(Map mp, const KeyRec *krec, const uint32_t *off, OrdRec *orec,
                                KParams kp)
 {
     const uint32_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= (uint32_t)kp.n_tiles * kWave) return;
-    const KeyRec r = krec[i];
+    const KeyRec r = krec[i];   // in bounds; issued before the member's tables
+    const uint32_t mb = uniform_u32(mp.tile_member[i >> 6]);
+    if (mb == kNone) return;
+    const Seg &sg = mp.seg[mb];
+    const Ctl &c = mp.ctl[mb];
+    if (!member_runs(sg, c, kp) || (i - sg.p0) >= c.n_cur) return;
     if (r.sub == kNone) return;
     // the bucket again, from the key and the member of this slot's tile (the
-    // same arithmetic as in the key kernel, so the same bucket)
-    const Seg &sg = mp.seg[mp.tile_member[i >> 6]];
+    // same arithmetic as in the key kernel and the push, so the same bucket)
     const uint32_t b = bucket_of(__longlong_as_double((long long)r.key), sg.inv_vol, sg.b0, sg.nb);
     orec[off[b] + r.sub] = OrdRec{r.key, r.uid, i};
 }
@@ -1346,7 +1361,8 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
                                                        Grave G, const double *coef,
                                                        const float *coef32, const double *qpre,
                                                        Tables tb, KParams kp, double *Eout,
-                                                       uint32_t *Eid)
+                                                       uint32_t *Eid, KeyRec *krec,
+                                                       uint32_t *hist)
 {
     // R, NF: the near field's precision; RF, NFF: the far field's
     using R = typename std::conditional<FP32 && !NEAR64, float, double>::type;
@@ -1627,6 +1643,19 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     out.pad[0] = out.pad[1] = out.pad[2] = 0u;
     A[p] = out;
     dead[p] = absorbed;
+    // the next step's sort record of this slot, when the member runs then
+    // (the same key, bucket and atomic slot as the key kernel would take;
+    // the histogram was cleared by this step's offsets kernel)
+    if (step + 1 < sg.n_steps) {
+        KeyRec kr{0ull, 0u, kNone};
+        if (!absorbed) {
+            const double k2 = key_r2(x, y, z);
+            kr.key = (uint64_t)__double_as_longlong(k2);
+            kr.uid = uid;
+            kr.sub = atomicAdd(&hist[bucket_of(k2, sg.inv_vol, sg.b0, sg.nb)], 1u);
+        }
+        krec[p] = kr;
+    }
     if (absorbed) {
         if (ion) atomicAdd(&ct.n_dead_ion, 1u);
         const uint32_t slot = sg.p0 + atomicAdd(&ct.n_dead, 1u);
@@ -1645,9 +1674,12 @@ __global__ void k_step_finish(Map mp, KParams kp)
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= kp.n_members) return;
     Ctl &c = mp.ctl[s];
-    if (!member_runs(mp.seg[s], c, kp)) return;
+    const Seg &sg = mp.seg[s];
+    if (!member_runs(sg, c, kp)) return;
     c.step += 1;
     c.n_cur = c.n_live;
+    // the push produced the sort records of the step the member runs next
+    if (c.step < sg.n_steps) c.keys_for = c.step;
 }
 
 // ---------------------------------------------------------------------------
@@ -2124,7 +2156,8 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
 #define MRP_FIELD(FULLV, FO, F32, N64)                                                   \
     k_field_push<FULLV, FO, F32, N64><<<gT, kBlock, 0, s>>>(mp, h->B, h->A, h->dead, h->G, \
                                                             h->coef, h->coef32, h->qpre,   \
-                                                            h->tb, kp, h->Eout, h->Eid)
+                                                            h->tb, kp, h->Eout, h->Eid,    \
+                                                            h->krec, h->hist)
 #define MRP_FIELD_P(FULLV, FO)                                           \
     do {                                                                 \
         if (lo.near64) MRP_FIELD(FULLV, FO, true, true);                 \
@@ -2541,7 +2574,10 @@ int engine_remove(sim *h, int32_t index)
     Member &mb = h->members[index];
     Seg off{};   // used = 0
     std::vector<uint32_t> tm(mb.seg.nt, kNone), cm(mb.seg.nc, kNone);
+    // the member's last push may have counted its particles into its buckets
+    // for a next step; the buckets go back to the pool cleared
     if (hipMemcpy(h->seg + index, &off, sizeof(Seg), hipMemcpyHostToDevice) ||
+        hipMemset(h->hist + mb.seg.b0, 0, sizeof(uint32_t) * mb.seg.nb) ||
         hipMemcpy(h->tile_member + mb.seg.t0, tm.data(), 4 * tm.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->chunk_member + mb.seg.c0, cm.data(), 4 * cm.size(), hipMemcpyHostToDevice)) {
         h->failed = true;

@@ -198,6 +198,40 @@ def test_deterministic_and_resumable():
     assert end["q_surface"] == full["q_surface"]
 
 
+def test_field_evaluation_between_steps_changes_nothing():
+    """A field evaluation between steps sorts on its own; the run stays
+    bitwise equal to an uninterrupted one (absorbing probe, fast particles so
+    that some are absorbed), repeated evaluations agree, and the field of a
+    finished run can still be evaluated."""
+    n, L, k = 3000, 6, 4
+    _say(f"[gpu] field evaluation between steps n={n} L={L} k={k}")
+    sp, _ = _params(n, L)
+    st = W.uniform_shell(n, 53, 1.6, 0.8)
+    u = W.gaussian_drive(3 * k, sp.dt, 20.0, 289.52, t_center=0.1)
+    with S.Sim(sp, st.pos, st.vel, u) as sim:
+        sim.step(3 * k)
+        ref = sim.read_state()
+        q_ref = sim.read_response(0, 3 * k)
+        E_end = sim.eval_field()
+    assert (ref["alive"] == 0).any()
+    with S.Sim(sp, st.pos, st.vel, u) as sim:
+        sim.step(k)
+        E1 = sim.eval_field()
+        E1b = sim.eval_field()
+        sim.step(k)
+        sim.eval_field()
+        sim.step(k)
+        got = sim.read_state()
+        q_got = sim.read_response(0, 3 * k)
+        E_end_b = sim.eval_field()
+    np.testing.assert_array_equal(E1, E1b)
+    np.testing.assert_array_equal(got["pos"], ref["pos"])
+    np.testing.assert_array_equal(got["vel"], ref["vel"])
+    np.testing.assert_array_equal(got["alive"], ref["alive"])
+    np.testing.assert_array_equal(q_got, q_ref)
+    np.testing.assert_array_equal(E_end_b, E_end)
+
+
 # --------------------------------------------------------------------------
 # FP32-compensated mode: same oracle, bar 1e-5 on the field
 # --------------------------------------------------------------------------
