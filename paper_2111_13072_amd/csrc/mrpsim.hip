@@ -428,8 +428,9 @@ __global__ void k_sort_scatter(Map mp, const KeyRec *krec, const uint32_t *off, 
 // Final position = bucket start + number of bucket mates with a smaller
 // (r^2, id) key (independent of the order inside the bucket), moved into the
 // member's slot range; the particle's state moves there.  A block's positions
-// cover a window of whole buckets, staged in LDS when it fits.
-constexpr int kRankWindow = 2048;
+// cover a window of whole buckets, staged in LDS when it fits (12 KB; with
+// 24 KB, six blocks per CU, the kernel took 5% longer).
+constexpr int kRankWindow = 1024;
 
 __device__ inline uint32_t bucket_of_rec(const Map &mp, const OrdRec &r)
 {
@@ -449,6 +450,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec 
     const uint32_t p0 = xcd_block(blockIdx.x, gridDim.x) * kBlock;
     if (p0 >= n) return;
     const uint32_t p_last = min(p0 + kBlock, n) - 1;
+    const uint32_t p = p0 + threadIdx.x;
+    const bool act = p < n;
+    // This lane's record, then its member's tables, its bucket's bounds and
+    // the gathered state: all issued before the block's window is staged, so
+    // that their round trips overlap the window's (lanes past n take the
+    // block's last record and leave after the barrier).
+    const OrdRec me = orec[act ? p : p_last];
+    const Seg &sg = mp.seg[mp.tile_member[me.idx >> 6]];
+    const PRec a = A[me.idx];
+    const uint32_t b = bucket_of(__longlong_as_double((long long)me.key), sg.inv_vol, sg.b0, sg.nb);
+    const uint32_t lo = off[b], hi = off[b + 1];
+    const uint32_t d0 = sg.p0 - off[sg.b0];   // the member's first slot, less its first offset
     const uint32_t w0 = off[bucket_of_rec(mp, orec[p0])];
     const uint32_t w1 = off[bucket_of_rec(mp, orec[p_last]) + 1];
     const bool staged = (w1 - w0) <= (uint32_t)kRankWindow;
@@ -460,11 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec 
         }
     }
     __syncthreads();
-    const uint32_t p = p0 + threadIdx.x;
-    if (p >= n) return;
-    const OrdRec me = orec[p];
-    const uint32_t b = bucket_of_rec(mp, me);
-    const uint32_t lo = off[b], hi = off[b + 1];
+    if (!act) return;
     const uint64_t k = me.key;
     const uint32_t u = me.uid;
     uint32_t rank = 0;
@@ -479,10 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec 
             rank += (rj.key < k) || (rj.key == k && rj.uid < u);
         }
     }
-    const uint32_t i = me.idx;
-    const Seg &sg = mp.seg[mp.tile_member[i >> 6]];
-    const uint32_t d = sg.p0 + (lo + rank - off[sg.b0]);
-    const PRec a = A[i];
+    const uint32_t d = d0 + (lo + rank);
     B.x[d] = a.x;
     B.y[d] = a.y;
     B.z[d] = a.z;

@@ -85,6 +85,34 @@ def test_members_equal_runs_alone(precision):
         assert np.array_equal(E, bE)
 
 
+def test_field_evaluations_mid_run_change_no_member():
+    """Field evaluations between batch steps, some while members are still
+    running and some after a member has finished, leave every member's run
+    bit for bit equal to the member run alone."""
+    cp = common(L=6)
+    picks = [MIXED[0], MIXED[2], MIXED[4]]            # 12, 7 and 10 steps
+    members = [make_member(n, seed, ns, **kw) for n, seed, ns, kw in picks]
+    _say(f"[gpu] batch field evaluations mid-run, {len(members)} members")
+    with S.Batch(cp, members) as b:
+        b.step(5)
+        E_mid = b.eval_field(0)
+        b.step(3)                                     # the 7-step member finishes here
+        b.eval_field(1)
+        b.eval_field(2)
+        b.step(4)
+        outs = [(b.read_response(i, 0, b.info(i)["step"]), b.read_state(i))
+                for i in range(len(members))]
+    with S.Batch(cp, [members[0]]) as a:
+        a.step(5)
+        assert np.array_equal(a.eval_field(0), E_mid)
+    for i, mb in enumerate(members):
+        q, st, _ = run_alone(cp, mb, 12)
+        bq, bst = outs[i]
+        assert np.array_equal(q, bq), i
+        for k in ("pos", "vel", "alive"):
+            assert np.array_equal(st[k], bst[k]), (i, k)
+
+
 def test_batch_member_matches_oracle():
     cp = common(L=6)
     members = [make_member(900, 51, 4), make_member(500, 52, 4, r_out=3.0)]
