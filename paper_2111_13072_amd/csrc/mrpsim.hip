@@ -13,7 +13,8 @@
 //   field:   per particle, the far field of all other tiles from the tile's
 //            coefficient vector, the near field of its own tile pair by pair,
 //            the self-image correction and the ion background; then the
-//            leapfrog kick/drift and the wall rules
+//            leapfrog kick/drift, the wall rules and the next step's sort key
+//            and bucket slot (the key kernel keys only what the push did not)
 // A handle holds one or more independent simulations ("members") that share
 // the probe geometry, the truncation l_max and the precision.  Each member
 // owns a tile-aligned range of particle slots, a range of carry chunks and a
