@@ -110,6 +110,35 @@ def test_steps_match_oracle_with_absorption():
     assert np.max(np.abs(out["vel"] - ref.vel)) <= 1e-12
 
 
+def test_concentrated_shell_ranks_past_the_lds_window():
+    """2000 of 3000 particles inside one sort bucket's shell (r in [2, 2.004];
+    the 375 buckets are 0.028 wide there): 250 times the mean occupancy, more
+    records than the rank kernel stages in LDS, so it ranks them from global
+    memory.  The field and three steps still match the oracle."""
+    n, L, steps, k = 3000, 6, 3, 2000
+    _say(f"[gpu] concentrated shell n={n} (k={k} in one bucket) L={L} steps={steps}")
+    sp, op = _params(n, L)
+    st = W.uniform_shell(n, 61, 5.0, 0.05)
+    g = np.random.Generator(np.random.PCG64(62))
+    pos = st.pos.copy()
+    r = 2.0 + 0.004 * g.random(k)
+    pos[:k] *= (r / np.sqrt(np.sum(pos[:k] ** 2, axis=1)))[:, None]
+    u = W.gaussian_drive(steps, sp.dt, 20.0, 289.52, t_center=0.1)
+    with S.Sim(sp, pos, st.vel, u) as sim:
+        E = sim.eval_field()
+        sim.step(steps)
+        qd = sim.read_response(0, steps)
+        out = sim.read_state()
+    Eo, _ = O.field(op, pos, u_asy=u[0])
+    assert _rel_err(E, Eo) <= FP64_FIELD_TOL
+    ref = O.run(op, pos, st.vel, u, steps)
+    np.testing.assert_array_equal(out["alive"], ref.alive)
+    scale = np.max(np.abs(ref.qdiff))
+    assert np.max(np.abs(qd - ref.qdiff)) <= 1e-12 * scale
+    assert np.max(np.abs(out["pos"] - ref.pos)) <= 1e-12
+    assert np.max(np.abs(out["vel"] - ref.vel)) <= 1e-12
+
+
 @pytest.mark.parametrize("probe_bc,wall_bc", [(S.SIM_BC_SPECULAR, S.SIM_BC_SPECULAR),
                                               (S.SIM_BC_DIFFUSE, S.SIM_BC_DIFFUSE)])
 def test_reflecting_walls_match_oracle(probe_bc, wall_bc):
