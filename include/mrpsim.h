@@ -165,7 +165,9 @@ int sim_read_state(sim_t *h, double *pos, double *vel, uint8_t *alive, double *q
  * Electric field E = -grad Phi at every alive particle for the current state
  * and step (Sec. 3 modified potential, truncated at l_max), in the order of
  * the creation arrays, [3n]; zero for absorbed particles.  Does not advance
- * the simulation.  Synchronises.
+ * the simulation.  Synchronises.  The evaluation sorts the state itself,
+ * using up the sort keys the last step prepared, so the next step computes
+ * them again (one extra pass over the particle records).
  */
 int sim_eval_field(sim_t *h, double *E);
 
