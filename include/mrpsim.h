@@ -93,9 +93,15 @@ typedef struct {
      * of the radial carries (the autotuner's knobs; 0 = built-in choice):
      * sort_bucket: mean particles per radial sort bucket, 1..256 (built-in 8);
      * carry_chunk: tiles per carry chunk, 8..1024 (built-in: a power of two
-     * in [8, 64], about a member's tiles / 256). */
+     * in [8, 64], about a member's tiles / 256);
+     * sort_keys: where the next step's radial sort keys and bucket slots
+     * are taken: 1 in the tail of the push, -1 in a pass of their own, 0 by
+     * launch size (the push from 2048 tiles of 64 particles on).  Results
+     * are bit-identical either way.  reserved1: unused. */
     int32_t sort_bucket;
     int32_t carry_chunk;
+    int32_t sort_keys;
+    int32_t reserved1;
 } sim_params;
 
 /* Fill *p with the defaults (d = 0.25, eps_r = 4, r_out = 5, dt = 0.05,

@@ -170,7 +170,14 @@ struct KParams {
     int n_members;  // member table size
     int fp32;       // SIM_FP32_COMP
     int field_only; // evaluation without a step: every used member runs
+    int fuse_keys;  // the push prepares the next step's sort records
 };
+
+// The push's tail takes over the key pass from this many tiles on: the
+// tail's atomic round trip costs ~3 us per step on a small launch (1e4
+// particles: 0.0658 -> 0.0674 ms), the key pass it replaces ~30 ns per
+// thousand particles plus its launch (2e6: 64 us against 16 in the push).
+constexpr int kFuseKeysMinTiles = 2048;
 
 // Device tables shared by the kernels.
 struct Map {
@@ -1653,7 +1660,7 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     // the next step's sort record of this slot, when the member runs then
     // (the same key, bucket and atomic slot as the key kernel would take;
     // the histogram was cleared by this step's offsets kernel)
-    if (step + 1 < sg.n_steps) {
+    if (kp.fuse_keys && step + 1 < sg.n_steps) {
         KeyRec kr{0ull, 0u, kNone};
         if (!absorbed) {
             const double k2 = key_r2(x, y, z);
@@ -1686,7 +1693,7 @@ __global__ void k_step_finish(Map mp, KParams kp)
     c.step += 1;
     c.n_cur = c.n_live;
     // the push produced the sort records of the step the member runs next
-    if (c.step < sg.n_steps) c.keys_for = c.step;
+    if (kp.fuse_keys && c.step < sg.n_steps) c.keys_for = c.step;
 }
 
 // ---------------------------------------------------------------------------
@@ -1709,6 +1716,7 @@ const char *kKernelNames[KN_COUNT] = {
 struct Tuning {
     int bucket = kBucketOccupancy;   // mean particles per sort bucket
     int chunk = 0;                   // tiles per carry chunk, 0: by member size
+    int keys = 0;                    // sort keys: 1 push, -1 own pass, 0 by extent
 };
 
 Tuning tuning_of(const sim_params *p)
@@ -1716,6 +1724,7 @@ Tuning tuning_of(const sim_params *p)
     Tuning t;
     if (p->sort_bucket > 0) t.bucket = p->sort_bucket;
     if (p->carry_chunk > 0) t.chunk = p->carry_chunk;
+    t.keys = p->sort_keys;
     return t;
 }
 
@@ -1783,6 +1792,7 @@ bool check_common(const sim_params *p, std::string *why)
     if (p->precision != SIM_FP64 && p->precision != SIM_FP32_COMP) { *why = "bad precision"; return false; }
     if (p->tile != 0 && p->tile != kWave) { *why = "tile must be 0 or 64"; return false; }
     if (p->sort_bucket < 0 || p->sort_bucket > 256) { *why = "sort_bucket must be 0 or in [1, 256]"; return false; }
+    if (p->sort_keys < -1 || p->sort_keys > 1) { *why = "sort_keys must be -1, 0 or 1"; return false; }
     if (p->carry_chunk != 0 && (p->carry_chunk < kChunkMin || p->carry_chunk > 1024)) {
         *why = "carry_chunk must be 0 or in [8, 1024]";
         return false;
@@ -2124,6 +2134,8 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     const Extent &ex = h->ext;
     KParams kp = h->kp;
     kp.field_only = field_only ? 1 : 0;
+    kp.fuse_keys = lo.tu.keys != 0 ? (lo.tu.keys > 0 ? 1 : 0)
+                                   : (ex.n_tiles >= kFuseKeysMinTiles ? 1 : 0);
     kp.n_tiles = ex.n_tiles;
     kp.n_chunks = ex.n_chunks;
     kp.nb = ex.nb;
@@ -2328,6 +2340,7 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
     kp.n_members = lo.n_members;
     kp.fp32 = lo.fp32 ? 1 : 0;
     kp.field_only = 0;
+    kp.fuse_keys = 0;
     h->map.seg = h->seg;
     h->map.ctl = h->ctl;
     h->map.tile_member = h->tile_member;

@@ -40,6 +40,7 @@ class sim_params(C.Structure):
         ("wall_bc", C.c_int32), ("precision", C.c_int32), ("tile", C.c_int32),
         ("seed", C.c_uint64), ("mem_limit_bytes", C.c_uint64),
         ("sort_bucket", C.c_int32), ("carry_chunk", C.c_int32),
+        ("sort_keys", C.c_int32), ("reserved1", C.c_int32),
     ]
 
 
@@ -158,12 +159,14 @@ class SimParams:
     # launch sizes chosen by paper_2111_13072_amd.tune (0: built-in choice)
     sort_bucket: int = 0
     carry_chunk: int = 0
+    # where the sort keys are taken: 1 push, -1 own pass, 0 by launch size
+    sort_keys: int = 0
 
     def to_c(self) -> sim_params:
         p = sim_params()
         lib().sim_params_default(C.byref(p))
         for f, _ in sim_params._fields_:
-            if f in ("struct_size", "reserved0"):
+            if f in ("struct_size", "reserved0", "reserved1"):
                 continue
             setattr(p, f, getattr(self, f))
         return p

@@ -31,8 +31,8 @@ def make_member(n, gen_seed, n_steps, r_out=5.0, v_th=0.08311, **kw):
                     r_out=r_out, **kw)
 
 
-def common(L=8, precision=S.SIM_FP64, m_mode=S.SIM_M_FULL):
-    return S.SimParams(l_max=L, precision=precision, m_mode=m_mode)
+def common(L=8, precision=S.SIM_FP64, m_mode=S.SIM_M_FULL, **kw):
+    return S.SimParams(l_max=L, precision=precision, m_mode=m_mode, **kw)
 
 
 def run_alone(cp, mb, steps):
@@ -89,7 +89,7 @@ def test_field_evaluations_mid_run_change_no_member():
     """Field evaluations between batch steps, some while members are still
     running and some after a member has finished, leave every member's run
     bit for bit equal to the member run alone."""
-    cp = common(L=6)
+    cp = common(L=6, sort_keys=1)
     picks = [MIXED[0], MIXED[2], MIXED[4]]            # 12, 7 and 10 steps
     members = [make_member(n, seed, ns, **kw) for n, seed, ns, kw in picks]
     _say(f"[gpu] batch field evaluations mid-run, {len(members)} members")
@@ -128,7 +128,9 @@ def test_batch_member_matches_oracle():
 
 
 def test_admit_and_retire_between_steps():
-    cp = common(L=4)
+    # sort keys from the push, so that a member retired while running leaves
+    # counts in its buckets for the next member to find cleared
+    cp = common(L=4, sort_keys=1)
     a = make_member(700, 61, 20)
     bm = make_member(300, 62, 8)
     c = make_member(650, 63, 5)

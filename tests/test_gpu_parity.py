@@ -87,12 +87,14 @@ def test_field_radius_tie_broken_by_id():
     assert _rel_err(E, Eo) <= FP64_FIELD_TOL
 
 
-def test_steps_match_oracle_with_absorption():
+@pytest.mark.parametrize("sort_keys", [1, -1], ids=["keys-in-push", "key-pass"])
+def test_steps_match_oracle_with_absorption(sort_keys):
     """Five steps with a strong drive: Q_diff, positions, velocities,
-    absorbed set and Q_S against the oracle's leapfrog."""
+    absorbed set and Q_S against the oracle's leapfrog, with the sort keys
+    taken in the push or in a pass of their own."""
     n, L, steps = 2000, 8, 5
-    _say(f"[gpu] stepping parity n={n} L={L} steps={steps}")
-    sp, op = _params(n, L, q_surface0=-2.0)
+    _say(f"[gpu] stepping parity n={n} L={L} steps={steps} sort_keys={sort_keys}")
+    sp, op = _params(n, L, q_surface0=-2.0, sort_keys=sort_keys)
     st = W.uniform_shell(n, 41, 5.0, 0.3)  # hot, so some reach the probe
     u = W.gaussian_drive(steps, sp.dt, 50.0, 289.52, t_center=0.1)
     with S.Sim(sp, st.pos, st.vel, u) as sim:
@@ -108,6 +110,30 @@ def test_steps_match_oracle_with_absorption():
     assert np.max(np.abs(qd - ref.qdiff)) <= 1e-12 * scale
     assert np.max(np.abs(out["pos"] - ref.pos)) <= 1e-12
     assert np.max(np.abs(out["vel"] - ref.vel)) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", [S.SIM_FP64, S.SIM_FP32_COMP], ids=["fp64", "fp32c"])
+def test_sort_key_paths_agree_bitwise(precision):
+    """Sort keys taken in the push and in a pass of their own give the same
+    run bit for bit (absorbing probe, diffuse outer wall, fast particles)."""
+    n, L, steps = 2500, 6, 6
+    _say(f"[gpu] sort-key paths n={n} L={L} steps={steps} precision={precision}")
+    st = W.uniform_shell(n, 57, 2.5, 0.6)
+    u = W.gaussian_drive(steps, 0.05, 30.0, 289.52, t_center=0.1)
+    outs = []
+    for keys in (1, -1):
+        sp, _ = _params(n, L, sort_keys=keys, precision=precision, wall_bc=S.SIM_BC_DIFFUSE,
+                        seed=77)
+        with S.Sim(sp, st.pos, st.vel, u) as sim:
+            sim.step(steps)
+            outs.append((sim.read_state(), sim.read_response(0, steps), sim.eval_field()))
+    (a, qa, Ea), (b, qb, Eb) = outs
+    assert (a["alive"] == 0).any()
+    for key in ("pos", "vel", "alive"):
+        np.testing.assert_array_equal(a[key], b[key])
+    assert a["q_surface"] == b["q_surface"]
+    np.testing.assert_array_equal(qa, qb)
+    np.testing.assert_array_equal(Ea, Eb)
 
 
 def test_concentrated_shell_ranks_past_the_lds_window():
@@ -194,12 +220,13 @@ def test_large_workload_sampled_field():
     assert err <= FP64_FIELD_TOL
 
 
-def test_deterministic_and_resumable():
+@pytest.mark.parametrize("sort_keys", [1, -1], ids=["keys-in-push", "key-pass"])
+def test_deterministic_and_resumable(sort_keys):
     """Same inputs give bitwise-equal states; k + k steps with a dump and a
     re-creation in between equal 2k uninterrupted steps bitwise."""
     n, L, k = 3000, 6, 4
-    _say(f"[gpu] determinism/resume n={n} L={L} k={k}")
-    sp, _ = _params(n, L)
+    _say(f"[gpu] determinism/resume n={n} L={L} k={k} sort_keys={sort_keys}")
+    sp, _ = _params(n, L, sort_keys=sort_keys)
     st = W.uniform_shell(n, 51, 5.0, 0.3)
     u = W.gaussian_drive(2 * k, sp.dt, 20.0, 289.52, t_center=0.1)
     outs = []
@@ -234,7 +261,7 @@ def test_field_evaluation_between_steps_changes_nothing():
     finished run can still be evaluated."""
     n, L, k = 3000, 6, 4
     _say(f"[gpu] field evaluation between steps n={n} L={L} k={k}")
-    sp, _ = _params(n, L)
+    sp, _ = _params(n, L, sort_keys=1)
     st = W.uniform_shell(n, 53, 1.6, 0.8)
     u = W.gaussian_drive(3 * k, sp.dt, 20.0, 289.52, t_center=0.1)
     with S.Sim(sp, st.pos, st.vel, u) as sim:
