@@ -220,6 +220,39 @@ def test_large_workload_sampled_field():
     assert err <= FP64_FIELD_TOL
 
 
+def test_large_workload_steps_with_keys_from_the_push():
+    """2e6 particles, l_max = 16, in the benchmark's launch configuration
+    (sort keys taken in the push at this size): ten steps equal bit for bit
+    the same steps with the keys taken in a pass of their own, and the field
+    of the stepped state matches the oracle at 48 sampled alive particles."""
+    wl = W.LARGE
+    steps = 10
+    _say(f"[gpu] stepped {wl.name}, {steps} steps, push-keyed vs key pass")
+    st = wl.particles()
+    u = wl.drive(steps + 1)
+    outs = []
+    for keys in (0, -1):
+        sp, op = _params(wl.n, wl.l_max, sort_keys=keys)
+        with S.Sim(sp, st.pos, st.vel, u) as sim:
+            sim.step(steps)
+            outs.append((sim.read_state(), sim.read_response(0, steps),
+                         sim.eval_field() if keys == 0 else None))
+    (a, qa, E), (b, qb, _) = outs
+    for key in ("pos", "vel", "alive"):
+        np.testing.assert_array_equal(a[key], b[key])
+    assert a["q_surface"] == b["q_surface"]
+    np.testing.assert_array_equal(qa, qb)
+    alive = a["alive"] == 1
+    rng = np.random.default_rng(6)
+    targets = np.sort(rng.choice(np.nonzero(alive)[0], 48, replace=False))
+    Eo, _ = O.field(op, a["pos"], alive=alive, q_surface=a["q_surface"], u_asy=u[steps],
+                    targets=targets)
+    rms = np.sqrt(np.mean(np.sum(Eo * Eo, axis=1)))
+    err = float(np.max(np.abs(E[targets] - Eo)) / rms)
+    _say(f"[gpu]   rel err {err:.3e}, absorbed {int((~alive).sum())}")
+    assert err <= FP64_FIELD_TOL
+
+
 @pytest.mark.parametrize("sort_keys", [1, -1], ids=["keys-in-push", "key-pass"])
 def test_deterministic_and_resumable(sort_keys):
     """Same inputs give bitwise-equal states; k + k steps with a dump and a
