@@ -394,6 +394,39 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(uint32_t *in, const uint32_t 
     }
 }
 
+// The same offsets from one block, walking the histogram kScanPerBlock entries
+// at a time with a running carry: for histograms of a few blocks' length it
+// replaces the two kernels above by one launch (small runs are launch-bound).
+constexpr int kScanSingleMaxBlocks = 4;
+
+__global__ __launch_bounds__(kBlock) void k_scan_single(uint32_t *in, uint32_t *out, int n)
+{
+    constexpr int per = kScanPerBlock / kBlock;
+    uint32_t carry = 0;
+    for (int base0 = 0; base0 < n; base0 += kScanPerBlock) {
+        const int base = base0 + threadIdx.x * per;
+        uint32_t v[per];
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            v[k] = (base + k < n) ? in[base + k] : 0u;
+            s += v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < per; ++k)
+            if (base + k < n) in[base + k] = 0u;
+        uint32_t tot;
+        uint32_t run = carry + block_exclusive_scan(s, &tot);
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            if (base + k < n) out[base + k] = run;
+            run += v[k];
+            if (base + k == n - 1) out[n] = run;
+        }
+        carry += tot;
+    }
+}
+
 // Per member: alive count (its buckets' share of the global offsets) and the
 // surface charge Q_S = q_surface0 + the charge absorbed so far, which enters
 // the field as an interior l = 0 charge (Q_S / (4 pi r), Sec. 3).  Done by
@@ -2152,10 +2185,16 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     };
     mark(KN_SORT_KEY);
     k_sort_key<<<gN, kBlock, 0, s>>>(mp, h->A, h->dead, h->krec, h->hist, kp);
-    mark(KN_SCAN_A);
-    k_scan_a<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, ex.nb);
-    mark(KN_SCAN_C);
-    k_scan_c<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, ex.nb);
+    if (ex.nb_blocks <= kScanSingleMaxBlocks) {
+        mark(KN_SCAN_A);
+        mark(KN_SCAN_C);
+        k_scan_single<<<1, kBlock, 0, s>>>(h->hist, h->off, ex.nb);
+    } else {
+        mark(KN_SCAN_A);
+        k_scan_a<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, ex.nb);
+        mark(KN_SCAN_C);
+        k_scan_c<<<ex.nb_blocks, kBlock, 0, s>>>(h->hist, h->bsum, h->off, ex.nb);
+    }
     mark(KN_SORT_SCATTER);
     k_sort_scatter<<<gN, kBlock, 0, s>>>(mp, h->krec, h->off, h->orec, kp);
     mark(KN_SORT_RANK);
