@@ -83,6 +83,8 @@ def lib():
         L.orc_energy.argtypes = [P, C.c_int64, dp, dp, C.POINTER(C.c_uint32),
                                  C.POINTER(C.c_uint8), C.c_double, C.c_double, dp, dp]
         L.orc_energy.restype = C.c_double
+        L.orc_diffuse_dir.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_int, dp, dp]
+        L.orc_diffuse_dir.restype = None
         L.orc_philox4x64_10.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                         C.POINTER(C.c_uint64)]
         _lib = L
@@ -239,3 +241,12 @@ def philox4x64_10(counter, key):
     P = C.POINTER(C.c_uint64)
     lib().orc_philox4x64_10(c.ctypes.data_as(P), k.ctypes.data_as(P), o.ctypes.data_as(P))
     return o
+
+
+def diffuse_dir(seed: int, pid: int, step: int, wall: int, normal):
+    """Direction the diffuse wall rule gives a particle (id, step) reflected
+    at `wall` (0 probe, 1 outer wall) with inward unit normal `normal`."""
+    n = _f64(normal, 3)
+    d = np.zeros(3)
+    lib().orc_diffuse_dir(int(seed), int(pid), int(step), int(wall), _dp(n), _dp(d))
+    return d

@@ -29,8 +29,9 @@
  * key (r^2, id) with r^2 = (x*x + y*y) + z*z evaluated without contraction
  * (build with -ffp-contract=off).
  *
- * Parity pins live in tests/test_oracle_pins.py; the diffuse wall law is the
- * one part that is "parity unpinned" beyond its random-number generator.
+ * Parity pins live in tests/test_oracle_pins.py, among them the diffuse wall
+ * law (Kolmogorov-Smirnov tests of its angular distribution) and its
+ * random-number generator (numpy's Philox).
  */
 #include <math.h>
 #include <stdint.h>
@@ -475,6 +476,14 @@ static void diffuse_dir(uint64_t seed, uint32_t id, int64_t step, int wall,
                     nz[0] * ex[1] - nz[1] * ex[0]};
     for (int j = 0; j < 3; ++j)
         dir[j] = ct * nz[j] + st * (cos(ph) * ex[j] + sin(ph) * ey[j]);
+}
+
+/* The diffuse-wall direction for a given inward unit normal, exported so
+ * that its angular law can be checked on its own. */
+void orc_diffuse_dir(uint64_t seed, uint32_t id, int64_t step, int wall, const double *nrm_in,
+                     double *dir)
+{
+    diffuse_dir(seed, id, step, wall, nrm_in, dir);
 }
 
 /* ------------------------------------------------------------------------ */
