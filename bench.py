@@ -2,13 +2,15 @@
 
 A step is one pass of the whole hot path (radial sort, harmonic moments,
 prefix/suffix carry scans, boundary response + drive, field + leapfrog push)
-over all particles.  Default workload: 2e6 electrons, l_max = 16, uniform
-shell 1 < r < 5, T_e = 2 eV, n_e = 1e15 m^-3, +-1 V Gaussian pulse.
+over all particles.  Default workload: the largest single-GPU run of the
+scale sweep, 1.6e7 electrons, l_max = 16, uniform shell 1 < r < 5, T_e = 3 eV,
+n_e = 1e15 m^-3, +-1 V Gaussian pulse, in the FP32-compensated mode, with the
+plain FP64 run of the same state timed beside it.
 
 Prints ONE JSON line.  `roofline` reports the dominant kernel (field_push)
-against the FP64 vector peak; `cpu_baseline` times the CPU oracle on a
-bounded sample of the same workload and also gives the field error of the
-GPU against it.
+against the vector peak of its precision; `cpu_baseline` times the CPU oracle
+on a bounded sample of the same state (all threads and one thread) and also
+gives the field error of the GPU against it.
 """
 from __future__ import annotations
 
@@ -67,41 +69,53 @@ def _traffic_from_profiles(kernel: str, workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, st, prm, E_gpu, u_now, q_s, budget_s: float):
-    """Oracle field + push at a bounded random sample of particles of the same
-    state; returns the baseline record and the GPU field error on the sample."""
+def cpu_baseline(wl, st, prm, u_now, q_s, budget_s: float, gpu_fields: dict):
+    """The oracle (plain FP64 pair sums + leapfrog push) on a bounded random
+    sample of particles of the same state, timed on the host cores with all
+    threads and with one; returns the baseline record and, for each GPU field
+    given, its error on the sample (max |dE| / RMS |E| of the oracle)."""
     import oracle as O
 
     op = O.Params(d=prm.d, eps_r=prm.eps_r, r_out=prm.r_out, dt=prm.dt, ntilde=prm.ntilde,
                   ion_density=prm.ion_density, l_max=prm.l_max, m_mode=prm.m_mode,
                   probe_bc=prm.probe_bc, wall_bc=prm.wall_bc, seed=prm.seed)
     rng = np.random.default_rng(12345)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    first = np.sort(rng.choice(wl.n, 8 * threads, replace=False))
-    t0 = time.perf_counter()
-    E0, _ = O.field(op, st.pos, q_surface=q_s, u_asy=u_now, targets=first)
-    t_first = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or (os.cpu_count() or 1)
+    order = rng.permutation(wl.n)
+
+    def timed(targets, nthreads):
+        O.set_threads(nthreads)
+        t0 = time.perf_counter()
+        E, _ = O.field(op, st.pos, q_surface=q_s, u_asy=u_now, targets=targets)
+        v = st.vel[targets] - E * prm.dt          # the push of the sampled particles
+        _ = st.pos[targets] + v * prm.dt
+        return E, time.perf_counter() - t0
+
+    # all threads: a first probe, then as many targets as fit the budget
+    first = np.sort(order[:2 * threads])
+    E0, t_first = timed(first, threads)
     per = t_first / len(first)
-    extra = int(max(0, (budget_s - t_first) / per))
-    rest = np.setdiff1d(np.sort(rng.choice(wl.n, min(extra, wl.n // 2), replace=False)), first)
-    t1 = time.perf_counter()
-    E1, _ = O.field(op, st.pos, q_surface=q_s, u_asy=u_now, targets=rest)
-    t_rest = time.perf_counter() - t1
+    extra = int(max(0, (0.75 * budget_s - t_first) / per))
+    rest = np.sort(order[len(first):len(first) + min(extra, wl.n // 2)])
+    E1, t_rest = timed(rest, threads) if len(rest) else (np.zeros((0, 3)), 0.0)
     targets = np.concatenate([first, rest])
     Eo = np.concatenate([E0, E1])
-    # the push of the sampled particles (part of a particle-step)
-    t2 = time.perf_counter()
-    v = st.vel[targets] - Eo * prm.dt
-    _ = st.pos[targets] + v * prm.dt
-    t_push = time.perf_counter() - t2
-    total = t_first + t_rest + t_push
+    rate_all = len(targets) / (t_first + t_rest)
+    # one thread: about a quarter of the budget
+    n1 = max(1, int(0.25 * budget_s / (per * threads)))
+    one = order[len(targets):len(targets) + n1]
+    _, t_one = timed(np.sort(one), 1)
+    O.set_threads(threads)
+    rate_one = len(one) / t_one
     rms = float(np.sqrt(np.mean(np.sum(Eo * Eo, axis=1))))
-    err = float(np.max(np.abs(E_gpu[targets] - Eo)) / rms)
-    rec = {"value": len(targets) / total, "unit": "particle-steps/s", "cores": threads,
-           "kind": "oracle",
+    errs = {k: float(np.max(np.abs(E[targets] - Eo)) / rms) for k, E in gpu_fields.items()}
+    rec = {"value": rate_all, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+           "value_1_thread": rate_one,
            "sample": f"pair-sum field + leapfrog push of {len(targets)} random particles of the "
-                     f"{wl.n}-particle, l_max={wl.l_max} state (one step), {total:.1f} s"}
-    return rec, err, len(targets)
+                     f"{wl.n}-particle, l_max={wl.l_max} state (one step) on {threads} threads in "
+                     f"{t_first + t_rest:.1f} s, and of {len(one)} others on 1 thread in "
+                     f"{t_one:.1f} s"}
+    return rec, errs, len(targets)
 
 
 # ---------------------------------------------------------------------------
@@ -551,8 +565,11 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=10)
-    ap.add_argument("--workload", default="large",
-                    choices=["large", "small", "batch64", "serve", "sweep"])
+    ap.add_argument("--workload", default="scale",
+                    choices=["scale", "large", "small", "batch64", "serve", "sweep"],
+                    help="scale: 1.6e7 electrons, l_max 16, T_e 3 eV, n_e 1e15 (the largest "
+                         "single-GPU run; FP32-compensated with the FP64 run beside it); large: "
+                         "2e6, l_max 16; small: 1e4, l_max 8")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="serve: length of the Poisson arrival window")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
@@ -561,11 +578,14 @@ def main(argv=None):
                          "(0: one pool per l_max)")
     ap.add_argument("--seq-steps", type=int, default=20,
                     help="batch64: timed steps of each member run alone, for comparison")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32c"],
+                    help="default: fp32c for the scale workload, fp64 otherwise")
+    ap.add_argument("--no-fp64-leg", action="store_true",
+                    help="fp32c single runs: skip the FP64 run of the same state")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
-                    help="large/small: choose sort bucket and carry chunk sizes by short timed "
-                         "trials first (outside the timed region)")
+                    help="single runs and batch64: choose sort bucket and carry chunk sizes by "
+                         "short timed trials first (outside the timed region)")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, launch a plain copy of this size (counter calibration)")
@@ -581,8 +601,9 @@ def main(argv=None):
         summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command)
         return 0
     if args.summarize_traffic:
-        wl_name = "shell-2e6-L16" if args.workload == "large" else "shell-1e4-L8"
-        if args.precision == "fp32c":
+        from paper_2111_13072_amd import workload as W
+        wl_name = {"scale": W.SCALE, "large": W.LARGE, "small": W.SMALL_FP64}[args.workload].name
+        if (args.precision or ("fp32c" if args.workload == "scale" else "fp64")) == "fp32c":
             wl_name += "-fp32c"
         summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1],
                           args.summarize_traffic[2], wl_name, "field_push",
@@ -597,14 +618,13 @@ def main(argv=None):
         return 0
 
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(one simulation is one GPU's work; see DESIGN.md for how it would shard)",
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported: this "
+              "build steps one simulation (or one batch) on one GPU and has no multi-GPU path",
               file=sys.stderr)
         return 2
 
     import torch
 
-    from paper_2111_13072_amd import sim as S
     from paper_2111_13072_amd import workload as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -615,78 +635,113 @@ def main(argv=None):
         return bench_serve(args)
     if args.workload == "sweep":
         return bench_sweep(args)
-    wl = W.LARGE if args.workload == "large" else W.SMALL_FP64
-    st = wl.particles()
-    n_total = args.warmup + args.steps + args.profile_steps + 1
-    u = wl.drive(max(n_total, 64))
-    fp32 = args.precision == "fp32c"
+    wl = {"scale": W.SCALE, "large": W.LARGE, "small": W.SMALL_FP64}[args.workload]
+    precision = args.precision or ("fp32c" if args.workload == "scale" else "fp64")
+    return bench_single(args, wl, precision)
+
+
+def _leg(wl, st, precision: str, args, u, field: bool):
+    """One handle of the workload in one precision: W warmup steps, then K
+    timed steps (HIP graph replays on torch's stream, bracketed by device
+    synchronisation), then per-kernel times from HIP events over a few more
+    steps.  Particle-steps count the particles alive at the start and the end
+    of the timed window (their mean)."""
+    import torch
+
+    from paper_2111_13072_amd import sim as S
+
     prm = S.SimParams(d=wl.d, eps_r=wl.eps_r, r_out=wl.r_out, dt=wl.dt, ntilde=wl.ntilde,
                       ion_density=1.0, l_max=wl.l_max,
-                      precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64)
-    print(f"[bench] workload {wl.name}: n={wl.n} l_max={wl.l_max} {args.precision}, "
-          f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
-    tuning = None
+                      precision=S.SIM_FP32_COMP if precision == "fp32c" else S.SIM_FP64)
+    out = {"params": prm}
     if args.autotune:
         from paper_2111_13072_amd import tune as T
         tuned = T.autotune(T.sim_builder(st.pos, st.vel), prm, wl.n)
         prm = tuned.apply(prm)
-        tuning = {"sort_bucket": tuned.sort_bucket, "carry_chunk": tuned.carry_chunk,
-                  "trial_ms_per_step": round(tuned.ms_per_step, 4),
-                  "default_trial_ms_per_step": round(tuned.default_ms_per_step, 4)}
-        print(f"[bench] autotune: {tuning}", file=sys.stderr, flush=True)
+        out["tuning"] = {"sort_bucket": tuned.sort_bucket, "carry_chunk": tuned.carry_chunk,
+                         "trial_ms_per_step": round(tuned.ms_per_step, 4),
+                         "default_trial_ms_per_step": round(tuned.default_ms_per_step, 4)}
+        print(f"[bench] autotune: {out['tuning']}", file=sys.stderr, flush=True)
+    print(f"[bench] {wl.name} {precision}: create", file=sys.stderr, flush=True)
+    with S.Sim(prm, st.pos, st.vel, u) as sim:
+        out["E"] = sim.eval_field() if field else None
+        sim.step(args.warmup)
+        n_before = sim.counts()["alive"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(args.steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        n_after = sim.counts()["alive"]
+        out["kms"] = sim.profile(args.profile_steps)
+    out["elapsed"] = t1 - t0
+    out["live"] = 0.5 * (n_before + n_after)
+    out["value"] = out["live"] * args.steps / out["elapsed"]
+    out["ms_per_step"] = 1e3 * out["elapsed"] / args.steps
+    print(f"[bench] {wl.name} {precision}: {args.steps} steps in {out['elapsed']:.3f} s, "
+          f"{out['value']:.4e} particle-steps/s", file=sys.stderr, flush=True)
+    return out
 
-    sim = S.Sim(prm, st.pos, st.vel, u)
-    E_gpu = sim.eval_field() if not args.no_cpu_baseline else None
-    s0 = sim.read_state()
-    u_now, q_s0 = float(u[0]), s0["q_surface"]
 
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    n_before = int(sim.read_state()["alive"].sum())
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    sim.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    n_after = int(sim.read_state()["alive"].sum())
-    elapsed = t1 - t0
-    particle_steps = 0.5 * (n_before + n_after) * args.steps
-    value = particle_steps / elapsed
-    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s: {value:.4e} particle-steps/s",
-          file=sys.stderr, flush=True)
+def bench_single(args, wl, precision: str):
+    """One simulation of the workload: the timed leg in `precision`, and for
+    the FP32-compensated mode the plain FP64 run of the same state beside it
+    (the per-run FP64 baseline on the same GPU).  The roofline is the field
+    kernel's; the CPU baseline times the oracle on a sample of the same state
+    and gives the field error of each leg on that sample."""
+    import torch
 
-    kms = sim.profile(args.profile_steps)
-    sim.close()
-    if args.calibrate_copy_mib:
-        calibrate_copy(args.calibrate_copy_mib * 2**20)
+    torch.cuda.set_device(0)
+    st = wl.particles()
+    n_total = args.warmup + args.steps + args.profile_steps + 1
+    u = wl.drive(max(n_total, 64))
+    fp32 = precision == "fp32c"
+    print(f"[bench] workload {wl.name}: n={wl.n} l_max={wl.l_max} {precision}, "
+          f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    want_field = not args.no_cpu_baseline
+    main_leg = _leg(wl, st, precision, args, u, want_field)
+    fp64_leg = None
+    if fp32 and not args.no_fp64_leg:
+        fp64_leg = _leg(wl, st, "fp64", args, u, want_field)
+    prm = main_leg["params"]
+    kms = main_leg["kms"]
     dom = "field_push"
-    t_dom = kms[dom] * 1e-3
-    flops = algorithmic_flops_per_particle(wl.l_max) * 0.5 * (n_before + n_after)
-    achieved = flops / t_dom / 1e12
+    flops = algorithmic_flops_per_particle(wl.l_max) * main_leg["live"]
+    achieved = flops / (kms[dom] * 1e-3) / 1e12
     traffic = _traffic_from_profiles(dom, wl.name + ("-fp32c" if fp32 else ""))
     peak = FP32_VECTOR_PEAK_TFLOPS if fp32 else FP64_VECTOR_PEAK_TFLOPS
     roof = {"bound": "alu", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
             "kernel": dom, "kernel_ms": kms[dom],
+            "flops_per_launch": flops,
             "per_kernel_ms": {k: round(v, 5) for k, v in kms.items()}}
-
-    line = {"metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32+f64" if fp32 else "f64",
-            "data": "synthetic",
-            "config": {"workload": wl.name, "n_particles": wl.n, "l_max": wl.l_max,
-                       "m_mode": "full", "precision": args.precision, "tile": 64,
+    line = {"metric": METRIC, "value": main_leg["value"], "unit": "particle-steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": main_leg["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64" if fp32 else "f64", "data": "synthetic",
+            "config": {"workload": wl.name, "n_particles": wl.n, "seed": wl.seed,
+                       "l_max": wl.l_max, "m_mode": "full", "precision": precision, "tile": 64,
                        "n_e_m3": wl.n_e, "T_e_eV": wl.t_e_ev, "r_out": wl.r_out, "dt": wl.dt,
                        "parallelism": "single-gpu"},
             "roofline": roof}
-    if tuning is not None:
-        line["tuning"] = tuning
+    if "tuning" in main_leg:
+        line["tuning"] = main_leg["tuning"]
+    if fp64_leg is not None:
+        line["fp64_run"] = {"value": fp64_leg["value"], "ms_per_step": fp64_leg["ms_per_step"],
+                            "speedup_of_fp32c": main_leg["value"] / fp64_leg["value"],
+                            "per_kernel_ms": {k: round(v, 5) for k, v in fp64_leg["kms"].items()}}
     if not args.no_cpu_baseline:
-        rec, err, ns = cpu_baseline(wl, st, prm, E_gpu, u_now, q_s0, args.cpu_budget_s)
+        fields = {precision: main_leg["E"]}
+        if fp64_leg is not None:
+            fields["fp64"] = fp64_leg["E"]
+        rec, errs, ns = cpu_baseline(wl, st, prm, float(u[0]), prm.q_surface0,
+                                     args.cpu_budget_s, fields)
         line["cpu_baseline"] = rec
-        line["field_rel_err_vs_oracle"] = err
+        line["field_rel_err_vs_oracle"] = errs[precision]
+        if fp64_leg is not None:
+            line["fp64_run"]["field_rel_err_vs_oracle"] = errs["fp64"]
         line["field_err_sample"] = ns
     print(json.dumps(line), flush=True)
     return 0

@@ -6,8 +6,15 @@
  *
  * Units are the paper's dimensionless ones (Sec. 4): lengths in the probe
  * radius R, times in 1/omega_pe, charges in e, masses in m_e, densities in
- * n_inf, potentials in e n_inf R^2 / eps0.  The particles are electrons
- * (q = -1, m = 1); the ions are an immobile uniform background.
+ * n_inf, potentials in e n_inf R^2 / eps0.  Particles are electrons (q = -1,
+ * m = 1) and, in batch members, optionally mobile ions (q = +1, mass m_i);
+ * ions not simulated as particles are an immobile background, uniform or a
+ * radial profile.
+ *
+ * Device memory: a handle makes one device allocation at creation, through
+ * the caller's sim_allocator (e.g. a framework's caching allocator) or
+ * hipMalloc, and frees it in sim_destroy.  Every other call allocates no
+ * device memory.
  *
  * Error convention: every int-returning call returns SIM_OK (0) or a
  * negative SIM_E* code; no exception crosses the ABI.  A handle whose device
@@ -20,6 +27,7 @@
 #ifndef MRPSIM_H
 #define MRPSIM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -27,6 +35,22 @@ extern "C" {
 #endif
 
 typedef struct sim sim_t;
+
+/*
+ * Device memory provider.  alloc returns `bytes` of device memory on the
+ * current device, 256-byte aligned, or NULL on failure; free releases it.
+ * `stream` is the hipStream_t given at creation, the one the memory is used
+ * on, or NULL when the handle runs on a stream of its own (created after the
+ * allocation; the memory is used on that stream only).  The library calls
+ * alloc once, at creation, and free once, in sim_destroy after all of the
+ * handle's work has completed, with the same size and stream.  ctx is passed
+ * through.  A NULL sim_allocator means hipMalloc / hipFree.
+ */
+typedef struct {
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, size_t bytes, void *stream);
+    void *ctx;
+} sim_allocator;
 
 enum {
     SIM_OK = 0,
@@ -109,7 +133,11 @@ typedef struct {
 void sim_params_default(sim_params *p);
 
 /*
- * Create a simulation and upload its state.
+ * Create a simulation and upload its state: the problem of Sec. 4 (the
+ * probe geometry of Sec. 2, the plasma as super-particles of density
+ * ntilde, an initial particle state and the antisymmetric drive u_asy(t)),
+ * in the canonical variables of Sec. 2 (positions, and velocities half a
+ * step behind for the leapfrog).
  *   n          number of electrons (> 0).
  *   pos, vel   host arrays [3n], particle-major (x0,y0,z0,x1,...); vel is the
  *              leapfrog half-step velocity v(t_start - dt/2).  Every particle
@@ -122,12 +150,13 @@ void sim_params_default(sim_params *p);
  *              u_1 - u_2 at t_s = s dt (Sec. 3); copied.
  *   start_step first step to run (checkpoint resume); 0 <= start_step <= n_steps.
  *   hip_stream hipStream_t to run on, or NULL for a stream of the handle's own.
+ *   alloc      device memory provider, or NULL for hipMalloc.
  * Returns SIM_EINVAL for invalid parameters or particles, SIM_ENOMEM when the
- * footprint exceeds mem_limit_bytes or an allocation fails.
+ * footprint exceeds mem_limit_bytes or the allocation fails.
  */
 int sim_create(const sim_params *p, int64_t n, const double *pos, const double *vel,
                const uint32_t *ids, const double *u_asy, int64_t n_steps, int64_t start_step,
-               void *hip_stream, sim_t **out);
+               void *hip_stream, const sim_allocator *alloc, sim_t **out);
 
 /*
  * Enqueue k time steps (asynchronous, on the handle's stream).  One step is
@@ -159,7 +188,9 @@ int sim_query(sim_t *h);
 int sim_read_response(sim_t *h, int64_t first, int64_t count, double *q_diff);
 
 /*
- * Copy the state at the current step boundary to host (synchronises), in the
+ * Copy the state at the current step boundary to host (synchronises): the
+ * canonical variables of Sec. 2 (positions and leapfrog half-step
+ * velocities) and the surface charge Q_S of Sec. 2-3, in the
  * order of the arrays given to sim_create.  pos/vel [3n] (vel = v at t - dt/2),
  * alive [n] (0 = absorbed; its pos/vel are those at absorption), q_surface
  * and step may each be NULL.
@@ -206,9 +237,10 @@ void sim_destroy(sim_t *h);
  * (index 0), so every sim_member_* call also applies to it.
  *
  * Each member occupies ceil(n/64) tiles of 64 particle slots, ceil(tiles/64)
- * carry chunks and max(1, n/8) sort buckets of the handle's capacity, plus
- * 16 bytes per step for its drive and response and 16 bytes per node of an
- * ion profile.
+ * carry chunks and max(1, n/8) sort buckets of the handle's capacity, and
+ * sim_member_data_bytes(n_steps, ion_profile_len) bytes of the batch's
+ * member data pool (its drive, response and ion profile).  Admission and
+ * retirement take and return these ranges without any device allocation.
  */
 typedef struct {
     uint32_t struct_size;  /* sizeof(sim_member) */
@@ -247,27 +279,37 @@ void sim_member_default(sim_member *m);
  * Create a batch.  common supplies d, eps_r, l_max, m_mode, precision, tile
  * and mem_limit_bytes (its per-member fields are ignored).  slot_capacity is
  * the number of particle slots to reserve (0: exactly what the initial
- * members need); max_members the size of the member table (0: n_members).
- * members[0 .. n_members) are admitted in order as indices 0, 1, ...
+ * members need); max_members the size of the member table (0: n_members);
+ * member_data_bytes the size of the member data pool (0: exactly what the
+ * initial members need; see sim_member_data_bytes).  members[0 .. n_members)
+ * are admitted in order as indices 0, 1, ...  alloc as in sim_create.
  * SIM_EINVAL on invalid parameters or members, SIM_ENOMEM when they do not
- * fit the capacity or the memory limit, or an allocation fails.
+ * fit the capacities or the memory limit, or the allocation fails.
  */
 int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t max_members,
-                     int32_t n_members, const sim_member *members, void *hip_stream, sim_t **out);
+                     int64_t member_data_bytes, int32_t n_members, const sim_member *members,
+                     void *hip_stream, const sim_allocator *alloc, sim_t **out);
 
-/* Device bytes of a batch's shared arrays (members add 16 B per step). */
+/* Device bytes of a batch (its one allocation) for these capacities; < 0 on
+ * invalid parameters. */
 int64_t sim_batch_footprint_bytes(const sim_params *common, int64_t slot_capacity,
-                                  int32_t max_members);
+                                  int32_t max_members, int64_t member_data_bytes);
+
+/* Bytes a member with n_steps steps and an ion profile of ion_profile_len
+ * nodes (0: none) takes of a batch's member data pool; < 0 on negative
+ * sizes. */
+int64_t sim_member_data_bytes(int64_t n_steps, int64_t ion_profile_len);
 
 /*
  * Admit a member between steps (synchronises the handle's stream).  *index
- * receives its slot in the member table.  SIM_ENOMEM when its tiles, chunks
- * or buckets find no free contiguous range, the member table is full or the
- * memory limit would be exceeded; the handle is unchanged then.
+ * receives its slot in the member table.  SIM_ENOMEM when its tiles, chunks,
+ * buckets or member data find no free contiguous range or the member table
+ * is full; the handle is unchanged then.  Allocates no device memory.
  */
 int sim_batch_add(sim_t *h, const sim_member *m, int32_t *index);
 
-/* Retire a member and free its ranges (synchronises).  Read its results first. */
+/* Retire a member and give its ranges back (synchronises; no device memory is
+ * freed).  Read its results first. */
 int sim_batch_remove(sim_t *h, int32_t index);
 
 /*
@@ -280,6 +322,11 @@ int sim_batch_step(sim_t *h, int64_t k);
  * enqueued so far (absolute step after them) and n_steps.  SIM_ERANGE for an
  * unused index. */
 int sim_member_info(sim_t *h, int32_t index, int64_t *n, int64_t *step, int64_t *n_steps);
+
+/* Particles of a member still in the domain (*alive) and absorbed by the
+ * probe so far (*absorbed, Sec. 2: their charge is on Q_S), and its current
+ * step (synchronises; each pointer may be NULL). */
+int sim_member_counts(sim_t *h, int32_t index, int64_t *alive, int64_t *absorbed, int64_t *step);
 
 /* As sim_read_response / sim_read_state / sim_eval_field, for one member. */
 int sim_member_read_response(sim_t *h, int32_t index, int64_t first, int64_t count,

@@ -83,6 +83,10 @@ def lib():
         L.orc_energy.argtypes = [P, C.c_int64, dp, dp, C.POINTER(C.c_uint32),
                                  C.POINTER(C.c_uint8), C.c_double, C.c_double, dp, dp]
         L.orc_energy.restype = C.c_double
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = C.c_int
         L.orc_diffuse_dir.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, C.c_int, dp, dp]
         L.orc_diffuse_dir.restype = None
         L.orc_philox4x64_10.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
@@ -250,3 +254,12 @@ def diffuse_dir(seed: int, pid: int, step: int, wall: int, normal):
     d = np.zeros(3)
     lib().orc_diffuse_dir(int(seed), int(pid), int(step), int(wall), _dp(n), _dp(d))
     return d
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())

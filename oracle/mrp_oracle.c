@@ -34,6 +34,7 @@
  * random-number generator (numpy's Philox).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -477,6 +478,10 @@ static void diffuse_dir(uint64_t seed, uint32_t id, int64_t step, int wall,
     for (int j = 0; j < 3; ++j)
         dir[j] = ct * nz[j] + st * (cos(ph) * ex[j] + sin(ph) * ey[j]);
 }
+
+/* Threads of the oracle's parallel loops (its CPU timing uses 1 and all). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* The diffuse-wall direction for a given inward unit normal, exported so
  * that its angular law can be checked on its own. */

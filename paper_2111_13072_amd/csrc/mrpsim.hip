@@ -1898,11 +1898,17 @@ struct Alloc {
     }
 };
 
+// Bytes of a member's arrays in the batch's data pool: drive and response
+// (8 B per step each) and, with an ion profile of prof_len nodes, its node
+// densities and enclosed charges (16 B per node), each 256-byte aligned.
+constexpr size_t kPoolUnit = 256;
+
+size_t align_unit(size_t b) { return (b + kPoolUnit - 1) & ~(kPoolUnit - 1); }
+
 size_t member_bytes(int64_t n_steps, int64_t prof_len)
 {
-    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return 2 * al((size_t)std::max<int64_t>(n_steps, 1) * 8) +
-           (prof_len > 0 ? al((size_t)prof_len * 16) : 0);
+    return 2 * align_unit((size_t)std::max<int64_t>(n_steps, 1) * 8) +
+           (prof_len > 0 ? align_unit((size_t)prof_len * 16) : 0);
 }
 
 // First-fit allocator of ranges [start, start + len) of a capacity.
@@ -1950,6 +1956,7 @@ private:
 struct Member {
     bool used = false;
     Seg seg{};
+    uint32_t md_start = 0, md_units = 0;   // the member's range of the data pool
     int64_t n = 0;
     int64_t step_host = 0;    // absolute step after all enqueued work
     int64_t start_step = 0;
@@ -1989,10 +1996,14 @@ struct sim {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool failed = false;
-    size_t shared_bytes = 0, member_total = 0;
-    std::vector<void *> mem;
+    size_t shared_bytes = 0;
+    // one device allocation holds every array, the members' data pool last
+    sim_allocator alloc{};      // caller's callbacks, or all NULL (hipMalloc / hipFree)
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    char *mdata = nullptr;      // members' drive, response and ion-profile arrays
     std::vector<Member> members;
-    Ranges tiles, chunks, buckets;
+    Ranges tiles, chunks, buckets, mdata_units;   // mdata_units: 256-byte units of mdata
 };
 
 namespace {
@@ -2038,7 +2049,7 @@ size_t lw4_32_offset(int L) { return fq4_32_offset(L) + 4 * (size_t)((L + 1) * (
 
 size_t tables32_len(int L) { return lw4_32_offset(L) + 4 * (size_t)(L + 1); }
 
-void plan_alloc(sim *h, Alloc &al)
+void plan_alloc(sim *h, Alloc &al, size_t pool_bytes)
 {
     const Layout &lo = h->lo;
     const size_t n = (size_t)lo.n_tiles * kWave;
@@ -2079,6 +2090,7 @@ void plan_alloc(sim *h, Alloc &al)
     al.add(&h->ctl, (size_t)lo.n_members);
     al.add(&h->tile_member, (size_t)lo.n_tiles);
     al.add(&h->chunk_member, (size_t)lo.n_chunks);
+    al.add(&h->mdata, std::max<size_t>(pool_bytes, kPoolUnit));
 }
 
 // Host-side coefficient tables.  f_l and b^P_l are the closed forms of App. A
@@ -2237,27 +2249,36 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     return e;
 }
 
-void free_member_arrays(Member &m)
+// Give a member's range of the data pool back (no device call).
+void free_member_arrays(sim *h, Member &m)
 {
-    if (m.seg.u_asy) (void)hipFree((void *)m.seg.u_asy);
-    if (m.seg.qdiff) (void)hipFree(m.seg.qdiff);
-    if (m.seg.ion_tab) (void)hipFree((void *)m.seg.ion_tab);
+    if (m.md_units) h->mdata_units.give(m.md_start, m.md_units);
+    m.md_units = 0;
     m.seg.u_asy = nullptr;
     m.seg.qdiff = nullptr;
     m.seg.ion_tab = nullptr;
 }
 
+// The handle's work completes before its graph and memory go: the stream is
+// drained first.
 void release(sim *h)
 {
     if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->exec) (void)hipGraphExecDestroy(h->exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
-    for (Member &m : h->members) free_member_arrays(m);
-    for (void *p : h->mem) (void)hipFree(p);
-    h->mem.clear();
+    h->exec = nullptr;
+    h->graph = nullptr;
+    if (h->arena) {
+        void *as = h->own_stream ? nullptr : (void *)h->stream;   // the stream given to alloc
+        if (h->alloc.free) h->alloc.free(h->alloc.ctx, h->arena, h->arena_bytes, as);
+        else (void)hipFree(h->arena);
+    }
+    h->arena = nullptr;
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    h->cap_stream = nullptr;
+    h->stream = nullptr;
 }
 
 int check_handle(sim *h)
@@ -2280,24 +2301,51 @@ int check_member_index(sim *h, int32_t index)
     return SIM_OK;
 }
 
-// Allocate the shared arrays, upload the tables, capture one step.
-int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream)
+// Allocate the arena (the shared arrays and the members' data pool, in one
+// allocation from the caller's allocator or hipMalloc), upload the tables.
+int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream,
+                const sim_allocator *alloc, size_t pool_bytes)
 {
     h->prm = *p;
     h->lo = lo;
+    if (alloc) {
+        if (!alloc->alloc || !alloc->free)
+            return fail(SIM_EINVAL, "sim_allocator needs both alloc and free");
+        h->alloc = *alloc;
+    }
     Alloc al;
-    plan_alloc(h, al);
+    plan_alloc(h, al, pool_bytes);
     h->shared_bytes = al.total();
     if (p->mem_limit_bytes && h->shared_bytes > p->mem_limit_bytes)
         return fail(SIM_ENOMEM, "footprint " + std::to_string(h->shared_bytes) +
                                     " B exceeds mem_limit_bytes");
-    for (auto &it : al.items) {
-        void *ptr = nullptr;
-        hipError_t e = hipMalloc(&ptr, std::max<size_t>(it.second, 1));
-        if (e != hipSuccess) return fail(SIM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-        h->mem.push_back(ptr);
-        *it.first = ptr;
+    // the arena first (before any stream exists: a caller's allocator that
+    // fails leaves no device state behind); its stream is the caller's, or
+    // NULL when the handle runs on a stream of its own
+    h->arena_bytes = h->shared_bytes;
+    if (h->alloc.alloc) {
+        h->arena = h->alloc.alloc(h->alloc.ctx, h->arena_bytes, hip_stream);
+        if (!h->arena) return fail(SIM_ENOMEM, "the caller's allocator returned NULL");
+        if (reinterpret_cast<uintptr_t>(h->arena) % kPoolUnit) {
+            h->alloc.free(h->alloc.ctx, h->arena, h->arena_bytes, hip_stream);
+            h->arena = nullptr;
+            return fail(SIM_EINVAL, "the caller's allocator must return 256-byte aligned memory");
+        }
+    } else {
+        hipError_t e = hipMalloc(&h->arena, h->arena_bytes);
+        if (e != hipSuccess) {
+            h->arena = nullptr;
+            return fail(SIM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
     }
+    {
+        char *at = static_cast<char *>(h->arena);
+        for (auto &it : al.items) {
+            *it.first = at;
+            at += align_unit(it.second);
+        }
+    }
+    h->mdata_units.reset((uint32_t)(std::max<size_t>(pool_bytes, kPoolUnit) / kPoolUnit));
     if (hip_stream) {
         h->stream = (hipStream_t)hip_stream;
     } else {
@@ -2494,10 +2542,9 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
         if (!h->members[k].used) { slot = k; break; }
     if (slot < 0) return fail(SIM_ENOMEM, "member table is full");
     const size_t mbytes = member_bytes(m->n_steps, m->ion_profile ? m->ion_profile_len : 0);
-    if (h->prm.mem_limit_bytes && h->shared_bytes + h->member_total + mbytes > h->prm.mem_limit_bytes)
-        return fail(SIM_ENOMEM, "member arrays would exceed mem_limit_bytes");
+    const uint32_t md_units = (uint32_t)(mbytes / kPoolUnit);
     const MemberShape sh = member_shape(n, h->lo.tu);
-    uint32_t t0 = 0, c0 = 0, b0 = 0;
+    uint32_t t0 = 0, c0 = 0, b0 = 0, md0 = 0;
     if (!h->tiles.take(sh.nt, &t0)) return fail(SIM_ENOMEM, "no free tile range for the member");
     if (!h->chunks.take(sh.nc, &c0)) {
         h->tiles.give(t0, sh.nt);
@@ -2508,7 +2555,16 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
         h->chunks.give(c0, sh.nc);
         return fail(SIM_ENOMEM, "no free bucket range for the member");
     }
+    if (!h->mdata_units.take(md_units, &md0)) {
+        h->tiles.give(t0, sh.nt);
+        h->chunks.give(c0, sh.nc);
+        h->buckets.give(b0, sh.nb);
+        return fail(SIM_ENOMEM, "the batch's member data pool has no room for the member's "
+                                "drive and response arrays");
+    }
     Member mb;
+    mb.md_start = md0;
+    mb.md_units = md_units;
     mb.used = true;
     mb.n = n;
     mb.step_host = m->start_step;
@@ -2539,17 +2595,17 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     sg.ion_qm = m->ion_mass > 0.0 ? 1.0 / m->ion_mass : 0.0;
     sg.used = 1;
     auto undo = [&](int code) {
-        free_member_arrays(mb);
+        free_member_arrays(h, mb);
         h->tiles.give(t0, sh.nt);
         h->chunks.give(c0, sh.nc);
         h->buckets.give(b0, sh.nb);
         return code;
     };
     const size_t ns = (size_t)std::max<int64_t>(m->n_steps, 1);
-    double *u_dev = nullptr, *q_dev = nullptr;
-    if (hipMalloc(&u_dev, 8 * ns) != hipSuccess) return undo(fail(SIM_ENOMEM, "hipMalloc of the drive failed"));
+    char *md = h->mdata + (size_t)md0 * kPoolUnit;
+    double *u_dev = reinterpret_cast<double *>(md);
+    double *q_dev = reinterpret_cast<double *>(md + align_unit(8 * ns));
     sg.u_asy = u_dev;
-    if (hipMalloc(&q_dev, 8 * ns) != hipSuccess) return undo(fail(SIM_ENOMEM, "hipMalloc of the response failed"));
     sg.qdiff = q_dev;
     std::vector<double> ion_tab;
     if (m->ion_profile) {
@@ -2570,10 +2626,7 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
             q += 4.0 * kPi * m->ntilde * seg;
         }
         ion_tab[2 * K + 1] = q;
-        double *t_dev = nullptr;
-        if (hipMalloc(&t_dev, 8 * ion_tab.size()) != hipSuccess)
-            return undo(fail(SIM_ENOMEM, "hipMalloc of the ion profile failed"));
-        sg.ion_tab = t_dev;
+        sg.ion_tab = reinterpret_cast<double *>(md + 2 * align_unit(8 * ns));
         sg.ion_k = (int32_t)K;
         sg.ion_h = h;
         sg.ion_inv_h = (double)K / (m->r_out - 1.0);
@@ -2617,7 +2670,6 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
         return undo(fail(SIM_EDEVICE, "member upload failed"));
     }
     h->members[slot] = std::move(mb);
-    h->member_total += mbytes;
     *index = slot;
     return SIM_OK;
 }
@@ -2642,11 +2694,10 @@ int engine_remove(sim *h, int32_t index)
         h->failed = true;
         return fail(SIM_EDEVICE, "member table update failed");
     }
-    free_member_arrays(mb);
+    free_member_arrays(h, mb);
     h->tiles.give(mb.seg.t0, mb.seg.nt);
     h->chunks.give(mb.seg.c0, mb.seg.nc);
     h->buckets.give(mb.seg.b0, mb.seg.nb);
-    h->member_total -= member_bytes(mb.seg.n_steps, mb.seg.ion_tab ? mb.seg.ion_k + 1 : 0);
     mb = Member();
     return SIM_OK;
 }
@@ -2730,7 +2781,8 @@ void sim_member_default(sim_member *m)
 
 namespace {
 
-int64_t footprint(const sim_params *common, int64_t slots, int32_t max_members, int64_t chunks)
+int64_t footprint(const sim_params *common, int64_t slots, int32_t max_members, int64_t chunks,
+                  size_t pool_bytes)
 {
     Layout lo;
     std::string why;
@@ -2738,7 +2790,7 @@ int64_t footprint(const sim_params *common, int64_t slots, int32_t max_members, 
     sim tmp;
     tmp.lo = lo;
     Alloc al;
-    plan_alloc(&tmp, al);
+    plan_alloc(&tmp, al, pool_bytes);
     return (int64_t)al.total();
 }
 
@@ -2746,10 +2798,17 @@ int64_t footprint(const sim_params *common, int64_t slots, int32_t max_members, 
 
 extern "C" {
 
-int64_t sim_batch_footprint_bytes(const sim_params *common, int64_t slot_capacity,
-                                  int32_t max_members)
+int64_t sim_member_data_bytes(int64_t n_steps, int64_t ion_profile_len)
 {
-    return footprint(common, slot_capacity, max_members, -1);
+    if (n_steps < 0 || ion_profile_len < 0) return fail(SIM_EINVAL, "negative size");
+    return (int64_t)member_bytes(n_steps, ion_profile_len);
+}
+
+int64_t sim_batch_footprint_bytes(const sim_params *common, int64_t slot_capacity,
+                                  int32_t max_members, int64_t member_data_bytes)
+{
+    if (member_data_bytes < 0) return fail(SIM_EINVAL, "member_data_bytes < 0");
+    return footprint(common, slot_capacity, max_members, -1, align_unit((size_t)member_data_bytes));
 }
 
 int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps)
@@ -2758,27 +2817,35 @@ int64_t sim_footprint_bytes(const sim_params *p, int64_t n, int64_t n_steps)
     if (!check_common(p, &why)) return fail(SIM_EINVAL, why);
     sim_member m = member_from_params(p, n, nullptr, nullptr, nullptr, nullptr, n_steps, 0);
     if (!check_member_scalars(&m, &why)) return fail(SIM_EINVAL, why);
-    const int64_t shared = footprint(p, slots_for(n), 1, member_shape(n, tuning_of(p)).nc);
-    if (shared < 0) return shared;
-    return shared + (int64_t)member_bytes(n_steps, 0);
+    return footprint(p, slots_for(n), 1, member_shape(n, tuning_of(p)).nc,
+                     member_bytes(n_steps, 0));
 }
 
 int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t max_members,
-                     int32_t n_members, const sim_member *members, void *hip_stream, sim_t **out)
+                     int64_t member_data_bytes, int32_t n_members, const sim_member *members,
+                     void *hip_stream, const sim_allocator *alloc, sim_t **out)
 {
     if (!out) return fail(SIM_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_members < 0 || (n_members > 0 && !members)) return fail(SIM_EINVAL, "bad member list");
+    if (member_data_bytes < 0) return fail(SIM_EINVAL, "member_data_bytes < 0");
     std::string why;
     if (!check_common(common, &why)) return fail(SIM_EINVAL, why);
     int64_t need = 0, chunks = 0;
+    size_t pool_need = 0;
     std::vector<Prepared> prep((size_t)n_members);
     for (int32_t i = 0; i < n_members; ++i) {
         if (prepare_member(&members[i], &prep[i]))
             return fail(SIM_EINVAL, "member " + std::to_string(i) + ": " + g_last_error);
         need += slots_for(members[i].n);
         chunks += member_shape(members[i].n, tuning_of(common)).nc;
+        pool_need += member_bytes(members[i].n_steps,
+                                  members[i].ion_profile ? members[i].ion_profile_len : 0);
     }
+    const size_t pool_bytes =
+        member_data_bytes == 0 ? pool_need : align_unit((size_t)member_data_bytes);
+    if (pool_bytes < pool_need)
+        return fail(SIM_ENOMEM, "members need more member data bytes than member_data_bytes");
     // exactly the initial members, or room for any later mix
     const bool exact = slot_capacity == 0 && (max_members == 0 || max_members == n_members);
     if (max_members == 0) max_members = n_members;
@@ -2795,7 +2862,7 @@ int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t ma
         delete h;
         return code;
     };
-    int rc = engine_init(h, common, lo, hip_stream);
+    int rc = engine_init(h, common, lo, hip_stream, alloc, pool_bytes);
     if (rc) return bail(rc);
     for (int32_t i = 0; i < n_members; ++i) {
         int32_t idx = -1;
@@ -2814,7 +2881,7 @@ int sim_batch_create(const sim_params *common, int64_t slot_capacity, int32_t ma
 
 int sim_create(const sim_params *p, int64_t n, const double *pos, const double *vel,
                const uint32_t *ids, const double *u_asy, int64_t n_steps, int64_t start_step,
-               void *hip_stream, sim_t **out)
+               void *hip_stream, const sim_allocator *alloc, sim_t **out)
 {
     if (!out) return fail(SIM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -2827,7 +2894,7 @@ int sim_create(const sim_params *p, int64_t n, const double *pos, const double *
         if (fp > (int64_t)p->mem_limit_bytes)
             return fail(SIM_ENOMEM, "footprint " + std::to_string(fp) + " B exceeds mem_limit_bytes");
     }
-    return sim_batch_create(p, 0, 1, 1, &m, hip_stream, out);
+    return sim_batch_create(p, 0, 1, 0, 1, &m, hip_stream, alloc, out);
 }
 
 int sim_batch_add(sim_t *h, const sim_member *m, int32_t *index)
@@ -2994,6 +3061,23 @@ int sim_member_read_state(sim_t *h, int32_t index, double *pos, double *vel, uin
     if (q_surface)
         *q_surface = (mb.q_surface0 + kQ * (double)(ctl.n_dead - ctl.n_dead_ion)) +
                      (double)ctl.n_dead_ion;
+    if (step) *step = ctl.step;
+    return SIM_OK;
+}
+
+int sim_member_counts(sim_t *h, int32_t index, int64_t *alive, int64_t *absorbed, int64_t *step)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    rc = check_member_index(h, index);
+    if (rc) return rc;
+    rc = sim_sync(h);
+    if (rc) return rc;
+    Ctl ctl;
+    if (hipMemcpy(&ctl, h->ctl + index, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess)
+        return mark_failed(h, fail(SIM_EDEVICE, "copy of control block failed"));
+    if (alive) *alive = h->members[index].n - (int64_t)ctl.n_dead;
+    if (absorbed) *absorbed = (int64_t)ctl.n_dead;
     if (step) *step = ctl.step;
     return SIM_OK;
 }

@@ -125,11 +125,14 @@ class Server:
 
     def __init__(self, budget_bytes: int, l_classes=(8, 16, 32), precision: int = S.SIM_FP64,
                  tick_steps: int = 50, max_members: int = 256, small_max: int = 0,
-                 small_share: float = 0.25):
+                 small_share: float = 0.25, max_steps: int = 20000, allocator="torch"):
         self.tick = tick_steps
         self.small_max = small_max
         self.pools = {}
         self.slots = {}   # particle slots of each pool
+        # every member slot can hold a request of up to max_steps steps: the
+        # members' drive and response arrays come from each pool's data pool
+        mdata = max_members * S.member_data_bytes(max_steps)
         per_particle = {}
         for L in l_classes:
             cp = S.SimParams(l_max=L, precision=precision)
@@ -149,7 +152,7 @@ class Server:
                 self.slots[(L, cls)] = max(n, 64)
                 self.pools[(L, cls)] = Pool((L, cls), S.Batch(
                     cp, [], slot_capacity=max(n, 64), max_members=max_members,
-                    use_torch_stream=False))
+                    member_data=mdata, use_torch_stream=False, allocator=allocator))
         self.rejected = []   # requests larger than their pool
 
     def pool_key(self, req: Request) -> tuple:

@@ -28,7 +28,64 @@ EXPORTED = ("sim_params_default", "sim_create", "sim_step", "sim_sync", "sim_que
             "sim_strerror", "sim_last_error", "sim_member_default", "sim_batch_create",
             "sim_batch_footprint_bytes", "sim_batch_add", "sim_batch_remove", "sim_batch_step",
             "sim_member_info", "sim_member_read_response", "sim_member_read_state",
-            "sim_member_eval_field")
+            "sim_member_eval_field", "sim_member_data_bytes", "sim_member_counts")
+
+
+# sim_allocator callbacks: alloc(ctx, bytes, stream) -> device pointer or NULL;
+# free(ctx, ptr, bytes, stream)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class sim_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class Allocator:
+    """A sim_allocator from two Python callables (kept alive with it):
+    alloc(nbytes, stream_handle) -> int device pointer (0 on failure) and
+    free(ptr, nbytes, stream_handle)."""
+
+    def __init__(self, alloc, free):
+        def _a(ctx, nbytes, stream):
+            try:
+                return int(alloc(int(nbytes), int(stream or 0))) or None
+            except Exception:
+                return None
+
+        def _f(ctx, ptr, nbytes, stream):
+            free(int(ptr), int(nbytes), int(stream or 0))
+
+        self._a, self._f = ALLOC_FN(_a), FREE_FN(_f)
+        self.c = sim_allocator(self._a, self._f, None)
+
+
+def torch_allocator() -> Allocator:
+    """Device memory from torch's caching allocator (current device), on the
+    handle's stream (stream 0: the handle's own stream, which torch does not
+    know; the block is then kept on torch's default stream)."""
+
+    def alloc(nbytes, stream):
+        import torch
+        return torch.cuda.caching_allocator_alloc(nbytes, torch.cuda.current_device(), stream)
+
+    def free(ptr, nbytes, stream):
+        import torch
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return Allocator(alloc, free)
+
+
+def _allocator(spec):
+    """None or "hip": hipMalloc inside the library; "torch": torch's caching
+    allocator; or an Allocator."""
+    if spec is None or spec == "hip":
+        return None
+    if spec == "torch":
+        return torch_allocator()
+    if isinstance(spec, Allocator):
+        return spec
+    raise ValueError(f"unknown allocator {spec!r}")
 
 
 class sim_params(C.Structure):
@@ -87,8 +144,9 @@ def lib():
     H = C.c_void_p
     L.sim_params_default.argtypes = [P]
     L.sim_params_default.restype = None
+    A = C.POINTER(sim_allocator)
     L.sim_create.argtypes = [P, C.c_int64, dp, dp, C.POINTER(C.c_uint32), dp, C.c_int64,
-                             C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]
+                             C.c_int64, C.c_void_p, A, C.POINTER(C.c_void_p)]
     L.sim_step.argtypes = [H, C.c_int64]
     L.sim_sync.argtypes = [H]
     L.sim_query.argtypes = [H]
@@ -113,10 +171,12 @@ def lib():
     i32p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
     L.sim_member_default.argtypes = [M]
     L.sim_member_default.restype = None
-    L.sim_batch_create.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, M, C.c_void_p,
-                                   C.POINTER(C.c_void_p)]
-    L.sim_batch_footprint_bytes.argtypes = [P, C.c_int64, C.c_int32]
+    L.sim_batch_create.argtypes = [P, C.c_int64, C.c_int32, C.c_int64, C.c_int32, M,
+                                   C.c_void_p, A, C.POINTER(C.c_void_p)]
+    L.sim_batch_footprint_bytes.argtypes = [P, C.c_int64, C.c_int32, C.c_int64]
     L.sim_batch_footprint_bytes.restype = C.c_int64
+    L.sim_member_data_bytes.argtypes = [C.c_int64, C.c_int64]
+    L.sim_member_data_bytes.restype = C.c_int64
     L.sim_batch_add.argtypes = [H, M, i32p]
     L.sim_batch_remove.argtypes = [H, C.c_int32]
     L.sim_batch_step.argtypes = [H, C.c_int64]
@@ -124,10 +184,12 @@ def lib():
     L.sim_member_read_response.argtypes = [H, C.c_int32, C.c_int64, C.c_int64, dp]
     L.sim_member_read_state.argtypes = [H, C.c_int32, dp, dp, C.POINTER(C.c_uint8), dp, i64p]
     L.sim_member_eval_field.argtypes = [H, C.c_int32, dp]
+    L.sim_member_counts.argtypes = [H, C.c_int32, i64p, i64p, i64p]
     for name in EXPORTED:
         if name not in ("sim_params_default", "sim_num_kernels", "sim_kernel_name",
                         "sim_footprint_bytes", "sim_destroy", "sim_strerror", "sim_last_error",
-                        "sim_member_default", "sim_batch_footprint_bytes"):
+                        "sim_member_default", "sim_batch_footprint_bytes",
+                        "sim_member_data_bytes"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -184,6 +246,12 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def _counts(handle, index: int) -> dict:
+    a, b, st = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().sim_member_counts(handle, index, C.byref(a), C.byref(b), C.byref(st)))
+    return dict(alive=a.value, absorbed=b.value, step=st.value)
+
+
 def _current_torch_stream():
     try:
         import torch
@@ -195,10 +263,12 @@ def _current_torch_stream():
 
 
 class Sim:
-    """One simulation handle (sim_create ... sim_destroy)."""
+    """One simulation handle (sim_create ... sim_destroy).  Its device memory
+    comes from `allocator`: "torch" (torch's caching allocator, the default),
+    "hip" (hipMalloc inside the library) or an Allocator."""
 
     def __init__(self, params: SimParams, pos, vel, u_asy, ids=None, start_step: int = 0,
-                 stream=None, use_torch_stream: bool = True):
+                 stream=None, use_torch_stream: bool = True, allocator="torch"):
         L = lib()
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)
@@ -213,10 +283,11 @@ class Sim:
         if stream is None and use_torch_stream:
             stream = _current_torch_stream()
         self._p = params.to_c()
+        self._alloc = _allocator(allocator)
         h = C.c_void_p()
         rc = L.sim_create(C.byref(self._p), n, _dp(pos), _dp(vel), idp,
                           _dp(u) if u.size else None, self.n_steps, start_step, stream,
-                          C.byref(h))
+                          C.byref(self._alloc.c) if self._alloc else None, C.byref(h))
         _check(rc)
         self._h = h
 
@@ -286,6 +357,10 @@ class Sim:
         _check(L.sim_profile(self._handle(), k, _dp(ms), nk))
         return {L.sim_kernel_name(i).decode(): float(ms[i]) for i in range(nk)}
 
+    def counts(self) -> dict:
+        """Alive and absorbed particle counts and the step (synchronises)."""
+        return _counts(self._handle(), 0)
+
     def info(self) -> dict:
         n = C.c_int64()
         t = C.c_int32()
@@ -351,9 +426,18 @@ class Member:
         return m, (pos, vel, u, ids, prof)
 
 
-def batch_footprint_bytes(params: SimParams, slot_capacity: int, max_members: int) -> int:
+def member_data_bytes(n_steps: int, ion_profile_len: int = 0) -> int:
+    """Bytes a member takes of a batch's member data pool."""
+    v = lib().sim_member_data_bytes(n_steps, ion_profile_len)
+    if v < 0:
+        _check(int(v))
+    return int(v)
+
+
+def batch_footprint_bytes(params: SimParams, slot_capacity: int, max_members: int,
+                          member_data: int = 0) -> int:
     p = params.to_c()
-    v = lib().sim_batch_footprint_bytes(C.byref(p), slot_capacity, max_members)
+    v = lib().sim_batch_footprint_bytes(C.byref(p), slot_capacity, max_members, member_data)
     if v < 0:
         _check(int(v))
     return int(v)
@@ -365,7 +449,10 @@ class Batch:
     between steps; each member's results equal those of the member run alone."""
 
     def __init__(self, common: SimParams, members=(), slot_capacity: int = 0,
-                 max_members: int = 0, stream=None, use_torch_stream: bool = True):
+                 max_members: int = 0, member_data: int = 0, stream=None,
+                 use_torch_stream: bool = True, allocator="torch"):
+        """member_data: bytes of the member data pool (0: what the initial
+        members need; see member_data_bytes)."""
         L = lib()
         self._p = common.to_c()
         cs, keep = [], []
@@ -377,8 +464,10 @@ class Batch:
         if stream is None and use_torch_stream:
             stream = _current_torch_stream()
         h = C.c_void_p()
-        _check(L.sim_batch_create(C.byref(self._p), slot_capacity, max_members, len(cs),
-                                  arr if cs else None, stream, C.byref(h)))
+        self._alloc = _allocator(allocator)
+        _check(L.sim_batch_create(C.byref(self._p), slot_capacity, max_members, member_data,
+                                  len(cs), arr if cs else None, stream,
+                                  C.byref(self._alloc.c) if self._alloc else None, C.byref(h)))
         self._h = h
         self._n = {i: mb.to_c()[0].n for i, mb in enumerate(members)}
 
@@ -437,6 +526,10 @@ class Batch:
         n, st, ns = C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib().sim_member_info(self._handle(), index, C.byref(n), C.byref(st), C.byref(ns)))
         return dict(n=n.value, step=st.value, n_steps=ns.value)
+
+    def counts(self, index: int) -> dict:
+        """Alive and absorbed particle counts and the step (synchronises)."""
+        return _counts(self._handle(), index)
 
     def read_response(self, index: int, first: int, count: int) -> np.ndarray:
         out = np.zeros(count)

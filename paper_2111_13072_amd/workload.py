@@ -173,6 +173,11 @@ def sweep_workload(l_max: int, n_e: float, t_e_ev: float) -> Workload:
                     l_max=l_max, n_steps=10_000, n_e=n_e, t_e_ev=t_e_ev)
 
 
+# The largest single-GPU run: the scale sweep at l_max 16, n_e 1e15 m^-3,
+# T_e 3 eV (the benchmark's default workload).
+SCALE = sweep_workload(16, 1e15, 3.0)
+
+
 def batch_workloads(count: int = 64, seed: int = 4, l_max: int = 16,
                     n_steps: int = 5000) -> list[Workload]:
     """Independent runs of a parameter scan, drawn in this order from one

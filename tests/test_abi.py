@@ -93,3 +93,40 @@ def test_memory_limit_is_enforced_before_allocation():
         S.Sim(S.SimParams(mem_limit_bytes=1024), pos, np.zeros((2, 3)), np.zeros(4),
               use_torch_stream=False)
     assert ei.value.code == S.SIM_ENOMEM
+
+
+def test_member_data_bytes_and_batch_footprint():
+    """A member takes 16 B per step (drive and response, each 256-byte
+    aligned) plus 16 B per ion-profile node of the batch's data pool, and the
+    pool is part of the batch's one allocation."""
+    assert S.member_data_bytes(1000) == 2 * 8192
+    assert S.member_data_bytes(1000, 100) == 2 * 8192 + 1792
+    assert S.member_data_bytes(0) == 2 * 256
+    cp = S.SimParams(l_max=8)
+    a = S.batch_footprint_bytes(cp, 1 << 14, 8)
+    b = S.batch_footprint_bytes(cp, 1 << 14, 8, member_data=1 << 20)
+    assert b - a == (1 << 20) - 256
+    with pytest.raises(S.SimError):
+        S.batch_footprint_bytes(cp, 1 << 14, 8, member_data=-1)
+
+
+def test_caller_allocator_is_asked_once_for_the_footprint():
+    """sim_create asks the caller's allocator for one block of exactly
+    sim_footprint_bytes before any other device call; when it returns NULL
+    the call fails with SIM_ENOMEM and nothing is freed."""
+    calls = []
+
+    def alloc(nbytes, stream):
+        calls.append(("alloc", nbytes, stream))
+        return 0
+
+    def free(ptr, nbytes, stream):
+        calls.append(("free", ptr, nbytes))
+
+    pos = np.array([[2.0, 0, 0], [0, 3.0, 0]])
+    prm = S.SimParams(l_max=4)
+    with pytest.raises(S.SimError) as ei:
+        S.Sim(prm, pos, np.zeros((2, 3)), np.zeros(7), use_torch_stream=False,
+              allocator=S.Allocator(alloc, free))
+    assert ei.value.code == S.SIM_ENOMEM
+    assert calls == [("alloc", S.footprint_bytes(prm, 2, 7), 0)]

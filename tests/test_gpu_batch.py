@@ -135,7 +135,8 @@ def test_admit_and_retire_between_steps():
     bm = make_member(300, 62, 8)
     c = make_member(650, 63, 5)
     _say("[gpu] pool: admit/retire")
-    with S.Batch(cp, [], slot_capacity=1600, max_members=3) as pool:
+    with S.Batch(cp, [], slot_capacity=1600, max_members=3,
+                 member_data=3 * S.member_data_bytes(20)) as pool:
         ia = pool.add(a)
         pool.step(5)
         ib = pool.add(bm)
@@ -159,9 +160,13 @@ def test_admit_and_retire_between_steps():
 def test_admission_limits_leave_the_pool_working():
     cp = common(L=3)
     a = make_member(500, 71, 6)
-    with S.Batch(cp, [a], slot_capacity=600, max_members=2) as pool:
+    with S.Batch(cp, [a], slot_capacity=600, max_members=2,
+                 member_data=2 * S.member_data_bytes(6)) as pool:
         with pytest.raises(S.SimError) as ei:
             pool.add(make_member(200, 72, 6))      # 512 + 256 slots > 640
+        assert ei.value.code == S.SIM_ENOMEM
+        with pytest.raises(S.SimError) as ei:
+            pool.add(make_member(50, 74, 40))      # its drive does not fit the data pool
         assert ei.value.code == S.SIM_ENOMEM
         with pytest.raises(S.SimError) as ei:
             pool.add(make_member(10, 73, 6, r_out=0.5))
@@ -207,3 +212,37 @@ def test_query_reports_completion():
         b.sync()
         assert b.query()
         assert b.info(0)["step"] == 40
+
+
+def test_torch_allocated_run_equals_hipmalloc_run():
+    """Device memory from torch's caching allocator (one block of the
+    footprint, visible in torch's accounting while the handle lives) or from
+    hipMalloc inside the library: the same run bit for bit, on torch's stream
+    and on a stream of the handle's own."""
+    import torch
+
+    n, L, steps = 3000, 6, 6
+    _say(f"[gpu] allocator: torch vs hipMalloc n={n} L={L} steps={steps}")
+    st = W.uniform_shell(n, 91, 5.0, 0.3)
+    sp = S.SimParams(ntilde=W.ntilde_for(n, 5.0), l_max=L, q_surface0=-3.0)
+    u = W.gaussian_drive(steps, sp.dt, 20.0, 289.52, t_center=0.1)
+    outs = []
+    for alloc, own in (("hip", False), ("torch", False), ("torch", True)):
+        torch.cuda.synchronize()
+        before = torch.cuda.memory_allocated()
+        with S.Sim(sp, st.pos, st.vel, u, allocator=alloc, use_torch_stream=not own) as sim:
+            held = torch.cuda.memory_allocated() - before
+            if alloc == "torch":
+                assert held >= S.footprint_bytes(sp, n, steps)
+            else:
+                assert held == 0
+            sim.step(steps)
+            outs.append((sim.read_state(), sim.read_response(0, steps), sim.eval_field()))
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == before
+    (a, qa, Ea) = outs[0]
+    for (b, qb, Eb) in outs[1:]:
+        for key in ("pos", "vel", "alive"):
+            np.testing.assert_array_equal(a[key], b[key])
+        np.testing.assert_array_equal(qa, qb)
+        np.testing.assert_array_equal(Ea, Eb)
