@@ -79,20 +79,29 @@ def cpu_baseline(wl, st, prm, u_now, q_s, budget_s: float, gpu_fields: dict):
     op = O.Params(d=prm.d, eps_r=prm.eps_r, r_out=prm.r_out, dt=prm.dt, ntilde=prm.ntilde,
                   ion_density=prm.ion_density, l_max=prm.l_max, m_mode=prm.m_mode,
                   probe_bc=prm.probe_bc, wall_bc=prm.wall_bc, seed=prm.seed)
+    from concurrent.futures import ThreadPoolExecutor
+
     rng = np.random.default_rng(12345)
     threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or (os.cpu_count() or 1)
     order = rng.permutation(wl.n)
+    ids = np.arange(wl.n, dtype=np.uint32)
+
+    def one_target(k):
+        E, _ = O.field(op, st.pos, ids=ids, q_surface=q_s, u_asy=u_now, targets=[k])
+        return E[0]
 
     def timed(targets, nthreads):
-        O.set_threads(nthreads)
+        """Oracle field + push of the targets, one target per call on
+        nthreads host threads (each call single-threaded)."""
         t0 = time.perf_counter()
-        E, _ = O.field(op, st.pos, q_surface=q_s, u_asy=u_now, targets=targets)
+        with ThreadPoolExecutor(nthreads, initializer=O.set_threads, initargs=(1,)) as ex:
+            E = np.array(list(ex.map(one_target, targets))).reshape(-1, 3)
         v = st.vel[targets] - E * prm.dt          # the push of the sampled particles
         _ = st.pos[targets] + v * prm.dt
         return E, time.perf_counter() - t0
 
     # all threads: a first probe, then as many targets as fit the budget
-    first = np.sort(order[:2 * threads])
+    first = np.sort(order[:threads])
     E0, t_first = timed(first, threads)
     per = t_first / len(first)
     extra = int(max(0, (0.75 * budget_s - t_first) / per))
@@ -105,7 +114,6 @@ def cpu_baseline(wl, st, prm, u_now, q_s, budget_s: float, gpu_fields: dict):
     n1 = max(1, int(0.25 * budget_s / (per * threads)))
     one = order[len(targets):len(targets) + n1]
     _, t_one = timed(np.sort(one), 1)
-    O.set_threads(threads)
     rate_one = len(one) / t_one
     rms = float(np.sqrt(np.mean(np.sum(Eo * Eo, axis=1))))
     errs = {k: float(np.max(np.abs(E[targets] - Eo)) / rms) for k, E in gpu_fields.items()}

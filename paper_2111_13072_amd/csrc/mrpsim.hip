@@ -187,14 +187,14 @@ struct Map {
     const uint32_t *chunk_member;  // [n_chunks], kNone for free chunks
 };
 
-// Charge of the immobile ions inside radius r, in super-particle units: the
-// uniform background n_i (4 pi / 3)(r^3 - 1) ntilde, or the profile, linear
-// in r on each segment [r_j, r_j + h], integrated in closed form in the
-// offset dd = r - r_j.
+// Charge of the immobile ions of a radial profile inside radius r, in
+// super-particle units: the density is linear in r on each segment
+// [r_j, r_j + h], integrated in closed form in the offset dd = r - r_j.
+// (A uniform background enters the field kernel as its field directly.)
 __device__ inline double ion_enclosed(const Seg &sg, double r, double r2)
 {
     constexpr double kFourPi = 4.0 * 3.14159265358979323846;
-    if (!sg.ion_tab) return sg.ntilde * sg.ion_density * (kFourPi / 3.0) * (r2 * r - 1.0);
+    (void)r2;
     const int K = sg.ion_k;
     int j = (int)((r - 1.0) * sg.ion_inv_h);
     j = max(0, min(j, K - 1));
@@ -233,14 +233,6 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nblocks)
     const uint32_t x = b % kXcds, k = b / kXcds;
     return x * q + min(x, r) + k;
 }
-
-// Reciprocal and reciprocal square root in the working precision: FP64 uses
-// the correctly rounded operations; FP32 the hardware approximations
-// (about 1 ulp), which the FP32 mode's error budget covers.
-__device__ inline double rcp_r(double v) { return 1.0 / v; }
-__device__ inline float rcp_r(float v) { return __builtin_amdgcn_rcpf(v); }
-__device__ inline double rsq_r(double v) { return 1.0 / sqrt(v); }
-__device__ inline float rsq_r(float v) { return __builtin_amdgcn_rsqf(v); }
 
 // Read of a table that no kernel writes while it runs, through the constant
 // address space: a wave-uniform index then becomes a scalar load through the
@@ -1027,13 +1019,36 @@ struct CfView {
 
 // stage(k0, k1) returns a view holding channels [k0, k1): the m = 0 block,
 // then one m block at a time, in stream order.
+//
+// The coordinates come in FP64.  In FP32 (R = float) the far field is
+// compensated: rounding the position to FP32 would shift every term of the
+// recurrences coherently (a degree-l term by ~l ulps), and the terms of the
+// tiles next to this one nearly cancel, which amplifies such shifts to
+// ~1e-5 of the field.  So r^2 and z enter the Qh recurrence as hi + lo FP32
+// pairs (the products with the lo parts are the first-order corrections,
+// exact to O(ulp^2)), and the per-m quantities C_m, S_m, r^-(2m+1) and the
+// directions are formed in FP64 and rounded once; what remains are the
+// independent roundings of the FP32 arithmetic.
 template <bool FULL, typename R, typename R4, typename Stage>
-__device__ inline void far_field(Stage &&stage, int L, const R4 *fq, R x, R y, R z, R &gx,
-                                 R &gy, R &gz)
+__device__ inline void far_field(Stage &&stage, int L, const R4 *fq, double xd, double yd,
+                                 double zd, R &gx, R &gy, R &gz)
 {
-    const R r2 = x * x + y * y + z * z;
-    const R inv_r2 = rcp_r(r2);
-    const R inv_r = rsq_r(r2);
+    constexpr bool kComp = sizeof(R) == 4;
+    const double r2d = xd * xd + yd * yd + zd * zd;
+    const double inv_r2d = 1.0 / r2d;
+    const double inv_rd = kComp ? sqrt(inv_r2d) : 1.0 / sqrt(r2d);
+    const R r2 = (R)r2d, z = (R)zd;
+    const R r2l = kComp ? (R)(r2d - (double)r2) : (R)0;   // lo parts (zero in FP64)
+    const R zl = kComp ? (R)(zd - (double)z) : (R)0;
+    const R inv_r2 = (R)inv_r2d;
+    // gamma r^2 and one step of the recurrences, with the lo corrections
+    auto gam_r2 = [&](R g) -> R { return kComp ? fma(g, r2, g * r2l) : g * r2; };
+    auto rec_q = [&](R Q1, R Q2, R gr2) -> R {
+        return kComp ? fma(z, Q1, fma(zl, Q1, -gr2 * Q2)) : z * Q1 - gr2 * Q2;
+    };
+    auto rec_d = [&](R Q1, R D1, R D2, R gr2) -> R {
+        return kComp ? fma(zl, D1, Q1 + z * D1) - gr2 * D2 : (Q1 + z * D1) - gr2 * D2;
+    };
     R Ga = 0, Gz = 0, Gx = 0, Gy = 0;
     // With t_c = b_c + s_l a_c (s_l = r^-(2l+1)) each (l, m) adds to the radial
     // sum Qh [(l - m) t - (2l+1) s_l a] = (l - m) Qh b - (l + m + 1) s_l Qh a,
@@ -1043,14 +1058,14 @@ __device__ inline void far_field(Stage &&stage, int L, const R4 *fq, R x, R y, R
     // the recurrence, its field is Gauss's law in the caller
     {
         R Q1 = 1, Q2 = 0, D1 = 0, D2 = 0;   // Qh_{l-1}, Qh_{l-2} and their D_z
-        R sl = inv_r * inv_r2;              // r^-(2l+1) at l = 1
+        R sl = (R)(inv_rd * inv_r2d);       // r^-(2l+1) at l = 1
         const CfView<R> v = stage(0, L);
 #pragma unroll 2
         for (int l = 1; l <= L; ++l) {
             const R4 e = fq[l];
-            const R gr2 = e.x * r2;
-            const R Qv = z * Q1 - gr2 * Q2;
-            const R Dz = (Q1 + z * D1) - gr2 * D2;
+            const R gr2 = gam_r2(e.x);
+            const R Qv = rec_q(Q1, Q2, gr2);
+            const R Dz = rec_d(Q1, D1, D2, gr2);
             const R ac = v.a(l - 1), bc = v.b(l - 1);
             const R Qs = Qv * sl, Qz = e.y * Qv, Qa = e.z * Qs, Ds = Dz * sl;
             Ga = fma(Qz, bc, Ga);
@@ -1067,16 +1082,19 @@ __device__ inline void far_field(Stage &&stage, int L, const R4 *fq, R x, R y, R
     if (FULL) {
         // C_m, S_m and C_{m-1}, S_{m-1} are common to all l of one m: the l
         // loop sums the cos and sin parts separately, combined once per m
-        R Cm = 1, Sm = 0;
-        R s_mm = inv_r;
+        double Cmd = 1, Smd = 0, s_mmd = inv_rd;
         int j = L + 1;   // stream index of (m, l = m)
         int k = L;       // channel position of (m, l = m), cos then sin
         for (int m = 1; m <= L; ++m) {
-            const R Cm1 = Cm, Sm1 = Sm;
-            Cm = x * Cm1 - y * Sm1;
-            Sm = x * Sm1 + y * Cm1;
-            s_mm *= inv_r2;
-            R sl = s_mm;
+            const R Cm1 = (R)Cmd, Sm1 = (R)Smd;
+            {
+                const double c1 = Cmd, s1 = Smd;
+                Cmd = xd * c1 - yd * s1;
+                Smd = xd * s1 + yd * c1;
+            }
+            s_mmd *= inv_r2d;
+            const R Cm = (R)Cmd, Sm = (R)Smd;
+            R sl = (R)s_mmd;
             // l = m: Qh = 1, D_z Qh = 0
             R Ac, As, Tc, Ts, Zc = 0, Zs = 0;
             const CfView<R> v = stage(k, k + 2 * (L - m + 1));
@@ -1097,9 +1115,9 @@ __device__ inline void far_field(Stage &&stage, int L, const R4 *fq, R x, R y, R
             for (int l = m + 1; l <= L; ++l) {
                 const R4 e = fq[j];
                 const R ac = v.a(k), bc = v.b(k), as = v.a(k + 1), bs = v.b(k + 1);
-                const R gr2 = e.x * r2;
-                const R Qv = z * Q1 - gr2 * Q2;
-                const R Dz = (Q1 + z * D1) - gr2 * D2;
+                const R gr2 = gam_r2(e.x);
+                const R Qv = rec_q(Q1, Q2, gr2);
+                const R Dz = rec_d(Q1, D1, D2, gr2);
                 const R Qs = Qv * sl, Qz = e.y * Qv, Qa = e.z * Qs, Ds = Dz * sl;
                 Tc = fma(Qv, bc, Tc);
                 Tc = fma(Qs, ac, Tc);
@@ -1128,7 +1146,8 @@ __device__ inline void far_field(Stage &&stage, int L, const R4 *fq, R x, R y, R
             Gy += dm * (Ts * Cm1 - Tc * Sm1);
         }
     }
-    const R xh = x * inv_r, yh = y * inv_r, c = z * inv_r;
+    const R inv_r = (R)inv_rd;
+    const R xh = (R)(xd * inv_rd), yh = (R)(yd * inv_rd), c = (R)(zd * inv_rd);
     const R radial = Ga * inv_r - c * Gz;
     gx = xh * radial + Gx;
     gy = yh * radial + Gy;
@@ -1236,6 +1255,8 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
 template <typename R>
 struct NearRows {
     R xh[2 * kWave], yh[2 * kWave], zh[2 * kWave], r[2 * kWave], ir[2 * kWave], q[2 * kWave];
+    // FP32 only: r / rho_t - 1 against the tile's reference radius rho_t
+    R s[sizeof(R) == 4 ? 2 * kWave : 1];
     double r2[2 * kWave];
     uint64_t uid[2 * kWave];   // 8 bytes like r2: one index scale for all rows
 };
@@ -1266,8 +1287,8 @@ __device__ inline float bpermute(int addr, float v)
 // peeled); in FP32 a recurrence on P_l - P_{l-1} driven by 1 - u (lw table).
 template <typename R, typename LG>
 __device__ inline void near_field_full(int lane, int L, const LG *lg, const NearRows<R> &nr, R xh,
-                                       R yh, R zh, R r, R ir, double r2, uint32_t uid, R qk,
-                                       double &ax, double &ay, double &az)
+                                       R yh, R zh, R r, R ir, R sk, R rho_t, double r2,
+                                       uint32_t uid, R qk, double &ax, double &ay, double &az)
 {
     double dck = 0.0, dbx = 0.0, dby = 0.0, dbz = 0.0;
     R ck = 0, bx = 0, by = 0, bz = 0;
@@ -1292,10 +1313,15 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
         const R qj = last && lane >= kWave / 2 ? (R)0 : nr.q[j];
         const bool k_outer = (r2 > r2j) | ((r2 == r2j) & (uid > uj));
         const R irmx = k_outer ? ir : irj;   // 1 / r_>
-        const R rmin = k_outer ? rj : r;     // r_<
-        const R rho = rmin * irmx;
         R u, S1, Sl, SB;
         if constexpr (sizeof(R) == 4) {
+            // rho = r_< / r_> = 1 - del with del = (s_> - s_<) rho_t / r_>
+            // from the offsets s = r / rho_t - 1 (FP64-exact, small): del
+            // keeps its relative precision, and the powers rho^l are stepped
+            // as rl - rl del, so no rounding of rho (an absolute 2^-24 near
+            // 1) is raised to the l-th power.
+            const R del = fabsf(sk - nr.s[j]) * (rho_t * irmx);
+            const R rho = 1.0f - del;
             // FP32: w = 1 - u = |xh_j - xh_k|^2 / 2 (for nearly parallel
             // directions the difference is exact, so w keeps its relative
             // precision where a dot product would leave 1 - u an absolute
@@ -1317,7 +1343,7 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
                 Dn = fmaf(c.x, D, c.y * (w * P));
                 Pn = P + Dn;
                 dPm = fmaf(c.z, P, dPm);   // P'_{l+1} = P'_{l-1} + (2l+1) P_l
-                rl *= rho;
+                rl = fmaf(-rl, del, rl);
                 const R t = rl * Pn;
                 S1 += t;
                 Sl = fmaf(c.w, t, Sl);
@@ -1330,6 +1356,8 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
             }
             if (l < L) degree(lg[l], Pa, Da, dPb, Pb, Db);
         } else {
+            const R rmin = k_outer ? rj : r;   // r_<
+            const R rho = rmin * irmx;
             u = xh * xj + yh * yj + zh * zj;
             // l = 1: P_1 = u, P'_1 = 1.  Then two degrees per pass with the
             // registers of Ph_l and Ph_{l-1} (and of P'_l, P'_{l-1}) trading
@@ -1468,17 +1496,19 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     Ctl &ct = mp.ctl[mb];
     const double ntilde = sg.ntilde, inv_nt = sg.inv_ntilde;
 
+    // FP32: the tile's reference radius rho_t, its first particle's (the far
+    // field's coordinates are scaled by it, matching the moments kernel and
+    // the pre-scaled coefficients; the near field measures radii from it).
+    double rho = 1.0;
+    if (FP32) {
+        const uint32_t p0 = tile * kWave;
+        rho = sqrt(key_r2(B.x[p0], B.y[p0], B.z[p0]));
+    }
+    const double inv_rho = 1.0 / rho;
+
     // ---- far field (all other tiles) ----
     double Ex, Ey, Ez;
     {
-        // FP32: coordinates scaled by the tile's first radius, matching the
-        // moments kernel and the pre-scaled coefficients; FP64: unscaled.
-        double rho = 1.0;
-        if (FP32) {
-            const uint32_t p0 = tile * kWave;
-            rho = sqrt(key_r2(B.x[p0], B.y[p0], B.z[p0]));
-        }
-        const double inv_rho = 1.0 / rho;
         RF gx, gy, gz;
         const RF *cfg;
         const NFF *fq;
@@ -1489,7 +1519,7 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
             cfg = coef + (size_t)tile * kp.C2;
             fq = tb.fq4;
         }
-        const RF xs = (RF)(x * inv_rho), ys = (RF)(y * inv_rho), zs = (RF)(z * inv_rho);
+        const double xs = x * inv_rho, ys = y * inv_rho, zs = z * inv_rho;
         // The tile's coefficients are read by every pass of every lane: they
         // go to LDS with coalesced loads (the far field reads them as
         // broadcasts), in windows of kWin channels (interior, then exterior)
@@ -1532,6 +1562,7 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
         nr.r[i] = (R)r;
         nr.ir[i] = (R)inv_r;
         nr.q[i] = valid ? (R)qk : (R)0;
+        if constexpr (sizeof(R) == 4) nr.s[i] = (R)(r * inv_rho - 1.0);
         nr.r2[i] = r2;
         nr.uid[i] = uid;
     }
@@ -1544,7 +1575,8 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
             const NF *lg;
             if constexpr (std::is_same<R, float>::value) lg = tb.lw4_32;
             else lg = tb.lg4;
-            near_field_full<R, NF>(lane, L, lg, nr, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
+            near_field_full<R, NF>(lane, L, lg, nr, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r,
+                                   (R)(r * inv_rho - 1.0), (R)rho, r2, uid,
                                    valid ? (R)qk : (R)0, ax, ay, az);
         } else {
             const NF *nf;
@@ -1602,16 +1634,23 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     // ---- l = 0: Gauss's law.  The l = 0 part of G~ is 1/(4 pi r_>), so only
     // the charge enclosed by r_k pushes: Q_S, the particles before k in the
     // radial order (those of earlier tiles, carried by the scan, and the
-    // lanes below in this tile) and the immobile ion background, all exact
-    // counts in super-particle units. ----
+    // lanes below in this tile), exact counts in super-particle units, and
+    // the immobile ion background.  The particles' and the uniform
+    // background's fields nearly cancel (to ~N^-1/2 of each), so each is
+    // formed at its own magnitude and only the two fields are added; a
+    // profile's enclosed charge is tabulated and joins the count. ----
     {
         const uint64_t below = (1ull << lane) - 1ull;
         const int n_below = __popcll(__ballot(valid) & below);
         const int i_below = __popcll(__ballot(ion) & below);
         const double before = qpre[tile] + ((double)i_below + kQ * (double)(n_below - i_below));
-        const double ions = ion_enclosed(sg, r, r2);
-        const double enclosed = (ct.q_surface + before) + ions;
-        const double e = enclosed / (4.0 * kPi * ntilde * r2);
+        double e;
+        if (sg.ion_tab) {
+            e = ((ct.q_surface + before) + ion_enclosed(sg, r, r2)) / (4.0 * kPi * ntilde * r2);
+        } else {
+            e = (ct.q_surface + before) / (4.0 * kPi * ntilde * r2) +
+                sg.ion_density * (r2 * r - 1.0) / (3.0 * r2);
+        }
         Ex += e * xh;
         Ey += e * yh;
         Ez += e * zh;
@@ -1761,12 +1800,15 @@ Tuning tuning_of(const sim_params *p)
     return t;
 }
 
-// In the FP32 mode the near field's FP32 error grows with l_max (pairs at
-// nearly equal radius sum slowly decaying Legendre series and their
-// derivatives); with the recurrence driven by 1 - u it stays under ~1e-5 of
-// the RMS field up to l_max 32 (2.9e-5 at 48).  From this degree on the near
-// field runs in FP64 while the far field stays FP32.
-constexpr int kNear64MinL = 33;
+// In the FP32 mode the near field's FP32 error grows with l_max: a pair at
+// nearly equal radius and angle contributes up to ~l_max^2 / (4 pi ntilde r^2)
+// to the field, many times the field's RMS when the tile is sparse, and the
+// FP32 evaluation of such a pair carries a few ulps of it.  With the radial
+// powers stepped from 1 - rho and the Legendre recurrence driven by 1 - u it
+// stays near 2-5e-6 of the RMS field up to l_max 19 on random shells of a few
+// thousand particles; from this degree on the near field runs in FP64 while
+// the far field stays FP32 (compensated).
+constexpr int kNear64MinL = 20;
 
 struct Layout {
     int L, C, C2;

@@ -1,7 +1,7 @@
 """GPU (HIP) against the CPU oracle on identical seeded inputs.
 
 Field metric: max_k |E_gpu - E_oracle| / RMS_k |E_oracle|; bar 1e-12 in FP64,
-1e-5 in the FP32-compensated mode (l_max <= 16; 2e-5 above).
+1e-5 in the FP32-compensated mode at every l_max.
 Every case prints its name, size and seed before touching the GPU.
 """
 from __future__ import annotations
@@ -326,38 +326,53 @@ def test_field_evaluation_between_steps_changes_nothing():
 # --------------------------------------------------------------------------
 
 FP32_FIELD_TOL = 1e-5
-# The FP32 near field (pairs inside a tile, at nearly equal radius) runs its
-# Legendre recurrence on 1 - u, which keeps its error under ~1e-5 up to
-# l_max 32; above, it runs in FP64.  Measured for l_max 20 to 48: 2e-6 to
-# 1.2e-5, the largest set by the FP32 far field; the bound stated there is
-# 2e-5 (FP64 mode meets 1e-12).
-FP32_FIELD_TOL_HIGH_L = 2e-5
 
 FP32_CASES = [
-    ("shell-3000-L8", 3000, 8, S.SIM_M_FULL, 61, FP32_FIELD_TOL),
-    ("ragged-777-L5", 777, 5, S.SIM_M_FULL, 62, FP32_FIELD_TOL),
-    ("shell-2000-L16", 2000, 16, S.SIM_M_FULL, 63, FP32_FIELD_TOL),
-    ("shell-1500-L20", 1500, 20, S.SIM_M_FULL, 70, FP32_FIELD_TOL_HIGH_L),
-    ("shell-1500-L24", 1500, 24, S.SIM_M_FULL, 71, FP32_FIELD_TOL_HIGH_L),
-    ("shell-1000-L32", 1000, 32, S.SIM_M_FULL, 64, FP32_FIELD_TOL_HIGH_L),
-    ("shell-700-L48", 700, 48, S.SIM_M_FULL, 72, FP32_FIELD_TOL_HIGH_L),
-    ("axisym-640-L6", 640, 6, S.SIM_M_AXISYM, 65, FP32_FIELD_TOL),
-    ("monopole-500-L0", 500, 0, S.SIM_M_FULL, 66, FP32_FIELD_TOL),
+    # name, n, l_max, m_mode, seed, r_out
+    ("shell-3000-L8", 3000, 8, S.SIM_M_FULL, 61, 5.0),
+    ("ragged-777-L5", 777, 5, S.SIM_M_FULL, 62, 5.0),
+    ("shell-2000-L16", 2000, 16, S.SIM_M_FULL, 63, 5.0),
+    ("shell-1500-L20", 1500, 20, S.SIM_M_FULL, 70, 5.0),
+    ("shell-1500-L24", 1500, 24, S.SIM_M_FULL, 71, 5.0),
+    ("shell-1000-L32", 1000, 32, S.SIM_M_FULL, 64, 5.0),
+    ("shell-700-L48", 700, 48, S.SIM_M_FULL, 72, 5.0),
+    ("shell-700-L64", 700, 64, S.SIM_M_FULL, 73, 5.0),
+    ("axisym-640-L6", 640, 6, S.SIM_M_AXISYM, 65, 5.0),
+    ("monopole-500-L0", 500, 0, S.SIM_M_FULL, 66, 5.0),
+    # the worst cases of an earlier search over random shells
+    ("shell-2109-L13-rout10", 2109, 13, S.SIM_M_FULL, 890459, 10.0),
+    ("shell-1390-L13", 1390, 13, S.SIM_M_FULL, 890459, 5.0),
 ]
 
 
-@pytest.mark.parametrize("name,n,L,mode,seed,tol", FP32_CASES, ids=[c[0] for c in FP32_CASES])
-def test_fp32_field_matches_oracle(name, n, L, mode, seed, tol):
-    _say(f"[gpu] fp32 field parity {name}: n={n} L={L} mode={mode} seed={seed}")
-    sp, op = _params(n, L, mode, q_surface0=-7.0, precision=S.SIM_FP32_COMP)
-    st = W.uniform_shell(n, seed, 5.0, 0.0831)
+def _random_fp32_cases(count=34):
+    """Seeded random shells: n in [200, 3000), l_max in [1, 16], outer wall at
+    2, 5 or 10 probe radii (denser and sparser than the workloads)."""
+    out = []
+    for i in range(count):
+        g = np.random.default_rng(20211126 + i)
+        n = int(g.integers(200, 3000))
+        L = int(g.integers(1, 17))
+        r_out = (2.0, 5.0, 10.0)[i % 3]
+        out.append((f"random{i}-{n}-L{L}-rout{r_out:g}", n, L, S.SIM_M_FULL, 7000 + i, r_out))
+    return out
+
+
+FP32_CASES += _random_fp32_cases()
+
+
+@pytest.mark.parametrize("name,n,L,mode,seed,r_out", FP32_CASES, ids=[c[0] for c in FP32_CASES])
+def test_fp32_field_matches_oracle(name, n, L, mode, seed, r_out):
+    _say(f"[gpu] fp32 field parity {name}: n={n} L={L} mode={mode} seed={seed} r_out={r_out}")
+    sp, op = _params(n, L, mode, r_out=r_out, q_surface0=-7.0, precision=S.SIM_FP32_COMP)
+    st = W.uniform_shell(n, seed, r_out, 0.0831)
     u = np.array([0.0, 0.0, 0.3, 0.0])
     with S.Sim(sp, st.pos, st.vel, u, start_step=2) as sim:
         E = sim.eval_field()
     Eo, _ = O.field(op, st.pos, q_surface=-7.0, u_asy=0.3)
     err = _rel_err(E, Eo)
     _say(f"[gpu]   rel err {err:.3e}")
-    assert err <= tol
+    assert err <= FP32_FIELD_TOL
 
 
 @pytest.mark.parametrize("precision,tol", [(S.SIM_FP64, FP64_FIELD_TOL),
@@ -413,8 +428,6 @@ def test_fp32_steps_track_oracle(L):
         out = sim.read_state()
     ref = O.run(op, st.pos, st.vel, u, steps, q_surface=-2.0)
     np.testing.assert_array_equal(out["alive"], ref.alive)
-    # a relative field error e moves a particle by < e |E| dt^2 per step: 1e-7
-    # for the 1e-5 bound up to l_max 16, 2e-7 for the 2e-5 bound above
-    field_tol = FP32_FIELD_TOL if L <= 16 else FP32_FIELD_TOL_HIGH_L
-    assert np.max(np.abs(out["pos"] - ref.pos)) <= 1e-2 * field_tol
-    assert np.max(np.abs(qd - ref.qdiff)) <= 0.1 * field_tol * np.max(np.abs(ref.qdiff))
+    # a relative field error e moves a particle by < e |E| dt^2 per step
+    assert np.max(np.abs(out["pos"] - ref.pos)) <= 1e-2 * FP32_FIELD_TOL
+    assert np.max(np.abs(qd - ref.qdiff)) <= 0.1 * FP32_FIELD_TOL * np.max(np.abs(ref.qdiff))
