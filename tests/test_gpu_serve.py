@@ -1,5 +1,6 @@
 """Continuous batching: requests arriving over time, admitted into resident
-pools between steps, each answered exactly as if it had run alone."""
+pools between steps, each answered exactly as if it had run alone, and as the
+CPU oracle answers it."""
 from __future__ import annotations
 
 import sys
@@ -7,10 +8,25 @@ import sys
 import numpy as np
 import pytest
 
+import oracle as O
 from paper_2111_13072_amd import serve as SV
 from paper_2111_13072_amd import sim as S
 
 pytestmark = pytest.mark.gpu
+
+_ORACLE = {}
+
+
+def oracle_response(r: SV.Request) -> np.ndarray:
+    """Q_diff of the request's simulation from the CPU oracle (same seeded
+    member: particles, drive, ntilde, walls), cached across the tests."""
+    if r.rid not in _ORACLE:
+        wl = r.workload()
+        st = wl.particles()
+        op = O.Params(d=wl.d, eps_r=wl.eps_r, r_out=wl.r_out, dt=wl.dt, ntilde=wl.ntilde,
+                      ion_density=1.0, l_max=r.l_max)
+        _ORACLE[r.rid] = O.run(op, st.pos, st.vel, wl.drive(r.n_steps), r.n_steps).qdiff
+    return _ORACLE[r.rid]
 
 
 def _say(msg):
@@ -48,6 +64,7 @@ def test_served_results_equal_runs_alone(small_max):
     assert sorted(d.rid for d in done) == list(range(len(reqs)))
     waited = [d for d in done if d.admitted > d.arrival + 1e-3]
     _say(f"[gpu] {len(waited)} requests waited for admission")
+    worst = 0.0
     for d in done:
         r = reqs[d.rid]
         assert d.q_diff.shape == (r.n_steps,)
@@ -56,6 +73,13 @@ def test_served_results_equal_runs_alone(small_max):
             b.step(r.n_steps)
             q = b.read_response(0, 0, r.n_steps)
         assert np.array_equal(q, d.q_diff), d.rid
+        # and the served response is the method's: the oracle's run of the
+        # same request, relative to the response's scale
+        qo = oracle_response(r)
+        dev = float(np.max(np.abs(d.q_diff - qo)) / np.max(np.abs(qo)))
+        worst = max(worst, dev)
+        assert dev <= 1e-12, (d.rid, dev)
+    _say(f"[gpu] served responses vs oracle: worst relative deviation {worst:.2e}")
     s = SV.latency_summary(done)
     assert s["requests"] == len(reqs) and 0 < s["p50_s"] <= s["p99_s"] <= s["max_s"]
 
