@@ -209,6 +209,34 @@ int sim_read_state(sim_t *h, double *pos, double *vel, uint8_t *alive, double *q
 int sim_eval_field(sim_t *h, double *E);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the field
+ * evaluation of sim_eval_field for a state given in device memory, with no
+ * handle and no allocation.  Every working array (sort records, tile sums,
+ * carries, coefficients, tables) lives in one static device buffer of
+ * 64 MiB per GPU, held until the process ends; sim_eval_field_static_bytes
+ * gives the part a call needs, and a call that needs more fails with
+ * SIM_ENOMEM (FP64: about 1.7e5 particles at l_max 16, 2.5e5 at l_max 8).
+ *   p          as for sim_create (ntilde, ion_density, r_out, ... of the one
+ *              simulation; mem_limit_bytes is ignored).
+ *   n          particles (electrons), ids 0..n-1 in array order (ties of
+ *              equal radius go by index, as sim_create with ids NULL).
+ *   pos        DEVICE array [3n], particle-major; every particle must satisfy
+ *              1 < r < r_out (not checked: other positions give undefined
+ *              fields, never an out-of-bounds access).
+ *   q_surface  Q_S, u_asy the drive at the evaluated time.
+ *   E          DEVICE array [3n] receiving E at every particle, array order.
+ *   hip_stream stream to run on (NULL: the null stream).
+ * Synchronises the stream before returning.  The buffer is shared by every
+ * call on a GPU and keeps the last call's contents (the call clears what
+ * must start at zero): calls that overlap on one GPU, from two threads or on
+ * two streams, race.
+ */
+int sim_eval_field_static(const sim_params *p, int64_t n, const double *pos, double q_surface,
+                          double u_asy, double *E, void *hip_stream);
+int64_t sim_eval_field_static_bytes(const sim_params *p, int64_t n);
+
+/*
  * Run k steps with a HIP event around every kernel and return the average
  * duration in milliseconds of each kernel kind (indices as sim_kernel_name).
  * kernel_ms has n_kernels entries; entries beyond sim_num_kernels() are left

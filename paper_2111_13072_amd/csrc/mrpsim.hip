@@ -32,6 +32,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -2343,6 +2344,119 @@ int check_member_index(sim *h, int32_t index)
     return SIM_OK;
 }
 
+// The host-side constant tables of a layout: the FP64 block of
+// build_tables, its FP32 copies, and the degree and normalisation of each
+// channel in stream order.
+struct HostTables {
+    std::vector<double> tab;
+    std::vector<float> tab32;
+    std::vector<int> chl;
+    std::vector<double> chn;
+};
+
+int make_host_tables(const sim_params &p, const Layout &lo, HostTables *ht)
+{
+    const int L = lo.L;
+    ht->tab = build_tables(p, lo);
+    const std::vector<double> &tab = ht->tab;
+    std::vector<float> &tab32 = ht->tab32;
+    tab32.assign(tables32_len(L), 0.f);
+    {
+        const size_t ntri = (size_t)(L + 1) * (L + 2) / 2;
+        const double *nf4 = tab.data() + nf4_offset(L);
+        for (int i = 0; i < 4 * (L + 1); ++i) tab32[nf4_32_offset(L) + i] = (float)nf4[i];
+        const double *lg = tab.data() + lg4_offset(L);
+        for (int i = 0; i < 4 * (L + 1); ++i) tab32[lg4_32_offset(L) + i] = (float)lg[i];
+        const double *fq = tab.data() + fq4_offset(L);
+        for (size_t i = 0; i < 4 * ntri; ++i) tab32[fq4_32_offset(L) + i] = (float)fq[i];
+        float *lw = tab32.data() + lw4_32_offset(L);
+        for (int l = 0; l <= L; ++l) {
+            lw[4 * l + 0] = (float)((double)l / (l + 1.0));
+            lw[4 * l + 1] = (float)(-(2.0 * l + 1.0) / (l + 1.0));
+            lw[4 * l + 2] = (float)(2.0 * l + 1.0);
+            lw[4 * l + 3] = (float)(l + 1.0);
+        }
+    }
+    // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
+    // and its far-field normalisation N_lm
+    std::vector<int> &chl = ht->chl;
+    std::vector<double> &chn = ht->chn;
+    chl.clear();
+    chn.clear();
+    {
+        const double *qmm = tab.data() + kQmmArray * (L + 1);
+        const double *alm = qmm + (L + 1);
+        for (int m = 0; m <= (lo.full ? L : 0); ++m) {
+            double nlm = qmm[m];   // N_mm
+            for (int l = m; l <= L; ++l) {
+                if (l > m) nlm *= alm[tri(l, m)];
+                if (l == 0) continue;
+                for (int sc = 0; sc < (m > 0 ? 2 : 1); ++sc) {
+                    chl.push_back(l);
+                    chn.push_back(nlm);
+                }
+            }
+        }
+    }
+    if ((int)chl.size() != lo.C) return fail(SIM_EDEVICE, "channel count mismatch");
+    if (chl.empty()) {
+        chl.push_back(0);
+        chn.push_back(0.0);
+    }
+    return SIM_OK;
+}
+
+// Point the kernels' table, parameter and map views at the handle's carved
+// arrays (its layout set).
+void bind_device_tables(sim *h)
+{
+    const Layout &lo = h->lo;
+    const int L = lo.L;
+    double *tb = h->tables;
+    h->tb.ftil = tb;
+    h->tb.wl = tb + (L + 1);
+    h->tb.drive_w = tb + 2 * (L + 1);
+    h->tb.self_w = tb + 3 * (L + 1);
+    h->tb.nfA = tb + 4 * (L + 1);
+    h->tb.nfB = tb + 5 * (L + 1);
+    h->tb.nf4 = reinterpret_cast<const double4 *>(tb + nf4_offset(L));
+    h->tb.lg4 = reinterpret_cast<const double4 *>(tb + lg4_offset(L));
+    h->tb.fq4 = reinterpret_cast<const double4 *>(tb + fq4_offset(L));
+    h->tb.chn = h->chn;
+    h->tb.chl = h->chl;
+    h->tb.nf4_32 = reinterpret_cast<const float4 *>(h->tables32 + nf4_32_offset(L));
+    h->tb.lg4_32 = reinterpret_cast<const float4 *>(h->tables32 + lg4_32_offset(L));
+    h->tb.fq4_32 = reinterpret_cast<const float4 *>(h->tables32 + fq4_32_offset(L));
+    h->tb.lw4_32 = reinterpret_cast<const float4 *>(h->tables32 + lw4_32_offset(L));
+    KParams &kp = h->kp;
+    kp.L = lo.L;
+    kp.C = lo.C;
+    kp.C2 = lo.C2;
+    kp.SW = lo.C2 + 1;
+    kp.n_tiles = lo.n_tiles;
+    kp.n_chunks = lo.n_chunks;
+    kp.nb = lo.nb;
+    kp.n_members = lo.n_members;
+    kp.fp32 = lo.fp32 ? 1 : 0;
+    kp.field_only = 0;
+    kp.fuse_keys = 0;
+    h->map.seg = h->seg;
+    h->map.ctl = h->ctl;
+    h->map.tile_member = h->tile_member;
+    h->map.chunk_member = h->chunk_member;
+}
+
+// Carve the arrays of plan_alloc out of one block at base, in order, each
+// 256-byte aligned.
+void carve(Alloc &al, void *base)
+{
+    char *at = static_cast<char *>(base);
+    for (auto &it : al.items) {
+        *it.first = at;
+        at += align_unit(it.second);
+    }
+}
+
 // Allocate the arena (the shared arrays and the members' data pool, in one
 // allocation from the caller's allocator or hipMalloc), upload the tables.
 int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream,
@@ -2380,13 +2494,7 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream,
             return fail(SIM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
     }
-    {
-        char *at = static_cast<char *>(h->arena);
-        for (auto &it : al.items) {
-            *it.first = at;
-            at += align_unit(it.second);
-        }
-    }
+    carve(al, h->arena);
     h->mdata_units.reset((uint32_t)(std::max<size_t>(pool_bytes, kPoolUnit) / kPoolUnit));
     if (hip_stream) {
         h->stream = (hipStream_t)hip_stream;
@@ -2398,82 +2506,9 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream,
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return fail(SIM_EDEVICE, "hipStreamCreate failed");
 
-    std::vector<double> tab = build_tables(*p, lo);
-    const int L = lo.L;
-    double *tb = h->tables;
-    h->tb.ftil = tb;
-    h->tb.wl = tb + (L + 1);
-    h->tb.drive_w = tb + 2 * (L + 1);
-    h->tb.self_w = tb + 3 * (L + 1);
-    h->tb.nfA = tb + 4 * (L + 1);
-    h->tb.nfB = tb + 5 * (L + 1);
-    h->tb.nf4 = reinterpret_cast<const double4 *>(tb + nf4_offset(L));
-    h->tb.lg4 = reinterpret_cast<const double4 *>(tb + lg4_offset(L));
-    h->tb.fq4 = reinterpret_cast<const double4 *>(tb + fq4_offset(L));
-    h->tb.chn = h->chn;
-    h->tb.chl = h->chl;
-    std::vector<float> tab32(tables32_len(L), 0.f);
-    {
-        const size_t ntri = (size_t)(L + 1) * (L + 2) / 2;
-        const double *nf4 = tab.data() + nf4_offset(L);
-        for (int i = 0; i < 4 * (L + 1); ++i) tab32[nf4_32_offset(L) + i] = (float)nf4[i];
-        const double *lg = tab.data() + lg4_offset(L);
-        for (int i = 0; i < 4 * (L + 1); ++i) tab32[lg4_32_offset(L) + i] = (float)lg[i];
-        const double *fq = tab.data() + fq4_offset(L);
-        for (size_t i = 0; i < 4 * ntri; ++i) tab32[fq4_32_offset(L) + i] = (float)fq[i];
-        float *lw = tab32.data() + lw4_32_offset(L);
-        for (int l = 0; l <= L; ++l) {
-            lw[4 * l + 0] = (float)((double)l / (l + 1.0));
-            lw[4 * l + 1] = (float)(-(2.0 * l + 1.0) / (l + 1.0));
-            lw[4 * l + 2] = (float)(2.0 * l + 1.0);
-            lw[4 * l + 3] = (float)(l + 1.0);
-        }
-    }
-    h->tb.nf4_32 = reinterpret_cast<const float4 *>(h->tables32 + nf4_32_offset(L));
-    h->tb.lg4_32 = reinterpret_cast<const float4 *>(h->tables32 + lg4_32_offset(L));
-    h->tb.fq4_32 = reinterpret_cast<const float4 *>(h->tables32 + fq4_32_offset(L));
-    h->tb.lw4_32 = reinterpret_cast<const float4 *>(h->tables32 + lw4_32_offset(L));
-    // degree of each channel in stream order (m outer, l = max(m,1)..L inner)
-    // and its far-field normalisation N_lm
-    std::vector<int> chl;
-    std::vector<double> chn;
-    {
-        const double *qmm = tab.data() + kQmmArray * (L + 1);
-        const double *alm = qmm + (L + 1);
-        for (int m = 0; m <= (lo.full ? L : 0); ++m) {
-            double nlm = qmm[m];   // N_mm
-            for (int l = m; l <= L; ++l) {
-                if (l > m) nlm *= alm[tri(l, m)];
-                if (l == 0) continue;
-                for (int sc = 0; sc < (m > 0 ? 2 : 1); ++sc) {
-                    chl.push_back(l);
-                    chn.push_back(nlm);
-                }
-            }
-        }
-    }
-    if ((int)chl.size() != lo.C) return fail(SIM_EDEVICE, "channel count mismatch");
-    if (chl.empty()) {
-        chl.push_back(0);
-        chn.push_back(0.0);
-    }
-
-    KParams &kp = h->kp;
-    kp.L = lo.L;
-    kp.C = lo.C;
-    kp.C2 = lo.C2;
-    kp.SW = lo.C2 + 1;
-    kp.n_tiles = lo.n_tiles;
-    kp.n_chunks = lo.n_chunks;
-    kp.nb = lo.nb;
-    kp.n_members = lo.n_members;
-    kp.fp32 = lo.fp32 ? 1 : 0;
-    kp.field_only = 0;
-    kp.fuse_keys = 0;
-    h->map.seg = h->seg;
-    h->map.ctl = h->ctl;
-    h->map.tile_member = h->tile_member;
-    h->map.chunk_member = h->chunk_member;
+    HostTables ht;
+    if (int rc = make_host_tables(*p, lo, &ht)) return rc;
+    bind_device_tables(h);
     h->tiles.reset((uint32_t)lo.n_tiles);
     h->chunks.reset((uint32_t)lo.n_chunks);
     h->buckets.reset((uint32_t)lo.nb);
@@ -2482,10 +2517,11 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream,
     std::vector<Seg> segs((size_t)lo.n_members);   // used = 0
     std::vector<Ctl> ctls((size_t)lo.n_members);
     std::vector<uint32_t> none_t((size_t)lo.n_tiles, kNone), none_c((size_t)lo.n_chunks, kNone);
-    if (hipMemcpy(h->tables, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) ||
-        hipMemcpy(h->chl, chl.data(), sizeof(int) * chl.size(), hipMemcpyHostToDevice) ||
-        hipMemcpy(h->chn, chn.data(), sizeof(double) * chn.size(), hipMemcpyHostToDevice) ||
-        hipMemcpy(h->tables32, tab32.data(), sizeof(float) * tab32.size(), hipMemcpyHostToDevice) ||
+    if (hipMemcpy(h->tables, ht.tab.data(), sizeof(double) * ht.tab.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->chl, ht.chl.data(), sizeof(int) * ht.chl.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->chn, ht.chn.data(), sizeof(double) * ht.chn.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->tables32, ht.tab32.data(), sizeof(float) * ht.tab32.size(),
+                  hipMemcpyHostToDevice) ||
         hipMemcpy(h->seg, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->ctl, ctls.data(), sizeof(Ctl) * ctls.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->tile_member, none_t.data(), 4 * none_t.size(), hipMemcpyHostToDevice) ||
@@ -2784,6 +2820,92 @@ sim_member member_from_params(const sim_params *p, int64_t n, const double *pos,
 }
 
 int64_t slots_for(int64_t n) { return (int64_t)tiles_for(n) * kWave; }
+
+// ---------------------------------------------------------------------------
+// Field evaluation without allocation: every working array in a static
+// device buffer
+// ---------------------------------------------------------------------------
+
+// One buffer per GPU the library runs on, held until the process ends.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of this device's scratch (looked up once per device; the
+// array's name in host code is a host-side stand-in, not this address).
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SIM_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SIM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                         hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SIM_OK;
+}
+
+// The tables and control words a one-member handle would hold before its
+// first step, written by a kernel (the buffer keeps the previous call's
+// contents): the member's description, its control block, the tile and
+// chunk maps, the absorbed flags and the bucket histogram cleared, and the
+// drive value of the evaluated step.
+__global__ void k_static_setup(Seg sg, Ctl ct, Seg *seg, Ctl *ctl, uint32_t *tile_member,
+                               uint32_t *chunk_member, uint8_t *dead, uint32_t *hist,
+                               double *u_dev, double u_asy, int n_tiles, int n_chunks, int nb)
+{
+    const int stride = gridDim.x * blockDim.x;
+    const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int i = i0; i < n_tiles * kWave; i += stride) dead[i] = 0;
+    for (int i = i0; i < n_tiles; i += stride) tile_member[i] = 0;
+    for (int i = i0; i < n_chunks; i += stride) chunk_member[i] = 0;
+    for (int i = i0; i <= nb; i += stride) hist[i] = 0;
+    if (i0 == 0) {
+        seg[0] = sg;
+        ctl[0] = ct;
+        u_dev[0] = u_asy;
+    }
+}
+
+// Particle records from positions [3n] (particle-major), id = index.
+__global__ void k_static_pack(const double *pos, uint32_t n, PRec *A)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    PRec r;
+    r.x = pos[3 * (size_t)i];
+    r.y = pos[3 * (size_t)i + 1];
+    r.z = pos[3 * (size_t)i + 2];
+    r.vx = r.vy = r.vz = 0.0;
+    r.uid = i;
+    r.pad[0] = r.pad[1] = r.pad[2] = 0u;
+    A[i] = r;
+}
+
+// The field at sorted position p back to the particle's index (its id).
+__global__ void k_static_unpack(const double *Eout, const uint32_t *Eid, uint32_t n, double *E)
+{
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const size_t k = Eid[p];
+    E[3 * k] = Eout[3 * (size_t)p];
+    E[3 * k + 1] = Eout[3 * (size_t)p + 1];
+    E[3 * k + 2] = Eout[3 * (size_t)p + 2];
+}
 
 }  // namespace
 
@@ -3162,6 +3284,101 @@ int sim_member_eval_field(sim_t *h, int32_t index, double *E)
 }
 
 int sim_eval_field(sim_t *h, double *E) { return sim_member_eval_field(h, 0, E); }
+
+int64_t sim_eval_field_static_bytes(const sim_params *p, int64_t n)
+{
+    std::string why;
+    if (!check_common(p, &why)) return fail(SIM_EINVAL, why);
+    if (n <= 0 || n > 0x7fffffffLL) return fail(SIM_EINVAL, "n must be in [1, 2^31)");
+    return footprint(p, slots_for(n), 1, member_shape(n, tuning_of(p)).nc, member_bytes(1, 0));
+}
+
+int sim_eval_field_static(const sim_params *p, int64_t n, const double *pos, double q_surface,
+                          double u_asy, double *E, void *hip_stream)
+{
+    std::string why;
+    if (!check_common(p, &why)) return fail(SIM_EINVAL, why);
+    if (n <= 0 || n > 0x7fffffffLL) return fail(SIM_EINVAL, "n must be in [1, 2^31)");
+    if (!pos || !E) return fail(SIM_EINVAL, "pos and E are required");
+    if (!std::isfinite(q_surface) || !std::isfinite(u_asy))
+        return fail(SIM_EINVAL, "q_surface and u_asy must be finite");
+    sim_member m = member_from_params(p, n, nullptr, nullptr, nullptr, nullptr, 1, 0);
+    if (!check_member_scalars(&m, &why)) return fail(SIM_EINVAL, why);
+    const MemberShape sh = member_shape(n, tuning_of(p));
+    // the same layout as sim_create's for these particles
+    sim h;
+    if (!make_layout(p, slots_for(n), 1, sh.nc, &h.lo, &why)) return fail(SIM_EINVAL, why);
+    h.prm = *p;
+    Alloc al;
+    plan_alloc(&h, al, member_bytes(1, 0));
+    if (al.total() > kScratchBytes)
+        return fail(SIM_ENOMEM, "evaluation needs " + std::to_string(al.total()) +
+                                    " B of working memory, more than the static buffer's " +
+                                    std::to_string(kScratchBytes) + " B");
+    void *base = nullptr;
+    if (int rc = scratch_address(&base)) return rc;
+    carve(al, base);
+    HostTables ht;
+    if (int rc = make_host_tables(*p, h.lo, &ht)) return rc;
+    bind_device_tables(&h);
+    h.ext.n_tiles = (int)sh.nt;
+    h.ext.n_chunks = (int)sh.nc;
+    h.ext.nb = (int)sh.nb;
+    h.ext.nb_blocks = ((int)sh.nb + kScanPerBlock - 1) / kScanPerBlock;
+    h.ext.n_members = 1;
+    Seg sg{};
+    sg.p0 = 0;
+    sg.cap = sh.nt * kWave;
+    sg.t0 = 0;
+    sg.nt = sh.nt;
+    sg.c0 = 0;
+    sg.nc = sh.nc;
+    sg.cl = sh.cl;
+    sg.b0 = 0;
+    sg.nb = sh.nb;
+    sg.inv_vol = 1.0 / (p->r_out * p->r_out * p->r_out - 1.0);
+    sg.ntilde = p->ntilde;
+    sg.inv_ntilde = 1.0 / p->ntilde;
+    sg.ion_density = p->ion_density;
+    sg.q_surface0 = q_surface;
+    sg.dt = p->dt;
+    sg.r_out = p->r_out;
+    sg.seed = p->seed;
+    sg.probe_bc = p->probe_bc;
+    sg.wall_bc = p->wall_bc;
+    sg.n_steps = 1;
+    sg.u_asy = reinterpret_cast<double *>(h.mdata);
+    sg.qdiff = reinterpret_cast<double *>(h.mdata + kPoolUnit);
+    sg.used = 1;
+    Ctl ct{};
+    ct.step = 0;
+    ct.n_cur = (uint32_t)n;
+    ct.n_live = (uint32_t)n;
+    ct.q_surface = q_surface;
+    ct.keys_for = -1;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const unsigned gSet = (unsigned)std::min<int64_t>(((int64_t)sh.nt * kWave + kBlock - 1) / kBlock, 4096);
+    const unsigned gN = (unsigned)((n + kBlock - 1) / kBlock);
+    k_static_setup<<<gSet, kBlock, 0, s>>>(sg, ct, h.seg, h.ctl, h.tile_member, h.chunk_member,
+                                           h.dead, h.hist, const_cast<double *>(sg.u_asy), u_asy,
+                                           (int)sh.nt, (int)sh.nc, h.lo.nb);
+    k_static_pack<<<gN, kBlock, 0, s>>>(pos, (uint32_t)n, h.A);
+    HIP_TRY(hipMemcpyAsync(h.tables, ht.tab.data(), sizeof(double) * ht.tab.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h.chl, ht.chl.data(), sizeof(int) * ht.chl.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h.chn, ht.chn.data(), sizeof(double) * ht.chn.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h.tables32, ht.tab32.data(), sizeof(float) * ht.tab32.size(),
+                           hipMemcpyHostToDevice, s));
+    if (int rc = launch_step(&h, s, true, nullptr)) return rc;
+    k_static_unpack<<<gN, kBlock, 0, s>>>(h.Eout, h.Eid, (uint32_t)n, E);
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return fail(SIM_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
+    // the host tables above are the copies' sources: done before they go
+    HIP_TRY(hipStreamSynchronize(s));
+    return SIM_OK;
+}
 
 int sim_profile(sim_t *h, int64_t k, double *kernel_ms, int32_t n_kernels)
 {

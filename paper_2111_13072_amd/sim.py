@@ -28,7 +28,8 @@ EXPORTED = ("sim_params_default", "sim_create", "sim_step", "sim_sync", "sim_que
             "sim_strerror", "sim_last_error", "sim_member_default", "sim_batch_create",
             "sim_batch_footprint_bytes", "sim_batch_add", "sim_batch_remove", "sim_batch_step",
             "sim_member_info", "sim_member_read_response", "sim_member_read_state",
-            "sim_member_eval_field", "sim_member_data_bytes", "sim_member_counts")
+            "sim_member_eval_field", "sim_member_data_bytes", "sim_member_counts",
+            "sim_eval_field_static", "sim_eval_field_static_bytes")
 
 
 # sim_allocator callbacks: alloc(ctx, bytes, stream) -> device pointer or NULL;
@@ -185,11 +186,15 @@ def lib():
     L.sim_member_read_state.argtypes = [H, C.c_int32, dp, dp, C.POINTER(C.c_uint8), dp, i64p]
     L.sim_member_eval_field.argtypes = [H, C.c_int32, dp]
     L.sim_member_counts.argtypes = [H, C.c_int32, i64p, i64p, i64p]
+    L.sim_eval_field_static.argtypes = [P, C.c_int64, C.c_void_p, C.c_double, C.c_double,
+                                        C.c_void_p, C.c_void_p]
+    L.sim_eval_field_static_bytes.argtypes = [P, C.c_int64]
+    L.sim_eval_field_static_bytes.restype = C.c_int64
     for name in EXPORTED:
         if name not in ("sim_params_default", "sim_num_kernels", "sim_kernel_name",
                         "sim_footprint_bytes", "sim_destroy", "sim_strerror", "sim_last_error",
                         "sim_member_default", "sim_batch_footprint_bytes",
-                        "sim_member_data_bytes"):
+                        "sim_member_data_bytes", "sim_eval_field_static_bytes"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -367,6 +372,33 @@ class Sim:
         c = C.c_int32()
         _check(lib().sim_info(self._handle(), C.byref(n), C.byref(t), C.byref(c)))
         return dict(n=n.value, tile=t.value, channels=c.value)
+
+
+def eval_field_static(params: SimParams, pos, E, q_surface: float = 0.0, u_asy: float = 0.0,
+                      stream=None):
+    """sim_eval_field_static: the field at device-resident positions pos
+    (torch tensor [n, 3], float64, on the GPU) into E (same shape), with no
+    device allocation (the library's static buffer).  Synchronises."""
+    n = int(pos.shape[0])
+    if tuple(pos.shape) != (n, 3) or tuple(E.shape) != (n, 3):
+        raise ValueError("pos and E must have shape [n, 3]")
+    if not (pos.is_contiguous() and E.is_contiguous()):
+        raise ValueError("pos and E must be contiguous")
+    if str(pos.dtype) != "torch.float64" or str(E.dtype) != "torch.float64":
+        raise ValueError("pos and E must be float64")
+    if stream is None:
+        stream = _current_torch_stream()
+    p = params.to_c()
+    _check(lib().sim_eval_field_static(C.byref(p), n, C.c_void_p(pos.data_ptr()), q_surface,
+                                       u_asy, C.c_void_p(E.data_ptr()), stream))
+
+
+def eval_field_static_bytes(params: SimParams, n: int) -> int:
+    p = params.to_c()
+    v = lib().sim_eval_field_static_bytes(C.byref(p), n)
+    if v < 0:
+        _check(int(v))
+    return int(v)
 
 
 @dataclass
