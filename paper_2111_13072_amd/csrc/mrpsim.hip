@@ -1166,9 +1166,8 @@ __device__ inline void far_field(Stage &&stage, int L, const R4 *fq, double xd, 
 // other particle of the pair).  Pair terms in R, accumulated in FP64.
 template <bool FULL, typename R, typename NF>
 __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R *sxh, const R *syh,
-                                  const R *szh, const R *sr, const R *sir, const double *sr2,
-                                  const uint64_t *suid, const R *sq, R xh, R yh, R zh, R r,
-                                  R inv_r, double r2, uint32_t uid, R qk, double &ax, double &ay,
+                                  const R *szh, const R *sr, const R *sir, const R *sq, R xh,
+                                  R yh, R zh, R r, R inv_r, R qk, double &ax, double &ay,
                                   double &az)
 {
     const R inv_r2 = inv_r * inv_r;
@@ -1177,10 +1176,10 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
         const bool active = lane < jn && j < jn && (sft < kWave / 2 || lane < kWave / 2);
         const R xj = sxh[j], yj = syh[j], zj = szh[j];
         const R rj = sr[j], irj = sir[j];
-        const double r2j = sr2[j];
-        const uint32_t uj = (uint32_t)suid[j];
         const R qj = sq[j];
-        const bool k_outer = (r2 > r2j) || (r2 == r2j && uid > uj);
+        // a tile's lanes are in radial order (key (r^2, id)): the partner
+        // (lane + sft) mod 64 is the inner one when it wraps below this lane
+        const bool k_outer = lane + sft >= kWave;
         const R rho = k_outer ? rj * inv_r : r * irj;
         const R sc_out = k_outer ? inv_r2 : irj * irj;   // 1 / r_>^2
         const R sc_in = inv_r * irj;                     // 1 / (r_< r_>)
@@ -1258,8 +1257,9 @@ struct NearRows {
     R xh[2 * kWave], yh[2 * kWave], zh[2 * kWave], r[2 * kWave], ir[2 * kWave], q[2 * kWave];
     // FP32 only: r / rho_t - 1 against the tile's reference radius rho_t
     R s[sizeof(R) == 4 ? 2 * kWave : 1];
-    double r2[2 * kWave];
-    uint64_t uid[2 * kWave];   // 8 bytes like r2: one index scale for all rows
+    // not read: keeps the wave's LDS (shared with the far field's coefficient
+    // window) at the size the window thresholds were measured with
+    double spare[4 * kWave];
 };
 
 __device__ inline double bpermute(int addr, double v)
@@ -1288,8 +1288,8 @@ __device__ inline float bpermute(int addr, float v)
 // peeled); in FP32 a recurrence on P_l - P_{l-1} driven by 1 - u (lw table).
 template <typename R, typename LG>
 __device__ inline void near_field_full(int lane, int L, const LG *lg, const NearRows<R> &nr, R xh,
-                                       R yh, R zh, R r, R ir, R sk, R rho_t, double r2,
-                                       uint32_t uid, R qk, double &ax, double &ay, double &az)
+                                       R yh, R zh, R r, R ir, R sk, R rho_t, R qk, double &ax,
+                                       double &ay, double &az)
 {
     double dck = 0.0, dbx = 0.0, dby = 0.0, dbz = 0.0;
     R ck = 0, bx = 0, by = 0, bz = 0;
@@ -1309,10 +1309,10 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
         const int j = lane + sft;   // partner, in the doubled row
         const R xj = nr.xh[j], yj = nr.yh[j], zj = nr.zh[j];
         const R rj = nr.r[j], irj = nr.ir[j];
-        const double r2j = nr.r2[j];
-        const uint32_t uj = (uint32_t)nr.uid[j];
         const R qj = last && lane >= kWave / 2 ? (R)0 : nr.q[j];
-        const bool k_outer = (r2 > r2j) | ((r2 == r2j) & (uid > uj));
+        // a tile's lanes are in radial order (key (r^2, id)): the partner
+        // lane + sft (mod 64) is the inner one when it wraps below this lane
+        const bool k_outer = j >= kWave;
         const R irmx = k_outer ? ir : irj;   // 1 / r_>
         R u, S1, Sl, SB;
         if constexpr (sizeof(R) == 4) {
@@ -1564,8 +1564,6 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
         nr.ir[i] = (R)inv_r;
         nr.q[i] = valid ? (R)qk : (R)0;
         if constexpr (sizeof(R) == 4) nr.s[i] = (R)(r * inv_rho - 1.0);
-        nr.r2[i] = r2;
-        nr.uid[i] = uid;
     }
     wave_lds_sync();   // the rows are this wave's own
     {
@@ -1577,15 +1575,14 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
             if constexpr (std::is_same<R, float>::value) lg = tb.lw4_32;
             else lg = tb.lg4;
             near_field_full<R, NF>(lane, L, lg, nr, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r,
-                                   (R)(r * inv_rho - 1.0), (R)rho, r2, uid,
-                                   valid ? (R)qk : (R)0, ax, ay, az);
+                                   (R)(r * inv_rho - 1.0), (R)rho, valid ? (R)qk : (R)0, ax,
+                                   ay, az);
         } else {
             const NF *nf;
             if constexpr (std::is_same<R, float>::value) nf = tb.nf4_32;
             else nf = tb.nf4;
-            near_field<FULL, R, NF>(lane, jn, L, nf, nr.xh, nr.yh, nr.zh, nr.r, nr.ir, nr.r2,
-                                    nr.uid, nr.q, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, r2, uid,
-                                    (R)qk, ax, ay, az);
+            near_field<FULL, R, NF>(lane, jn, L, nf, nr.xh, nr.yh, nr.zh, nr.r, nr.ir, nr.q,
+                                    (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, (R)qk, ax, ay, az);
         }
         const double cn = -1.0 / (4.0 * kPi * ntilde);
         Ex += cn * ax;
