@@ -452,19 +452,28 @@ def bench_batch(args):
 
 def bench_serve(args):
     """Continuous batching of Poisson arrivals (N log-uniform in [1e4, 4e6],
-    l_max in {8, 16, 32}, 200-2000 steps, T_e 1-5 eV, n_e 1e14-1e16) at 80%
-    offered load: latency percentiles from arrival to completion, and the
-    aggregate particle-steps/s over the whole service."""
+    l_max in {8, 16, 32}, 2e3-2e4 steps, T_e 1-5 eV, n_e 1e14-1e16) at 80%
+    offered device load, with resident pools holding 80% of the GPU's HBM:
+    latency percentiles from arrival to completion, and the aggregate
+    particle-steps/s over the whole service."""
     from paper_2111_13072_amd import serve as SV
     from paper_2111_13072_amd import sim as S
 
+    import torch
+
     fp32 = args.precision == "fp32c"
-    reqs = SV.request_stream(seed=5, duration_s=args.serve_seconds, load=0.8)
-    print(f"[bench] serving {len(reqs)} requests over {args.serve_seconds:.0f} s, budget "
-          f"{args.serve_budget_gib:g} GiB", file=sys.stderr, flush=True)
-    srv = SV.Server(int(args.serve_budget_gib * 2**30),
-                    precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64, tick_steps=50,
-                    small_max=args.serve_small_max)
+    steps_range = tuple(int(float(v)) for v in args.serve_steps.split(","))
+    reqs = SV.request_stream(seed=5, duration_s=args.serve_seconds, load=0.8,
+                             steps_range=steps_range)
+    free_b, total_b = torch.cuda.mem_get_info()
+    budget = (int(args.serve_budget_gib * 2**30) if args.serve_budget_gib > 0
+              else int(args.serve_hbm_fraction * total_b))
+    print(f"[bench] serving {len(reqs)} requests over {args.serve_seconds:.0f} s, steps "
+          f"{steps_range}, pools of {budget / 2**30:.1f} GiB ({budget / total_b:.0%} of "
+          f"{total_b / 2**30:.0f} GiB HBM)", file=sys.stderr, flush=True)
+    srv = SV.Server(budget, precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64, tick_steps=50,
+                    small_max=args.serve_small_max, max_steps=steps_range[1])
+    held = torch.cuda.memory_reserved()
     t0 = time.perf_counter()
     try:
         done = srv.run(reqs, log=lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True))
@@ -472,6 +481,8 @@ def bench_serve(args):
         srv.close()
     wall = time.perf_counter() - t0
     work = sum(d.n * d.n_steps for d in done)
+    # time-averaged fraction of the pools' particle slots holding a request
+    occupancy = sum(d.n * (d.finished - d.admitted) for d in done) / (wall * sum(srv.slots.values()))
     lat = SV.latency_summary(done)
     isolated = _isolated_fp64(done, reqs, args)
     line = {"metric": METRIC, "value": work / wall, "unit": "particle-steps/s", "n_gpus": 1,
@@ -480,11 +491,14 @@ def bench_serve(args):
             "data": "synthetic",
             "config": {"workload": "served-poisson", "requests": len(reqs),
                        "arrival_window_s": args.serve_seconds, "offered_load": 0.8,
-                       "l_max": [8, 16, 32], "n_range": [1e4, 4e6], "steps_range": [200, 2000],
-                       "budget_gib": args.serve_budget_gib, "tick_steps": 50,
+                       "l_max": [8, 16, 32], "n_range": [1e4, 4e6],
+                       "steps_range": list(steps_range),
+                       "pools_gib": budget / 2**30, "hbm_gib": total_b / 2**30,
+                       "pools_fraction_of_hbm": held / total_b, "tick_steps": 50,
                        "small_max": args.serve_small_max,
                        "precision": args.precision, "parallelism": "single-gpu"},
             "latency_s": lat, "rejected": len(srv.rejected), "wall_s": wall,
+            "slot_occupancy": occupancy,
             "isolated_fp64": isolated}
     print(json.dumps(line), flush=True)
     return 0
@@ -580,7 +594,11 @@ def main(argv=None):
                          "2e6, l_max 16; small: 1e4, l_max 8")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="serve: length of the Poisson arrival window")
-    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=0.0,
+                    help="serve: device memory of the pools (0: --serve-hbm-fraction of HBM)")
+    ap.add_argument("--serve-hbm-fraction", type=float, default=0.8)
+    ap.add_argument("--serve-steps", default="2000,20000",
+                    help="serve: range of the requests' step counts")
     ap.add_argument("--serve-small-max", type=int, default=200000,
                     help="serve: requests of at most this many particles get pools of their own "
                          "(0: one pool per l_max)")

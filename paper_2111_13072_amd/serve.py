@@ -59,7 +59,7 @@ def gpu_seconds_estimate(n: int, l_max: int, n_steps: int,
 
 
 def request_stream(seed: int = 5, duration_s: float = 60.0, load: float = 0.8,
-                   n_range=(1e4, 4e6), l_choices=(8, 16, 32), steps_range=(200, 2000)) -> list:
+                   n_range=(1e4, 4e6), l_choices=(8, 16, 32), steps_range=(2000, 20000)) -> list:
     """Poisson arrivals over duration_s.  N is log-uniform in n_range, l_max
     uniform over l_choices, steps uniform in steps_range, T_e ~ U(1, 5) eV,
     log10 n_e ~ U(14, 16).  The rate is set so that the offered device work
