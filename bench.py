@@ -471,7 +471,8 @@ def bench_serve(args):
     print(f"[bench] serving {len(reqs)} requests over {args.serve_seconds:.0f} s, steps "
           f"{steps_range}, pools of {budget / 2**30:.1f} GiB ({budget / total_b:.0%} of "
           f"{total_b / 2**30:.0f} GiB HBM)", file=sys.stderr, flush=True)
-    srv = SV.Server(budget, precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64, tick_steps=50,
+    srv = SV.Server(budget, precision=S.SIM_FP32_COMP if fp32 else S.SIM_FP64,
+                    tick_steps=args.serve_tick_steps, tick_seconds=args.serve_tick_seconds,
                     small_max=args.serve_small_max, max_steps=steps_range[1])
     held = torch.cuda.memory_reserved()
     t0 = time.perf_counter()
@@ -494,7 +495,9 @@ def bench_serve(args):
                        "l_max": [8, 16, 32], "n_range": [1e4, 4e6],
                        "steps_range": list(steps_range),
                        "pools_gib": budget / 2**30, "hbm_gib": total_b / 2**30,
-                       "pools_fraction_of_hbm": held / total_b, "tick_steps": 50,
+                       "pools_fraction_of_hbm": held / total_b,
+                       "tick_steps": args.serve_tick_steps,
+                       "tick_seconds": args.serve_tick_seconds,
                        "small_max": args.serve_small_max,
                        "precision": args.precision, "parallelism": "single-gpu"},
             "latency_s": lat, "rejected": len(srv.rejected), "wall_s": wall,
@@ -597,6 +600,10 @@ def main(argv=None):
     ap.add_argument("--serve-budget-gib", type=float, default=0.0,
                     help="serve: device memory of the pools (0: --serve-hbm-fraction of HBM)")
     ap.add_argument("--serve-hbm-fraction", type=float, default=0.8)
+    ap.add_argument("--serve-tick-steps", type=int, default=500,
+                    help="serve: most steps per tick of a pool")
+    ap.add_argument("--serve-tick-seconds", type=float, default=0.025,
+                    help="serve: a pool's tick is about this long (0: always --serve-tick-steps)")
     ap.add_argument("--serve-steps", default="2000,20000",
                     help="serve: range of the requests' step counts")
     ap.add_argument("--serve-small-max", type=int, default=200000,

@@ -106,11 +106,13 @@ class Done:
 @dataclass
 class Pool:
     """One resident batch: the requests it runs (member index -> [request,
-    admission time, steps done]) and whether a tick is in flight."""
+    admission time, steps done]), whether a tick is in flight and how many
+    steps it has."""
     key: tuple                      # (l_max, size class)
     batch: S.Batch
     running: dict = field(default_factory=dict)
     busy: bool = False
+    tick: int = 0
 
 
 class Server:
@@ -125,8 +127,15 @@ class Server:
 
     def __init__(self, budget_bytes: int, l_classes=(8, 16, 32), precision: int = S.SIM_FP64,
                  tick_steps: int = 50, max_members: int = 256, small_max: int = 0,
-                 small_share: float = 0.25, max_steps: int = 20000, allocator="torch"):
+                 small_share: float = 0.25, max_steps: int = 20000, allocator="torch",
+                 tick_seconds: float = 0.0):
+        """tick_steps: steps per tick; with tick_seconds > 0 a pool's tick is
+        instead as many steps as take about tick_seconds at the estimated cost
+        of a step of its members (at most tick_steps), so that a pool of large
+        requests does not hold the device queue it may share with a small
+        pool for long."""
         self.tick = tick_steps
+        self.tick_seconds = tick_seconds
         self.small_max = small_max
         self.pools = {}
         self.slots = {}   # particle slots of each pool
@@ -182,12 +191,21 @@ class Server:
         pool.running[idx] = [req, now, 0]
         return True
 
+    def tick_for(self, pool: Pool) -> int:
+        """Steps of the pool's next tick."""
+        if self.tick_seconds <= 0 or not pool.running:
+            return self.tick
+        L = pool.key[0]
+        n = sum(rec[0].n for rec in pool.running.values())
+        step_s = gpu_seconds_estimate(n, L, 1) + 1e-4   # plus ~10 launches
+        return int(max(1, min(self.tick, round(self.tick_seconds / step_s))))
+
     def _retire(self, pool: Pool, now, done, log):
         """After a tick: the members whose step count reached their length
         (counted on the host, confirmed by the library) answer and leave."""
         for idx, rec in list(pool.running.items()):
             r, adm, steps = rec
-            rec[2] = steps = min(steps + self.tick, r.n_steps)
+            rec[2] = steps = min(steps + pool.tick, r.n_steps)
             if steps < r.n_steps:
                 continue
             info = pool.batch.info(idx)
@@ -237,7 +255,8 @@ class Server:
                         wq.popleft()
                         progressed = True
                     if pool.running:
-                        pool.batch.step(self.tick)
+                        pool.tick = self.tick_for(pool)
+                        pool.batch.step(pool.tick)
                         pool.busy = True
                         progressed = True
                 if not progressed:

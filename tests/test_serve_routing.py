@@ -44,3 +44,17 @@ def test_one_pool_per_class_without_a_split():
 def test_unknown_l_max_is_refused():
     with pytest.raises(ValueError):
         _shell(1500).pool_key(_req(100, L=6))
+
+
+def test_time_bounded_ticks_shrink_for_large_pools():
+    """With tick_seconds, a pool of large requests ticks in fewer steps than a
+    pool of small ones (each tick ~tick_seconds at the estimated step cost),
+    within [1, tick_steps]."""
+    srv = _shell(0)
+    srv.tick, srv.tick_seconds = 500, 0.025
+    small = SV.Pool((8, 0), None, running={0: [_req(20_000, L=8), 0.0, 0]})
+    large = SV.Pool((8, 0), None, running={0: [_req(4_000_000, L=8), 0.0, 0]})
+    assert srv.tick_for(small) == 500 or srv.tick_for(small) > 100
+    assert 1 <= srv.tick_for(large) < 100
+    srv.tick_seconds = 0.0
+    assert srv.tick_for(large) == 500
