@@ -40,6 +40,7 @@
 #include <string.h>
 
 #define ORC_PI 3.14159265358979323846
+#define ORC_PIL 3.14159265358979323846264338327950288L
 
 /* Electrons: charge -1 (units of e), mass 1 (units of m_e), Sec. 4.  A
  * particle whose id has bit 31 set is an ion: charge +1, mass ion_mass. */
@@ -136,23 +137,30 @@ static double key_r2(const double *x)
     return (xx + yy) + zz;
 }
 
+/* |x| in long double; the radial order still comes from the double key. */
+static long double norm_ld(const double *x)
+{
+    long double a = x[0], b = x[1], c = x[2];
+    return sqrtl(a * a + b * b + c * c);
+}
+
 static int key_less(double r2a, uint32_t ida, double r2b, uint32_t idb)
 {
     return (r2a < r2b) || (r2a == r2b && ida < idb);
 }
 
 /* P_l(u) and P'_l(u) for l = 0..L (Bonnet recurrence and its derivative). */
-static void legendre(double u, int L, double *P, double *dP)
+static void legendre(long double u, int L, long double *P, long double *dP)
 {
-    P[0] = 1.0;
-    dP[0] = 0.0;
+    P[0] = 1.0L;
+    dP[0] = 0.0L;
     if (L >= 1) {
         P[1] = u;
-        dP[1] = 1.0;
+        dP[1] = 1.0L;
     }
     for (int l = 1; l < L; ++l) {
-        P[l + 1] = ((2.0 * l + 1.0) * u * P[l] - l * P[l - 1]) / (l + 1.0);
-        dP[l + 1] = dP[l - 1] + (2.0 * l + 1.0) * P[l];
+        P[l + 1] = ((2.0L * l + 1.0L) * u * P[l] - l * P[l - 1]) / (l + 1.0L);
+        dP[l + 1] = dP[l - 1] + (2.0L * l + 1.0L) * P[l];
     }
 }
 
@@ -167,45 +175,52 @@ static void legendre(double u, int L, double *P, double *dP)
  * the two is r_> (it matters only for the gradient at an exact radius tie).
  * f[] are the image coefficients (f[0] unused: the l = 0 image cancels
  * against the floating-potential term Psi_sym(r) / (4 pi r'), Sec. 3).
+ *
+ * Every step runs in long double.  With the super-particle weight of Sec. 4
+ * the field a particle feels is what is left after the pair sum and the ion
+ * background cancel, and that remainder falls as N^-1/2 while the rounding
+ * of each pair term does not; near-coincident pairs (r_x ~ r_y, xhat.yhat
+ * ~ 1) carry the largest terms and the largest recurrence error, and in
+ * double their rounding reaches 1e-12 of the RMS field at 1.6e7 particles.
  */
 static void greens(const orc_params *p, const double *f, const double *x, const double *y,
-                   int x_outer, double *G, double *grad)
+                   int x_outer, long double *G, long double *grad)
 {
     int L = p->l_max;
-    double rx = sqrt(key_r2(x));
-    double ry = sqrt(key_r2(y));
-    double xh[3] = {x[0] / rx, x[1] / rx, x[2] / rx};
-    double yh[3] = {y[0] / ry, y[1] / ry, y[2] / ry};
-    double P[ORC_LMAX_CAP + 1], dP[ORC_LMAX_CAP + 1];
-    double Py[ORC_LMAX_CAP + 1], dPy[ORC_LMAX_CAP + 1];
-    double gu[3];     /* gradient in x of the angular argument */
+    long double rx = norm_ld(x);
+    long double ry = norm_ld(y);
+    long double xh[3] = {x[0] / rx, x[1] / rx, x[2] / rx};
+    long double yh[3] = {y[0] / ry, y[1] / ry, y[2] / ry};
+    long double P[ORC_LMAX_CAP + 1], dP[ORC_LMAX_CAP + 1];
+    long double Py[ORC_LMAX_CAP + 1], dPy[ORC_LMAX_CAP + 1];
+    long double gu[3];     /* gradient in x of the angular argument */
     int axisym = (p->m_mode == ORC_M_AXISYM);
 
     if (!axisym) {
-        double u = xh[0] * yh[0] + xh[1] * yh[1] + xh[2] * yh[2];
+        long double u = xh[0] * yh[0] + xh[1] * yh[1] + xh[2] * yh[2];
         legendre(u, L, P, dP);
         for (int j = 0; j < 3; ++j) gu[j] = (yh[j] - u * xh[j]) / rx;
     } else {
-        double cx = xh[2], cy = yh[2];
+        long double cx = xh[2], cy = yh[2];
         legendre(cx, L, P, dP);
         legendre(cy, L, Py, dPy);
-        for (int j = 0; j < 3; ++j) gu[j] = ((j == 2 ? 1.0 : 0.0) - cx * xh[j]) / rx;
+        for (int j = 0; j < 3; ++j) gu[j] = ((j == 2 ? 1.0L : 0.0L) - cx * xh[j]) / rx;
     }
 
     /* Radial factors by running products:
      *   x outer: r_<^l / r_>^(l+1) = rho^l / r_x,  d/dr_x = -(l+1) rho^l / r_x^2, rho = r_y/r_x
      *   x inner: r_<^l / r_>^(l+1) = rho^l / r_y,  d/dr_x = l rho^(l-1) / r_y^2,  rho = r_x/r_y
      *   image:   -f_l w^(l+1),  d/dr_x = (l+1) f_l w^(l+1) / r_x,               w = 1/(r_x r_y) */
-    double rho = x_outer ? ry / rx : rx / ry;
-    double w = 1.0 / (rx * ry);
-    double rho_l = 1.0;      /* rho^l */
-    double rho_lm1 = 0.0;    /* rho^(l-1), zero for l = 0 */
-    double w_l1 = w;         /* w^(l+1) */
-    double g = 0.0;
-    double gr = 0.0;   /* coefficient of xhat */
-    double ga = 0.0;   /* coefficient of gu */
+    long double rho = x_outer ? ry / rx : rx / ry;
+    long double w = 1.0L / (rx * ry);
+    long double rho_l = 1.0L;      /* rho^l */
+    long double rho_lm1 = 0.0L;    /* rho^(l-1), zero for l = 0 */
+    long double w_l1 = w;          /* w^(l+1) */
+    long double g = 0.0L;
+    long double gr = 0.0L;   /* coefficient of xhat */
+    long double ga = 0.0L;   /* coefficient of gu */
     for (int l = 0; l <= L; ++l) {
-        double ang, dang;
+        long double ang, dang;
         if (!axisym) {
             ang = P[l];
             dang = dP[l];
@@ -213,18 +228,18 @@ static void greens(const orc_params *p, const double *f, const double *x, const 
             ang = P[l] * Py[l];
             dang = dP[l] * Py[l];
         }
-        double dir, ddir;  /* direct term r_<^l / r_>^(l+1): value and d/d r_x */
+        long double dir, ddir;  /* direct term r_<^l / r_>^(l+1): value and d/d r_x */
         if (x_outer) {
             dir = rho_l / rx;
-            ddir = -(l + 1.0) * rho_l / (rx * rx);
+            ddir = -(l + 1.0L) * rho_l / (rx * rx);
         } else {
             dir = rho_l / ry;
             ddir = l * rho_lm1 / (ry * ry);
         }
-        double img = 0.0, dimg = 0.0;
+        long double img = 0.0L, dimg = 0.0L;
         if (l >= 1) {
             img = -f[l] * w_l1;
-            dimg = (l + 1.0) * f[l] * w_l1 / rx;
+            dimg = (l + 1.0L) * f[l] * w_l1 / rx;
         }
         g += (dir + img) * ang;
         gr += (ddir + dimg) * ang;
@@ -233,8 +248,9 @@ static void greens(const orc_params *p, const double *f, const double *x, const 
         rho_l *= rho;
         w_l1 *= w;
     }
-    *G = g / (4.0 * ORC_PI);
-    for (int j = 0; j < 3; ++j) grad[j] = (gr * xh[j] + ga * gu[j]) / (4.0 * ORC_PI);
+    const long double four_pi = 4.0L * ORC_PIL;
+    *G = g / four_pi;
+    for (int j = 0; j < 3; ++j) grad[j] = (gr * xh[j] + ga * gu[j]) / four_pi;
 }
 
 /* Psi_anti,L and its gradient: sum over odd l <= L of c_l b^P_l r^-(l+1)
@@ -246,8 +262,13 @@ static void psi_anti(const orc_params *p, const double *bP, const double *c, con
     double r = sqrt(key_r2(x));
     double xh[3] = {x[0] / r, x[1] / r, x[2] / r};
     double ct = xh[2];
+    long double Pl[ORC_LMAX_CAP + 1], dPl[ORC_LMAX_CAP + 1];
     double P[ORC_LMAX_CAP + 1], dP[ORC_LMAX_CAP + 1];
-    legendre(ct, L, P, dP);
+    legendre(ct, L, Pl, dPl);
+    for (int l = 0; l <= L; ++l) {
+        P[l] = (double)Pl[l];
+        dP[l] = (double)dPl[l];
+    }
     double s = 0.0, sr = 0.0, sa = 0.0;
     for (int l = 1; l <= L; l += 2) {
         double w = c[l] * bP[l];
@@ -321,7 +342,10 @@ int orc_greens(const orc_params *p, const double *x, const double *y, int x_oute
     if (p->l_max < 0 || p->l_max > ORC_LMAX_CAP) return -1;
     double f[ORC_LMAX_CAP + 1], bP[ORC_LMAX_CAP + 1], c[ORC_LMAX_CAP + 1];
     orc_coeffs(p->eps_r, p->d, p->l_max, f, bP, c);
-    greens(p, f, x, y, x_outer, G, grad);
+    long double Gl, gl[3];
+    greens(p, f, x, y, x_outer, &Gl, gl);
+    *G = (double)Gl;
+    for (int j = 0; j < 3; ++j) grad[j] = (double)gl[j];
     return 0;
 }
 
@@ -377,21 +401,26 @@ int orc_field(const orc_params *p, int64_t n, const double *pos, const uint32_t 
             if (alive && !alive[i]) continue;
             const double *xi = pos + 3 * i;
             int k_outer = key_less(key_r2(xi), ids[i], r2k, ids[k]);
-            double G, g[3];
+            long double G, g[3];
             greens(p, f, xk, xi, k_outer, &G, g);
             const double qi = charge_of(ids[i]);
             phi += qi * G;
             for (int j = 0; j < 3; ++j) gsum[j] += qi * g[j];
         }
         double rk = sqrt(r2k);
-        double xh[3] = {xk[0] / rk, xk[1] / rk, xk[2] / rk};
+        long double rkl = norm_ld(xk);
+        long double xh[3] = {xk[0] / rkl, xk[1] / rkl, xk[2] / rkl};
         double psi, gpsi[3];
         psi_anti(p, bP, c, xk, &psi, gpsi);
-        double e_surf = inv_nt * q_surface / (4.0 * ORC_PI * rk * rk);
-        double e_ion = eion_r(p, rk);
+        /* Radial field of the surface charge and of the ions, also in long
+         * double: it cancels the l = 0 part of the pair sum. */
+        long double e_rad = (long double)q_surface / (p->ntilde * 4.0L * ORC_PIL * rkl * rkl);
+        if (p->ion_prof)
+            e_rad += (long double)eion_r(p, rk);
+        else
+            e_rad += p->ion_density * (rkl * rkl * rkl - 1.0L) / (3.0L * rkl * rkl);
         for (int j = 0; j < 3; ++j)
-            E[j] = (double)(-(long double)inv_nt * gsum[j] +
-                            (long double)((e_surf + e_ion) * xh[j]) -
+            E[j] = (double)(-gsum[j] / p->ntilde + e_rad * xh[j] -
                             (long double)(u_asy * gpsi[j]));
         if (phi_out)
             phi_out[t] = (double)((long double)inv_nt * phi +
