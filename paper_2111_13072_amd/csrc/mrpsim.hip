@@ -777,6 +777,23 @@ __device__ inline bool chunk_tiles(const Map &mp, const KParams &kp, int j, uint
     return true;
 }
 
+// A running FP64 sum that carries its own rounding error (Knuth's
+// error-free TwoSum): the sum of n terms is good to about one rounding of
+// the result instead of ~sqrt(n) of them.  The carries sum the tile sums of
+// up to ~2.5e5 tiles per member; these kernels are bound by HBM, so the
+// extra operations cost no time.
+struct CompSum {
+    double s = 0.0, e = 0.0;
+    __device__ void add(double v)
+    {
+        const double t = s + v;
+        const double z = t - s;
+        e += (s - (t - z)) + (v - z);
+        s = t;
+    }
+    __device__ double value() const { return s + e; }
+};
+
 // The tile loops of the carry kernels issue the loads of kCarryBatch tiles
 // before using them (a chunk is 8-64 tiles, or the tuned length, walked by one thread, and one
 // HBM round trip per tile would dominate); the sums keep the tile order.
@@ -794,17 +811,17 @@ __global__ __launch_bounds__(kBlock) void k_chunk_sums(Map mp, const double *__r
     const size_t sw = (size_t)kp.SW;
     const double *src = S + (size_t)t0 * sw + c;
     const int nt = t1 - t0;
-    double s = 0.0;
+    CompSum s;
     int t = 0;
     for (; t + kCarryBatch <= nt; t += kCarryBatch) {
         double v[kCarryBatch];
 #pragma unroll
         for (int k = 0; k < kCarryBatch; ++k) v[k] = src[(size_t)(t + k) * sw];
 #pragma unroll
-        for (int k = 0; k < kCarryBatch; ++k) s += v[k];
+        for (int k = 0; k < kCarryBatch; ++k) s.add(v[k]);
     }
-    for (; t < nt; ++t) s += src[(size_t)t * sw];
-    chunkS[(size_t)j * kp.SW + c] = s;
+    for (; t < nt; ++t) s.add(src[(size_t)t * sw]);
+    chunkS[(size_t)j * kp.SW + c] = s.value();
 }
 
 // Per member (blockIdx.y) and channel (one wave each): exclusive prefix of the
@@ -828,22 +845,28 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(Map mp, const double *chu
     const int per = (nc + kWave - 1) / kWave;
     const int q0 = lane * per, q1 = min(q0 + per, nc);   // this lane's run in scan order
     auto chunk = [&](int q) { return interior ? q : nc - 1 - q; };
-    double part = 0.0;
-    for (int q = q0; q < q1; ++q) part += cS[(size_t)chunk(q) * kp.SW];
-    double incl = part;
+    CompSum part;
+    for (int q = q0; q < q1; ++q) part.add(cS[(size_t)chunk(q) * kp.SW]);
+    // inclusive scan of the runs' compensated sums (value and error term)
+    CompSum incl = part;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
-        const double t = __shfl_up(incl, o);
-        if (lane >= o) incl += t;
+        const double ts = __shfl_up(incl.s, o), te = __shfl_up(incl.e, o);
+        if (lane >= o) {
+            incl.add(ts);
+            incl.e += te;
+        }
     }
-    double run = __shfl_up(incl, 1);
-    if (lane == 0) run = 0.0;
+    CompSum run;
+    run.s = __shfl_up(incl.s, 1);
+    run.e = __shfl_up(incl.e, 1);
+    if (lane == 0) run = CompSum();
     for (int q = q0; q < q1; ++q) {
         const size_t at = (size_t)chunk(q) * kp.SW;
-        cC[at] = run;
-        run += cS[at];
+        cC[at] = run.value();
+        run.add(cS[at]);
     }
-    if (!interior && lane == kWave - 1) T[(size_t)s * kp.C + (c - kp.C)] = incl;
+    if (!interior && lane == kWave - 1) T[(size_t)s * kp.C + (c - kp.C)] = incl.value();
 }
 
 // Per-tile coefficients of the field kernel.  Interior coefficient of tile
@@ -881,10 +904,11 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *__
     if (c >= kp.SW) return;
     const double inv_nt = sg.inv_ntilde;
     const size_t sw = (size_t)kp.SW;
-    double run = chunkC[(size_t)j * kp.SW + c];
+    CompSum run;
+    run.s = chunkC[(size_t)j * kp.SW + c];
     // Walks the chunk's tiles in scan order (dir +1 from t0, -1 from t1 - 1),
     // calling f(t, carry before t) with the loads of kCarryBatch tiles issued
-    // ahead; the carry accumulates in tile order.
+    // ahead; the carry accumulates in tile order, compensated.
     auto walk = [&](int dir, auto f) {
         const int nt = t1 - t0;
         const int first = dir > 0 ? t0 : t1 - 1;
@@ -895,14 +919,14 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *__
             for (int k = 0; k < kCarryBatch; ++k) v[k] = S[(size_t)(first + dir * (i + k)) * sw + c];
 #pragma unroll
             for (int k = 0; k < kCarryBatch; ++k) {
-                f(first + dir * (i + k), run);
-                run += v[k];
+                f(first + dir * (i + k), run.value());
+                run.add(v[k]);
             }
         }
         for (; i < nt; ++i) {
             const int t = first + dir * i;
-            f(t, run);
-            run += S[(size_t)t * sw + c];
+            f(t, run.value());
+            run.add(S[(size_t)t * sw + c]);
         }
     };
     if (c == kp.C2) {   // charge of the member's particles before each tile
@@ -991,6 +1015,79 @@ struct Grave {
     double *x, *y, *z, *vx, *vy, *vz;
     uint32_t *uid;
 };
+
+// Double-double values (hi + lo, |lo| <= ulp(hi) / 2) for the l = 0 field,
+// where two fields of ~N^(1/2) times the result cancel: error-free products
+// through the FMA and error-free sums (Knuth's TwoSum).
+struct DD {
+    double hi, lo;
+};
+
+__device__ inline DD dd_from_sum(double a, double b)
+{
+    const double s = a + b;
+    const double z = s - a;
+    return DD{s, (a - (s - z)) + (b - z)};
+}
+
+__device__ inline DD dd_add(DD a, DD b)
+{
+    const DD s = dd_from_sum(a.hi, b.hi);
+    return dd_from_sum(s.hi, s.lo + (a.lo + b.lo));
+}
+
+__device__ inline DD dd_mul(DD a, double b)
+{
+    const double p = a.hi * b;
+    const double e = fma(a.hi, b, -p);
+    return dd_from_sum(p, fma(a.lo, b, e));
+}
+
+__device__ inline DD dd_div(DD a, DD b)
+{
+    const double q = a.hi / b.hi;
+    // remainder a - q b, its leading part exact through the FMA
+    const double r = (fma(-q, b.hi, a.hi) + a.lo) - q * b.lo;
+    return dd_from_sum(q, r / b.hi);
+}
+
+__device__ inline DD dd_mul_dd(DD a, DD b)
+{
+    const double p = a.hi * b.hi;
+    const double e = fma(a.hi, b.hi, -p);
+    return dd_from_sum(p, e + (a.hi * b.lo + a.lo * b.hi));
+}
+
+// x*x + y*y + z*z in double-double: error-free squares, compensated sums.
+__device__ inline DD dd_norm2(double x, double y, double z)
+{
+    const double xx = x * x, yy = y * y, zz = z * z;
+    DD s = dd_add(DD{xx, fma(x, x, -xx)}, DD{yy, fma(y, y, -yy)});
+    return dd_add(s, DD{zz, fma(z, z, -zz)});
+}
+
+// The l = 0 field (radial component) of the charge enclosed by radius r:
+// the surface charge and the particles below, `charge` (exact), and the
+// uniform ion background n_i: charge / (4 pi ntilde r^2) + n_i (r^3 - 1) / (3 r^2),
+// formed in double-double from the position itself and rounded once.  The
+// two terms are ~N^(1/2) times their sum at N particles, and taking r from
+// the rounded radial key shifts both the same way for every particle near
+// that radius: a few 1e-13 of the RMS field at 1.6e7 particles.
+__device__ inline double gauss_field_uniform(double charge, double ntilde, double ion_density,
+                                             double x, double y, double z)
+{
+    const DD r2 = dd_norm2(x, y, z);
+    // r = sqrt(r2) to double-double: one Newton correction of the FP64 root
+    const double rh = sqrt(r2.hi);
+    const DD r{rh, (fma(-rh, rh, r2.hi) + r2.lo) / (2.0 * rh)};
+    const DD r3 = dd_mul_dd(r, r2);
+    const DD num2 = dd_mul(dd_add(r3, DD{-1.0, 0.0}), ion_density);
+    const DD den2 = dd_mul(r2, 3.0);
+    const DD four_pi{4.0 * 3.141592653589793116, 4.0 * 1.2246467991473532e-16};
+    const DD den1 = dd_mul_dd(dd_mul(r2, ntilde), four_pi);
+    const DD f = dd_add(dd_div(DD{charge, 0.0}, den1), dd_div(num2, den2));
+    return f.hi + f.lo;
+}
 
 // Far field of all other tiles through this tile's coefficient vector
 // (interior alpha then exterior beta, stream order), evaluated at scaled
@@ -1634,9 +1731,9 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     // radial order (those of earlier tiles, carried by the scan, and the
     // lanes below in this tile), exact counts in super-particle units, and
     // the immobile ion background.  The particles' and the uniform
-    // background's fields nearly cancel (to ~N^-1/2 of each), so each is
-    // formed at its own magnitude and only the two fields are added; a
-    // profile's enclosed charge is tabulated and joins the count. ----
+    // background's fields nearly cancel (to ~N^-1/2 of each), so they are
+    // formed and added in double-double; a profile's enclosed charge is
+    // tabulated and joins the count. ----
     {
         const uint64_t below = (1ull << lane) - 1ull;
         const int n_below = __popcll(__ballot(valid) & below);
@@ -1646,8 +1743,7 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
         if (sg.ion_tab) {
             e = ((ct.q_surface + before) + ion_enclosed(sg, r, r2)) / (4.0 * kPi * ntilde * r2);
         } else {
-            e = (ct.q_surface + before) / (4.0 * kPi * ntilde * r2) +
-                sg.ion_density * (r2 * r - 1.0) / (3.0 * r2);
+            e = gauss_field_uniform(ct.q_surface + before, ntilde, sg.ion_density, x, y, z);
         }
         Ex += e * xh;
         Ey += e * yh;
