@@ -120,3 +120,23 @@ def test_impulse_trajectory_matches_stored_oracle_run():
         dev = np.abs(got - want)
         _say(f"[gpu]   max deviation {dev.max():.3e} (bound at the end {bound[-1]:.3e})")
         assert np.all(dev <= bound)
+
+
+def test_experiment_pipeline_runs_end_to_end_small():
+    """The paper's experiment (App. D equilibrium, driven run and undriven
+    twin, damped-sine fit, admittance of the fit, Drude match, K) at a tenth
+    of its particles and 1500 steps: every stage produces finite, physical
+    numbers (a damped resonance below omega_pe, a positive sheath and
+    collision rate).  Parity of K with the paper's printed value is unpinned
+    (its setup leaves eps_r and the Q_diff normalisation open)."""
+    from paper_2111_13072_amd import experiments as X
+
+    _say("[gpu] experiment pipeline: T_e 3 eV, n 1e5, 1500 steps, l_max 1")
+    res, t, diff = X.probe_response(3.0, steps=1500, n=100_000, fit_window=15.0)
+    _say(f"[gpu]   c={res.fit_frequency:.3f} b={res.fit_damping:.3f} delta={res.sheath:.3f} "
+         f"nu={res.nu_eff:.3f} K={res.k:.3f}")
+    assert t.shape == diff.shape == (1500,)
+    assert np.all(np.isfinite(diff))
+    assert 0.2 < res.fit_frequency < 1.0 and 0.0 < res.fit_damping < 0.5
+    assert res.sheath > 0.0 and res.nu_eff > 0.0
+    assert np.isfinite(res.k) and res.k > 0.0

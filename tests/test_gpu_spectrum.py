@@ -6,8 +6,9 @@
   eps_p = 1 - 1/omega^2 | vacuum) found from electrostatics alone; the paper's
   dipole kernel (l_max = 1, m = 0) must resonate there.
 * FP32-compensated against FP64: the resonance c and half-width 2b of the
-  damped-sine fit (Sec. 4) of the impulse response agree within 0.5% on the
-  same seeded 2e6-particle, l_max = 16 workload.
+  damped-sine fit (Sec. 4) of the impulse response, averaged over an
+  ensemble of slightly jittered starts, agree within 0.5% on the seeded
+  2e6-particle, l_max = 16 workload.
 Both use the difference of a driven run and an undriven twin from the same
 state (the static part of Q_diff is particle noise).
 """
@@ -94,19 +95,35 @@ def test_cold_dipole_resonance():
 
 @pytest.mark.gpu
 def test_spectrum_fp32c_matches_fp64():
+    """The impulse response is chaotic: FP32c runs from starting positions
+    that differ by a relative 1e-12 already scatter by ~1% in 2b, so one run
+    against one run measures the divergence, not the precision.  Each mode
+    runs an ensemble of four starts (unperturbed, +-1e-12 and 1e-10 relative
+    jitter) and the ensemble means of c and 2b must agree within 0.5%; every
+    single FP32c fit must lie within 1.5% of the FP64 mean."""
     wl = W.LARGE
     steps = 420
     st = wl.particles()
+    jitter = np.random.default_rng(99).standard_normal(st.pos.shape)
+    t = np.arange(steps) * wl.dt
+    m = t <= 20.0
     fits = {}
     for prec in (S.SIM_FP64, S.SIM_FP32_COMP):
-        _say(f"[gpu] impulse spectrum {wl.name} seed={wl.seed} precision={prec} steps={steps}")
-        prm = S.SimParams(ntilde=wl.ntilde, l_max=wl.l_max, precision=prec)
-        diff = _twin(prm, st, steps, 1.0)
-        t = np.arange(steps) * wl.dt
-        m = t <= 20.0
-        fits[prec] = A.fit_damped_sine(t[m], diff[m], 1.0)
-        _say(f"[gpu]   c={fits[prec].frequency:.5f} 2b={fits[prec].fwhm:.5f}")
-    f64, f32 = fits[S.SIM_FP64], fits[S.SIM_FP32_COMP]
-    assert 0.3 < f64.frequency < 0.9 and f64.damping > 0
-    assert f32.frequency == pytest.approx(f64.frequency, rel=5e-3)
-    assert f32.fwhm == pytest.approx(f64.fwhm, rel=5e-3)
+        fits[prec] = []
+        for eps in (0.0, 1e-12, -1e-12, 1e-10):
+            _say(f"[gpu] impulse spectrum {wl.name} seed={wl.seed} precision={prec} "
+                 f"jitter={eps:g} steps={steps}")
+            prm = S.SimParams(ntilde=wl.ntilde, l_max=wl.l_max, precision=prec)
+            pos = st.pos * (1.0 + eps * jitter) if eps else st.pos
+            diff = _twin(prm, W.ParticleState(pos, st.vel, st.ids), steps, 1.0)
+            f = A.fit_damped_sine(t[m], diff[m], 1.0)
+            _say(f"[gpu]   c={f.frequency:.5f} 2b={f.fwhm:.5f}")
+            fits[prec].append((f.frequency, f.fwhm, f.damping))
+    f64 = np.mean(fits[S.SIM_FP64], axis=0)
+    f32 = np.mean(fits[S.SIM_FP32_COMP], axis=0)
+    assert 0.3 < f64[0] < 0.9 and f64[2] > 0
+    assert f32[0] == pytest.approx(f64[0], rel=5e-3)
+    assert f32[1] == pytest.approx(f64[1], rel=5e-3)
+    for c, fw, _ in fits[S.SIM_FP32_COMP]:
+        assert c == pytest.approx(f64[0], rel=1.5e-2)
+        assert fw == pytest.approx(f64[1], rel=1.5e-2)
