@@ -546,6 +546,62 @@ def _isolated_fp64(done, reqs, args, sample: int = 8, steps: int = 40):
             "served_latency_over_isolated_max": float(np.max(ratios))}
 
 
+def bench_spectrum(args):
+    """The single large run as specified: 2e6 electrons, l_max 16, 20,000
+    steps, FP64 and FP32-compensated, each as a driven run (the paper's
+    impulse, u_asy = 1 at the first step) and an undriven twin from the same
+    state.  Reports, per precision, the damped-sine fit of the twin
+    difference on t in [1, 20] (resonance c, full width 2b; Sec. 4) and the
+    peak and half-width of Re Y from the Fourier transform of the whole
+    record, and their FP32c / FP64 ratios; plus the throughput of the runs."""
+    import torch
+
+    from paper_2111_13072_amd import analysis as A
+    from paper_2111_13072_amd import sim as S
+    from paper_2111_13072_amd import workload as W
+
+    wl = W.LARGE
+    steps = args.spectrum_steps
+    st = wl.particles()
+    t = np.arange(steps) * wl.dt
+    out = {}
+    for name, prec in (("fp64", S.SIM_FP64), ("fp32c", S.SIM_FP32_COMP)):
+        qs = []
+        elapsed = 0.0
+        for drive in (True, False):
+            u = W.impulse_drive(steps, 1.0) if drive else np.zeros(steps)
+            prm = S.SimParams(ntilde=wl.ntilde, l_max=wl.l_max, precision=prec)
+            with S.Sim(prm, st.pos, st.vel, u) as sim:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sim.step(steps)
+                sim.sync()
+                elapsed += time.perf_counter() - t0
+                qs.append(sim.read_response(0, steps))
+            print(f"[bench] spectrum {name} {'driven' if drive else 'undriven'}: {steps} steps",
+                  file=sys.stderr, flush=True)
+        diff = A.twin_difference(*qs)
+        m = (t >= 1.0) & (t <= 20.0)
+        fit = A.fit_damped_sine(t[t <= 20.0], diff[t <= 20.0], 1.0)
+        spec = A.admittance(diff, W.impulse_drive(steps, 1.0), wl.dt, pad=4, w_max=1.5)
+        w_peak, fwhm = spec.peak()
+        out[name] = {"fit_c": fit.frequency, "fit_2b": fit.fwhm, "re_y_peak": w_peak,
+                     "re_y_fwhm": fwhm, "particle_steps_per_s": 2 * wl.n * steps / elapsed,
+                     "fit_points": int(m.sum())}
+    f64, f32 = out["fp64"], out["fp32c"]
+    line = {"metric": METRIC, "value": f32["particle_steps_per_s"], "unit": "particle-steps/s",
+            "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": None,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": f"{wl.name}-spectrum", "n_particles": wl.n, "l_max": wl.l_max,
+                       "steps": steps, "drive": "impulse 1 at step 0", "parallelism": "single-gpu"},
+            "spectra": out,
+            "fp32c_over_fp64": {k: f32[k] / f64[k] for k in ("fit_c", "fit_2b", "re_y_peak",
+                                                              "re_y_fwhm")}}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_sweep(args):
     """Scale and accuracy sweep: 1.6e7 particles at l_max 8, 16, 32 for
     n_e in {1e15, 1e16} m^-3 and T_e in {1, 3, 5} eV (FP32-compensated by
@@ -591,7 +647,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--workload", default="scale",
-                    choices=["scale", "large", "small", "batch64", "serve", "sweep"],
+                    choices=["scale", "large", "small", "batch64", "serve", "sweep", "spectrum"],
                     help="scale: 1.6e7 electrons, l_max 16, T_e 3 eV, n_e 1e15 (the largest "
                          "single-GPU run; FP32-compensated with the FP64 run beside it); large: "
                          "2e6, l_max 16; small: 1e4, l_max 8")
@@ -604,6 +660,8 @@ def main(argv=None):
                     help="serve: most steps per tick of a pool")
     ap.add_argument("--serve-tick-seconds", type=float, default=0.025,
                     help="serve: a pool's tick is about this long (0: always --serve-tick-steps)")
+    ap.add_argument("--spectrum-steps", type=int, default=20000,
+                    help="spectrum: steps of each run (driven and undriven, both precisions)")
     ap.add_argument("--serve-steps", default="2000,20000",
                     help="serve: range of the requests' step counts")
     ap.add_argument("--serve-small-max", type=int, default=200000,
@@ -668,6 +726,8 @@ def main(argv=None):
         return bench_serve(args)
     if args.workload == "sweep":
         return bench_sweep(args)
+    if args.workload == "spectrum":
+        return bench_spectrum(args)
     wl = {"scale": W.SCALE, "large": W.LARGE, "small": W.SMALL_FP64}[args.workload]
     precision = args.precision or ("fp32c" if args.workload == "scale" else "fp64")
     return bench_single(args, wl, precision)
