@@ -1,7 +1,7 @@
 """GPU against the oracle for the paper's own setup (the App. D equilibrium:
 radial ion profile, static surface charge, diffuse walls, r_out = 10,
-dt = 0.01), and the impulse-driven trajectory of the 1e4-particle workload
-against the stored oracle run."""
+dt = 0.01), and the impulse- and Gaussian-driven runs of the 1e4-particle
+workload against the stored oracle runs."""
 from __future__ import annotations
 
 import os
@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from paper_2111_13072_amd import analysis as A
 from paper_2111_13072_amd import equilibrium as EQ
 from paper_2111_13072_amd import sim as S
 from paper_2111_13072_amd import workload as W
@@ -18,6 +19,7 @@ from paper_2111_13072_amd import workload as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "shell-1e4-L8_impulse_qdiff.txt")
+GOLDEN_GAUSS = os.path.join(os.path.dirname(__file__), "golden", "shell-1e4-L8_gaussian_qdiff.txt")
 
 
 def _say(msg):
@@ -120,6 +122,41 @@ def test_impulse_trajectory_matches_stored_oracle_run():
         dev = np.abs(got - want)
         _say(f"[gpu]   max deviation {dev.max():.3e} (bound at the end {bound[-1]:.3e})")
         assert np.all(dev <= bound)
+
+
+def test_gaussian_pulse_run_and_admittance_match_stored_oracle_run():
+    """Config-1 workload as specified: 1e4 particles, l_max 8, 1000 steps of
+    the +-1 V Gaussian pulse on the hemispheres, and its undriven twin.
+    Q_diff from the GPU tracks the stored oracle runs within the divergence
+    envelope of the oracle's 1e-12-perturbed twin, and the admittance of the
+    twin difference (Sec. 4: Y = i omega Q^ / u^ from the Fourier transform
+    of Q_diff) peaks at the oracle's frequency with the oracle's half-width,
+    both within 0.5%."""
+    ref = np.loadtxt(GOLDEN_GAUSS)
+    drv, und, per = ref.T
+    steps = ref.shape[0]
+    wl = W.SMALL_FP64
+    st = wl.particles()
+    u = wl.drive(steps)
+    prm = S.SimParams(ntilde=wl.ntilde, l_max=wl.l_max)
+    out = []
+    for drive in (u, np.zeros(steps)):
+        _say(f"[gpu] Gaussian pulse {wl.name}: {steps} steps, drive peak {drive.max():.4g}")
+        with S.Sim(prm, st.pos, st.vel, drive) as sim:
+            sim.step(steps)
+            out.append(sim.read_response(0, steps))
+    envelope = np.maximum.accumulate(np.abs(drv - per))
+    bound = 1e-12 * np.max(np.abs(drv)) + 10.0 * envelope
+    for got, want in zip(out, (drv, und)):
+        dev = np.abs(got - want)
+        _say(f"[gpu]   max deviation {dev.max():.3e} (bound at the end {bound[-1]:.3e})")
+        assert np.all(dev <= bound)
+    y_gpu = A.admittance(A.twin_difference(*out), u, wl.dt).peak()
+    y_ora = A.admittance(A.twin_difference(drv, und), u, wl.dt).peak()
+    _say(f"[gpu]   Re Y peak {y_gpu[0]:.5f} (oracle {y_ora[0]:.5f}), "
+         f"FWHM {y_gpu[1]:.5f} (oracle {y_ora[1]:.5f})")
+    assert y_gpu[0] == pytest.approx(y_ora[0], rel=5e-3)
+    assert y_gpu[1] == pytest.approx(y_ora[1], rel=5e-3)
 
 
 def test_experiment_pipeline_runs_end_to_end_small():
