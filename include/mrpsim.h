@@ -116,16 +116,22 @@ typedef struct {
     /* Launch sizes that leave the results unchanged up to the rounding order
      * of the radial carries (the autotuner's knobs; 0 = built-in choice):
      * sort_bucket: mean particles per radial sort bucket, 1..256 (built-in 8);
-     * carry_chunk: tiles per carry chunk, 8..1024 (built-in: a power of two
-     * in [8, 64], about a member's tiles / 256);
+     * carry_chunk: groups of 256 particle slots per carry chunk, 8..1024
+     * (built-in: a power of two in [8, 64], about a member's groups / 256);
      * sort_keys: where the next step's radial sort keys and bucket slots
      * are taken: 1 in the tail of the push, -1 in a pass of their own, 0 by
      * launch size (the push from 2048 tiles of 64 particles on).  Results
-     * are bit-identical either way.  reserved1: unused. */
+     * are bit-identical either way.
+     * near_split: the near field's pair sums run over blocks of 32 radially
+     * consecutive particles (1) or 64 (-1), the pairs across blocks through
+     * the radial scan; 0: by member, 32 in FP64 and, in FP32, where
+     * l_max^2 <= sqrt(n) (a close pair's force, about l_max^2 / sqrt(n) of the
+     * RMS field, keeps FP32 relative precision only inside a block).  The
+     * same sum split differently: results agree to rounding. */
     int32_t sort_bucket;
     int32_t carry_chunk;
     int32_t sort_keys;
-    int32_t reserved1;
+    int32_t near_split;
 } sim_params;
 
 /* Fill *p with the defaults (d = 0.25, eps_r = 4, r_out = 5, dt = 0.05,

@@ -52,8 +52,16 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxL = 64;
-// Tiles per chunk of the carry scan, per member: a power of two in
-// [kChunkMin, kChunkMax], about a member's tiles / kChunkTarget, so that small
+// A tile (one wave's 64 radially consecutive particles) is two halves of 32:
+// the pair sums of the near field run inside a half, and the moments are
+// summed per half.  A group is the four tiles of one workgroup of the moments
+// and field kernels (256 slots): the carry scan runs over groups, and a
+// member's particle slots are whole groups.
+constexpr int kHalf = kWave / 2;
+constexpr int kTilesPerGroup = kWavesPerBlock;
+constexpr int kGroupSlots = kTilesPerGroup * kWave;
+// Groups per chunk of the carry scan, per member: a power of two in
+// [kChunkMin, kChunkMax], about a member's groups / kChunkTarget, so that small
 // members get short serial chains and large ones few chunks.
 constexpr int kChunkMin = 8, kChunkMax = 64, kChunkTarget = 256;
 constexpr int kScanPerBlock = 1024;  // histogram entries per block of the bucket scan
@@ -101,10 +109,11 @@ struct Ctl {
 
 // Per-member description (device table, written by the host between steps).
 struct Seg {
-    uint32_t p0, cap;   // particle slots [p0, p0 + cap); p0 is a multiple of 64
+    uint32_t p0, cap;   // particle slots [p0, p0 + cap); p0 is a multiple of 256
     uint32_t t0, nt;    // tiles [t0, t0 + nt), t0 = p0 / 64
+    uint32_t g0, ng;    // groups [g0, g0 + ng), g0 = p0 / 256
     uint32_t c0, nc;    // carry chunks [c0, c0 + nc)
-    uint32_t cl;        // tiles per chunk
+    uint32_t cl;        // groups per chunk
     uint32_t b0, nb;    // sort buckets [b0, b0 + nb)
     double inv_vol;     // 1 / (r_out^3 - 1)
     double ntilde, inv_ntilde, ion_density, q_surface0, dt, r_out;
@@ -119,6 +128,7 @@ struct Seg {
     double ion_h, ion_inv_h;
     double ion_qm;      // charge / mass of ion particles (+1 / ion_mass)
     int32_t ion_k;
+    int32_t near_w;     // particles of a near-field block: 32 (a half tile) or 64 (the tile)
     int32_t used;
 };
 
@@ -135,6 +145,9 @@ struct Tables {
     const double *nfB;      // l/(l+1)
     const double4 *nf4;     // {(2l+1)/(l+1), l/(l+1), 2l+1, l}, one wide load per l
     const int *chl;         // degree l of each channel in stream order
+    // per channel: the factor that turns a sum of rescaled harmonics (Qh) into
+    // a field coefficient, N_lm^2 / (2l+1) (times 1 / ntilde at use)
+    const double *chg;
     // Legendre constants of the full near field, per l: {c_l, l c_l,
     // gamma_{l+1}, (2l+1) c_l}, where P_l = c_l Ph_l and the rescaled
     // polynomials obey Ph_{l+1} = u Ph_l - gamma_{l+1} Ph_{l-1}
@@ -164,8 +177,11 @@ struct KParams {
     int L;          // l_max
     int C;          // channels: (L+1)^2 - 1 (full) or L (axisymmetric)
     int C2;         // 2C: interior then exterior
-    int SW;         // C2 + 1: tile sums also carry the tile's total charge
-    int n_tiles;    // tile capacity (particle slots / 64)
+    int SW;         // C2 + 1: group sums also carry the group's total charge
+    int HW;         // 4C + 2: a tile's half sums (interior h0, h1, exterior h0,
+                    // h1) and the charges of its halves
+    int n_tiles;    // tile capacity (particle slots / 64, a multiple of 4)
+    int n_groups;   // n_tiles / 4
     int n_chunks;   // chunk capacity
     int nb;         // bucket capacity
     int n_members;  // member table size
@@ -544,17 +560,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_rank_move(Map mp, const OrdRec 
 // recurrence); the carries restore N_lm.
 
 // A slot holds two channels, one LDS row each: the wave's 64 lanes after the
-// fold across wave halves, interior partial sums (lanes 0-31) at row offsets
-// 0-31 and exterior ones (lanes 32-63) at kHalfOff.  With kRowLen = 66 and
-// kHalfOff = 33 the rows' lanes fall on distinct banks both when a wave writes
-// a row and when it reads a batch back (each group of kLanesPerQ lanes one
-// half row).
+// fold across 16-lane rows, four quarter rows of 16 partial sums: interior of
+// half 0 (lanes 0-15), exterior of half 0 (16-31), interior of half 1 (32-47)
+// and exterior of half 1 (48-63), quarter q at row offset q * kQuarterOff.  A
+// batch of kSlots slots is read back by pairs of lanes, each pair summing one
+// quarter row (kPartials entries each, then one lane exchange).  With
+// kQuarterOff = 17 and kRowLen = 68 the 16 lanes of each quarter of the wave
+// start their reads on distinct banks.
 constexpr int kSlots = 4;                          // slots per batch
-constexpr int kRowLen = 66;
-constexpr int kHalfOff = 33;
-constexpr int kLanesPerQ = kWave / (4 * kSlots);   // lanes that sum one half row
-constexpr int kPartials = 32 / kLanesPerQ;         // entries each of them adds
-static_assert(kLanesPerQ == 2 || kLanesPerQ == 4, "a half row is summed by 2 or 4 lanes");
+constexpr int kQuarterOff = 17;
+constexpr int kRowLen = 4 * kQuarterOff;
+constexpr int kPartials = 8;                       // entries per lane: 16 / 2
+static_assert(kWave == 2 * (2 * kSlots) * 4, "one lane pair per quarter row of a batch");
 
 // Orders this wave's LDS accesses at this point: LDS instructions of one wave
 // complete in issue order, so rows a wave wrote are visible to its later
@@ -567,13 +584,14 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Exchange the upper 32 lanes of a with the lower 32 lanes of b.
-__device__ inline void swap_wave_halves(double &a, double &b)
+// Exchange the odd 16-lane rows of a with the even rows of b: afterwards a
+// holds the rows {a0, b0, a2, b2} and b the rows {a1, b1, a3, b3}.
+__device__ inline void swap_rows16(double &a, double &b)
 {
     const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
-    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
     const auto hi =
-        __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+        __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
     a = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | (uint64_t)lo[0]));
     b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | (uint64_t)lo[1]));
 }
@@ -591,26 +609,35 @@ __device__ inline double dpp_quad(double v)
     return __longlong_as_double((long long)(((uint64_t)phi << 32) | plo));
 }
 
+// The column block of a tile's row that quarter q of a folded row goes to:
+// the row is [interior h0 | interior h1 | exterior h0 | exterior h1 | charges].
+__device__ inline int quarter_block(int q) { return q == 0 ? 0 : q == 1 ? 2 : q == 2 ? 1 : 3; }
+
 template <bool FULL>
 __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, KParams kp,
-                                                    double *S, double *lgrho)
+                                                    double *H, double *GS)
 {
-    // Per wave (one tile of 64 particles), the lane sums of q R (interior)
-    // and q I (exterior) of every channel, in a tree:
-    //  1. R and I of one channel are folded across the wave halves (lanes
-    //     0-31 then hold R over particle pairs, lanes 32-63 I), and the
-    //     result is one LDS row of a slot; a slot holds two channels (cos
-    //     and sin of one (l, m), or two degrees of m = 0);
-    //  2. every kSlots slots each group of kLanesPerQ lanes sums one half
-    //     row (kPartials entries each, then lane exchanges within the quad)
-    //     and the group's first lane stores it.
+    // Per wave (one tile of 64 particles), the sums of q R (interior) and
+    // q I (exterior) of every channel over each half of the tile, in a tree:
+    //  1. R and I of one channel are folded across 16-lane rows (lanes 0-15
+    //     then hold R over particle pairs of half 0, lanes 16-31 I of half 0,
+    //     lanes 32-63 the same for half 1), and the result is one LDS row of a
+    //     slot; a slot holds two channels (cos and sin of one (l, m), or two
+    //     degrees of m = 0);
+    //  2. every kSlots slots each pair of lanes sums one quarter row
+    //     (kPartials entries each, then a lane exchange) and the pair's first
+    //     lane stores it in the tile's row of H.
+    // Last, the block adds its group's four tile rows into the group's row of
+    // the carry scan (GS: interior, exterior, charge).
     // The m = 0 block is padded to an even count with a zero channel, so a
     // slot always holds two positions of the padded channel order.
     __shared__ double buf[kWavesPerBlock][kSlots * 2 * kRowLen];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + w);
-    // the tile's member; n = its alive count, lt = the tile's index in it
+    const uint32_t group = blockIdx.x;
+    const uint32_t tile = uniform_u32(group * kTilesPerGroup + w);
+    // the member (the same for the group's four tiles: a member's slots are
+    // whole groups); n = its alive count, lt = the tile's index in it
     bool tile_ok = false;
     uint32_t n = 0, lt = 0;
     if ((int)tile < kp.n_tiles) {
@@ -637,30 +664,27 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     const double inv_r = 1.0 / sqrt(r2);
     const int L = kp.L;
     const int C = kp.C;
-    double *St = S + (size_t)tile * kp.SW;
+    double *Ht = H + (size_t)tile * kp.HW;
     {
-        // the tile's total charge (exact: a count of ions and electrons)
-        const int n_val = __popcll(__ballot(valid)), n_ion = __popcll(__ballot(valid && ion));
-        if (tile_ok && lane == 0) St[kp.C2] = (double)n_ion + kQ * (double)(n_val - n_ion);
-    }
-    if (kp.fp32 && tile_ok && lane == 0) {
-        // reference radius of the tile for the FP32 field: its first particle
-        double rho = 1.0;
-        if (lt * kWave < n) {
-            const uint32_t p0 = tile * kWave;
-            rho = sqrt(key_r2(B.x[p0], B.y[p0], B.z[p0]));
+        // the charges of the tile's halves (exact: counts of ions and electrons)
+        const uint64_t vb = __ballot(valid), ib = __ballot(valid && ion);
+        if (tile_ok && lane < 2) {
+            const uint64_t hm = lane ? 0xffffffff00000000ull : 0x00000000ffffffffull;
+            const int n_val = __popcll(vb & hm), n_ion = __popcll(ib & hm);
+            Ht[4 * C + lane] = (double)n_ion + kQ * (double)(n_val - n_ion);
         }
-        lgrho[tile] = log2(rho);
     }
 
     double *wb = buf[w];
     // writer: lane -> its entry of a row
-    double *wr = wb + lane + (lane >= 32 ? kHalfOff - 32 : 0);
-    // reader: lane group v = 4 s + 2 j + h (slot s, its channel j, interior
-    // or exterior h) sums half row h of row (s, j); part t of it
-    const int v = lane / kLanesPerQ, t = lane % kLanesPerQ;
-    const int rs = v >> 2, rj = (v >> 1) & 1, rh = v & 1;
-    const double *rd = wb + (2 * rs + rj) * kRowLen + rh * kHalfOff + t * kPartials;
+    double *wr = wb + (lane >> 4) * kQuarterOff + (lane & 15);
+    // reader: lane pair v = 4 rr + rq (row rr = 2 s + j of the batch: slot s,
+    // its channel j; quarter rq) sums that quarter row; part t of it
+    const int v = lane >> 1, t = lane & 1;
+    const int rr = v >> 2, rq = v & 3;
+    const int rs = rr >> 1;
+    const double *rd = wb + rr * kRowLen + rq * kQuarterOff + t * kPartials;
+    double *hdst = Ht + quarter_block(rq) * C;
     const int pad0 = L & 1;             // zero channel after the m = 0 block
     const int n_pos = C + pad0;         // padded channel positions
     int slot = 0, base = 0;             // base: padded position of slot 0
@@ -670,20 +694,18 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
 #pragma unroll
         for (int k = 1; k < kPartials; ++k) acc += rd[k];
         acc += dpp_quad<0xB1>(acc);
-        if (kLanesPerQ == 4) acc += dpp_quad<0x4E>(acc);
-        const int pos = base + 2 * rs + rj;   // padded position
+        const int pos = base + rr;      // padded position
         // padded position -> channel: the m = 0 block is positions 0..L-1
         const int ch = pos < L ? pos : pos - pad0;
-        if (tile_ok && t == 0 && rs < slot && pos < n_pos && !(pad0 && pos == L))
-            St[rh * C + ch] = acc;
+        if (tile_ok && t == 0 && rs < slot && pos < n_pos && !(pad0 && pos == L)) hdst[ch] = acc;
         wave_lds_sync();
         base += 2 * kSlots;
         slot = 0;
     };
     // one slot from two channels (R, I each)
     auto put2 = [&](double r0, double i0, double r1, double i1) {
-        swap_wave_halves(r0, i0);
-        swap_wave_halves(r1, i1);
+        swap_rows16(r0, i0);
+        swap_rows16(r1, i1);
         double *row = wr + slot * 2 * kRowLen;
         row[0] = r0 + i0;
         row[kRowLen] = r1 + i1;
@@ -758,29 +780,47 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         }
     }
     if (slot > 0) flush();   // last, partial batch: slots >= slot hold stale values
+
+    // The group's row of the carry scan: its four tiles' half sums, read back
+    // from memory once every wave of the block has stored its row.
+    __threadfence_block();
+    __syncthreads();
+    if (!tile_ok) return;   // the same for the group's four tiles
+    const double *Hg = H + (size_t)group * kTilesPerGroup * kp.HW;
+    double *Gs = GS + (size_t)group * kp.SW;
+    for (int c = threadIdx.x; c < kp.SW; c += kBlock) {
+        // group column c (interior channel, exterior channel, or the charge)
+        // and the two half columns of a tile row it sums
+        const int a = c < C ? c : (c < kp.C2 ? C + c : 4 * C);
+        const int b = c < C ? C + c : (c < kp.C2 ? 2 * C + c : 4 * C + 1);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kTilesPerGroup; ++k) s += Hg[k * kp.HW + a] + Hg[k * kp.HW + b];
+        Gs[c] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Carries: prefix/suffix scans over tiles, totals, coefficients, Q_diff
+// Carries: prefix/suffix scans over groups, totals, coefficients, Q_diff
 // ---------------------------------------------------------------------------
 
-// The chunk's member and its tile range; false if the member does not run.
-__device__ inline bool chunk_tiles(const Map &mp, const KParams &kp, int j, uint32_t *mb,
-                                   int *t0, int *t1)
+// The chunk's member and its group range; false if the member does not run.
+__device__ inline bool chunk_groups(const Map &mp, const KParams &kp, int j, uint32_t *mb,
+                                    int *g0, int *g1)
 {
     const uint32_t m = mp.chunk_member[j];
     if (m == kNone || !member_runs(mp.seg[m], mp.ctl[m], kp)) return false;
     const Seg &sg = mp.seg[m];
     *mb = m;
-    *t0 = (int)(sg.t0 + (uint32_t)(j - (int)sg.c0) * sg.cl);
-    *t1 = min(*t0 + (int)sg.cl, (int)(sg.t0 + sg.nt));
+    *g0 = (int)(sg.g0 + (uint32_t)(j - (int)sg.c0) * sg.cl);
+    *g1 = min(*g0 + (int)sg.cl, (int)(sg.g0 + sg.ng));
     return true;
 }
 
 // A running FP64 sum that carries its own rounding error (Knuth's
 // error-free TwoSum): the sum of n terms is good to about one rounding of
-// the result instead of ~sqrt(n) of them.  The carries sum the tile sums of
-// up to ~2.5e5 tiles per member; these kernels are bound by HBM, so the
+// the result instead of ~sqrt(n) of them.  The carries sum the group sums of
+// up to ~6e4 groups per member; these kernels are bound by HBM, so the
 // extra operations cost no time.
 struct CompSum {
     double s = 0.0, e = 0.0;
@@ -794,33 +834,34 @@ struct CompSum {
     __device__ double value() const { return s + e; }
 };
 
-// The tile loops of the carry kernels issue the loads of kCarryBatch tiles
-// before using them (a chunk is 8-64 tiles, or the tuned length, walked by one thread, and one
-// HBM round trip per tile would dominate); the sums keep the tile order.
+// The group loops of the carry kernels issue the loads of kCarryBatch groups
+// before using them (a chunk is 8-64 groups, or the tuned length, walked by
+// one thread, and one HBM round trip per group would dominate); the sums
+// keep the group order.
 constexpr int kCarryBatch = 8;
 
-__global__ __launch_bounds__(kBlock) void k_chunk_sums(Map mp, const double *__restrict__ S,
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(Map mp, const double *__restrict__ GS,
                                                        double *__restrict__ chunkS, KParams kp)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
     if (c >= kp.SW) return;
     const int j = blockIdx.x;
     uint32_t mb;
-    int t0, t1;
-    if (!chunk_tiles(mp, kp, j, &mb, &t0, &t1)) return;
+    int g0, g1;
+    if (!chunk_groups(mp, kp, j, &mb, &g0, &g1)) return;
     const size_t sw = (size_t)kp.SW;
-    const double *src = S + (size_t)t0 * sw + c;
-    const int nt = t1 - t0;
+    const double *src = GS + (size_t)g0 * sw + c;
+    const int ng = g1 - g0;
     CompSum s;
-    int t = 0;
-    for (; t + kCarryBatch <= nt; t += kCarryBatch) {
+    int g = 0;
+    for (; g + kCarryBatch <= ng; g += kCarryBatch) {
         double v[kCarryBatch];
 #pragma unroll
-        for (int k = 0; k < kCarryBatch; ++k) v[k] = src[(size_t)(t + k) * sw];
+        for (int k = 0; k < kCarryBatch; ++k) v[k] = src[(size_t)(g + k) * sw];
 #pragma unroll
         for (int k = 0; k < kCarryBatch; ++k) s.add(v[k]);
     }
-    for (; t < nt; ++t) s.add(src[(size_t)t * sw]);
+    for (; g < ng; ++g) s.add(src[(size_t)g * sw]);
     chunkS[(size_t)j * kp.SW + c] = s.value();
 }
 
@@ -869,28 +910,25 @@ __global__ __launch_bounds__(kBlock) void k_chunk_scan(Map mp, const double *chu
     if (!interior && lane == kWave - 1) T[(size_t)s * kp.C + (c - kp.C)] = incl.value();
 }
 
-// Per-tile coefficients of the field kernel.  Interior coefficient of tile
-// t: the carry of the tiles before it, plus the constant part: the image
-// response -f_l T_lm and the hemisphere drive (odd l, m = 0; stream positions
-// 0..L-1 hold m = 0, l = 1..L).  Exterior: the carry of the tiles after it.
-// FP64 mode: absolute FP64 values.  FP32 mode: values pre-scaled to the
-// tile's coordinates x / rho (interior rho^-(l+1), exterior rho^l), stored
-// as FP32.  The block of the member's first chunk also records the probe
-// response Q_diff(t_step) from the totals.
-__global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *__restrict__ S,
+// Per-group coefficients of the field kernel (FP64, absolute).  Interior
+// coefficient of group g: the carry of the groups before it, plus the
+// constant part: the image response -f_l T_lm and the hemisphere drive (odd
+// l, m = 0; stream positions 0..L-1 hold m = 0, l = 1..L).  Exterior: the
+// carry of the groups after it.  The field kernel adds the sums of the
+// group's own tiles and halves.  Column C2: the charge of the member's
+// particles before the group.  The block of the member's first chunk also
+// records the probe response Q_diff(t_step) from the totals.
+__global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *__restrict__ GS,
                                                         const double *__restrict__ chunkC,
                                                         const double *__restrict__ T, Tables tb,
-                                                        KParams kp,
-                                                        const double *__restrict__ lgrho,
-                                                        double *__restrict__ coef,
-                                                        float *__restrict__ coef32,
+                                                        KParams kp, double *__restrict__ CR,
                                                         double *__restrict__ qpre)
 {
     const int c = blockIdx.y * kBlock + threadIdx.x;
     const int j = blockIdx.x;
     uint32_t mb;
-    int t0, t1;
-    if (!chunk_tiles(mp, kp, j, &mb, &t0, &t1)) return;
+    int g0, g1;
+    if (!chunk_groups(mp, kp, j, &mb, &g0, &g1)) return;
     const Seg &sg = mp.seg[mb];
     const int64_t step = mp.ctl[mb].step;
     const bool in_run = step >= 0 && step < sg.n_steps;
@@ -906,56 +944,43 @@ __global__ __launch_bounds__(kBlock) void k_chunk_apply(Map mp, const double *__
     const size_t sw = (size_t)kp.SW;
     CompSum run;
     run.s = chunkC[(size_t)j * kp.SW + c];
-    // Walks the chunk's tiles in scan order (dir +1 from t0, -1 from t1 - 1),
-    // calling f(t, carry before t) with the loads of kCarryBatch tiles issued
-    // ahead; the carry accumulates in tile order, compensated.
+    // Walks the chunk's groups in scan order (dir +1 from g0, -1 from g1 - 1),
+    // calling f(g, carry before g) with the loads of kCarryBatch groups issued
+    // ahead; the carry accumulates in group order, compensated.
     auto walk = [&](int dir, auto f) {
-        const int nt = t1 - t0;
-        const int first = dir > 0 ? t0 : t1 - 1;
+        const int ng = g1 - g0;
+        const int first = dir > 0 ? g0 : g1 - 1;
         int i = 0;
-        for (; i + kCarryBatch <= nt; i += kCarryBatch) {
+        for (; i + kCarryBatch <= ng; i += kCarryBatch) {
             double v[kCarryBatch];
 #pragma unroll
-            for (int k = 0; k < kCarryBatch; ++k) v[k] = S[(size_t)(first + dir * (i + k)) * sw + c];
+            for (int k = 0; k < kCarryBatch; ++k) v[k] = GS[(size_t)(first + dir * (i + k)) * sw + c];
 #pragma unroll
             for (int k = 0; k < kCarryBatch; ++k) {
                 f(first + dir * (i + k), run.value());
                 run.add(v[k]);
             }
         }
-        for (; i < nt; ++i) {
-            const int t = first + dir * i;
-            f(t, run.value());
-            run.add(S[(size_t)t * sw + c]);
+        for (; i < ng; ++i) {
+            const int g = first + dir * i;
+            f(g, run.value());
+            run.add(GS[(size_t)g * sw + c]);
         }
     };
-    if (c == kp.C2) {   // charge of the member's particles before each tile
-        walk(1, [&](int t, double carry) { qpre[t] = carry; });
+    if (c == kp.C2) {   // charge of the member's particles before each group
+        walk(1, [&](int g, double carry) { qpre[g] = carry; });
     } else if (c < kp.C) {
         const int l = tb.chl[c];
         const double nrm = tb.chn[c];
         const double w = tb.wl[l] * inv_nt * nrm;   // the sums are of Qh = Q / N_lm
         double k = -tb.ftil[l] * Ts[c] * w;
         if (c < kp.L && in_run) k += sg.u_asy[step] * tb.drive_w[l];
-        if (kp.fp32) {
-            walk(1, [&](int t, double carry) {
-                const double v = (carry * w + k) * nrm;
-                coef32[(size_t)t * kp.C2 + c] = (float)(v * exp2(-(l + 1.0) * lgrho[t]));
-            });
-        } else {
-            walk(1, [&](int t, double carry) { coef[(size_t)t * kp.C2 + c] = (carry * w + k) * nrm; });
-        }
+        walk(1, [&](int g, double carry) { CR[(size_t)g * kp.C2 + c] = (carry * w + k) * nrm; });
     } else {
         const int l = tb.chl[c - kp.C];
         const double nrm = tb.chn[c - kp.C];
         const double w = tb.wl[l] * inv_nt * nrm * nrm;   // sums of Qh; the field's Qh
-        if (kp.fp32) {
-            walk(-1, [&](int t, double carry) {
-                coef32[(size_t)t * kp.C2 + c] = (float)(carry * w * exp2((double)l * lgrho[t]));
-            });
-        } else {
-            walk(-1, [&](int t, double carry) { coef[(size_t)t * kp.C2 + c] = carry * w; });
-        }
+        walk(-1, [&](int g, double carry) { CR[(size_t)g * kp.C2 + c] = carry * w; });
     }
 }
 
@@ -1252,31 +1277,38 @@ __device__ inline void far_field(Stage &&stage, int L, const R4 *fq, double xd, 
     gz = c * Ga * inv_r + (xh * xh + yh * yh) * Gz;
 }
 
-// Near field: the direct part of G~_L between the particles of one tile,
-// pair by pair.  For the pair (k, j) with rho = r_< / r_>, u = angular argument:
+// Near field: the direct part of G~_L between the particles of one block of
+// W = 32 (a half tile) or 64 (the tile) radially consecutive particles (the
+// pairs across blocks go through the coefficients), pair by pair.  For the pair (k, j) with
+// rho = r_< / r_>, u = angular argument:
 //   outer one: grad D = (1/r_>^2)       sum_l rho^l [-(l+1) P_l xh + P'_l v]
 //   inner one: grad D = (1/(r_< r_>))   sum_l rho^l [ l P_l xh     + P'_l v]
 // where v = xh_other - u xh (full) or e_z - cos(th) xh (axisymmetric).  The
 // three sums are symmetric in (k, j), so each pair is evaluated once: at step
-// s lane k takes partner (k + s) mod 64 and hands the partner's gradient to it
-// through a lane rotation.  Each term carries the charge of its source (the
-// other particle of the pair).  Pair terms in R, accumulated in FP64.
+// s lane k takes partner k + s (mod W, inside its block) and hands the
+// partner's gradient to it through a lane rotation.  Each term carries the
+// charge of its source (the other particle of the pair).  Pair terms in R,
+// accumulated in FP64.  The rows hold each block twice (entries h + i and
+// h + i + W for the i-th particle of the block starting at entry h = 2 W b),
+// so the partner of every shift is a plain offset.
 template <bool FULL, typename R, typename NF>
-__device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R *sxh, const R *syh,
-                                  const R *szh, const R *sr, const R *sir, const R *sq, R xh,
-                                  R yh, R zh, R r, R inv_r, R qk, double &ax, double &ay,
-                                  double &az)
+__device__ inline void near_field(int lane, int W, int jn, int L, const NF *nf, const R *sxh,
+                                  const R *syh, const R *szh, const R *sr, const R *sir,
+                                  const R *sq, R xh, R yh, R zh, R r, R inv_r, R qk, double &ax,
+                                  double &ay, double &az)
 {
     const R inv_r2 = inv_r * inv_r;
-    for (int sft = 1; sft <= kWave / 2; ++sft) {
-        const int j = (lane + sft) & (kWave - 1);
-        const bool active = lane < jn && j < jn && (sft < kWave / 2 || lane < kWave / 2);
+    const int hl = lane & (W - 1), hb = 2 * (lane & W);
+    for (int sft = 1; sft <= W / 2; ++sft) {
+        const int jl = (lane & W) | ((hl + sft) & (W - 1));   // partner lane
+        const int j = hb + hl + sft;
+        const bool active = lane < jn && jl < jn && (sft < W / 2 || hl < W / 2);
         const R xj = sxh[j], yj = syh[j], zj = szh[j];
         const R rj = sr[j], irj = sir[j];
         const R qj = sq[j];
-        // a tile's lanes are in radial order (key (r^2, id)): the partner
-        // (lane + sft) mod 64 is the inner one when it wraps below this lane
-        const bool k_outer = lane + sft >= kWave;
+        // a block's lanes are in radial order (key (r^2, id)): the partner
+        // is the inner one when it wraps below this lane
+        const bool k_outer = hl + sft >= W;
         const R rho = k_outer ? rj * inv_r : r * irj;
         const R sc_out = k_outer ? inv_r2 : irj * irj;   // 1 / r_>^2
         const R sc_in = inv_r * irj;                     // 1 / (r_< r_>)
@@ -1339,24 +1371,20 @@ __device__ inline void near_field(int lane, int jn, int L, const NF *nf, const R
             gjy = 0;
             gjz = 0;
         }
-        const int src = (lane - sft) & (kWave - 1);
+        const int src = (lane & W) | ((hl - sft) & (W - 1));
         ax += (double)__shfl(gjx, src);
         ay += (double)__shfl(gjy, src);
         az += (double)__shfl(gjz, src);
     }
 }
 
-// One wave's particles for the near field, each row written twice (entries
-// i and i + 64), so that the partner k + s and the sender k - s + 64 of a
-// lane k are plain offsets from the lane's own entry for every shift s.
+// One wave's particles for the near field: each block's rows written twice
+// (see above).
 template <typename R>
 struct NearRows {
     R xh[2 * kWave], yh[2 * kWave], zh[2 * kWave], r[2 * kWave], ir[2 * kWave], q[2 * kWave];
     // FP32 only: r / rho_t - 1 against the tile's reference radius rho_t
     R s[sizeof(R) == 4 ? 2 * kWave : 1];
-    // not read: keeps the wave's LDS (shared with the far field's coefficient
-    // window) at the size the window thresholds were measured with
-    double spare[4 * kWave];
 };
 
 __device__ inline double bpermute(int addr, double v)
@@ -1384,9 +1412,9 @@ __device__ inline float bpermute(int addr, float v)
 // rescaled polynomials of the lg table (a two-operation recurrence; l = 1 is
 // peeled); in FP32 a recurrence on P_l - P_{l-1} driven by 1 - u (lw table).
 template <typename R, typename LG>
-__device__ inline void near_field_full(int lane, int L, const LG *lg, const NearRows<R> &nr, R xh,
-                                       R yh, R zh, R r, R ir, R sk, R rho_t, R qk, double &ax,
-                                       double &ay, double &az)
+__device__ inline void near_field_full(int lane, int W, int L, const LG *lg, const NearRows<R> &nr,
+                                       R xh, R yh, R zh, R r, R ir, R sk, R rho_t, R qk,
+                                       double &ax, double &ay, double &az)
 {
     double dck = 0.0, dbx = 0.0, dby = 0.0, dbz = 0.0;
     R ck = 0, bx = 0, by = 0, bz = 0;
@@ -1401,15 +1429,15 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
         bz = 0;
     };
     const LG c1 = lg[1];
-    const int lane4 = lane * 4;
+    const int hl = lane & (W - 1), hb = 2 * (lane & W);
     auto shift = [&](const int sft, R qk_s, bool last) {
-        const int j = lane + sft;   // partner, in the doubled row
+        const int j = hb + hl + sft;   // partner, in the doubled block row
         const R xj = nr.xh[j], yj = nr.yh[j], zj = nr.zh[j];
         const R rj = nr.r[j], irj = nr.ir[j];
-        const R qj = last && lane >= kWave / 2 ? (R)0 : nr.q[j];
-        // a tile's lanes are in radial order (key (r^2, id)): the partner
-        // lane + sft (mod 64) is the inner one when it wraps below this lane
-        const bool k_outer = j >= kWave;
+        const R qj = last && hl >= W / 2 ? (R)0 : nr.q[j];
+        // a block's lanes are in radial order (key (r^2, id)): the partner
+        // hl + sft (mod W) is the inner one when it wraps below this lane
+        const bool k_outer = hl + sft >= W;
         const R irmx = k_outer ? ir : irj;   // 1 / r_>
         R u, S1, Sl, SB;
         if constexpr (sizeof(R) == 4) {
@@ -1500,27 +1528,29 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
         by = fma(bk, yj, by);
         bz = fma(bk, zj, bz);
         const R cj = fma(-bj, u, wj * SAj);
-        // lane k's partner is k + sft, so lane k receives from k - sft
-        const int src_addr = (lane4 + 4 * (kWave - sft)) & (4 * kWave - 1);
+        // lane k's partner is k + sft (in its block), so lane k receives from
+        // k - sft
+        const int src_addr = 4 * ((lane & W) | ((hl - sft) & (W - 1)));
         const R cr = bpermute(src_addr, cj), br = bpermute(src_addr, bj);
-        const int src = lane + kWave - sft;   // in the doubled row
+        const int src = hb + hl + W - sft;   // in the doubled block row
         ck += cr;
         bx = fma(br, nr.xh[src], bx);
         by = fma(br, nr.yh[src], by);
         bz = fma(br, nr.zh[src], bz);
     };
     if constexpr (sizeof(R) == 4) {
-        for (int s0 = 1; s0 < kWave / 2; s0 += 8) {
+        for (int s0 = 1; s0 < W / 2; s0 += 8) {
 #pragma unroll 1
-            for (int sft = s0; sft < min(s0 + 8, kWave / 2); ++sft) shift(sft, qk, false);
+            for (int sft = s0; sft < min(s0 + 8, W / 2); ++sft) shift(sft, qk, false);
             flush();
         }
     } else {
 #pragma unroll 1
-        for (int sft = 1; sft < kWave / 2; ++sft) shift(sft, qk, false);
+        for (int sft = 1; sft < W / 2; ++sft) shift(sft, qk, false);
     }
-    // the pairs (k, k + 32) and (k + 32, k) are one pair: lanes 0-31 take it
-    shift(kWave / 2, lane >= kWave / 2 ? (R)0 : qk, true);
+    // the pairs (k, k + W/2) and (k + W/2, k) of a block are one pair: the
+    // block's lanes below W/2 take it
+    shift(W / 2, hl >= W / 2 ? (R)0 : qk, true);
     flush();
     ax += dck * (double)xh + dbx;
     ay += dck * (double)yh + dby;
@@ -1531,8 +1561,8 @@ __device__ inline void near_field_full(int lane, int L, const LG *lg, const Near
 // NEAR64: FP32 far field with the near field in FP64 (FP32 mode at high l_max)
 template <bool FULL, bool FIELD_ONLY, bool FP32, bool NEAR64>
 __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(Map mp, State B, PRec *A, uint8_t *dead,
-                                                       Grave G, const double *coef,
-                                                       const float *coef32, const double *qpre,
+                                                       Grave G, const double *H,
+                                                       const double *CR, const double *qpre,
                                                        Tables tb, KParams kp, double *Eout,
                                                        uint32_t *Eid, KeyRec *krec,
                                                        uint32_t *hist)
@@ -1542,17 +1572,25 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     using NF = typename std::conditional<FP32 && !NEAR64, float4, double4>::type;
     using RF = typename std::conditional<FP32, float, double>::type;
     using NFF = typename std::conditional<FP32, float4, double4>::type;
-    // Per wave: the tile's coefficients while the far field runs (when they
-    // fit), then the near field's rows.
+    // Per wave: the two halves' coefficients while the far field runs, then
+    // the near field's rows.  The size keeps the block's LDS within a CU's
+    // 160 KB at the kernel's occupancy (four blocks FP64, six FP32) and holds
+    // a window of 288 FP64 channels (all of l_max 16) or 384 FP32 ones; the
+    // second half's coefficients start kHalfPad bytes further, so that the two
+    // addresses of a read fall on different banks.
+    constexpr int kHalfPad = 16;
+    constexpr int kLdsBytes = (FP32 && !NEAR64 ? 6144 : 9216) + kHalfPad;
+    static_assert(sizeof(NearRows<R>) <= (size_t)kLdsBytes, "near-field rows exceed the wave's LDS");
     union WaveLds {
         NearRows<R> rows;
-        R cf[sizeof(NearRows<R>) / sizeof(R)];
+        RF cf[kLdsBytes / sizeof(RF)];
     };
     __shared__ WaveLds lds[kWavesPerBlock];
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const uint32_t tile = uniform_u32(blockIdx.x * kWavesPerBlock + w);
+    const uint32_t group = blockIdx.x;
+    const uint32_t tile = uniform_u32(group * kTilesPerGroup + w);
     // the tile's member: n = its alive count, pl = this lane's position in
     // its radial order
     uint32_t mb = kNone, n = 0, lt = 0;
@@ -1593,10 +1631,16 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     const Seg &sg = mp.seg[mb];
     Ctl &ct = mp.ctl[mb];
     const double ntilde = sg.ntilde, inv_nt = sg.inv_ntilde;
+    // the rows of the group's tiles (half sums, half charges)
+    const double *Hg = H + (size_t)group * kTilesPerGroup * kp.HW;
+    // the near field's block: a half tile (the halves' coefficients differ by
+    // the other half's sums) or the whole tile (they are the same)
+    const int NW = (int)uniform_u32((uint32_t)sg.near_w);
+    const bool split = NW == kHalf;
 
     // FP32: the tile's reference radius rho_t, its first particle's (the far
-    // field's coordinates are scaled by it, matching the moments kernel and
-    // the pre-scaled coefficients; the near field measures radii from it).
+    // field's coordinates and coefficients are scaled by it; the near field
+    // measures radii from it).
     double rho = 1.0;
     if (FP32) {
         const uint32_t p0 = tile * kWave;
@@ -1604,44 +1648,84 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
     }
     const double inv_rho = 1.0 / rho;
 
-    // ---- far field (all other tiles) ----
+    // ---- far field (all particles outside this lane's near-field block) ----
     double Ex, Ey, Ez;
     {
         RF gx, gy, gz;
-        const RF *cfg;
         const NFF *fq;
-        if constexpr (FP32) {
-            cfg = coef32 + (size_t)tile * kp.C2;
-            fq = tb.fq4_32;
-        } else {
-            cfg = coef + (size_t)tile * kp.C2;
-            fq = tb.fq4;
-        }
+        if constexpr (FP32) fq = tb.fq4_32;
+        else fq = tb.fq4;
         const double xs = x * inv_rho, ys = y * inv_rho, zs = z * inv_rho;
-        // The tile's coefficients are read by every pass of every lane: they
-        // go to LDS with coalesced loads (the far field reads them as
-        // broadcasts), in windows of kWin channels (interior, then exterior)
-        // that hold whole m blocks; a window moves on when the next block
-        // does not fit (never at l_max <= 21 in FP64, 24 in FP32).  An m block
+        // Coefficients of channel c for half h of this tile: the group's
+        // (carries of the groups before and after it, the image response and
+        // the drive) plus the sums of the group's own particles on each side:
+        //   interior: the tiles before this one, and for h = 1 half 0;
+        //   exterior: the tiles after this one, and for h = 0 half 1;
+        // (the halves' own terms only with a near field per half tile)
+        // as raw sums of Qh times N_lm^2 / ((2l+1) ntilde).  FP32: scaled to
+        // the tile's coordinates x / rho (interior rho^-(l+1), exterior
+        // rho^l) in FP64, then rounded once.  Every pass of every lane reads
+        // them, so they go to LDS (the far field reads them as broadcasts, one
+        // address per half), in windows of kWin channels (interior and
+        // exterior of both halves) that hold whole m blocks; a window moves on
+        // when the next block does not fit (never at l_max <= 16).  An m block
         // has at most 2 l_max <= 128 channels.
-        constexpr int kWin = (int)(sizeof(WaveLds) / sizeof(RF)) / 2;
+        constexpr int kWin = (kLdsBytes - kHalfPad) / (int)sizeof(RF) / 4;
+        constexpr int kH1 = 2 * kWin + kHalfPad / (int)sizeof(RF);   // half 1's offset
         static_assert(kWin >= 2 * kMaxL, "an m block must fit a window");
         RF *cbuf = reinterpret_cast<RF *>(lds[w].cf);
         const int C = kp.C;
+        const double *CRg = CR + (size_t)group * kp.C2;
+        // FP32: rho^-(l+1) and rho^l of degree l = lane + 1, fetched per
+        // channel from the lane of its degree
+        double pw_in = 1.0, pw_out = 1.0;
+        if (FP32) {
+            const double lg = log2(rho);
+            pw_in = exp2(-(lane + 2.0) * lg);
+            pw_out = exp2((lane + 1.0) * lg);
+        }
         int win0 = 0, win_len = -1;   // resident channels [win0, win0 + win_len)
         auto stage = [&](int k0, int k1) {
             if (win_len < 0 || k1 > win0 + win_len) {
                 if (win_len >= 0) wave_lds_sync();   // the old window's reads are done
                 const int len = min(kWin, C - k0);
-                for (int i = lane; i < len; i += kWave) {
-                    cbuf[i] = cfg[k0 + i];
-                    cbuf[kWin + i] = cfg[C + k0 + i];
+                const int n_iter = (len + kWave - 1) / kWave;
+                for (int it = 0; it < n_iter; ++it) {
+                    const int i = it * kWave + lane;
+                    const bool in_win = i < len;
+                    const int c = k0 + (in_win ? i : 0);
+                    double yin = 0.0, yout = 0.0;
+                    for (int t = 0; t < w; ++t)
+                        yin += Hg[t * kp.HW + c] + Hg[t * kp.HW + C + c];
+                    for (int t = kTilesPerGroup - 1; t > w; --t)
+                        yout += Hg[t * kp.HW + 2 * C + c] + Hg[t * kp.HW + 3 * C + c];
+                    const double *Ht = Hg + w * kp.HW;
+                    const double gsc = tb.chg[c] * inv_nt;
+                    const double ci = CRg[c], co = CRg[C + c];
+                    const double hin = split ? Ht[c] : 0.0, hout = split ? Ht[3 * C + c] : 0.0;
+                    double a0 = ci + gsc * yin, a1 = ci + gsc * (yin + hin);
+                    double b1 = co + gsc * yout, b0 = co + gsc * (yout + hout);
+                    if (FP32) {
+                        // every lane takes part in the fetches
+                        const int src = 4 * (tb.chl[c] - 1);
+                        const double si = bpermute(src, pw_in), so = bpermute(src, pw_out);
+                        a0 *= si;
+                        a1 *= si;
+                        b0 *= so;
+                        b1 *= so;
+                    }
+                    if (in_win) {
+                        cbuf[i] = (RF)a0;
+                        cbuf[kWin + i] = (RF)b0;
+                        cbuf[kH1 + i] = (RF)a1;
+                        cbuf[kH1 + kWin + i] = (RF)b1;
+                    }
                 }
                 wave_lds_sync();
                 win0 = k0;
                 win_len = len;
             }
-            return CfView<RF>{cbuf, win0, kWin};
+            return CfView<RF>{cbuf + (lane >= kHalf ? kH1 : 0), win0, kWin};
         };
         far_field<FULL, RF>(stage, L, fq, xs, ys, zs, gx, gy, gz);
         wave_lds_sync();   // read before the rows below overwrite them
@@ -1650,17 +1734,20 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
         Ez = -(double)gz * inv_rho;
     }
 
-    // ---- near field (own tile); E += -(1 / (4 pi nt)) sum_j q_j grad D ----
+    // ---- near field (own block); E += -(1 / (4 pi nt)) sum_j q_j grad D ----
     NearRows<R> &nr = lds[w].rows;
-    for (int c = 0; c < 2; ++c) {
-        const int i = lane + c * kWave;
-        nr.xh[i] = (R)xh;
-        nr.yh[i] = (R)yh;
-        nr.zh[i] = (R)zh;
-        nr.r[i] = (R)r;
-        nr.ir[i] = (R)inv_r;
-        nr.q[i] = valid ? (R)qk : (R)0;
-        if constexpr (sizeof(R) == 4) nr.s[i] = (R)(r * inv_rho - 1.0);
+    {
+        const int e0 = 2 * (lane & NW) + (lane & (NW - 1));   // entries e0, e0 + NW
+        for (int c = 0; c < 2; ++c) {
+            const int i = e0 + c * NW;
+            nr.xh[i] = (R)xh;
+            nr.yh[i] = (R)yh;
+            nr.zh[i] = (R)zh;
+            nr.r[i] = (R)r;
+            nr.ir[i] = (R)inv_r;
+            nr.q[i] = valid ? (R)qk : (R)0;
+            if constexpr (sizeof(R) == 4) nr.s[i] = (R)(r * inv_rho - 1.0);
+        }
     }
     wave_lds_sync();   // the rows are this wave's own
     {
@@ -1671,14 +1758,14 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
             const NF *lg;
             if constexpr (std::is_same<R, float>::value) lg = tb.lw4_32;
             else lg = tb.lg4;
-            near_field_full<R, NF>(lane, L, lg, nr, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r,
+            near_field_full<R, NF>(lane, NW, L, lg, nr, (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r,
                                    (R)(r * inv_rho - 1.0), (R)rho, valid ? (R)qk : (R)0, ax,
                                    ay, az);
         } else {
             const NF *nf;
             if constexpr (std::is_same<R, float>::value) nf = tb.nf4_32;
             else nf = tb.nf4;
-            near_field<FULL, R, NF>(lane, jn, L, nf, nr.xh, nr.yh, nr.zh, nr.r, nr.ir, nr.q,
+            near_field<FULL, R, NF>(lane, NW, jn, L, nf, nr.xh, nr.yh, nr.zh, nr.r, nr.ir, nr.q,
                                     (R)xh, (R)yh, (R)zh, (R)r, (R)inv_r, (R)qk, ax, ay, az);
         }
         const double cn = -1.0 / (4.0 * kPi * ntilde);
@@ -1738,7 +1825,11 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
         const uint64_t below = (1ull << lane) - 1ull;
         const int n_below = __popcll(__ballot(valid) & below);
         const int i_below = __popcll(__ballot(ion) & below);
-        const double before = qpre[tile] + ((double)i_below + kQ * (double)(n_below - i_below));
+        // the group's particles before this tile: whole half charges (exact)
+        double in_group = 0.0;
+        for (int t = 0; t < w; ++t) in_group += Hg[t * kp.HW + 4 * kp.C] + Hg[t * kp.HW + 4 * kp.C + 1];
+        const double before =
+            (qpre[group] + in_group) + ((double)i_below + kQ * (double)(n_below - i_below));
         double e;
         if (sg.ion_tab) {
             e = ((ct.q_surface + before) + ion_enclosed(sg, r, r2)) / (4.0 * kPi * ntilde * r2);
@@ -1881,8 +1972,9 @@ const char *kKernelNames[KN_COUNT] = {
 // choice (bucket) or kept as "automatic" (chunk).
 struct Tuning {
     int bucket = kBucketOccupancy;   // mean particles per sort bucket
-    int chunk = 0;                   // tiles per carry chunk, 0: by member size
+    int chunk = 0;                   // groups per carry chunk, 0: by member size
     int keys = 0;                    // sort keys: 1 push, -1 own pass, 0 by extent
+    int split = 0;                   // near field: 1 half tiles, -1 whole tiles, 0 by member
 };
 
 Tuning tuning_of(const sim_params *p)
@@ -1891,7 +1983,21 @@ Tuning tuning_of(const sim_params *p)
     if (p->sort_bucket > 0) t.bucket = p->sort_bucket;
     if (p->carry_chunk > 0) t.chunk = p->carry_chunk;
     t.keys = p->sort_keys;
+    t.split = p->near_split;
     return t;
+}
+
+// Particles of a member's near-field block.  Half tiles halve the pair sums;
+// the pairs across the halves then go through the coefficients.  In FP32 the
+// coefficients carry the force of a close pair to a few ulps times l_max,
+// while the pair's force is about l_max^2 / sqrt(n) of the RMS field (the
+// collective field of n particles grows as sqrt(n)): half tiles are used
+// where l_max^2 <= sqrt(n).  FP64 always splits.
+int near_width(const Tuning &tu, bool fp32, int L, int64_t n)
+{
+    if (tu.split != 0) return tu.split > 0 ? kHalf : kWave;
+    if (!fp32) return kHalf;
+    return (double)L * (double)L <= std::sqrt((double)n) ? kHalf : kWave;
 }
 
 // In the FP32 mode the near field's FP32 error grows with l_max: a pair at
@@ -1908,7 +2014,8 @@ struct Layout {
     int L, C, C2;
     bool full, fp32;
     bool near64;     // FP32 mode with an FP64 near field (l_max >= kNear64MinL)
-    int n_tiles;     // particle slots / 64
+    int n_tiles;     // particle slots / 64 (whole groups)
+    int n_groups;    // n_tiles / 4
     int n_chunks;
     int nb, nb_blocks;
     int n_members;
@@ -1920,7 +2027,7 @@ struct Layout {
 // extent, not the capacity, so a large, sparsely filled handle steps at the
 // cost of what it holds.
 struct Extent {
-    int n_tiles = 1, n_chunks = 1, nb = 1, nb_blocks = 1, n_members = 1;
+    int n_tiles = kTilesPerGroup, n_chunks = 1, nb = 1, nb_blocks = 1, n_members = 1;
     bool operator==(const Extent &o) const
     {
         return n_tiles == o.n_tiles && n_chunks == o.n_chunks && nb == o.nb &&
@@ -1928,24 +2035,25 @@ struct Extent {
     }
 };
 
-// Per-member sizes.
+// Per-member sizes: groups, tiles (4 per group), chunks, buckets, groups per chunk.
 struct MemberShape {
-    uint32_t nt, nc, nb, cl;
+    uint32_t ng, nt, nc, nb, cl;
 };
 
-uint32_t tiles_for(int64_t n) { return (uint32_t)((n + kWave - 1) / kWave); }
+uint32_t groups_for(int64_t n) { return (uint32_t)((n + kGroupSlots - 1) / kGroupSlots); }
 
 MemberShape member_shape(int64_t n, const Tuning &tu)
 {
     MemberShape m;
-    m.nt = tiles_for(n);
+    m.ng = groups_for(n);
+    m.nt = m.ng * kTilesPerGroup;
     if (tu.chunk > 0) {
         m.cl = (uint32_t)tu.chunk;
     } else {
         m.cl = kChunkMin;
-        while (m.cl < (uint32_t)kChunkMax && (uint64_t)m.cl * kChunkTarget < m.nt) m.cl *= 2;
+        while (m.cl < (uint32_t)kChunkMax && (uint64_t)m.cl * kChunkTarget < m.ng) m.cl *= 2;
     }
-    m.nc = (m.nt + m.cl - 1) / m.cl;
+    m.nc = (m.ng + m.cl - 1) / m.cl;
     m.nb = (uint32_t)std::max<int64_t>(1, n / tu.bucket);
     return m;
 }
@@ -1962,6 +2070,7 @@ bool check_common(const sim_params *p, std::string *why)
     if (p->tile != 0 && p->tile != kWave) { *why = "tile must be 0 or 64"; return false; }
     if (p->sort_bucket < 0 || p->sort_bucket > 256) { *why = "sort_bucket must be 0 or in [1, 256]"; return false; }
     if (p->sort_keys < -1 || p->sort_keys > 1) { *why = "sort_keys must be -1, 0 or 1"; return false; }
+    if (p->near_split < -1 || p->near_split > 1) { *why = "near_split must be -1, 0 or 1"; return false; }
     if (p->carry_chunk != 0 && (p->carry_chunk < kChunkMin || p->carry_chunk > 1024)) {
         *why = "carry_chunk must be 0 or in [8, 1024]";
         return false;
@@ -2004,7 +2113,7 @@ bool make_layout(const sim_params *p, int64_t slots, int32_t max_members, int64_
                  Layout *lo, std::string *why)
 {
     if (!check_common(p, why)) return false;
-    if (slots <= 0 || slots > 0x7fffffffLL - kWave) { *why = "slot capacity must be in [1, 2^31 - 64)"; return false; }
+    if (slots <= 0 || slots > 0x7fffffffLL - kGroupSlots) { *why = "slot capacity must be in [1, 2^31 - 256)"; return false; }
     if (max_members <= 0 || max_members > (1 << 20)) { *why = "max_members must be in [1, 2^20]"; return false; }
     lo->L = p->l_max;
     lo->full = p->m_mode == SIM_M_FULL;
@@ -2012,13 +2121,14 @@ bool make_layout(const sim_params *p, int64_t slots, int32_t max_members, int64_
     lo->near64 = lo->fp32 && p->l_max >= kNear64MinL;
     lo->C = lo->full ? (p->l_max + 1) * (p->l_max + 1) - 1 : p->l_max;
     lo->C2 = 2 * lo->C;
-    lo->n_tiles = (int)((slots + kWave - 1) / kWave);
+    lo->n_groups = (int)groups_for(slots);
+    lo->n_tiles = lo->n_groups * kTilesPerGroup;
     lo->n_members = max_members;
     lo->tu = tuning_of(p);
     // every member rounds its chunks and buckets up by at most one
     const int cl_min = lo->tu.chunk > 0 ? lo->tu.chunk : kChunkMin;
     lo->n_chunks = chunks >= 0 ? (int)std::max<int64_t>(1, chunks)
-                               : (lo->n_tiles + cl_min - 1) / cl_min + max_members;
+                               : (lo->n_groups + cl_min - 1) / cl_min + max_members;
     lo->nb = (int)std::max<int64_t>(1, slots / lo->tu.bucket) + (max_members > 1 ? max_members : 0);
     lo->nb_blocks = (lo->nb + kScanPerBlock - 1) / kScanPerBlock;
     return true;
@@ -2117,12 +2227,11 @@ struct sim {
     KeyRec *krec = nullptr;
     OrdRec *orec = nullptr;
     uint32_t *hist = nullptr, *off = nullptr, *bsum = nullptr;
-    double *S = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr,
-           *coef = nullptr, *tables = nullptr, *Eout = nullptr, *qpre = nullptr;
+    double *H = nullptr, *GS = nullptr, *chunkS = nullptr, *chunkC = nullptr, *T = nullptr,
+           *CR = nullptr, *tables = nullptr, *Eout = nullptr, *qpre = nullptr;
     int *chl = nullptr;
-    double *chn = nullptr;
-    float *coef32 = nullptr, *tables32 = nullptr;
-    double *lgrho = nullptr;
+    double *chn = nullptr, *chg = nullptr;
+    float *tables32 = nullptr;
     uint32_t *Eid = nullptr;
     Seg *seg = nullptr;
     Ctl *ctl = nullptr;
@@ -2139,7 +2248,7 @@ struct sim {
     size_t arena_bytes = 0;
     char *mdata = nullptr;      // members' drive, response and ion-profile arrays
     std::vector<Member> members;
-    Ranges tiles, chunks, buckets, mdata_units;   // mdata_units: 256-byte units of mdata
+    Ranges groups, chunks, buckets, mdata_units;   // mdata_units: 256-byte units of mdata
 };
 
 namespace {
@@ -2202,17 +2311,10 @@ void plan_alloc(sim *h, Alloc &al, size_t pool_bytes)
     al.add(&h->hist, (size_t)lo.nb + 1);
     al.add(&h->off, (size_t)lo.nb + 1);
     al.add(&h->bsum, (size_t)lo.nb_blocks + 1);
-    al.add(&h->S, (size_t)lo.n_tiles * (lo.C2 + 1));
-    al.add(&h->qpre, (size_t)lo.n_tiles);
-    if (lo.fp32) {
-        al.add(&h->coef32, (size_t)lo.n_tiles * lo.C2);
-        al.add(&h->lgrho, (size_t)lo.n_tiles);
-        al.add(&h->coef, 1);
-    } else {
-        al.add(&h->coef, (size_t)lo.n_tiles * lo.C2);
-        al.add(&h->coef32, 1);
-        al.add(&h->lgrho, 1);
-    }
+    al.add(&h->H, (size_t)lo.n_tiles * (4 * lo.C + 2));
+    al.add(&h->GS, (size_t)lo.n_groups * (lo.C2 + 1));
+    al.add(&h->CR, (size_t)lo.n_groups * std::max(lo.C2, 1));
+    al.add(&h->qpre, (size_t)lo.n_groups);
     al.add(&h->tables32, tables32_len(lo.L));
     al.add(&h->chunkS, (size_t)lo.n_chunks * (lo.C2 + 1));
     al.add(&h->chunkC, (size_t)lo.n_chunks * (lo.C2 + 1));
@@ -2220,6 +2322,7 @@ void plan_alloc(sim *h, Alloc &al, size_t pool_bytes)
     al.add(&h->tables, tables_len(lo.L));
     al.add(&h->chl, (size_t)std::max(lo.C, 1));
     al.add(&h->chn, (size_t)std::max(lo.C, 1));
+    al.add(&h->chg, (size_t)std::max(lo.C, 1));
     al.add(&h->Eout, 3 * n);
     al.add(&h->Eid, n);
     al.add(&h->seg, (size_t)lo.n_members);
@@ -2318,14 +2421,15 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     kp.fuse_keys = lo.tu.keys != 0 ? (lo.tu.keys > 0 ? 1 : 0)
                                    : (ex.n_tiles >= kFuseKeysMinTiles ? 1 : 0);
     kp.n_tiles = ex.n_tiles;
+    kp.n_groups = ex.n_tiles / kTilesPerGroup;
     kp.n_chunks = ex.n_chunks;
     kp.nb = ex.nb;
     kp.n_members = ex.n_members;
     const Map &mp = h->map;
     const unsigned n = (unsigned)ex.n_tiles * kWave;
     const unsigned gN = (n + kBlock - 1) / kBlock;
-    const unsigned gT = (unsigned)((ex.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock);
-    const unsigned gC = (unsigned)((lo.C2 + 1 + kBlock - 1) / kBlock);   // tile-sum columns
+    const unsigned gT = (unsigned)(ex.n_tiles / kTilesPerGroup);   // one block per group
+    const unsigned gC = (unsigned)((lo.C2 + 1 + kBlock - 1) / kBlock);   // group-sum columns
     const unsigned gM = (unsigned)((ex.n_members + kBlock - 1) / kBlock);
     int e = 0;
     auto mark = [&](int k) {
@@ -2348,20 +2452,20 @@ int launch_step(sim *h, hipStream_t s, bool field_only, hipEvent_t *ev)
     mark(KN_SORT_RANK);
     k_sort_rank_move<<<gN, kBlock, 0, s>>>(mp, h->orec, h->off, h->A, h->B, kp);
     mark(KN_MOMENTS);
-    if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
-    else k_moments<false><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->S, h->lgrho);
+    if (lo.full) k_moments<true><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->H, h->GS);
+    else k_moments<false><<<gT, kBlock, 0, s>>>(mp, h->B, h->tb, kp, h->H, h->GS);
     mark(KN_CHUNK_SUMS);
-    k_chunk_sums<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkS, kp);
+    k_chunk_sums<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->GS, h->chunkS, kp);
     mark(KN_CHUNK_SCAN);
     k_chunk_scan<<<dim3((lo.C2 + 1 + kWavesPerBlock - 1) / kWavesPerBlock, ex.n_members), kBlock, 0,
                    s>>>(mp, h->chunkS, h->chunkC, h->T, kp);
     mark(KN_CHUNK_APPLY);
-    k_chunk_apply<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->S, h->chunkC, h->T, h->tb, kp,
-                                                           h->lgrho, h->coef, h->coef32, h->qpre);
+    k_chunk_apply<<<dim3(ex.n_chunks, gC), kBlock, 0, s>>>(mp, h->GS, h->chunkC, h->T, h->tb, kp,
+                                                           h->CR, h->qpre);
     mark(KN_FIELD_PUSH);
 #define MRP_FIELD(FULLV, FO, F32, N64)                                                   \
     k_field_push<FULLV, FO, F32, N64><<<gT, kBlock, 0, s>>>(mp, h->B, h->A, h->dead, h->G, \
-                                                            h->coef, h->coef32, h->qpre,   \
+                                                            h->H, h->CR, h->qpre,          \
                                                             h->tb, kp, h->Eout, h->Eid,    \
                                                             h->krec, h->hist)
 #define MRP_FIELD_P(FULLV, FO)                                           \
@@ -2444,7 +2548,7 @@ struct HostTables {
     std::vector<double> tab;
     std::vector<float> tab32;
     std::vector<int> chl;
-    std::vector<double> chn;
+    std::vector<double> chn, chg;
 };
 
 int make_host_tables(const sim_params &p, const Layout &lo, HostTables *ht)
@@ -2492,9 +2596,13 @@ int make_host_tables(const sim_params &p, const Layout &lo, HostTables *ht)
         }
     }
     if ((int)chl.size() != lo.C) return fail(SIM_EDEVICE, "channel count mismatch");
+    // N_lm^2 / (2l+1): a raw sum of Qh to a field coefficient (times 1 / ntilde)
+    ht->chg.resize(chl.size());
+    for (size_t c = 0; c < chl.size(); ++c) ht->chg[c] = chn[c] * chn[c] / (2.0 * chl[c] + 1.0);
     if (chl.empty()) {
         chl.push_back(0);
         chn.push_back(0.0);
+        ht->chg.push_back(0.0);
     }
     return SIM_OK;
 }
@@ -2517,6 +2625,7 @@ void bind_device_tables(sim *h)
     h->tb.fq4 = reinterpret_cast<const double4 *>(tb + fq4_offset(L));
     h->tb.chn = h->chn;
     h->tb.chl = h->chl;
+    h->tb.chg = h->chg;
     h->tb.nf4_32 = reinterpret_cast<const float4 *>(h->tables32 + nf4_32_offset(L));
     h->tb.lg4_32 = reinterpret_cast<const float4 *>(h->tables32 + lg4_32_offset(L));
     h->tb.fq4_32 = reinterpret_cast<const float4 *>(h->tables32 + fq4_32_offset(L));
@@ -2526,7 +2635,9 @@ void bind_device_tables(sim *h)
     kp.C = lo.C;
     kp.C2 = lo.C2;
     kp.SW = lo.C2 + 1;
+    kp.HW = 4 * lo.C + 2;
     kp.n_tiles = lo.n_tiles;
+    kp.n_groups = lo.n_groups;
     kp.n_chunks = lo.n_chunks;
     kp.nb = lo.nb;
     kp.n_members = lo.n_members;
@@ -2602,7 +2713,7 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream,
     HostTables ht;
     if (int rc = make_host_tables(*p, lo, &ht)) return rc;
     bind_device_tables(h);
-    h->tiles.reset((uint32_t)lo.n_tiles);
+    h->groups.reset((uint32_t)lo.n_groups);
     h->chunks.reset((uint32_t)lo.n_chunks);
     h->buckets.reset((uint32_t)lo.nb);
     h->members.assign((size_t)lo.n_members, Member());
@@ -2613,6 +2724,7 @@ int engine_init(sim *h, const sim_params *p, const Layout &lo, void *hip_stream,
     if (hipMemcpy(h->tables, ht.tab.data(), sizeof(double) * ht.tab.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->chl, ht.chl.data(), sizeof(int) * ht.chl.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->chn, ht.chn.data(), sizeof(double) * ht.chn.size(), hipMemcpyHostToDevice) ||
+        hipMemcpy(h->chg, ht.chg.data(), sizeof(double) * ht.chg.size(), hipMemcpyHostToDevice) ||
         hipMemcpy(h->tables32, ht.tab32.data(), sizeof(float) * ht.tab32.size(),
                   hipMemcpyHostToDevice) ||
         hipMemcpy(h->seg, segs.data(), sizeof(Seg) * segs.size(), hipMemcpyHostToDevice) ||
@@ -2715,19 +2827,19 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     const size_t mbytes = member_bytes(m->n_steps, m->ion_profile ? m->ion_profile_len : 0);
     const uint32_t md_units = (uint32_t)(mbytes / kPoolUnit);
     const MemberShape sh = member_shape(n, h->lo.tu);
-    uint32_t t0 = 0, c0 = 0, b0 = 0, md0 = 0;
-    if (!h->tiles.take(sh.nt, &t0)) return fail(SIM_ENOMEM, "no free tile range for the member");
+    uint32_t g0 = 0, c0 = 0, b0 = 0, md0 = 0;
+    if (!h->groups.take(sh.ng, &g0)) return fail(SIM_ENOMEM, "no free slot range for the member");
     if (!h->chunks.take(sh.nc, &c0)) {
-        h->tiles.give(t0, sh.nt);
+        h->groups.give(g0, sh.ng);
         return fail(SIM_ENOMEM, "no free chunk range for the member");
     }
     if (!h->buckets.take(sh.nb, &b0)) {
-        h->tiles.give(t0, sh.nt);
+        h->groups.give(g0, sh.ng);
         h->chunks.give(c0, sh.nc);
         return fail(SIM_ENOMEM, "no free bucket range for the member");
     }
     if (!h->mdata_units.take(md_units, &md0)) {
-        h->tiles.give(t0, sh.nt);
+        h->groups.give(g0, sh.ng);
         h->chunks.give(c0, sh.nc);
         h->buckets.give(b0, sh.nb);
         return fail(SIM_ENOMEM, "the batch's member data pool has no room for the member's "
@@ -2743,10 +2855,13 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     mb.q_surface0 = m->q_surface0;
     mb.id_index = std::move(pr.idx);
     Seg &sg = mb.seg;
-    sg.p0 = t0 * kWave;
-    sg.cap = sh.nt * kWave;
+    const uint32_t t0 = g0 * kTilesPerGroup;
+    sg.p0 = g0 * kGroupSlots;
+    sg.cap = sh.ng * kGroupSlots;
     sg.t0 = t0;
     sg.nt = sh.nt;
+    sg.g0 = g0;
+    sg.ng = sh.ng;
     sg.c0 = c0;
     sg.nc = sh.nc;
     sg.cl = sh.cl;
@@ -2764,10 +2879,11 @@ int engine_add(sim *h, const sim_member *m, Prepared &pr, int32_t *index)
     sg.wall_bc = m->wall_bc;
     sg.n_steps = m->n_steps;
     sg.ion_qm = m->ion_mass > 0.0 ? 1.0 / m->ion_mass : 0.0;
+    sg.near_w = near_width(h->lo.tu, h->lo.fp32, h->lo.L, n);
     sg.used = 1;
     auto undo = [&](int code) {
         free_member_arrays(h, mb);
-        h->tiles.give(t0, sh.nt);
+        h->groups.give(g0, sh.ng);
         h->chunks.give(c0, sh.nc);
         h->buckets.give(b0, sh.nb);
         return code;
@@ -2866,7 +2982,7 @@ int engine_remove(sim *h, int32_t index)
         return fail(SIM_EDEVICE, "member table update failed");
     }
     free_member_arrays(h, mb);
-    h->tiles.give(mb.seg.t0, mb.seg.nt);
+    h->groups.give(mb.seg.g0, mb.seg.ng);
     h->chunks.give(mb.seg.c0, mb.seg.nc);
     h->buckets.give(mb.seg.b0, mb.seg.nb);
     mb = Member();
@@ -2912,7 +3028,7 @@ sim_member member_from_params(const sim_params *p, int64_t n, const double *pos,
     return m;
 }
 
-int64_t slots_for(int64_t n) { return (int64_t)tiles_for(n) * kWave; }
+int64_t slots_for(int64_t n) { return (int64_t)groups_for(n) * kGroupSlots; }
 
 // ---------------------------------------------------------------------------
 // Field evaluation without allocation: every working array in a static
@@ -3421,9 +3537,11 @@ int sim_eval_field_static(const sim_params *p, int64_t n, const double *pos, dou
     h.ext.n_members = 1;
     Seg sg{};
     sg.p0 = 0;
-    sg.cap = sh.nt * kWave;
+    sg.cap = sh.ng * kGroupSlots;
     sg.t0 = 0;
     sg.nt = sh.nt;
+    sg.g0 = 0;
+    sg.ng = sh.ng;
     sg.c0 = 0;
     sg.nc = sh.nc;
     sg.cl = sh.cl;
@@ -3442,6 +3560,7 @@ int sim_eval_field_static(const sim_params *p, int64_t n, const double *pos, dou
     sg.n_steps = 1;
     sg.u_asy = reinterpret_cast<double *>(h.mdata);
     sg.qdiff = reinterpret_cast<double *>(h.mdata + kPoolUnit);
+    sg.near_w = near_width(h.lo.tu, h.lo.fp32, h.lo.L, n);
     sg.used = 1;
     Ctl ct{};
     ct.step = 0;
@@ -3461,6 +3580,8 @@ int sim_eval_field_static(const sim_params *p, int64_t n, const double *pos, dou
     HIP_TRY(hipMemcpyAsync(h.chl, ht.chl.data(), sizeof(int) * ht.chl.size(),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(h.chn, ht.chn.data(), sizeof(double) * ht.chn.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h.chg, ht.chg.data(), sizeof(double) * ht.chg.size(),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(h.tables32, ht.tab32.data(), sizeof(float) * ht.tab32.size(),
                            hipMemcpyHostToDevice, s));

@@ -5,7 +5,7 @@ over time.  The server keeps resident batches ("pools") per l_max class, and
 optionally per size class, each on its own HIP stream.  Whenever a pool's
 tick (a fixed number of steps of all its members) has completed, the server
 retires the members that reached their length after reading their response,
-admits waiting requests when its tiles, chunks, buckets and memory allow
+admits waiting requests when its slots, chunks, buckets and memory allow
 (first come, first served within the pool), and launches the next tick; it
 never waits on one pool to tend another.  A request's response equals, bit
 for bit, that of the same request run alone (members never interact).
@@ -151,16 +151,16 @@ class Server:
         for L in l_classes:
             cp = S.SimParams(l_max=L, precision=precision)
             # equal particle capacity per class: bytes in proportion to footprint
-            slots = int(budget_bytes / total) // 64 * 64
+            slots = int(budget_bytes / total) // S.SLOT_GROUP * S.SLOT_GROUP
             if small_max > 0:
-                small = int(slots * small_share) // 64 * 64
+                small = int(slots * small_share) // S.SLOT_GROUP * S.SLOT_GROUP
                 shares = {0: small, 1: slots - small}
             else:
                 shares = {0: slots}
             for cls, n in shares.items():
-                self.slots[(L, cls)] = max(n, 64)
+                self.slots[(L, cls)] = max(n, S.SLOT_GROUP)
                 self.pools[(L, cls)] = Pool((L, cls), S.Batch(
-                    cp, [], slot_capacity=max(n, 64), max_members=max_members,
+                    cp, [], slot_capacity=max(n, S.SLOT_GROUP), max_members=max_members,
                     member_data=mdata, use_torch_stream=False, allocator=allocator))
         self.rejected = []   # requests larger than their pool
 
@@ -172,8 +172,8 @@ class Server:
             raise ValueError(f"no pool for l_max {req.l_max}")
         if self.small_max <= 0:
             return (req.l_max, 0)
-        tiles = -(-req.n // 64) * 64
-        small = req.n <= self.small_max and tiles <= self.slots[(req.l_max, 0)]
+        slots = -(-req.n // S.SLOT_GROUP) * S.SLOT_GROUP
+        small = req.n <= self.small_max and slots <= self.slots[(req.l_max, 0)]
         return (req.l_max, 0 if small else 1)
 
     def close(self):

@@ -19,6 +19,8 @@ SIM_BUSY = 1   # sim_query: work still running
 SIM_M_FULL, SIM_M_AXISYM = 0, 1
 SIM_BC_ABSORB, SIM_BC_SPECULAR, SIM_BC_DIFFUSE = 0, 1, 2
 SIM_FP64, SIM_FP32_COMP = 0, 1
+# A member occupies whole groups of this many particle slots (four tiles of 64).
+SLOT_GROUP = 256
 
 # Every function include/mrpsim.h declares.
 EXPORTED = ("sim_params_default", "sim_create", "sim_step", "sim_sync", "sim_query",
@@ -98,7 +100,7 @@ class sim_params(C.Structure):
         ("wall_bc", C.c_int32), ("precision", C.c_int32), ("tile", C.c_int32),
         ("seed", C.c_uint64), ("mem_limit_bytes", C.c_uint64),
         ("sort_bucket", C.c_int32), ("carry_chunk", C.c_int32),
-        ("sort_keys", C.c_int32), ("reserved1", C.c_int32),
+        ("sort_keys", C.c_int32), ("near_split", C.c_int32),
     ]
 
 
@@ -228,12 +230,14 @@ class SimParams:
     carry_chunk: int = 0
     # where the sort keys are taken: 1 push, -1 own pass, 0 by launch size
     sort_keys: int = 0
+    # near-field block: 1 half tiles (32), -1 whole tiles (64), 0 by member
+    near_split: int = 0
 
     def to_c(self) -> sim_params:
         p = sim_params()
         lib().sim_params_default(C.byref(p))
         for f, _ in sim_params._fields_:
-            if f in ("struct_size", "reserved0", "reserved1"):
+            if f in ("struct_size", "reserved0"):
                 continue
             setattr(p, f, getattr(self, f))
         return p

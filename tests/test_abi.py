@@ -36,7 +36,7 @@ def test_params_layout_matches_header():
     S.lib().sim_params_default(C.byref(p))
     assert p.struct_size == C.sizeof(S.sim_params) == 120
     assert (p.d, p.eps_r, p.r_out, p.dt, p.l_max) == (0.25, 4.0, 5.0, 0.05, 8)
-    assert (p.sort_bucket, p.carry_chunk, p.sort_keys, p.reserved1) == (0, 0, 0, 0)
+    assert (p.sort_bucket, p.carry_chunk, p.sort_keys, p.near_split) == (0, 0, 0, 0)
 
 
 def test_strerror_covers_codes():
@@ -61,7 +61,7 @@ def test_footprint_grows_with_size_and_rejects_bad_params():
     for bad in (dict(l_max=65), dict(l_max=-1), dict(d=0.0), dict(eps_r=0.0), dict(r_out=1.0),
                 dict(m_mode=3), dict(wall_bc=0), dict(tile=48), dict(sort_bucket=-1),
                 dict(sort_bucket=257), dict(carry_chunk=4), dict(carry_chunk=2048),
-                dict(sort_keys=2), dict(sort_keys=-2)):
+                dict(sort_keys=2), dict(sort_keys=-2), dict(near_split=2), dict(near_split=-2)):
         with pytest.raises(S.SimError) as ei:
             S.footprint_bytes(S.SimParams(**bad), 1000, 10)
         assert ei.value.code == S.SIM_EINVAL

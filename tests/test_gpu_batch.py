@@ -142,7 +142,7 @@ def test_admit_and_retire_between_steps():
         ib = pool.add(bm)
         pool.step(5)
         qa_mid = pool.read_response(ia, 0, 10)
-        pool.remove(ia)                              # frees 704 slots
+        pool.remove(ia)                              # frees 768 slots (3 groups)
         ic = pool.add(c)                             # reuses them
         pool.step(10)
         qb = pool.read_response(ib, 0, 8)
@@ -163,7 +163,7 @@ def test_admission_limits_leave_the_pool_working():
     with S.Batch(cp, [a], slot_capacity=600, max_members=2,
                  member_data=2 * S.member_data_bytes(6)) as pool:
         with pytest.raises(S.SimError) as ei:
-            pool.add(make_member(200, 72, 6))      # 512 + 256 slots > 640
+            pool.add(make_member(300, 72, 6))      # 512 + 512 slots > 768
         assert ei.value.code == S.SIM_ENOMEM
         with pytest.raises(S.SimError) as ei:
             pool.add(make_member(50, 74, 40))      # its drive does not fit the data pool

@@ -71,6 +71,28 @@ def test_field_matches_oracle(name, n, L, mode, seed):
     assert err <= FP64_FIELD_TOL
 
 
+WHOLE_TILE_CASES = [c for c in FIELD_CASES if c[0] in
+                    ("shell-3000-L8", "ragged-777-L5", "axisym-640-L6", "shell-2000-L16",
+                     "two-tiles-65-L3", "shell-700-L64")]
+
+
+@pytest.mark.parametrize("name,n,L,mode,seed", WHOLE_TILE_CASES,
+                         ids=[c[0] for c in WHOLE_TILE_CASES])
+def test_field_matches_oracle_with_whole_tile_near_field(name, n, L, mode, seed):
+    """The near field's pair sums over whole tiles of 64 (the FP64 default
+    is half tiles of 32): the same sum split differently, the same bar."""
+    _say(f"[gpu] field parity, near field per tile, {name}: n={n} L={L} mode={mode} seed={seed}")
+    sp, op = _params(n, L, mode, q_surface0=-7.0, near_split=-1)
+    st = W.uniform_shell(n, seed, 5.0, 0.0831)
+    u = np.array([0.0, 0.0, 0.3, 0.0])
+    with S.Sim(sp, st.pos, st.vel, u, start_step=2) as sim:
+        E = sim.eval_field()
+    Eo, _ = O.field(op, st.pos, q_surface=-7.0, u_asy=0.3)
+    err = _rel_err(E, Eo)
+    _say(f"[gpu]   rel err {err:.3e}")
+    assert err <= FP64_FIELD_TOL
+
+
 def test_field_radius_tie_broken_by_id():
     """Two particles at exactly equal r^2 (coordinates swapped): the order,
     and so the gradient branch of r_< / r_>, follows the id."""
@@ -396,6 +418,25 @@ def test_near_probe_stress(precision, tol):
     near = _rel_err(E, Eo, mask=np.isin(np.arange(n), k))
     _say(f"[gpu]   rel err {err:.3e} (near-probe subset {near:.3e})")
     assert err <= tol
+
+
+@pytest.mark.parametrize("n,L,seed", [(40_000, 8, 91), (40_000, 14, 92), (60_000, 4, 93)],
+                         ids=["40k-L8", "40k-L14", "60k-L4"])
+def test_fp32_half_tile_near_field_sampled(n, L, seed):
+    """FP32 with the near field per half tile (the default where
+    l_max^2 <= sqrt(n)), at 200 sampled particles against the oracle."""
+    _say(f"[gpu] fp32 half-tile near field n={n} L={L} seed={seed}")
+    sp, op = _params(n, L, q_surface0=-9.0, precision=S.SIM_FP32_COMP, near_split=1)
+    st = W.uniform_shell(n, seed, 5.0, 0.0831)
+    u = np.array([0.0, 0.0, 0.3, 0.0])
+    with S.Sim(sp, st.pos, st.vel, u, start_step=2) as sim:
+        E = sim.eval_field()
+    targets = np.sort(np.random.default_rng(seed).choice(n, 200, replace=False))
+    Eo, _ = O.field(op, st.pos, q_surface=-9.0, u_asy=0.3, targets=targets)
+    rms = np.sqrt(np.mean(np.sum(Eo * Eo, axis=1)))
+    err = float(np.max(np.abs(E[targets] - Eo)) / rms)
+    _say(f"[gpu]   rel err {err:.3e}")
+    assert err <= FP32_FIELD_TOL
 
 
 def test_fp32_large_workload_sampled_field():

@@ -9,7 +9,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 from paper_2111_13072_amd import serve as SV  # noqa: E402
 
 
-def _shell(small_max, small_slots=1472, large_slots=4480, classes=(4, 8)):
+def _shell(small_max, small_slots=1536, large_slots=4608, classes=(4, 8)):
     """A server's routing state without its device pools."""
     srv = SV.Server.__new__(SV.Server)
     srv.small_max = small_max
@@ -27,11 +27,11 @@ def _req(n, L=4):
 
 
 def test_small_requests_go_to_the_small_pool_when_they_fit():
-    srv = _shell(1500)
+    srv = _shell(1600)
     assert srv.pool_key(_req(300)) == (4, 0)
-    assert srv.pool_key(_req(1472)) == (4, 0)       # 23 whole tiles: fits 1472 slots
-    assert srv.pool_key(_req(1473)) == (4, 1)       # 24 tiles: too big for the small pool
-    assert srv.pool_key(_req(1501)) == (4, 1)       # above small_max
+    assert srv.pool_key(_req(1536)) == (4, 0)       # 6 whole groups of 256: fits 1536 slots
+    assert srv.pool_key(_req(1537)) == (4, 1)       # 7 groups: too big for the small pool
+    assert srv.pool_key(_req(1601)) == (4, 1)       # above small_max
     assert srv.pool_key(_req(300, L=8)) == (8, 0)
 
 
