@@ -845,6 +845,8 @@ def bench_single(args, wl, precision: str):
             line["fp64_run"]["field_rel_err_vs_oracle"] = errs["fp64"]
         line["field_err_sample"] = ns
     print(json.dumps(line), flush=True)
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib * 2**20)
     return 0
 
 

@@ -1833,6 +1833,11 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
         double e;
         if (sg.ion_tab) {
             e = ((ct.q_surface + before) + ion_enclosed(sg, r, r2)) / (4.0 * kPi * ntilde * r2);
+        } else if constexpr (FP32) {
+            // FP64 rounding of the two opposing terms leaves ~1e-16 sqrt(N) of
+            // the field, far below the FP32 mode's error
+            const double q_enc = ct.q_surface + before;
+            e = (q_enc / (4.0 * kPi * ntilde) + sg.ion_density * (r2 * r - 1.0) / 3.0) * inv_r2;
         } else {
             e = gauss_field_uniform(ct.q_surface + before, ntilde, sg.ion_density, x, y, z);
         }
