@@ -420,18 +420,19 @@ def test_near_probe_stress(precision, tol):
     assert err <= tol
 
 
-@pytest.mark.parametrize("n,L,seed", [(40_000, 8, 91), (40_000, 14, 92), (60_000, 4, 93)],
-                         ids=["40k-L8", "40k-L14", "60k-L4"])
-def test_fp32_half_tile_near_field_sampled(n, L, seed):
-    """FP32 with the near field per half tile (the default where
-    l_max^2 <= sqrt(n)), at 200 sampled particles against the oracle."""
-    _say(f"[gpu] fp32 half-tile near field n={n} L={L} seed={seed}")
-    sp, op = _params(n, L, q_surface0=-9.0, precision=S.SIM_FP32_COMP, near_split=1)
+@pytest.mark.parametrize("n,L,seed,n_t", [(40_000, 8, 91, 200), (40_000, 14, 92, 200),
+                                           (60_000, 4, 93, 200), (1_200_000, 32, 94, 64)],
+                         ids=["40k-L8", "40k-L14", "60k-L4", "1.2M-L32"])
+def test_fp32_dense_sampled(n, L, seed, n_t):
+    """FP32 where l_max^2 <= sqrt(n) (the near field per half tile by
+    default), at sampled particles against the oracle."""
+    _say(f"[gpu] fp32 dense n={n} L={L} seed={seed}")
+    sp, op = _params(n, L, q_surface0=-9.0, precision=S.SIM_FP32_COMP)
     st = W.uniform_shell(n, seed, 5.0, 0.0831)
     u = np.array([0.0, 0.0, 0.3, 0.0])
     with S.Sim(sp, st.pos, st.vel, u, start_step=2) as sim:
         E = sim.eval_field()
-    targets = np.sort(np.random.default_rng(seed).choice(n, 200, replace=False))
+    targets = np.sort(np.random.default_rng(seed).choice(n, n_t, replace=False))
     Eo, _ = O.field(op, st.pos, q_surface=-9.0, u_asy=0.3, targets=targets)
     rms = np.sqrt(np.mean(np.sum(Eo * Eo, axis=1)))
     err = float(np.max(np.abs(E[targets] - Eo)) / rms)
