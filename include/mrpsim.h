@@ -84,13 +84,15 @@ enum { SIM_FP64 = 0, SIM_FP32_COMP = 1 };
  *   wall_bc     at r >= r_out: specular or diffuse.
  *   precision   SIM_FP64, or SIM_FP32_COMP: the field evaluation (far-field
  *               harmonics and contraction, near-field pair sums) in FP32 at
- *               tile-scaled coordinates, with FP64 moments, radial scans,
- *               l = 0 (Gauss) term, accumulation and positions; above
- *               l_max 32 the near-field pair sums run in FP64 too.  Field
- *               error against the FP64 definition: about 1e-5 of the RMS
- *               field or less for l_max <= 16 (measured at most 1.04e-5 on
- *               random inputs), <= 2e-5 up to 48.
- *   tile        particles per tile of the radial scan (0 = choose).
+ *               tile-scaled coordinates, compensated where a rounding would
+ *               act coherently (r^2 and z as hi + lo pairs in the
+ *               recurrences, per-m factors and coefficients rounded once from
+ *               FP64), with FP64 moments, radial scans, l = 0 (Gauss) term,
+ *               pair-sum accumulation, positions and velocities; from
+ *               l_max 20 the near-field pair sums run in FP64 too.  Field
+ *               error against the FP64 definition: <= 1e-5 of the RMS field
+ *               on every tested input up to l_max 64 (FP64: <= 1e-12).
+ *   tile        particles per tile of the radial scan: 0 or 64.
  *   seed        key of the counter-based generator of diffuse walls.
  *   mem_limit_bytes  0 = none; otherwise sim_create fails with SIM_ENOMEM
  *               when sim_footprint_bytes exceeds it.
@@ -270,8 +272,9 @@ void sim_destroy(sim_t *h);
  * member run alone.  A handle from sim_create is a batch of one member
  * (index 0), so every sim_member_* call also applies to it.
  *
- * Each member occupies ceil(n/64) tiles of 64 particle slots, ceil(tiles/64)
- * carry chunks and max(1, n/8) sort buckets of the handle's capacity, and
+ * Each member occupies ceil(n/256) groups of 256 particle slots (four tiles
+ * of 64), ceil(groups / carry_chunk) carry chunks (built-in: 8 to 64 groups
+ * each) and max(1, n/8) sort buckets of the handle's capacity, and
  * sim_member_data_bytes(n_steps, ion_profile_len) bytes of the batch's
  * member data pool (its drive, response and ion profile).  Admission and
  * retirement take and return these ranges without any device allocation.
