@@ -387,6 +387,7 @@ def bench_batch(args):
         tuned = T.autotune(T.batch_builder(members), cp, n_all, steps=5, warmup=2)
         cp = tuned.apply(cp)
         tuning = {"sort_bucket": tuned.sort_bucket, "carry_chunk": tuned.carry_chunk,
+                  "near_split": tuned.near_split,
                   "trial_ms_per_step": round(tuned.ms_per_step, 4),
                   "default_trial_ms_per_step": round(tuned.default_ms_per_step, 4)}
         print(f"[bench] autotune: {tuning}", file=sys.stderr, flush=True)
@@ -619,9 +620,13 @@ def bench_sweep(args):
     from paper_2111_13072_amd import workload as W
 
     fp32 = args.precision == "fp32c"
-    for L in (8, 16, 32):
-        for n_e in (1e15, 1e16):
-            for te in (1.0, 3.0, 5.0):
+    ls = tuple(int(v) for v in args.sweep_l.split(","))
+    plasmas = [(n_e, te) for n_e in (1e15, 1e16) for te in (1.0, 3.0, 5.0)]
+    if args.sweep_one_plasma:
+        plasmas = [(1e15, 3.0)]
+    for L in ls:
+        for n_e, te in plasmas:
+            if True:
                 wl = W.sweep_workload(L, n_e, te)
                 st = wl.particles()
                 n_total = args.warmup + args.steps + args.profile_steps + 1
@@ -675,6 +680,9 @@ def main(argv=None):
     ap.add_argument("--serve-small-max", type=int, default=200000,
                     help="serve: requests of at most this many particles get pools of their own "
                          "(0: one pool per l_max)")
+    ap.add_argument("--sweep-l", default="8,16,32", help="sweep: the l_max values")
+    ap.add_argument("--sweep-one-plasma", action="store_true",
+                    help="sweep: only n_e 1e15 m^-3, T_e 3 eV")
     ap.add_argument("--seq-steps", type=int, default=20,
                     help="batch64: timed steps of each member run alone, for comparison")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32c"],
@@ -760,6 +768,7 @@ def _leg(wl, st, precision: str, args, u, field: bool):
         tuned = T.autotune(T.sim_builder(st.pos, st.vel), prm, wl.n)
         prm = tuned.apply(prm)
         out["tuning"] = {"sort_bucket": tuned.sort_bucket, "carry_chunk": tuned.carry_chunk,
+                         "near_split": tuned.near_split,
                          "trial_ms_per_step": round(tuned.ms_per_step, 4),
                          "default_trial_ms_per_step": round(tuned.default_ms_per_step, 4)}
         print(f"[bench] autotune: {out['tuning']}", file=sys.stderr, flush=True)

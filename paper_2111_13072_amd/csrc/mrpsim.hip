@@ -178,8 +178,8 @@ struct KParams {
     int C;          // channels: (L+1)^2 - 1 (full) or L (axisymmetric)
     int C2;         // 2C: interior then exterior
     int SW;         // C2 + 1: group sums also carry the group's total charge
-    int HW;         // 4C + 2: a tile's half sums (interior h0, h1, exterior h0,
-                    // h1) and the charges of its halves
+    int HW;         // 4C + 2: a tile's row of H (interior and exterior sums
+                    // of the group's other tiles, of its own halves, charges)
     int n_tiles;    // tile capacity (particle slots / 64, a multiple of 4)
     int n_groups;   // n_tiles / 4
     int n_chunks;   // chunk capacity
@@ -609,9 +609,24 @@ __device__ inline double dpp_quad(double v)
     return __longlong_as_double((long long)(((uint64_t)phi << 32) | plo));
 }
 
-// The column block of a tile's row that quarter q of a folded row goes to:
-// the row is [interior h0 | interior h1 | exterior h0 | exterior h1 | charges].
-__device__ inline int quarter_block(int q) { return q == 0 ? 0 : q == 1 ? 2 : q == 2 ? 1 : 3; }
+// A tile's row of H: [interior | interior, half 0 | exterior | exterior,
+// half 1 | charges].  The flush stores the whole-tile sums in the interior
+// and exterior blocks and the charges of the two halves; the group tail then
+// replaces them by what the field kernel reads: the interior sums of the
+// group's tiles before this one, the exterior sums of those after it, and the
+// charge of the tiles before it.  The halves' own sums give a half the other
+// half's part.
+
+// The value of lane + 4 within its row of 16 lanes (DPP row_shl:4; the last
+// four lanes of a row read zero).
+__device__ inline double dpp_row_shl4(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x104, 0xF, 0xF, true);
+    const uint32_t phi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x104, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((uint64_t)phi << 32) | plo));
+}
 
 template <bool FULL>
 __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, KParams kp,
@@ -625,10 +640,14 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     //     slot; a slot holds two channels (cos and sin of one (l, m), or two
     //     degrees of m = 0);
     //  2. every kSlots slots each pair of lanes sums one quarter row
-    //     (kPartials entries each, then a lane exchange) and the pair's first
-    //     lane stores it in the tile's row of H.
-    // Last, the block adds its group's four tile rows into the group's row of
-    // the carry scan (GS: interior, exterior, charge).
+    //     (kPartials entries each, then a lane exchange); the pairs of half 0
+    //     add half 1's sum from four lanes on (the whole-tile sums) and the
+    //     pairs' first lanes store the whole-tile sums, the interior of half 0
+    //     and the exterior of half 1 in the tile's row of H.
+    // Last, the block adds its group's four whole-tile sums into the group's
+    // row of the carry scan (GS: interior, exterior, charge) and turns them
+    // into the in-group sums before (interior, charge) and after (exterior)
+    // each tile.
     // The m = 0 block is padded to an even count with a zero channel, so a
     // slot always holds two positions of the padded channel order.
     __shared__ double buf[kWavesPerBlock][kSlots * 2 * kRowLen];
@@ -638,7 +657,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     const uint32_t tile = uniform_u32(group * kTilesPerGroup + w);
     // the member (the same for the group's four tiles: a member's slots are
     // whole groups); n = its alive count, lt = the tile's index in it
-    bool tile_ok = false;
+    bool tile_ok = false, halves = false;
     uint32_t n = 0, lt = 0;
     if ((int)tile < kp.n_tiles) {
         const uint32_t mb = uniform_u32(mp.tile_member[tile]);
@@ -646,6 +665,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
             tile_ok = true;
             n = mp.ctl[mb].n_live;
             lt = tile - mp.seg[mb].t0;
+            // the halves' own sums only where the field kernel uses them
+            halves = uniform_u32((uint32_t)mp.seg[mb].near_w) == (uint32_t)kHalf;
         }
     }
     const uint32_t p = tile * kWave + lane;
@@ -684,7 +705,11 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     const int rr = v >> 2, rq = v & 3;
     const int rs = rr >> 1;
     const double *rd = wb + rr * kRowLen + rq * kQuarterOff + t * kPartials;
-    double *hdst = Ht + quarter_block(rq) * C;
+    // quarter rq = 0 (interior h0) stores the interior whole-tile sum and
+    // itself; 1 (exterior h0) the exterior whole-tile sum; 3 (exterior h1)
+    // itself; 2 (interior h1) nothing
+    double *hdst_sum = Ht + (rq == 0 ? 0 : 2) * C;
+    double *hdst_own = Ht + (rq == 0 ? 1 : 3) * C;
     const int pad0 = L & 1;             // zero channel after the m = 0 block
     const int n_pos = C + pad0;         // padded channel positions
     int slot = 0, base = 0;             // base: padded position of slot 0
@@ -694,10 +719,14 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
 #pragma unroll
         for (int k = 1; k < kPartials; ++k) acc += rd[k];
         acc += dpp_quad<0xB1>(acc);
+        const double whole = acc + dpp_row_shl4(acc);   // quarters 0, 1: + quarters 2, 3
         const int pos = base + rr;      // padded position
         // padded position -> channel: the m = 0 block is positions 0..L-1
         const int ch = pos < L ? pos : pos - pad0;
-        if (tile_ok && t == 0 && rs < slot && pos < n_pos && !(pad0 && pos == L)) hdst[ch] = acc;
+        if (tile_ok && t == 0 && rs < slot && pos < n_pos && !(pad0 && pos == L)) {
+            if (rq < 2) hdst_sum[ch] = whole;
+            if (halves && (rq == 0 || rq == 3)) hdst_own[ch] = acc;
+        }
         wave_lds_sync();
         base += 2 * kSlots;
         slot = 0;
@@ -781,22 +810,47 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     }
     if (slot > 0) flush();   // last, partial batch: slots >= slot hold stale values
 
-    // The group's row of the carry scan: its four tiles' half sums, read back
-    // from memory once every wave of the block has stored its row.
+    // The group's row of the carry scan: its four tiles' whole-tile sums, read
+    // back from memory once every wave of the block has stored its row; each
+    // column of the tile rows is then replaced by its in-group sum before the
+    // tile (interior, charge: tiles 0.. t-1, in that order) or after it
+    // (exterior: tiles 3 .. t+1).
     __threadfence_block();
     __syncthreads();
     if (!tile_ok) return;   // the same for the group's four tiles
-    const double *Hg = H + (size_t)group * kTilesPerGroup * kp.HW;
+    double *Hg = H + (size_t)group * kTilesPerGroup * kp.HW;
     double *Gs = GS + (size_t)group * kp.SW;
     for (int c = threadIdx.x; c < kp.SW; c += kBlock) {
-        // group column c (interior channel, exterior channel, or the charge)
-        // and the two half columns of a tile row it sums
-        const int a = c < C ? c : (c < kp.C2 ? C + c : 4 * C);
-        const int b = c < C ? C + c : (c < kp.C2 ? 2 * C + c : 4 * C + 1);
-        double s = 0.0;
+        double v[kTilesPerGroup];
+        if (c < kp.C2) {
+            const int a = c < C ? c : C + c;   // the column of a tile row
 #pragma unroll
-        for (int k = 0; k < kTilesPerGroup; ++k) s += Hg[k * kp.HW + a] + Hg[k * kp.HW + b];
-        Gs[c] = s;
+            for (int k = 0; k < kTilesPerGroup; ++k) v[k] = Hg[k * kp.HW + a];
+            double s = 0.0;
+            if (c < C) {
+#pragma unroll
+                for (int k = 0; k < kTilesPerGroup; ++k) {
+                    Hg[k * kp.HW + a] = s;
+                    s += v[k];
+                }
+            } else {
+#pragma unroll
+                for (int k = kTilesPerGroup - 1; k >= 0; --k) {
+                    Hg[k * kp.HW + a] = s;
+                    s += v[k];
+                }
+            }
+            Gs[c] = s;
+        } else {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < kTilesPerGroup; ++k) {
+                const double q = Hg[k * kp.HW + 4 * C] + Hg[k * kp.HW + 4 * C + 1];
+                Hg[k * kp.HW + 4 * C] = s;
+                s += q;
+            }
+            Gs[c] = s;
+        }
     }
 }
 
@@ -1685,45 +1739,66 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
             pw_out = exp2((lane + 1.0) * lg);
         }
         int win0 = 0, win_len = -1;   // resident channels [win0, win0 + win_len)
-        auto stage = [&](int k0, int k1) {
-            if (win_len < 0 || k1 > win0 + win_len) {
-                if (win_len >= 0) wave_lds_sync();   // the old window's reads are done
-                const int len = min(kWin, C - k0);
-                const int n_iter = (len + kWave - 1) / kWave;
-                for (int it = 0; it < n_iter; ++it) {
-                    const int i = it * kWave + lane;
-                    const bool in_win = i < len;
-                    const int c = k0 + (in_win ? i : 0);
-                    double yin = 0.0, yout = 0.0;
-                    for (int t = 0; t < w; ++t)
-                        yin += Hg[t * kp.HW + c] + Hg[t * kp.HW + C + c];
-                    for (int t = kTilesPerGroup - 1; t > w; --t)
-                        yout += Hg[t * kp.HW + 2 * C + c] + Hg[t * kp.HW + 3 * C + c];
+        // Fills the window with channels [k0, k0 + len), U channels per lane at a
+        // time with all their loads issued before the first use.  The first
+        // window is filled before the far field starts (no other work of the
+        // wave could hide its loads then, and few registers are live: U = 2);
+        // a window moved inside the far field fills two channels at a time at
+        // four waves per SIMD, one at six.
+        auto fill = [&](int k0, int len, auto u_tag) {
+            constexpr int U = decltype(u_tag)::value;
+            const int n_iter = (len + kWave - 1) / kWave;
+            for (int it0 = 0; it0 < n_iter; it0 += U) {
+                double yin[U], yout[U], hin[U], hout[U], ci[U], co[U], gsc[U];
+                int src[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int i = (it0 + u) * kWave + lane;
+                    const int c = k0 + (i < len ? i : 0);
+                    // the interior sums of the group's tiles before this one,
+                    // the exterior sums of those after it, and the halves' own
+                    // sums
                     const double *Ht = Hg + w * kp.HW;
-                    const double gsc = tb.chg[c] * inv_nt;
-                    const double ci = CRg[c], co = CRg[C + c];
-                    const double hin = split ? Ht[c] : 0.0, hout = split ? Ht[3 * C + c] : 0.0;
-                    double a0 = ci + gsc * yin, a1 = ci + gsc * (yin + hin);
-                    double b1 = co + gsc * yout, b0 = co + gsc * (yout + hout);
+                    yin[u] = Ht[c];
+                    yout[u] = Ht[2 * C + c];
+                    hin[u] = split ? Ht[C + c] : 0.0;
+                    hout[u] = split ? Ht[3 * C + c] : 0.0;
+                    ci[u] = CRg[c];
+                    co[u] = CRg[C + c];
+                    gsc[u] = tb.chg[c] * inv_nt;
+                    src[u] = FP32 ? 4 * (tb.chl[c] - 1) : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int i = (it0 + u) * kWave + lane;
+                    double a0 = ci[u] + gsc[u] * yin[u], a1 = ci[u] + gsc[u] * (yin[u] + hin[u]);
+                    double b1 = co[u] + gsc[u] * yout[u], b0 = co[u] + gsc[u] * (yout[u] + hout[u]);
                     if (FP32) {
                         // every lane takes part in the fetches
-                        const int src = 4 * (tb.chl[c] - 1);
-                        const double si = bpermute(src, pw_in), so = bpermute(src, pw_out);
+                        const double si = bpermute(src[u], pw_in), so = bpermute(src[u], pw_out);
                         a0 *= si;
                         a1 *= si;
                         b0 *= so;
                         b1 *= so;
                     }
-                    if (in_win) {
+                    if (i < len) {
                         cbuf[i] = (RF)a0;
                         cbuf[kWin + i] = (RF)b0;
                         cbuf[kH1 + i] = (RF)a1;
                         cbuf[kH1 + kWin + i] = (RF)b1;
                     }
                 }
-                wave_lds_sync();
-                win0 = k0;
-                win_len = len;
+            }
+            wave_lds_sync();
+            win0 = k0;
+            win_len = len;
+        };
+        fill(0, min(kWin, C), std::integral_constant<int, 2>());
+        auto stage = [&](int k0, int k1) {
+            if (k1 > win0 + win_len) {
+                wave_lds_sync();   // the old window's reads are done
+                // (the FP32 kernel at six waves per SIMD has no registers to spare)
+                fill(k0, min(kWin, C - k0), std::integral_constant<int, FP32 && !NEAR64 ? 1 : 2>());
             }
             return CfView<RF>{cbuf + (lane >= kHalf ? kH1 : 0), win0, kWin};
         };
@@ -1825,9 +1900,8 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
         const uint64_t below = (1ull << lane) - 1ull;
         const int n_below = __popcll(__ballot(valid) & below);
         const int i_below = __popcll(__ballot(ion) & below);
-        // the group's particles before this tile: whole half charges (exact)
-        double in_group = 0.0;
-        for (int t = 0; t < w; ++t) in_group += Hg[t * kp.HW + 4 * kp.C] + Hg[t * kp.HW + 4 * kp.C + 1];
+        // the group's particles before this tile (exact counts)
+        const double in_group = Hg[w * kp.HW + 4 * kp.C];
         const double before =
             (qpre[group] + in_group) + ((double)i_below + kQ * (double)(n_below - i_below));
         double e;

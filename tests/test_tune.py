@@ -1,6 +1,6 @@
-"""The launch-size autotuner (sort bucket, carry chunk): its search and cache
-on the CPU with a synthetic timing model; on the GPU, that tuned sizes give
-the field of the default sizes."""
+"""The launch-size autotuner (sort bucket, carry chunk, near-field
+block): its search and cache on the CPU with a synthetic timing model; on the
+GPU, that tuned sizes give the field of the default sizes."""
 import json
 
 import numpy as np
@@ -18,9 +18,9 @@ class _Fake:
         self.built = []
 
     def __call__(self, p):
-        self.built.append((p.sort_bucket, p.carry_chunk))
+        self.built.append((p.sort_bucket, p.carry_chunk, p.near_split))
         h = T.RunnerHandle(lambda k: None, lambda: None)
-        h.cost = self.cost(p.sort_bucket, p.carry_chunk)
+        h.cost = self.cost(p.sort_bucket, p.carry_chunk) + (0.25 if p.near_split < 0 else 0.0)
         return h
 
 
@@ -35,9 +35,26 @@ def test_coordinate_search_finds_the_minimum_along_its_path():
     t = T.autotune(f, S.SimParams(l_max=8), 100_000, measure=_measure)
     assert (t.sort_bucket, t.carry_chunk) == (16, 32)
     assert t.ms_per_step == cost(16, 32) and t.default_ms_per_step == cost(8, 0)
-    # every candidate built at most once, each one closed
-    assert len(f.built) == len(set(f.built)) == len(T.BUCKETS) + len(T.CHUNKS) - 1
+    # every candidate built at most once, each one closed; the near-field
+    # block is a third coordinate (whole tiles cost more here)
+    assert len(f.built) == len(set(f.built)) == len(T.BUCKETS) + len(T.CHUNKS) - 1 + 1
+    assert t.near_split == 0
     assert t.apply(S.SimParams(l_max=8)).sort_bucket == 16
+
+
+def test_near_field_block_is_searched_never_forcing_half_tiles():
+    f = _Fake(lambda b, c: 1.0)
+    t = T.autotune(f, S.SimParams(precision=S.SIM_FP32_COMP), 1000, measure=_measure)
+    assert all(s in (0, -1) for _, _, s in f.built) and t.near_split == 0
+    g = _Fake(lambda b, c: 1.0)
+
+    def cheaper_whole_tiles(p):
+        h = g(p)
+        h.cost = 0.5 if p.near_split < 0 else 1.0
+        return h
+
+    t = T.autotune(cheaper_whole_tiles, S.SimParams(), 1000, measure=_measure)
+    assert t.near_split == -1 and t.apply(S.SimParams()).near_split == -1
 
 
 def test_ties_keep_the_smaller_size_and_default_is_a_candidate():
@@ -85,13 +102,13 @@ def test_tuned_sizes_keep_the_field():
     print(f"[gpu] autotune n={n} L=8", file=sys.stderr, flush=True)
     t = T.autotune(T.sim_builder(st.pos, st.vel), prm, n, steps=3, warmup=1, reps=1)
     assert t.sort_bucket in T.BUCKETS and t.carry_chunk in T.CHUNKS
-    assert len(t.trials) == len(T.BUCKETS) + len(T.CHUNKS) - 1
+    assert len(t.trials) == len(T.BUCKETS) + len(T.CHUNKS) - 1 + 1
     u = np.zeros(4)
     with S.Sim(prm, st.pos, st.vel, u) as s:
         E0 = s.eval_field()
     rms = np.sqrt(np.mean(np.sum(E0 * E0, axis=1)))
-    for b, c in ((t.sort_bucket, t.carry_chunk), (4, 8), (64, 128)):
-        with S.Sim(S.SimParams(ntilde=prm.ntilde, l_max=8, sort_bucket=b, carry_chunk=c),
-                   st.pos, st.vel, u) as s:
+    for b, c, sp in ((t.sort_bucket, t.carry_chunk, t.near_split), (4, 8, 0), (64, 128, -1)):
+        with S.Sim(S.SimParams(ntilde=prm.ntilde, l_max=8, sort_bucket=b, carry_chunk=c,
+                               near_split=sp), st.pos, st.vel, u) as s:
             E = s.eval_field()
-        assert np.max(np.abs(E - E0)) <= 1e-13 * rms, (b, c)
+        assert np.max(np.abs(E - E0)) <= 1e-13 * rms, (b, c, sp)
