@@ -610,12 +610,10 @@ __device__ inline double dpp_quad(double v)
 }
 
 // A tile's row of H: [interior | interior, half 0 | exterior | exterior,
-// half 1 | charges].  The flush stores the whole-tile sums in the interior
-// and exterior blocks and the charges of the two halves; the group tail then
-// replaces them by what the field kernel reads: the interior sums of the
-// group's tiles before this one, the exterior sums of those after it, and the
-// charge of the tiles before it.  The halves' own sums give a half the other
-// half's part.
+// half 1 | charge, unused]: the interior sums of the group's tiles before
+// this one, the halves' own sums (a half's coefficients take the other half's
+// part from them), the exterior sums of the group's tiles after this one, and
+// the charge of the group's tiles before this one.
 
 // The value of lane + 4 within its row of 16 lanes (DPP row_shl:4; the last
 // four lanes of a row read zero).
@@ -629,7 +627,7 @@ __device__ inline double dpp_row_shl4(double v)
 }
 
 template <bool FULL>
-__global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, KParams kp,
+__global__ __launch_bounds__(kBlock, 8) void k_moments(Map mp, State B, Tables tb, KParams kp,
                                                     double *H, double *GS)
 {
     // Per wave (one tile of 64 particles), the sums of q R (interior) and
@@ -641,16 +639,26 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     //     degrees of m = 0);
     //  2. every kSlots slots each pair of lanes sums one quarter row
     //     (kPartials entries each, then a lane exchange); the pairs of half 0
-    //     add half 1's sum from four lanes on (the whole-tile sums) and the
-    //     pairs' first lanes store the whole-tile sums, the interior of half 0
-    //     and the exterior of half 1 in the tile's row of H.
-    // Last, the block adds its group's four whole-tile sums into the group's
-    // row of the carry scan (GS: interior, exterior, charge) and turns them
-    // into the in-group sums before (interior, charge) and after (exterior)
-    // each tile.
+    //     add half 1's sum from four lanes on (the whole-tile sums), and the
+    //     halves' own sums (interior of half 0, exterior of half 1) go to the
+    //     tile's row of H;
+    //  3. every kXBatches batches the four waves of the block (the group's
+    //     tiles) trade their whole-tile sums through LDS, one channel and
+    //     side per lane: each stores in its tile's row of H the interior
+    //     sums of the tiles before it and the exterior sums of those after
+    //     it; the last and first wave store the group's interior and
+    //     exterior totals in its row of the carry scan (GS: interior,
+    //     exterior, charge).
     // The m = 0 block is padded to an even count with a zero channel, so a
     // slot always holds two positions of the padded channel order.
     __shared__ double buf[kWavesPerBlock][kSlots * 2 * kRowLen];
+    // whole-tile sums of kXBatches batches, per wave (interior, exterior),
+    // two sets in turn so that one barrier per exchange suffices
+    constexpr int kXBatches = 2;
+    constexpr int kXLen = kXBatches * 2 * kSlots;
+    static_assert(2 * kXLen <= kWave, "one channel and side per lane in an exchange");
+    __shared__ double xch[2][kWavesPerBlock][2][kXLen];
+    __shared__ double qx[kWavesPerBlock];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const uint32_t group = blockIdx.x;
@@ -686,13 +694,19 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     const int L = kp.L;
     const int C = kp.C;
     double *Ht = H + (size_t)tile * kp.HW;
+    double *Gs = GS + (size_t)group * kp.SW;
     {
-        // the charges of the tile's halves (exact: counts of ions and electrons)
+        // the tile's charge (exact: counts of ions and electrons), then the
+        // group's tiles before this one (in tile order) and the group's total
         const uint64_t vb = __ballot(valid), ib = __ballot(valid && ion);
-        if (tile_ok && lane < 2) {
-            const uint64_t hm = lane ? 0xffffffff00000000ull : 0x00000000ffffffffull;
-            const int n_val = __popcll(vb & hm), n_ion = __popcll(ib & hm);
-            Ht[4 * C + lane] = (double)n_ion + kQ * (double)(n_val - n_ion);
+        const int n_val = __popcll(vb), n_ion = __popcll(ib);
+        if (lane == 0) qx[w] = (double)n_ion + kQ * (double)(n_val - n_ion);
+        __syncthreads();
+        if (tile_ok && lane == 0) {
+            double sq = 0.0;
+            for (int k = 0; k < w; ++k) sq += qx[k];
+            Ht[4 * C] = sq;
+            if (w == kWavesPerBlock - 1) Gs[kp.C2] = sq + qx[w];
         }
     }
 
@@ -705,14 +719,42 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
     const int rr = v >> 2, rq = v & 3;
     const int rs = rr >> 1;
     const double *rd = wb + rr * kRowLen + rq * kQuarterOff + t * kPartials;
-    // quarter rq = 0 (interior h0) stores the interior whole-tile sum and
-    // itself; 1 (exterior h0) the exterior whole-tile sum; 3 (exterior h1)
-    // itself; 2 (interior h1) nothing
-    double *hdst_sum = Ht + (rq == 0 ? 0 : 2) * C;
+    // quarters rq = 0 (interior h0) and 1 (exterior h0) pass on the
+    // whole-tile sums; 0 and 3 (exterior h1) store their own sums
     double *hdst_own = Ht + (rq == 0 ? 1 : 3) * C;
     const int pad0 = L & 1;             // zero channel after the m = 0 block
     const int n_pos = C + pad0;         // padded channel positions
     int slot = 0, base = 0;             // base: padded position of slot 0
+    int xs = 0, xb = 0, xbase = 0;      // exchange set, its batches, its first position
+    // an exchange's lane: side io (0: interior, 1: exterior), entry xj; the
+    // weights of the four tiles' sums in its in-group sum
+    const bool x_on = lane < 2 * kXLen;
+    const int io = (lane / kXLen) & 1, xj = lane & (kXLen - 1);
+    double xw[kWavesPerBlock];
+#pragma unroll
+    for (int k = 0; k < kWavesPerBlock; ++k) xw[k] = (io == 0 ? k < w : k > w) ? 1.0 : 0.0;
+    auto exchange = [&]() {
+        __syncthreads();
+        const int pos = xbase + xj;
+        double v[kWavesPerBlock];
+#pragma unroll
+        for (int k = 0; k < kWavesPerBlock; ++k) v[k] = xch[xs][k][io][xj];
+        // interior: the tiles before this one; exterior: those after it (the
+        // 0/1 weights make the FMAs plain sums)
+        double sp = 0.0;
+#pragma unroll
+        for (int k = 0; k < kWavesPerBlock; ++k) sp = fma(xw[k], v[k], sp);
+        const int ch = pos < L ? pos : pos - pad0;
+        if (x_on && tile_ok && pos < xbase + xb * 2 * kSlots && pos < n_pos &&
+            !(pad0 && pos == L)) {
+            Ht[2 * io * C + ch] = sp;
+            if (io == 0 && w == kWavesPerBlock - 1) Gs[ch] = sp + v[kWavesPerBlock - 1];
+            if (io == 1 && w == 0) Gs[C + ch] = sp + v[0];
+        }
+        xs ^= 1;
+        xbase += xb * 2 * kSlots;
+        xb = 0;
+    };
     auto flush = [&]() {
         wave_lds_sync();
         double acc = rd[0];
@@ -720,16 +762,17 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         for (int k = 1; k < kPartials; ++k) acc += rd[k];
         acc += dpp_quad<0xB1>(acc);
         const double whole = acc + dpp_row_shl4(acc);   // quarters 0, 1: + quarters 2, 3
+        if (t == 0 && rq < 2) xch[xs][w][rq][xb * 2 * kSlots + rr] = whole;
         const int pos = base + rr;      // padded position
         // padded position -> channel: the m = 0 block is positions 0..L-1
         const int ch = pos < L ? pos : pos - pad0;
-        if (tile_ok && t == 0 && rs < slot && pos < n_pos && !(pad0 && pos == L)) {
-            if (rq < 2) hdst_sum[ch] = whole;
-            if (halves && (rq == 0 || rq == 3)) hdst_own[ch] = acc;
-        }
+        if (halves && tile_ok && t == 0 && (rq == 0 || rq == 3) && rs < slot && pos < n_pos &&
+            !(pad0 && pos == L))
+            hdst_own[ch] = acc;
         wave_lds_sync();
         base += 2 * kSlots;
         slot = 0;
+        if (++xb == kXBatches) exchange();
     };
     // one slot from two channels (R, I each)
     auto put2 = [&](double r0, double i0, double r1, double i1) {
@@ -809,49 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Map mp, State B, Tables tb, 
         }
     }
     if (slot > 0) flush();   // last, partial batch: slots >= slot hold stale values
-
-    // The group's row of the carry scan: its four tiles' whole-tile sums, read
-    // back from memory once every wave of the block has stored its row; each
-    // column of the tile rows is then replaced by its in-group sum before the
-    // tile (interior, charge: tiles 0.. t-1, in that order) or after it
-    // (exterior: tiles 3 .. t+1).
-    __threadfence_block();
-    __syncthreads();
-    if (!tile_ok) return;   // the same for the group's four tiles
-    double *Hg = H + (size_t)group * kTilesPerGroup * kp.HW;
-    double *Gs = GS + (size_t)group * kp.SW;
-    for (int c = threadIdx.x; c < kp.SW; c += kBlock) {
-        double v[kTilesPerGroup];
-        if (c < kp.C2) {
-            const int a = c < C ? c : C + c;   // the column of a tile row
-#pragma unroll
-            for (int k = 0; k < kTilesPerGroup; ++k) v[k] = Hg[k * kp.HW + a];
-            double s = 0.0;
-            if (c < C) {
-#pragma unroll
-                for (int k = 0; k < kTilesPerGroup; ++k) {
-                    Hg[k * kp.HW + a] = s;
-                    s += v[k];
-                }
-            } else {
-#pragma unroll
-                for (int k = kTilesPerGroup - 1; k >= 0; --k) {
-                    Hg[k * kp.HW + a] = s;
-                    s += v[k];
-                }
-            }
-            Gs[c] = s;
-        } else {
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < kTilesPerGroup; ++k) {
-                const double q = Hg[k * kp.HW + 4 * C] + Hg[k * kp.HW + 4 * C + 1];
-                Hg[k * kp.HW + 4 * C] = s;
-                s += q;
-            }
-            Gs[c] = s;
-        }
-    }
+    if (xb > 0) exchange();
 }
 
 // ---------------------------------------------------------------------------
