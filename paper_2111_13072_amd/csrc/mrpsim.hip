@@ -1185,14 +1185,16 @@ __device__ inline double gauss_field_uniform(double charge, double ntilde, doubl
 //              + (e_z - cos th rhat) sum U D_z Qh + (sum Qh dU/dx, sum Qh dU/dy, 0).
 // (Assembling the radial part from the two partial derivatives of Q instead
 // loses a factor ~l to cancellation.)
-// Where the far field reads the coefficients of channel k: interior at
-// p[k - base], exterior at p[stride + k - base].
+// Where the far field reads the coefficients of channel k: interior and
+// exterior side by side at p[2 (k - base)] and p[2 (k - base) + 1] (the
+// channels of a few consecutive degrees lie within one LDS instruction's
+// offset range of a single address).
 template <typename R>
 struct CfView {
     const R *p;
-    int base, stride;
-    __device__ R a(int k) const { return p[k - base]; }
-    __device__ R b(int k) const { return p[stride + k - base]; }
+    int base;
+    __device__ R a(int k) const { return p[2 * (k - base)]; }
+    __device__ R b(int k) const { return p[2 * (k - base) + 1]; }
 };
 
 // stage(k0, k1) returns a view holding channels [k0, k1): the m = 0 block,
@@ -1506,10 +1508,11 @@ __device__ inline void near_field_full(int lane, int W, int L, const LG *lg, con
             // FP32: w = 1 - u = |xh_j - xh_k|^2 / 2 (for nearly parallel
             // directions the difference is exact, so w keeps its relative
             // precision where a dot product would leave 1 - u an absolute
-            // 2^-24), and the Legendre recurrence runs on the differences
-            // D_l = P_l - P_{l-1}: (l+1) D_{l+1} = l D_l - (2l+1) w P_l.  Near
-            // u = 1, where the sums of rho^l P_l and rho^l P'_l amplify errors
-            // in u, this keeps P_l to FP32 relative precision.
+            // 2^-24), and the Legendre recurrence runs on the scaled
+            // differences E_l = l (P_l - P_{l-1}): E_{l+1} = E_l - (2l+1) w P_l,
+            // P_{l+1} = P_l + E_{l+1} / (l+1).  Near u = 1, where the sums of
+            // rho^l P_l and rho^l P'_l amplify errors in u, this keeps P_l to
+            // FP32 relative precision.
             const R dx = xj - xh, dy = yj - yh, dz = zj - zh;
             const R w = 0.5f * fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             u = 1.0f - w;
@@ -1517,12 +1520,12 @@ __device__ inline void near_field_full(int lane, int W, int L, const LG *lg, con
             Sl = S1;
             SB = rho;
             // two degrees per pass, the registers of degree l and l + 1
-            // trading roles: (Pa, Da, dPa) hold P_l, D_l, P'_l and dPb
+            // trading roles: (Pa, Da, dPa) hold P_l, E_l, P'_l and dPb
             // P'_{l-1}, which the first half overwrites with P'_{l+1}
             R Pa = u, Da = -w, dPa = 1, dPb = 0, rl = rho, Pb, Db;
             auto degree = [&](const LG c, R &P, R &D, R &dPm, R &Pn, R &Dn) {
-                Dn = fmaf(c.x, D, c.y * (w * P));
-                Pn = P + Dn;
+                Dn = fmaf(-(c.z * w), P, D);
+                Pn = fmaf(c.x, Dn, P);
                 dPm = fmaf(c.z, P, dPm);   // P'_{l+1} = P'_{l-1} + (2l+1) P_l
                 rl = fmaf(-rl, del, rl);
                 const R t = rl * Pn;
@@ -1783,10 +1786,10 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
                         b1 *= so;
                     }
                     if (i < len) {
-                        cbuf[i] = (RF)a0;
-                        cbuf[kWin + i] = (RF)b0;
-                        cbuf[kH1 + i] = (RF)a1;
-                        cbuf[kH1 + kWin + i] = (RF)b1;
+                        cbuf[2 * i] = (RF)a0;
+                        cbuf[2 * i + 1] = (RF)b0;
+                        cbuf[kH1 + 2 * i] = (RF)a1;
+                        cbuf[kH1 + 2 * i + 1] = (RF)b1;
                     }
                 }
             }
@@ -1801,7 +1804,7 @@ __global__ __launch_bounds__(kBlock, FP32 && !NEAR64 ? 6 : 4) void k_field_push(
                 // (the FP32 kernel at six waves per SIMD has no registers to spare)
                 fill(k0, min(kWin, C - k0), std::integral_constant<int, FP32 && !NEAR64 ? 1 : 2>());
             }
-            return CfView<RF>{cbuf + (lane >= kHalf ? kH1 : 0), win0, kWin};
+            return CfView<RF>{cbuf + (lane >= kHalf ? kH1 : 0), win0};
         };
         far_field<FULL, RF>(stage, L, fq, xs, ys, zs, gx, gy, gz);
         wave_lds_sync();   // read before the rows below overwrite them
@@ -2648,8 +2651,8 @@ int make_host_tables(const sim_params &p, const Layout &lo, HostTables *ht)
         for (size_t i = 0; i < 4 * ntri; ++i) tab32[fq4_32_offset(L) + i] = (float)fq[i];
         float *lw = tab32.data() + lw4_32_offset(L);
         for (int l = 0; l <= L; ++l) {
-            lw[4 * l + 0] = (float)((double)l / (l + 1.0));
-            lw[4 * l + 1] = (float)(-(2.0 * l + 1.0) / (l + 1.0));
+            lw[4 * l + 0] = (float)(1.0 / (l + 1.0));
+            lw[4 * l + 1] = 0.0f;
             lw[4 * l + 2] = (float)(2.0 * l + 1.0);
             lw[4 * l + 3] = (float)(l + 1.0);
         }
