@@ -613,9 +613,10 @@ def bench_spectrum(args):
 
 def bench_sweep(args):
     """Scale and accuracy sweep: 1.6e7 particles at l_max 8, 16, 32 for
-    n_e in {1e15, 1e16} m^-3 and T_e in {1, 3, 5} eV (FP32-compensated by
-    default): one JSON line per run with its particle-steps/s and kernel
-    times, each timed over --steps steps after --warmup."""
+    n_e in {1e15, 1e16} m^-3 and T_e in {1, 3, 5} eV (FP64, or
+    FP32-compensated with --precision fp32c): one JSON line per run with its
+    particle-steps/s and kernel times, each timed over --steps steps after
+    --warmup."""
     from paper_2111_13072_amd import sim as S
     from paper_2111_13072_amd import workload as W
 

@@ -652,12 +652,13 @@ __global__ __launch_bounds__(kBlock, 8) void k_moments(Map mp, State B, Tables t
     // The m = 0 block is padded to an even count with a zero channel, so a
     // slot always holds two positions of the padded channel order.
     __shared__ double buf[kWavesPerBlock][kSlots * 2 * kRowLen];
-    // whole-tile sums of kXBatches batches, per wave (interior, exterior),
-    // two sets in turn so that one barrier per exchange suffices
-    constexpr int kXBatches = 2;
+    // whole-tile sums of kXBatches batches, per wave (interior, exterior):
+    // one channel and side per lane of an exchange (one set, with a barrier
+    // before and after its reads, keeps eight waves per SIMD)
+    constexpr int kXBatches = 4;
     constexpr int kXLen = kXBatches * 2 * kSlots;
     static_assert(2 * kXLen <= kWave, "one channel and side per lane in an exchange");
-    __shared__ double xch[2][kWavesPerBlock][2][kXLen];
+    __shared__ double xch[kWavesPerBlock][2][kXLen];
     __shared__ double qx[kWavesPerBlock];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -725,7 +726,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_moments(Map mp, State B, Tables t
     const int pad0 = L & 1;             // zero channel after the m = 0 block
     const int n_pos = C + pad0;         // padded channel positions
     int slot = 0, base = 0;             // base: padded position of slot 0
-    int xs = 0, xb = 0, xbase = 0;      // exchange set, its batches, its first position
+    int xb = 0, xbase = 0;              // the exchange's batches, its first position
     // an exchange's lane: side io (0: interior, 1: exterior), entry xj; the
     // weights of the four tiles' sums in its in-group sum
     const bool x_on = lane < 2 * kXLen;
@@ -733,12 +734,13 @@ __global__ __launch_bounds__(kBlock, 8) void k_moments(Map mp, State B, Tables t
     double xw[kWavesPerBlock];
 #pragma unroll
     for (int k = 0; k < kWavesPerBlock; ++k) xw[k] = (io == 0 ? k < w : k > w) ? 1.0 : 0.0;
+    const bool own_q = halves && tile_ok && t == 0 && (rq == 0 || rq == 3);
     auto exchange = [&]() {
         __syncthreads();
         const int pos = xbase + xj;
         double v[kWavesPerBlock];
 #pragma unroll
-        for (int k = 0; k < kWavesPerBlock; ++k) v[k] = xch[xs][k][io][xj];
+        for (int k = 0; k < kWavesPerBlock; ++k) v[k] = xch[k][io][xj];
         // interior: the tiles before this one; exterior: those after it (the
         // 0/1 weights make the FMAs plain sums)
         double sp = 0.0;
@@ -751,7 +753,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_moments(Map mp, State B, Tables t
             if (io == 0 && w == kWavesPerBlock - 1) Gs[ch] = sp + v[kWavesPerBlock - 1];
             if (io == 1 && w == 0) Gs[C + ch] = sp + v[0];
         }
-        xs ^= 1;
+        __syncthreads();
         xbase += xb * 2 * kSlots;
         xb = 0;
     };
@@ -762,12 +764,11 @@ __global__ __launch_bounds__(kBlock, 8) void k_moments(Map mp, State B, Tables t
         for (int k = 1; k < kPartials; ++k) acc += rd[k];
         acc += dpp_quad<0xB1>(acc);
         const double whole = acc + dpp_row_shl4(acc);   // quarters 0, 1: + quarters 2, 3
-        if (t == 0 && rq < 2) xch[xs][w][rq][xb * 2 * kSlots + rr] = whole;
+        if (t == 0 && rq < 2) xch[w][rq][xb * 2 * kSlots + rr] = whole;
         const int pos = base + rr;      // padded position
         // padded position -> channel: the m = 0 block is positions 0..L-1
         const int ch = pos < L ? pos : pos - pad0;
-        if (halves && tile_ok && t == 0 && (rq == 0 || rq == 3) && rs < slot && pos < n_pos &&
-            !(pad0 && pos == L))
+        if (own_q && rs < slot && pos < n_pos && !(pad0 && pos == L))
             hdst_own[ch] = acc;
         wave_lds_sync();
         base += 2 * kSlots;
