@@ -169,6 +169,18 @@ def _counter_by_kernel(pmc_dir, counter):
     return acc
 
 
+def _copy_scales(cf, cw, copy_bytes: int):
+    """Scales of FETCH_SIZE and WRITE_SIZE from the plain copy's readings (KiB)
+    of copy_bytes in and out; 1 where the run holds no copy kernel.  A copy
+    without its size would scale every figure to zero, so it is an error."""
+    if (cf or cw) and copy_bytes <= 0:
+        raise ValueError("the counters hold the calibration copy: give its size "
+                         "(--calibrate-copy-mib)")
+    sf = copy_bytes / (cf * 1024.0) if cf else 1.0
+    sw = copy_bytes / (cw * 1024.0) if cw else 1.0
+    return sf, sw
+
+
 def summarize_traffic(fetch_dir: str, write_dir: str, out_json: str, workload: str,
                       kernel: str, copy_bytes: int, commands: list):
     """HBM bytes per launch of `kernel` from FETCH_SIZE / WRITE_SIZE (KiB per
@@ -189,8 +201,7 @@ def summarize_traffic(fetch_dir: str, write_dir: str, out_json: str, workload: s
 
     kf, kw = pick(f, kernel), pick(w, kernel)
     cf, cw = pick_copy(f), pick_copy(w)
-    sf = copy_bytes / (cf * 1024.0) if cf else 1.0
-    sw = copy_bytes / (cw * 1024.0) if cw else 1.0
+    sf, sw = _copy_scales(cf, cw, copy_bytes)
     d = {"kernel": kernel, "workload": workload, "fetch_kib_per_launch": kf,
          "write_kib_per_launch": kw, "copy_fetch_kib": cf, "copy_write_kib": cw,
          "copy_bytes": copy_bytes, "fetch_scale": sf, "write_scale": sw,
@@ -253,8 +264,7 @@ def summarize_util(trace_dir: str, valu_dir: str, fetch_dir: str, write_dir: str
         return float(np.median(c[0])) if c else None
 
     cf, cw = copy_kib(f), copy_kib(w)
-    sf = copy_bytes / (cf * 1024.0) if cf else 1.0
-    sw = copy_bytes / (cw * 1024.0) if cw else 1.0
+    sf, sw = _copy_scales(cf, cw, copy_bytes)
     cnt = {c: by_short(_counter_by_kernel(valu_dir, c)) for c in
            ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FLOPS_FP32")}
 

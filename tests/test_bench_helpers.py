@@ -5,6 +5,8 @@ import sys
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
+import pytest
+
 import bench  # noqa: E402
 
 SRC = """// header comment
@@ -86,3 +88,7 @@ def test_util_summary_from_counters(tmp_path):
     assert cells[2] == "3.0" and cells[3] == "3"
     assert cells[5] == "1000"                      # VALU instructions per wave
     assert cells[7] == "1.00"                      # 1e9 flops in 1 ms = 1 TFLOP/s
+    # counters that hold the calibration copy need its size (else every figure would read 0)
+    with pytest.raises(ValueError):
+        bench.summarize_util(str(tmp_path / "trace"), str(tmp_path / "v"), str(tmp_path / "f"),
+                             str(tmp_path / "w"), str(out), 0, ["cmd"])
